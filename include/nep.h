@@ -1,0 +1,198 @@
+/*
+ * nep.h -- C-ABI of libnep: the neuroevolution-potential (NEP) energy, force
+ * and virial evaluation and the MD step built on it, for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The operation (paper Sec. II.A, Eqs. 2-8; Sec. II.C.1, Eqs. 15-16): given
+ * bead positions, types, an orthorhombic box and NEP parameters, compute the
+ * site energies
+ *     U_i = sum_mu w1_mu tanh(sum_nu w0_mu,nu q^i_nu - b0_mu) - b1       (Eq. 2)
+ * from the radial descriptor q_n = sum_j g_n(r_ij) (Eq. 3) and the 3-body
+ * angular descriptor q_nl = sum_m (-1)^m A_nlm A_nl(-m),
+ * A_nlm = sum_j g_n(r_ij) Y_lm(r_ij) (Eqs. 4-5), with Chebyshev radial
+ * functions and a cosine cutoff (Eqs. 6-8); the forces
+ *     F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji),  r_ij = r_j - r_i,
+ * the per-site virial W_i = sum_j r_ij (x) dU_j/dr_ji (Eq. 15) and the totals
+ * E = sum_i U_i, W = sum_i W_i (Eq. 16).
+ *
+ * Units: nm, eV, amu, fs.  Forces in eV/nm, virials and energies in eV.
+ *
+ * Conventions for every call:
+ *  - Array pointers are DEVICE pointers owned by the caller unless a comment
+ *    says "host".  The library never frees caller memory and allocates device
+ *    memory only in nep_model_create.
+ *  - Work is enqueued on `stream` (a hipStream_t, NULL = default stream) and
+ *    is asynchronous unless the call's comment says it synchronises.
+ *  - Return value: NEP_OK (0) or a negative nep_status.  nep_last_error()
+ *    returns a thread-local message describing the last failure.
+ *  - Calls on distinct streams with distinct buffers may run concurrently.
+ *
+ * Supported hyperparameters: n_max_R = 8, n_max_A = 6, basis_R = basis_A = 8,
+ * l_max = 4 (37 descriptor components; the 4- and 5-body terms are not part
+ * of the descriptor), 1 <= n_hidden <= 64, 1 <= n_types <= 4,
+ * rc_A <= rc_R elementwise.  Others return NEP_ERR_UNSUPPORTED.
+ */
+#ifndef NEP_H
+#define NEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NEP_OK = 0,
+    NEP_ERR_ARG = -1,                /* invalid argument (message says which) */
+    NEP_ERR_HIP = -2,                /* a HIP runtime call failed */
+    NEP_ERR_NEIGHBOR_OVERFLOW = -3,  /* list capacity too small; see status */
+    NEP_ERR_SKIN_VIOLATION = -4,     /* a bead moved more than skin/2 since the build */
+    NEP_ERR_NONFINITE = -5,          /* NaN/Inf position */
+    NEP_ERR_OVERLAP = -6,            /* two beads (or a bead and its image) at distance 0 */
+    NEP_ERR_UNSUPPORTED = -7,        /* hyperparameters or box outside what is built */
+    NEP_ERR_OUTSIDE_BOX = -8         /* periodic coordinate not in [0, L) at a build */
+} nep_status;
+
+/* Bits of status[0] (device word written by the kernels). */
+#define NEP_FLAG_OVERFLOW_R   1
+#define NEP_FLAG_OVERFLOW_A   2
+#define NEP_FLAG_SKIN         4
+#define NEP_FLAG_NONFINITE    8
+#define NEP_FLAG_OUTSIDE_BOX 16
+#define NEP_FLAG_OVERLAP     32
+#define NEP_FLAG_IMAGE_RANGE 64
+#define NEP_FLAG_BAD_TYPE   128
+
+/* ------------------------------------------------------------------------ */
+/* model                                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n_types;        /* number of species (atom or bead types), Sec. II.A, II.C.2 */
+    int n_max_R;        /* radial components are n = 0..n_max_R (Eq. 3) */
+    int n_max_A;        /* angular n = 0..n_max_A (Eq. 5) */
+    int basis_R;        /* N_bas^R: Chebyshev k = 0..basis_R (Eq. 6) */
+    int basis_A;        /* N_bas^A */
+    int l_max;          /* l = 1..l_max (Eq. 4) */
+    int n_hidden;       /* N_neu, tanh neurons (Eq. 2) */
+    const float *rc_R;  /* host [n_types*n_types] radial cutoff per ordered type pair, nm, symmetric */
+    const float *rc_A;  /* host [n_types*n_types] angular cutoff, <= rc_R */
+} nep_hyper;
+
+typedef struct nep_model_t *nep_model;
+
+/* Number of floats in the flat parameter vector:
+ *   w0[t][mu][nu], b0[t][mu], w1[t][mu], b1, cR[ti][tj][n][k], cA[ti][tj][n][k]
+ * with nu = n for radial components and nu = (n_max_R+1) + (l-1)(n_max_A+1) + n
+ * for angular ones.  The coefficients c are indexed by the ordered type pair
+ * (t_i, t_j) of centre and neighbour (the species encoding of Sec. II.A); the
+ * network weights are per centre type, b1 is shared.  Returns 0 on bad input. */
+size_t nep_param_count(const nep_hyper *hyper);
+
+/* Copies the host parameter vector to the device (the only allocation the
+ * library makes).  The model is immutable afterwards and may be shared by
+ * concurrent calls.  Synchronous. */
+int nep_model_create(const nep_hyper *hyper, const float *params_host, size_t n_params,
+                     nep_model *out);
+int nep_model_destroy(nep_model model);
+
+/* ------------------------------------------------------------------------ */
+/* system and neighbour lists                                                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n;                /* number of beads */
+    float *x, *y, *z;     /* device [n] each (SoA).  On periodic dimensions a build
+                             needs 0 <= x < L; an MD step wraps them at rebuilds. */
+    const uint8_t *type;  /* device [n], values < n_types */
+    float box[3];         /* box lengths, nm.  On open dimensions box[d] sets the
+                             extent [0, box[d]) of the cell grid. */
+    int pbc[3];           /* 1 = periodic */
+} nep_system;
+
+/* Neighbour lists within r_c + skin (Sec. II.A "local environment within a
+ * cutoff"), one row per bead, stored slot-major so that lanes of a wavefront
+ * read consecutive beads:
+ *   nbr[p*n + i], p < cnt[i]        entry p of bead i, packed as
+ *                                    j | (code << 25), code = (nx+2) + 5(ny+2) + 25(nz+2)
+ *                                    for the periodic image r_j + (nx Lx, ny Ly, nz Lz)
+ *   the first cnt[n+i] entries      are the angular candidates (within r_c^A + skin),
+ *                                    the rest the radial-only ones
+ *   rev[p*n + i], p < cnt[n+i]      flat index q*n + j of the reverse entry (i in row j),
+ *                                    or -1 when rounding left it out of row j
+ * Rows are in a fixed order (neighbour cells, then index), so every later sum
+ * has one canonical order.  The pair predicate is exact in float32:
+ * s = fl(n*L); dx = fl(fl(x_j + s) - x_i); d2 = fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz));
+ * keep iff d2 < fl32((r_c(t_i,t_j) + skin)^2).                                      */
+typedef struct {
+    int cap;             /* slots per row (all entries) */
+    int cap_A;           /* slots per row for the angular prefix (<= cap) */
+    uint32_t *nbr;       /* device [cap][n] */
+    int32_t *rev;        /* device [cap_A][n] */
+    int32_t *cnt;        /* device [2][n]: cnt[i] all entries, cnt[n+i] angular prefix */
+    float *ref;          /* device [3][n]: positions at the last build (skin check) */
+    float skin;          /* nm */
+    int32_t *status;     /* device [4]: flags, max row length seen, max angular length, spare */
+} nep_neighbors;
+
+/* Device workspace needed by the calls below for n beads and capacities cap,
+ * cap_A.  Contents are scratch; nothing persists between calls. */
+size_t nep_workspace_bytes(nep_model model, int n, int cap, int cap_A);
+
+/* Builds the lists for the current positions (cell lists with cells no smaller
+ * than r_c + skin; images enumerated for boxes smaller than two cells).
+ * Synchronises the stream to read the status word: returns
+ * NEP_ERR_NEIGHBOR_OVERFLOW when a row did not fit (status[1], status[2] hold
+ * the required cap and cap_A; grow the buffers and call again),
+ * NEP_ERR_NONFINITE, NEP_ERR_OUTSIDE_BOX, NEP_ERR_OVERLAP, or
+ * NEP_ERR_UNSUPPORTED when an image beyond +-2 boxes would be needed. */
+int nep_build_neighbors(nep_model model, const nep_system *sys, nep_neighbors *nbrs,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* energy / force / virial (Eqs. 2-8, 15-16)                                 */
+/* ------------------------------------------------------------------------ */
+/* U: device [n] site energies or NULL.  F: device [3][n] (Fx, Fy, Fz planes).
+ * W: device [9][n] per-site virial W_i[a][b] (plane 3a+b) or NULL.
+ * E_tot: device double[1] or NULL.  W_tot: device double[9] or NULL.
+ * Totals are reduced in a fixed order in FP64.  Lists must come from
+ * nep_build_neighbors with the same model and skin.  Asynchronous. */
+int nep_compute_efv(nep_model model, const nep_system *sys, const nep_neighbors *nbrs,
+                    float *U, float *F, float *W, double *E_tot, double *W_tot,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* velocity-Verlet MD                                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    float dt_fs;              /* time step */
+    int n_steps;              /* steps in this call */
+    int rebuild_every;        /* lists are rebuilt when (step+1) % rebuild_every == 0 */
+    float mass[4];            /* amu per type */
+    double strain_rate[3];    /* engineering strain per step: L_d(s) = box0_d (1 + rate_d s) */
+    double box0[3];           /* reference box of the strain */
+    int64_t step;             /* global step counter s; advanced by n_steps (in/out) */
+    int check_status;         /* 1: synchronise at the end and report status errors */
+} nep_md_params;
+
+/* Advances sys by n_steps:  v += dt/2 a(F);  x += dt v;  affine strain;
+ * [wrap + rebuild];  F = F(x);  v += dt/2 a(F),  with a = 9.648533212e-5 F/m
+ * (nm/fs^2 from eV/nm and amu).  On entry F (device [3][n]) must hold the
+ * forces at the current positions and the lists must be valid; on exit both
+ * hold for the final positions.  v: device [3][n] nm/fs.  U: device [n] or
+ * NULL (site energies at the last step).  E_pot / E_kin: device double
+ * [n_steps] traces or NULL.  sys->box and params->step are updated on the
+ * host.  A bead that moves more than skin/2 between rebuilds sets
+ * NEP_FLAG_SKIN (reported as NEP_ERR_SKIN_VIOLATION when check_status). */
+int nep_md_step(nep_model model, nep_system *sys, float *v, nep_md_params *params,
+                nep_neighbors *nbrs, float *F, float *U, double *E_pot, double *E_kin,
+                void *ws, size_t ws_bytes, void *stream);
+
+/* Reads the status word (synchronises the stream) and maps it to a status. */
+int nep_check_status(const nep_neighbors *nbrs, int32_t host_status_out[4], void *stream);
+
+const char *nep_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEP_H */

@@ -1,0 +1,155 @@
+"""ctypes binding of libnep (include/nep.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; PyTorch supplies device
+memory (tensor storage) and the current HIP stream.  If libnep.so is missing
+the import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_void_p
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnep.so")
+
+NEP_OK = 0
+NEP_ERR_ARG = -1
+NEP_ERR_HIP = -2
+NEP_ERR_NEIGHBOR_OVERFLOW = -3
+NEP_ERR_SKIN_VIOLATION = -4
+NEP_ERR_NONFINITE = -5
+NEP_ERR_OVERLAP = -6
+NEP_ERR_UNSUPPORTED = -7
+NEP_ERR_OUTSIDE_BOX = -8
+
+FLAG_OVERFLOW_R, FLAG_OVERFLOW_A, FLAG_SKIN = 1, 2, 4
+FLAG_NONFINITE, FLAG_OUTSIDE_BOX, FLAG_OVERLAP, FLAG_IMAGE_RANGE = 8, 16, 32, 64
+
+EXPORTS = ["nep_param_count", "nep_model_create", "nep_model_destroy", "nep_workspace_bytes",
+           "nep_build_neighbors", "nep_compute_efv", "nep_md_step", "nep_check_status",
+           "nep_last_error"]
+
+
+class NepError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libnep error {code}: {msg}")
+        self.code = code
+
+
+class Hyper(ctypes.Structure):
+    _fields_ = [("n_types", c_int), ("n_max_R", c_int), ("n_max_A", c_int), ("basis_R", c_int),
+                ("basis_A", c_int), ("l_max", c_int), ("n_hidden", c_int),
+                ("rc_R", POINTER(c_float)), ("rc_A", POINTER(c_float))]
+
+
+class System(ctypes.Structure):
+    _fields_ = [("n", c_int), ("x", c_void_p), ("y", c_void_p), ("z", c_void_p), ("type", c_void_p),
+                ("box", c_float * 3), ("pbc", c_int * 3)]
+
+
+class Neighbors(ctypes.Structure):
+    _fields_ = [("cap", c_int), ("cap_A", c_int), ("nbr", c_void_p), ("rev", c_void_p),
+                ("cnt", c_void_p), ("ref", c_void_p), ("skin", c_float), ("status", c_void_p)]
+
+
+class MdParams(ctypes.Structure):
+    _fields_ = [("dt_fs", c_float), ("n_steps", c_int), ("rebuild_every", c_int), ("mass", c_float * 4),
+                ("strain_rate", c_double * 3), ("box0", c_double * 3), ("step", c_int64),
+                ("check_status", c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libnep.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_01234_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.nep_param_count.argtypes = [POINTER(Hyper)]
+        L.nep_param_count.restype = c_size_t
+        L.nep_model_create.argtypes = [POINTER(Hyper), POINTER(c_float), c_size_t, POINTER(c_void_p)]
+        L.nep_model_create.restype = c_int
+        L.nep_model_destroy.argtypes = [c_void_p]
+        L.nep_model_destroy.restype = c_int
+        L.nep_workspace_bytes.argtypes = [c_void_p, c_int, c_int, c_int]
+        L.nep_workspace_bytes.restype = c_size_t
+        L.nep_build_neighbors.argtypes = [c_void_p, POINTER(System), POINTER(Neighbors), c_void_p, c_size_t, c_void_p]
+        L.nep_build_neighbors.restype = c_int
+        L.nep_compute_efv.argtypes = [c_void_p, POINTER(System), POINTER(Neighbors), c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.nep_compute_efv.restype = c_int
+        L.nep_md_step.argtypes = [c_void_p, POINTER(System), c_void_p, POINTER(MdParams), POINTER(Neighbors),
+                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.nep_md_step.restype = c_int
+        L.nep_check_status.argtypes = [POINTER(Neighbors), POINTER(c_int32), c_void_p]
+        L.nep_check_status.restype = c_int
+        L.nep_last_error.argtypes = []
+        L.nep_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().nep_last_error().decode()
+
+
+def check(code: int):
+    if code != NEP_OK:
+        raise NepError(code, last_error())
+    return code
+
+
+def make_hyper(n_types, n_hidden, rc_R, rc_A, n_max_R=8, n_max_A=6, basis_R=8, basis_A=8, l_max=4):
+    rr = np.ascontiguousarray(np.asarray(rc_R, dtype=np.float32).reshape(-1))
+    ra = np.ascontiguousarray(np.asarray(rc_A, dtype=np.float32).reshape(-1))
+    h = Hyper(n_types, n_max_R, n_max_A, basis_R, basis_A, l_max, n_hidden,
+              rr.ctypes.data_as(POINTER(c_float)), ra.ctypes.data_as(POINTER(c_float)))
+    h._keep = (rr, ra)  # keep the host tables alive with the struct
+    return h
+
+
+def nep_param_count(h: Hyper) -> int:
+    return int(lib().nep_param_count(ctypes.byref(h)))
+
+
+def nep_model_create(h: Hyper, params: np.ndarray) -> int:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    out = c_void_p()
+    check(lib().nep_model_create(ctypes.byref(h), p.ctypes.data_as(POINTER(c_float)), p.size, ctypes.byref(out)))
+    return out.value
+
+
+def nep_model_destroy(model: int) -> None:
+    check(lib().nep_model_destroy(model))
+
+
+def nep_workspace_bytes(model: int, n: int, cap: int, cap_A: int) -> int:
+    return int(lib().nep_workspace_bytes(model, n, cap, cap_A))
+
+
+def nep_build_neighbors(model, sys: System, nb: Neighbors, ws_ptr, ws_bytes, stream) -> int:
+    return lib().nep_build_neighbors(model, ctypes.byref(sys), ctypes.byref(nb), ws_ptr, ws_bytes, stream)
+
+
+def nep_compute_efv(model, sys: System, nb: Neighbors, U, F, W, E_tot, W_tot, ws_ptr, ws_bytes, stream) -> int:
+    return lib().nep_compute_efv(model, ctypes.byref(sys), ctypes.byref(nb), U, F, W, E_tot, W_tot,
+                                 ws_ptr, ws_bytes, stream)
+
+
+def nep_md_step(model, sys: System, v, mp: MdParams, nb: Neighbors, F, U, E_pot, E_kin, ws_ptr, ws_bytes,
+                stream) -> int:
+    return lib().nep_md_step(model, ctypes.byref(sys), v, ctypes.byref(mp), ctypes.byref(nb), F, U, E_pot,
+                             E_kin, ws_ptr, ws_bytes, stream)
+
+
+def nep_check_status(nb: Neighbors, stream):
+    out = (c_int32 * 4)()
+    code = lib().nep_check_status(ctypes.byref(nb), out, stream)
+    return code, list(out)

@@ -1,0 +1,486 @@
+// C-ABI of libnep: argument validation, workspace layout, cell-grid choice and
+// stream-ordered launches.  Declarations and contracts are in include/nep.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nep_internal.h"
+
+using namespace nep;
+
+struct nep_model_t {
+    Model m;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(NEP_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+struct WsLayout {
+    size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
+        cell_list, scan_tmp, total;
+    int ncell_max, nblocks;
+};
+
+WsLayout ws_layout(int T, int n, int cap, int cap_A) {
+    WsLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    L.nblocks = (int)((nn + BLOCK - 1) / BLOCK);
+    L.ncell_max = std::max(64, 2 * n);
+    L.pos4 = take(nn * 16);
+    L.bvec = take(nn * (size_t)T * 48);
+    L.angbuf = take((size_t)std::max(cap_A, 1) * nn * 16);
+    L.fown = take(nn * 16);
+    L.partial = take((size_t)L.nblocks * 16 * sizeof(double));
+    L.U = take(nn * 4);
+    L.cell_id = take(nn * 4);
+    L.cell_count = take((size_t)L.ncell_max * 4);
+    L.cell_start = take((size_t)(L.ncell_max + 1) * 4);
+    L.cell_cursor = take((size_t)L.ncell_max * 4);
+    L.cell_list = take(nn * 4);
+    L.scan_tmp = take((size_t)(L.ncell_max / 1024 + 2) * 4);
+    L.total = off;
+    return L;
+}
+
+template <typename P>
+P *at(void *ws, size_t off) {
+    return reinterpret_cast<P *>(static_cast<char *>(ws) + off);
+}
+
+int check_model(nep_model m) {
+    if (!m || !m->m.d_params) return fail(NEP_ERR_ARG, "model is null");
+    return NEP_OK;
+}
+
+int check_system(const Model &M, const nep_system *s) {
+    if (!s) return fail(NEP_ERR_ARG, "system is null");
+    if (s->n < 0 || s->n > (int)J_MASK) return fail(NEP_ERR_ARG, "n out of range (0 .. 2^25-1)");
+    if (s->n > 0 && (!s->x || !s->y || !s->z || !s->type))
+        return fail(NEP_ERR_ARG, "system arrays are null");
+    for (int d = 0; d < 3; ++d)
+        if (!(s->box[d] > 0.0f) || !std::isfinite(s->box[d]))
+            return fail(NEP_ERR_ARG, "box lengths must be positive and finite");
+    (void)M;
+    return NEP_OK;
+}
+
+int check_nbrs(const nep_system *s, const nep_neighbors *nb) {
+    if (!nb) return fail(NEP_ERR_ARG, "neighbour struct is null");
+    if (nb->cap < 1 || nb->cap_A < 1 || nb->cap_A > nb->cap || nb->cap > 4096)
+        return fail(NEP_ERR_ARG, "need 1 <= cap_A <= cap <= 4096");
+    if ((size_t)nb->cap * (size_t)(s->n > 0 ? s->n : 1) >= (1ull << 31))
+        return fail(NEP_ERR_ARG, "cap * n must stay below 2^31");
+    if (s->n > 0 && (!nb->nbr || !nb->rev || !nb->cnt || !nb->ref || !nb->status))
+        return fail(NEP_ERR_ARG, "neighbour arrays are null");
+    if (!nb->status) return fail(NEP_ERR_ARG, "status is null");
+    if (!(nb->skin >= 0.0f) || !std::isfinite(nb->skin)) return fail(NEP_ERR_ARG, "skin must be >= 0");
+    return NEP_OK;
+}
+
+int check_ws(const Model &M, const nep_system *s, const nep_neighbors *nb, void *ws, size_t bytes,
+             WsLayout &L) {
+    L = ws_layout(M.T, s->n, nb->cap, nb->cap_A);
+    if (!ws) return fail(NEP_ERR_ARG, "workspace is null");
+    if (((uintptr_t)ws) % 256) return fail(NEP_ERR_ARG, "workspace must be 256-byte aligned");
+    if (bytes < L.total)
+        return fail(NEP_ERR_ARG, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    return NEP_OK;
+}
+
+Cut make_cut(const Model &M) {
+    Cut c{};
+    for (int k = 0; k < M.T * M.T; ++k) {
+        c.rcR[k] = M.rcR[k];
+        c.inv_rcR[k] = 1.0f / M.rcR[k];
+        c.rcR2[k] = M.rcR[k] * M.rcR[k];
+        c.rcA[k] = M.rcA[k];
+        c.inv_rcA[k] = 1.0f / M.rcA[k];
+        c.rcA2[k] = M.rcA[k] * M.rcA[k];
+    }
+    return c;
+}
+
+// Cell grid: cells no smaller than (r_c + skin)(1 + 1e-3), so a pair within
+// reach differs by at most one cell index even after float rounding of the
+// cell coordinate; coarsened until the cell count fits the workspace.
+int make_grid(const Model &M, const nep_system *s, float skin, int ncell_max, NbArgs &a) {
+    double reach = 0.0;
+    for (int k = 0; k < M.T * M.T; ++k) reach = std::max(reach, (double)M.rcR[k]);
+    reach += (double)skin;
+    double target = reach * (1.0 + 1e-3);
+    long nc[3];
+    for (int d = 0; d < 3; ++d) {
+        double ext = s->box[d];
+        long c = (long)std::floor(ext / target);
+        nc[d] = std::min(std::max(c, 1L), 4096L);
+    }
+    while (nc[0] * nc[1] * nc[2] > ncell_max) {
+        int big = 0;
+        for (int d = 1; d < 3; ++d)
+            if (nc[d] > nc[big]) big = d;
+        nc[big] = (nc[big] + 1) / 2;
+    }
+    for (int d = 0; d < 3; ++d) {
+        double cs = (double)s->box[d] / (double)nc[d];
+        long m = (long)std::ceil(target / cs);
+        if (m < 1) m = 1;
+        if (!s->pbc[d]) m = std::min(m, nc[d]);
+        if (s->pbc[d] && m > 2)
+            return fail(NEP_ERR_UNSUPPORTED,
+                        "periodic box length below half of r_c + skin needs images beyond +-2");
+        a.nc[d] = (int)nc[d];
+        a.m[d] = (int)m;
+        a.inv_cs[d] = (float)((double)nc[d] / (double)s->box[d]);
+        a.box[d] = s->box[d];
+        a.pbc[d] = s->pbc[d] ? 1 : 0;
+    }
+    a.ncell = (int)(nc[0] * nc[1] * nc[2]);
+    for (int k = 0; k < M.T * M.T; ++k) {
+        double r = (double)M.rcR[k] + (double)skin;
+        double ra = (double)M.rcA[k] + (double)skin;
+        a.list2R[k] = (float)(r * r);
+        a.list2A[k] = (float)(ra * ra);
+    }
+    a.T = M.T;
+    return NEP_OK;
+}
+
+int status_to_code(const int32_t st[4]) {
+    int f = st[0];
+    if (f & NEP_FLAG_NONFINITE) return fail(NEP_ERR_NONFINITE, "non-finite position");
+    if (f & NEP_FLAG_OUTSIDE_BOX)
+        return fail(NEP_ERR_OUTSIDE_BOX, "periodic coordinate outside [0, L) at a neighbour build");
+    if (f & NEP_FLAG_IMAGE_RANGE) return fail(NEP_ERR_UNSUPPORTED, "periodic image beyond +-2 needed");
+    if (f & NEP_FLAG_BAD_TYPE) return fail(NEP_ERR_ARG, "a type value is not below n_types");
+    if (f & (NEP_FLAG_OVERFLOW_R | NEP_FLAG_OVERFLOW_A))
+        return fail(NEP_ERR_NEIGHBOR_OVERFLOW, "neighbour overflow: need cap >= " + std::to_string(st[1]) +
+                                                   ", cap_A >= " + std::to_string(st[2]));
+    if (f & NEP_FLAG_OVERLAP) return fail(NEP_ERR_OVERLAP, "two beads at zero distance");
+    if (f & NEP_FLAG_SKIN)
+        return fail(NEP_ERR_SKIN_VIOLATION, "a bead moved more than skin/2 between rebuilds");
+    return NEP_OK;
+}
+
+int read_status(const nep_neighbors *nb, int32_t out[4], hipStream_t s) {
+    int32_t h[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(h, nb->status, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (out) std::memcpy(out, h, sizeof h);
+    return status_to_code(h);
+}
+
+int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, const WsLayout &L,
+            int clear_status, NbArgs &a) {
+    a = NbArgs{};
+    int rc = make_grid(M, s, nb->skin, L.ncell_max, a);
+    if (rc) return rc;
+    a.n = s->n;
+    a.cap = nb->cap;
+    a.cap_A = nb->cap_A;
+    a.x = s->x;
+    a.y = s->y;
+    a.z = s->z;
+    a.type = s->type;
+    a.pos4 = at<float4>(ws, L.pos4);
+    a.cell_id = at<int32_t>(ws, L.cell_id);
+    a.cell_count = at<int32_t>(ws, L.cell_count);
+    a.cell_start = at<int32_t>(ws, L.cell_start);
+    a.cell_cursor = at<int32_t>(ws, L.cell_cursor);
+    a.cell_list = at<int32_t>(ws, L.cell_list);
+    a.scan_tmp = at<int32_t>(ws, L.scan_tmp);
+    a.nbr = nb->nbr;
+    a.rev = nb->rev;
+    a.cnt = nb->cnt;
+    a.ref = nb->ref;
+    a.status = nb->status;
+    a.clear_status = clear_status;
+    return NEP_OK;
+}
+
+int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, float *U, float *F, float *W,
+               bool want_total_virial, void *ws, const WsLayout &L, hipStream_t st, bool md, float *v,
+               const nep_md_params *mp) {
+    const int n = s->n;
+    EfvArgs a{};
+    a.n = n;
+    a.H = M.H;
+    for (int d = 0; d < 3; ++d) a.box[d] = s->box[d];
+    a.pos4 = at<float4>(ws, L.pos4);
+    a.nbr = nb->nbr;
+    a.cnt = nb->cnt;
+    a.params = M.d_params;
+    a.tab = M.d_tab;
+    a.cut = make_cut(M);
+    a.U = U ? U : at<float>(ws, L.U);
+    a.bvec = at<float4>(ws, L.bvec);
+    a.angbuf = at<float4>(ws, L.angbuf);
+    a.fown = at<float4>(ws, L.fown);
+    size_t lds = ((size_t)M.T * M.H * (ND + 2) + 1 + (size_t)M.T * M.T * TAB_PER_PAIR) * sizeof(float);
+    HIPCHK(launch_efv_main(M.T, a, lds, st));
+    GatherArgs g{};
+    g.n = n;
+    for (int d = 0; d < 3; ++d) g.box[d] = s->box[d];
+    g.pos4 = a.pos4;
+    g.nbr = nb->nbr;
+    g.rev = nb->rev;
+    g.cnt = nb->cnt;
+    g.bvec = a.bvec;
+    g.angbuf = a.angbuf;
+    g.fown = a.fown;
+    g.cut = a.cut;
+    g.U = a.U;
+    g.F = F;
+    g.W = W;
+    g.partial = at<double>(ws, L.partial);
+    if (md) {
+        g.v = v;
+        g.half_dt_accel = 0.5f * mp->dt_fs * ACCEL;
+        for (int t = 0; t < M.T; ++t) {
+            g.inv_mass[t] = 1.0f / mp->mass[t];
+            g.mass[t] = mp->mass[t];
+        }
+    }
+    HIPCHK(launch_efv_gather(M.T, W != nullptr || want_total_virial, md, g, st));
+    return NEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nep_last_error(void) { return g_err.c_str(); }
+
+size_t nep_param_count(const nep_hyper *h) {
+    if (!h || h->n_types < 1 || h->n_hidden < 1 || h->n_max_R < 0 || h->n_max_A < 0 || h->basis_R < 0 ||
+        h->basis_A < 0 || h->l_max < 1)
+        return 0;
+    size_t T = h->n_types, H = h->n_hidden;
+    size_t nR = h->n_max_R + 1, nA = h->n_max_A + 1;
+    size_t D = nR + nA * h->l_max;
+    return T * H * D + 2 * T * H + 1 + T * T * nR * (h->basis_R + 1) + T * T * nA * (h->basis_A + 1);
+}
+
+int nep_model_create(const nep_hyper *h, const float *params, size_t n_params, nep_model *out) {
+    if (!h || !params || !out) return fail(NEP_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (h->n_types < 1 || h->n_types > MAXT) return fail(NEP_ERR_UNSUPPORTED, "n_types must be 1..4");
+    if (h->n_max_R != NR - 1 || h->n_max_A != NA - 1 || h->basis_R != KB - 1 || h->basis_A != KB - 1 ||
+        h->l_max != 4)
+        return fail(NEP_ERR_UNSUPPORTED, "built for n_max_R=8, n_max_A=6, basis_R=basis_A=8, l_max=4");
+    if (h->n_hidden < 1 || h->n_hidden > MAXH) return fail(NEP_ERR_UNSUPPORTED, "n_hidden must be 1..64");
+    if (!h->rc_R || !h->rc_A) return fail(NEP_ERR_ARG, "cutoff tables are null");
+    size_t need = nep_param_count(h);
+    if (n_params != need)
+        return fail(NEP_ERR_ARG, "parameter vector has " + std::to_string(n_params) + " floats, expected " +
+                                     std::to_string(need));
+    const int T = h->n_types, H = h->n_hidden;
+    for (int a = 0; a < T; ++a)
+        for (int b = 0; b < T; ++b) {
+            float r = h->rc_R[a * T + b], ra = h->rc_A[a * T + b];
+            if (!(r > 0.0f) || !std::isfinite(r) || !(ra > 0.0f) || !std::isfinite(ra))
+                return fail(NEP_ERR_ARG, "cutoffs must be positive and finite");
+            if (r != h->rc_R[b * T + a] || ra != h->rc_A[b * T + a])
+                return fail(NEP_ERR_ARG, "cutoff tables must be symmetric");
+            if (ra > r) return fail(NEP_ERR_UNSUPPORTED, "angular cutoff above the radial one");
+        }
+    for (size_t k = 0; k < n_params; ++k)
+        if (!std::isfinite(params[k])) return fail(NEP_ERR_ARG, "non-finite parameter");
+    // derived coefficient tables per ordered type pair:
+    //   cR'[n][k], cA'[n][k]: k = 0 entry is c_n0 + sum_k c_nk  (f_k = hfc (T_k + 1))
+    //   cA_d[n][k-1] = k c_nk                                    (T_k' = k U_{k-1})
+    const size_t D = ND;
+    const float *cR = params + (size_t)T * H * D + 2 * (size_t)T * H + 1;
+    const float *cA = cR + (size_t)T * T * NR * KB;
+    std::vector<float> tab((size_t)T * T * TAB_PER_PAIR);
+    for (int tp = 0; tp < T * T; ++tp) {
+        float *o = tab.data() + (size_t)tp * TAB_PER_PAIR;
+        const float *r = cR + (size_t)tp * NR * KB;
+        const float *ang = cA + (size_t)tp * NA * KB;
+        for (int q = 0; q < NR; ++q) {
+            double s = 0.0;
+            for (int k = 0; k < KB; ++k) s += r[q * KB + k];
+            o[q * KB] = (float)((double)r[q * KB] + s);
+            for (int k = 1; k < KB; ++k) o[q * KB + k] = r[q * KB + k];
+        }
+        float *oa = o + NR * KB;
+        float *od = oa + NA * KB;
+        for (int q = 0; q < NA; ++q) {
+            double s = 0.0;
+            for (int k = 0; k < KB; ++k) s += ang[q * KB + k];
+            oa[q * KB] = (float)((double)ang[q * KB] + s);
+            for (int k = 1; k < KB; ++k) {
+                oa[q * KB + k] = ang[q * KB + k];
+                od[q * (KB - 1) + k - 1] = (float)k * ang[q * KB + k];
+            }
+        }
+    }
+    nep_model_t *m = new nep_model_t();
+    m->m.T = T;
+    m->m.H = H;
+    for (int k = 0; k < T * T; ++k) {
+        m->m.rcR[k] = h->rc_R[k];
+        m->m.rcA[k] = h->rc_A[k];
+    }
+    m->m.n_params = n_params;
+    hipError_t e = hipGetDevice(&m->m.device);
+    if (e == hipSuccess) e = hipMalloc(&m->m.d_params, n_params * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m->m.d_tab, tab.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(m->m.d_params, params, n_params * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->m.d_tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (m->m.d_params) (void)hipFree(m->m.d_params);
+        if (m->m.d_tab) (void)hipFree(m->m.d_tab);
+        delete m;
+        return fail(NEP_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
+    }
+    *out = m;
+    return NEP_OK;
+}
+
+int nep_model_destroy(nep_model m) {
+    if (!m) return NEP_OK;
+    if (m->m.d_params) (void)hipFree(m->m.d_params);
+    if (m->m.d_tab) (void)hipFree(m->m.d_tab);
+    delete m;
+    return NEP_OK;
+}
+
+size_t nep_workspace_bytes(nep_model m, int n, int cap, int cap_A) {
+    if (!m || n < 0) return 0;
+    return ws_layout(m->m.T, n, cap, cap_A).total;
+}
+
+int nep_build_neighbors(nep_model model, const nep_system *s, nep_neighbors *nb, void *ws, size_t ws_bytes,
+                        void *stream) {
+    int rc;
+    if ((rc = check_model(model))) return rc;
+    const Model &M = model->m;
+    if ((rc = check_system(M, s))) return rc;
+    if ((rc = check_nbrs(s, nb))) return rc;
+    WsLayout L;
+    if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    NbArgs a;
+    if ((rc = fill_nb(M, s, nb, ws, L, 1, a))) return rc;
+    HIPCHK(launch_build(a, st));
+    return read_status(nb, nullptr, st);
+}
+
+int nep_compute_efv(nep_model model, const nep_system *s, const nep_neighbors *nb, float *U, float *F,
+                    float *W, double *E_tot, double *W_tot, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_model(model))) return rc;
+    const Model &M = model->m;
+    if ((rc = check_system(M, s))) return rc;
+    if ((rc = check_nbrs(s, nb))) return rc;
+    if (s->n > 0 && !F) return fail(NEP_ERR_ARG, "F is null");
+    WsLayout L;
+    if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (s->n > 0) {
+        HIPCHK(launch_pack(s->n, M.T, s->x, s->y, s->z, s->type, at<float4>(ws, L.pos4), st));
+        if ((rc = launch_efv(M, s, nb, U, F, W, W_tot != nullptr, ws, L, st, false, nullptr, nullptr))) return rc;
+    }
+    // an empty system reduces zero blocks, so the totals come out as zero
+    if (E_tot || W_tot)
+        HIPCHK(launch_reduce(at<double>(ws, L.partial), s->n > 0 ? L.nblocks : 0, E_tot, W_tot, nullptr, nullptr,
+                             nullptr, st));
+    return NEP_OK;
+}
+
+int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep_neighbors *nb, float *F,
+                float *U, double *E_pot, double *E_kin, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_model(model))) return rc;
+    const Model &M = model->m;
+    if ((rc = check_system(M, s))) return rc;
+    if ((rc = check_nbrs(s, nb))) return rc;
+    if (!mp) return fail(NEP_ERR_ARG, "md params are null");
+    if (s->n > 0 && (!F || !v)) return fail(NEP_ERR_ARG, "F and v must not be null");
+    if (!(mp->dt_fs > 0.0f) || mp->n_steps < 0 || mp->rebuild_every < 1)
+        return fail(NEP_ERR_ARG, "need dt > 0, n_steps >= 0, rebuild_every >= 1");
+    for (int t = 0; t < M.T; ++t)
+        if (!(mp->mass[t] > 0.0f)) return fail(NEP_ERR_ARG, "masses must be positive");
+    WsLayout L;
+    if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int n = s->n;
+    if (n == 0) {
+        mp->step += mp->n_steps;
+        return NEP_OK;
+    }
+    if (mp->check_status) HIPCHK(launch_clear_status(nb->status, st));
+    for (int k = 0; k < mp->n_steps; ++k) {
+        const int64_t step = mp->step;
+        KickDriftArgs kd{};
+        kd.n = n;
+        kd.x = s->x;
+        kd.y = s->y;
+        kd.z = s->z;
+        kd.v = v;
+        kd.F = F;
+        kd.type = s->type;
+        kd.pos4 = at<float4>(ws, L.pos4);
+        kd.ref = nb->ref;
+        kd.half_dt_accel = 0.5f * mp->dt_fs * ACCEL;
+        kd.dt = mp->dt_fs;
+        kd.T = M.T;
+        for (int t = 0; t < M.T; ++t) kd.inv_mass[t] = 1.0f / mp->mass[t];
+        for (int d = 0; d < 3; ++d) {
+            kd.lam[d] = 1.0f;
+            if (mp->strain_rate[d] != 0.0) {
+                double Lo = mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)step);
+                double Ln = mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)(step + 1));
+                kd.lam[d] = (float)(Ln / Lo);
+                s->box[d] = (float)Ln;
+            }
+            kd.box[d] = s->box[d];
+            kd.pbc[d] = s->pbc[d] ? 1 : 0;
+        }
+        const bool rebuild = ((step + 1) % mp->rebuild_every) == 0;
+        kd.wrap = rebuild ? 1 : 0;
+        kd.half_skin2 = 0.25f * nb->skin * nb->skin;
+        kd.status = nb->status;
+        HIPCHK(launch_kick_drift(kd, st));
+        if (rebuild) {
+            NbArgs a;
+            if ((rc = fill_nb(M, s, nb, ws, L, 0, a))) return rc;
+            HIPCHK(launch_build(a, st));
+        }
+        if ((rc = launch_efv(M, s, nb, U, F, nullptr, false, ws, L, st, true, v, mp))) return rc;
+        HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
+                             E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr, st));
+        mp->step = step + 1;
+    }
+    if (mp->check_status) return read_status(nb, nullptr, st);
+    return NEP_OK;
+}
+
+int nep_check_status(const nep_neighbors *nb, int32_t out[4], void *stream) {
+    if (!nb || !nb->status) return fail(NEP_ERR_ARG, "status is null");
+    return read_status(nb, out, (hipStream_t)stream);
+}
+
+}  // extern "C"

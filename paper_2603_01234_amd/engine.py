@@ -1,0 +1,215 @@
+"""Device-resident systems on top of the C-ABI.
+
+PyTorch is used only to own device memory and to hand the current HIP stream to
+libnep; every step of the NEP evaluation, the neighbour build and the
+integrator runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+class Model:
+    """An immutable NEP model on the current device."""
+
+    def __init__(self, n_types: int, n_hidden: int, rc_R, rc_A, params: np.ndarray):
+        self.n_types = int(n_types)
+        self.n_hidden = int(n_hidden)
+        self.rc_R = np.asarray(rc_R, dtype=np.float32).reshape(n_types, n_types)
+        self.rc_A = np.asarray(rc_A, dtype=np.float32).reshape(n_types, n_types)
+        self.hyper = B.make_hyper(n_types, n_hidden, self.rc_R, self.rc_A)
+        self.params = np.ascontiguousarray(params, dtype=np.float32)
+        self.handle = B.nep_model_create(self.hyper, self.params)
+
+    @classmethod
+    def from_spec(cls, spec, params):
+        return cls(spec.n_types, spec.n_hidden, spec.rc_R, spec.rc_A, params)
+
+    def close(self):
+        if self.handle:
+            B.nep_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def estimate_caps(n, box, pbc, rc_max, rcA_max, skin, pos=None):
+    """Row capacities from the mean density with head-room; overflow grows them."""
+    vol = float(np.prod(box))
+    if pos is not None and not all(pbc):
+        ext = np.ptp(pos, axis=0) + 1e-3
+        for d in range(3):
+            if not pbc[d]:
+                vol = vol / box[d] * max(ext[d], 1.0)
+    rho = n / max(vol, 1e-9)
+    cap = int(1.6 * rho * 4.0 / 3.0 * math.pi * (rc_max + skin) ** 3) + 16
+    cap_A = int(1.6 * rho * 4.0 / 3.0 * math.pi * (rcA_max + skin) ** 3) + 16
+    return max(cap, 8), max(min(cap_A, cap), 4)
+
+
+class Replica:
+    """One system resident on the device: positions, velocities, forces, lists, workspace."""
+
+    def __init__(self, model: Model, pos: np.ndarray, types: np.ndarray, box, pbc, skin: float = 0.1,
+                 vel: Optional[np.ndarray] = None, cap: Optional[int] = None, cap_A: Optional[int] = None,
+                 device: str = "cuda"):
+        self.model = model
+        self.device = torch.device(device)
+        pos = np.asarray(pos, dtype=np.float32).reshape(-1, 3)
+        self.n = pos.shape[0]
+        self.box0 = np.asarray(box, dtype=np.float64).copy()
+        self.box = np.asarray(box, dtype=np.float32).copy()
+        self.pbc = [int(bool(p)) for p in pbc]
+        self.skin = float(skin)
+        dev = self.device
+        n = max(self.n, 1)
+        self.xyz = torch.zeros((3, n), dtype=torch.float32, device=dev)
+        if self.n:
+            self.xyz[:, :self.n] = torch.from_numpy(np.ascontiguousarray(pos.T)).to(dev)
+        self.type = torch.zeros(n, dtype=torch.uint8, device=dev)
+        if self.n:
+            self.type[:self.n] = torch.from_numpy(np.asarray(types, dtype=np.uint8)).to(dev)
+        self.v = torch.zeros((3, n), dtype=torch.float32, device=dev)
+        if vel is not None and self.n:
+            self.v[:, :self.n] = torch.from_numpy(np.ascontiguousarray(np.asarray(vel, np.float32).T)).to(dev)
+        self.F = torch.zeros((3, n), dtype=torch.float32, device=dev)
+        self.U = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.W = None
+        self.E_tot = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.W_tot = torch.zeros(9, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(4, dtype=torch.int32, device=dev)
+        self.ref = torch.zeros((3, n), dtype=torch.float32, device=dev)
+        self.cnt = torch.zeros((2, n), dtype=torch.int32, device=dev)
+        if cap is None or cap_A is None:
+            c, ca = estimate_caps(self.n, self.box, self.pbc, float(model.rc_R.max()), float(model.rc_A.max()),
+                                  self.skin, pos)
+            cap = cap or c
+            cap_A = cap_A or ca
+        self._alloc_lists(cap, cap_A)
+        self.step = 0
+        self.lists_valid = False
+
+    # -- buffers ----------------------------------------------------------------
+    def _alloc_lists(self, cap, cap_A):
+        n = max(self.n, 1)
+        self.cap, self.cap_A = int(cap), int(min(cap_A, cap))
+        self.nbr = torch.zeros((self.cap, n), dtype=torch.int32, device=self.device)
+        self.rev = torch.zeros((self.cap_A, n), dtype=torch.int32, device=self.device)
+        self.ws_bytes = B.nep_workspace_bytes(self.model.handle, self.n, self.cap, self.cap_A)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def c_system(self) -> B.System:
+        s = B.System()
+        s.n = self.n
+        s.x, s.y, s.z = self.xyz[0].data_ptr(), self.xyz[1].data_ptr(), self.xyz[2].data_ptr()
+        s.type = self.type.data_ptr()
+        for d in range(3):
+            s.box[d] = float(self.box[d])
+            s.pbc[d] = self.pbc[d]
+        return s
+
+    def c_neighbors(self) -> B.Neighbors:
+        nb = B.Neighbors()
+        nb.cap, nb.cap_A = self.cap, self.cap_A
+        nb.nbr, nb.rev, nb.cnt, nb.ref = (self.nbr.data_ptr(), self.rev.data_ptr(), self.cnt.data_ptr(),
+                                          self.ref.data_ptr())
+        nb.skin = self.skin
+        nb.status = self.status.data_ptr()
+        return nb
+
+    # -- calls ------------------------------------------------------------------
+    def build(self, max_tries: int = 4):
+        """nep_build_neighbors, growing the row capacities after an overflow."""
+        for _ in range(max_tries):
+            s, nb = self.c_system(), self.c_neighbors()
+            code = B.nep_build_neighbors(self.model.handle, s, nb, self.ws.data_ptr(), self.ws_bytes, _stream())
+            if code == B.NEP_ERR_NEIGHBOR_OVERFLOW:
+                st = self.status.cpu().tolist()
+                self._alloc_lists(max(self.cap, int(st[1] * 1.2) + 8), max(self.cap_A, int(st[2] * 1.2) + 8))
+                continue
+            B.check(code)
+            self.lists_valid = True
+            return
+        raise B.NepError(B.NEP_ERR_NEIGHBOR_OVERFLOW, "capacity growth did not converge")
+
+    def efv(self, per_bead_virial: bool = True):
+        if not self.lists_valid:
+            self.build()
+        if per_bead_virial and self.W is None:
+            self.W = torch.zeros((9, max(self.n, 1)), dtype=torch.float32, device=self.device)
+        s, nb = self.c_system(), self.c_neighbors()
+        B.check(B.nep_compute_efv(self.model.handle, s, nb, _ptr(self.U), _ptr(self.F),
+                                  _ptr(self.W) if per_bead_virial else None, _ptr(self.E_tot), _ptr(self.W_tot),
+                                  self.ws.data_ptr(), self.ws_bytes, _stream()))
+        return self
+
+    def md(self, n_steps: int, dt: float, masses: Sequence[float], rebuild_every: int = 10,
+           strain_rate=(0.0, 0.0, 0.0), E_pot: Optional[torch.Tensor] = None,
+           E_kin: Optional[torch.Tensor] = None, check_status: bool = True):
+        mp = B.MdParams()
+        mp.dt_fs = float(dt)
+        mp.n_steps = int(n_steps)
+        mp.rebuild_every = int(rebuild_every)
+        for t in range(4):
+            mp.mass[t] = float(masses[t]) if t < len(masses) else 1.0
+        for d in range(3):
+            mp.strain_rate[d] = float(strain_rate[d])
+            mp.box0[d] = float(self.box0[d])
+        mp.step = int(self.step)
+        mp.check_status = int(check_status)
+        s, nb = self.c_system(), self.c_neighbors()
+        code = B.nep_md_step(self.model.handle, s, _ptr(self.v), mp, nb, _ptr(self.F), _ptr(self.U),
+                             _ptr(E_pot), _ptr(E_kin), self.ws.data_ptr(), self.ws_bytes, _stream())
+        self.step = int(mp.step)
+        for d in range(3):
+            self.box[d] = s.box[d]
+        B.check(code)
+        return self
+
+    # -- host views ---------------------------------------------------------------
+    def positions(self) -> np.ndarray:
+        return self.xyz[:, :self.n].T.contiguous().cpu().numpy()
+
+    def forces(self) -> np.ndarray:
+        return self.F[:, :self.n].T.contiguous().cpu().numpy()
+
+    def velocities(self) -> np.ndarray:
+        return self.v[:, :self.n].T.contiguous().cpu().numpy()
+
+    def site_energies(self) -> np.ndarray:
+        return self.U[:self.n].cpu().numpy()
+
+    def virials(self) -> np.ndarray:
+        return self.W[:, :self.n].T.contiguous().cpu().numpy().reshape(-1, 3, 3)
+
+    def neighbor_rows(self):
+        """Host copy of the lists: (entries [cap, n] uint32, counts [2, n])."""
+        return (self.nbr.cpu().numpy().view(np.uint32), self.cnt.cpu().numpy())
+
+
+def decode_row(entries: np.ndarray):
+    e = entries.astype(np.uint64)
+    j = (e & 0x1FFFFFF).astype(np.int64)
+    code = (e >> 25).astype(np.int64)
+    nx = code % 5 - 2
+    ny = (code // 5) % 5 - 2
+    nz = code // 25 - 2
+    return j, nx, ny, nz

@@ -1,0 +1,106 @@
+"""Velocity-Verlet MD through nep_md_step against the FP64 oracle (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import compare_efv
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _rep(spec, params, system, skin=0.1):
+    from paper_2603_01234_amd import engine as E
+    model = E.Model.from_spec(spec, params)
+    rep = E.Replica(model, system.pos_f32(), system.types, system.box, system.pbc, skin=skin, vel=system.vel)
+    rep._keep = model
+    return rep
+
+
+def test_md_config0_tracks_oracle():
+    """512 beads from rest, dt = 2 fs, 100 steps: energies per step and final
+    state against the FP64 oracle integrating the same equations."""
+    spec, params, system, opts = W.config0()
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv()
+    n_steps = opts["steps"]
+    Ep = torch.zeros(n_steps, dtype=torch.float64, device="cuda")
+    Ek = torch.zeros(n_steps, dtype=torch.float64, device="cuda")
+    rep.md(n_steps, opts["dt"], [W.WATER_MASS], rebuild_every=opts["rebuild_every"], E_pot=Ep, E_kin=Ek)
+    Ep, Ek = Ep.cpu().numpy(), Ek.cpu().numpy()
+    p32 = system.pos_f32().astype(np.float64)
+    pos, vel, F, box, Epo, Eko = oracle.md(spec, params.astype(np.float32).astype(np.float64), p32,
+                                           np.zeros_like(p32), system.types, [W.WATER_MASS], system.box.astype(np.float32),
+                                           system.pbc, opts["dt"], n_steps)
+    n = system.n
+    dE = np.abs(Ep - Epo).max() / n
+    dK = np.abs(Ek - Eko).max() / n
+    # unwrap the GPU positions the same way as the oracle's (the oracle never wraps)
+    L = system.box.astype(np.float32).astype(np.float64)
+    dpos = rep.positions().astype(np.float64) - pos
+    dpos -= L * np.round(dpos / L)
+    print(f"md config0: max |dE_pot|/N {dE:.2e}, |dE_kin|/N {dK:.2e}, max |dx| {np.abs(dpos).max():.2e}")
+    assert dE < 1e-5 and dK < 1e-5
+    assert np.abs(dpos).max() < 1e-4
+    # energy conservation: the FP32 run stays within the oracle's envelope
+    env_gpu = np.abs((Ep + Ek) - (Ep[0] + Ek[0])).max()
+    env_or = np.abs((Epo + Eko) - (Epo[0] + Eko[0])).max()
+    print(f"energy envelope: gpu {env_gpu:.3e} eV, oracle {env_or:.3e} eV")
+    assert env_gpu <= 2.0 * env_or + 1e-6 * n
+
+
+def test_md_is_bitwise_reproducible():
+    spec, params, system, opts = W.config0()
+    outs = []
+    for _ in range(2):
+        rep = _rep(spec, params, system, opts["skin"])
+        rep.efv()
+        rep.md(30, opts["dt"], [W.WATER_MASS], rebuild_every=10)
+        outs.append((rep.xyz.clone(), rep.v.clone(), rep.F.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+
+
+def test_md_config1_short_run_then_sampled_parity():
+    """The timed workload (216,000 beads, rebuild every 10 steps, 0.1 nm skin):
+    20 steps, then the final forces against the oracle on sampled beads."""
+    spec, params, system, opts = W.config1()
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv(per_bead_virial=False)
+    rep.md(20, opts["dt"], [W.WATER_MASS], rebuild_every=opts["rebuild_every"])
+    targets = np.random.default_rng(3).choice(system.n, 150, replace=False)
+    pos = rep.positions().astype(np.float64)
+    ref = oracle.efv(spec, params.astype(np.float32).astype(np.float64), pos, system.types,
+                     system.box.astype(np.float32).astype(np.float64), system.pbc, targets=targets)
+    compare_efv(rep, ref, system.n, check_virial=False, targets=targets, label="config1-md20")
+
+
+def test_md_strain_updates_box_and_stays_consistent():
+    """Affine engineering strain along z (the nanowire loading): the box follows
+    L(s) = L0 (1 + rate s) and forces at the end match the oracle."""
+    rng = np.random.default_rng(12)
+    spec = W.aacg_gold_spec(50)
+    params = W.draw_params(spec, rng)
+    seq = np.random.SeedSequence(99)
+    wire = W.gold_nanowire(seq, n_target=6000, core_radius=0.9)
+    rep = _rep(spec, params, wire, 0.1)
+    rep.efv(per_bead_virial=False)
+    rate = 1e-4
+    rep.md(25, 5.0, wire.masses, rebuild_every=10, strain_rate=(0.0, 0.0, rate))
+    assert abs(rep.box[2] - np.float32(wire.box[2] * (1 + rate * 25))) <= 1e-5 * wire.box[2]
+    targets = rng.choice(wire.n, 150, replace=False)
+    ref = oracle.efv(spec, params.astype(np.float32).astype(np.float64), rep.positions().astype(np.float64),
+                     wire.types, np.asarray(rep.box, np.float32).astype(np.float64), wire.pbc, targets=targets)
+    compare_efv(rep, ref, wire.n, check_virial=False, targets=targets, label="wire-strained")
+
+
+def test_skin_violation_is_reported():
+    from paper_2603_01234_amd import binding as B
+    spec, params, system, opts = W.config0()
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv()
+    rep.v[0, 5] = 0.05          # 0.1 nm per 2 fs step: beyond skin/2 after one step
+    with pytest.raises(B.NepError) as ei:
+        rep.md(3, 2.0, [W.WATER_MASS], rebuild_every=10)
+    assert ei.value.code == B.NEP_ERR_SKIN_VIOLATION
