@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the NEP energy/force/virial MD path on one MI355X.
+
+Workload (one "step" = one full pass of the hot path): velocity-Verlet MD of
+the 216,000-bead CG water-like box (60^3 jittered simple-cubic lattice at
+33.4 beads/nm^3, Maxwell 300 K), NEP with radial/angular cutoffs 0.8/0.5 nm,
+Chebyshev basis 8, n_max 8/6, l_max 4, 30 tanh neurons, random N(0, 0.1^2)
+weights; dt = 2 fs, 18 amu; neighbour lists rebuilt every 10 steps on a
+0.1 nm skin.  Each step: half-kick + drift, [wrap + rebuild], fused
+descriptor/network/angular-force kernel, gather kernel (forces + second
+half-kick + energy sums), FP64 energy reduction.
+
+Prints ONE JSON line.  `value` is bead-steps/s with every input resident in
+HBM.  The roofline entry prices the dominant kernel's algorithmic FP32 work,
+timed with HIP events on its own stream inside the timed region.  The CPU
+baseline is the FP64 oracle (the correctness reference, not a tuned CPU code)
+on one full force evaluation of the same snapshot.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NEP force-eval bead-steps/s at 1 GPU; batched/served vs plain; p50/p99 ms"
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector, published
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops(nR: np.ndarray, nA: np.ndarray, H: int, T: int):
+    """Per-kernel split of the fixed accounting convention (FMA = 2 flops):
+         radial pair   2 nR KR + 11 KR + 60, angular pair 4 nA KA + 6 nA L + 14 L + 9 KA + 60,
+         per bead      4 H Ndes + 6 H + 4 nA L + 2 nR KR T.
+    The fused kernel owns the descriptor sums (2 nR KR + 4 KR + 20 per radial pair),
+    every angular and per-bead term; the gather kernel the radial derivatives,
+    force and virial (7 KR + 40 per radial pair)."""
+    n_R, K_R, n_A, K_A, L, N_des = 9, 9, 7, 9, 24, 37
+    rad_main = 2 * n_R * K_R + 4 * K_R + 20
+    rad_gather = 7 * K_R + 40
+    ang = 4 * n_A * K_A + 6 * n_A * L + 14 * L + 9 * K_A + 60
+    bead = 4 * H * N_des + 6 * H + 4 * n_A * L + 2 * n_R * K_R * T
+    main = float(nR.sum()) * rad_main + float(nA.sum()) * ang + nR.size * bead
+    gather = float(nR.sum()) * rad_gather
+    return main, gather
+
+
+def pair_counts(rep, spec):
+    """Neighbours within r_c (not r_c + skin) per bead, from the device lists."""
+    from paper_2603_01234_amd.engine import decode_row
+    nbr, cnt = rep.neighbor_rows()
+    pos = rep.positions().astype(np.float64)
+    box = np.asarray(rep.box, np.float64)
+    n = rep.n
+    nR = np.zeros(n, np.int64)
+    nA = np.zeros(n, np.int64)
+    rcR = float(spec.rc_R.max())
+    rcA = float(spec.rc_A.max())
+    chunk = 16
+    for p0 in range(0, nbr.shape[0], chunk):
+        rows = nbr[p0:p0 + chunk]                       # (c, n)
+        slot = np.arange(p0, p0 + rows.shape[0])[:, None]
+        valid = slot < cnt[0][None, :]
+        j, nx, ny, nz = decode_row(rows)
+        j = np.where(valid, j, np.arange(n)[None, :])
+        d = np.stack([pos[j, 0] + nx * box[0], pos[j, 1] + ny * box[1], pos[j, 2] + nz * box[2]], -1)
+        d -= pos[None, :, :]
+        r = np.sqrt((d * d).sum(-1))
+        nR += (valid & (r < rcR)).sum(0)
+        nA += (valid & (slot < cnt[1][None, :]) & (r < rcA)).sum(0)
+    return nR, nA
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("efv.hip", "nep_internal.h"):
+        with open(os.path.join(ROOT, "paper_2603_01234_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(n_launch_units: int):
+    """HBM bytes per launch of the fused kernel from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "efv_main_config1_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        c = json.load(f)
+    if c.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(spec, params, system, pos, min_seconds=10.0):
+    import oracle
+    p64 = params.astype(np.float32).astype(np.float64)
+    box = system.box.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.efv(spec, p64, pos, system.types, box, system.pbc)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds or reps >= 3:
+            break
+    return {"value": system.n * reps / el, "unit": "bead-steps/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} full FP64 force evaluation(s) of the 216,000-bead snapshot after warm-up "
+                      f"({el:.1f} s wall); the MD update itself is negligible"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy (reference for the HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2603_01234_amd import binding as B
+    from paper_2603_01234_amd import engine
+
+    torch.cuda.set_device(0)
+    spec, params, system, opts = W.config1()
+    model = engine.Model.from_spec(spec, params)
+    rep = engine.Replica(model, system.pos_f32(), system.types, system.box, system.pbc,
+                         skin=opts["skin"], vel=system.vel)
+    rep.efv(per_bead_virial=False)          # lists + forces at t = 0
+    masses = [W.WATER_MASS]
+    dt, every = opts["dt"], opts["rebuild_every"]
+    if args.warmup:
+        rep.md(args.warmup, dt, masses, rebuild_every=every)
+    torch.cuda.synchronize()
+    nR, nA = pair_counts(rep, spec)          # neighbours within the cutoffs at the start of the timed run
+    print(f"bench: N={system.n}, mean neighbours within r_c: radial {nR.mean():.2f}, angular {nA.mean():.2f}",
+          file=sys.stderr, flush=True)
+
+    # row capacities with head-room for the density fluctuations of the run
+    st = rep.status.cpu().tolist()
+    rep._alloc_lists(max(rep.cap, int(st[1] * 1.5) + 16), max(rep.cap_A, int(st[2] * 1.5) + 16))
+    rep.build()
+    K = args.steps
+    counts = torch.zeros(2, dtype=torch.float64, device="cuda")
+    B.nep_timing_begin(8 * K + 64)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    rb0 = rep.n_rebuilds
+    rep.md(K, dt, masses, rebuild_every=every, pair_counts=counts)
+    rebuilds = rep.n_rebuilds - rb0
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms, launches = B.nep_timing_end()
+    elapsed = max(wall, gpu_ms / 1e3)
+    value = system.n * K / elapsed
+    ms_step = elapsed * 1e3 / K
+    # algorithmic work of the timed region from the pairs the kernels evaluated
+    tot_R, tot_A = counts.cpu().numpy().tolist()
+    nR_run = np.full(system.n, tot_R / (K * system.n))
+    nA_run = np.full(system.n, tot_A / (K * system.n))
+    f_main, f_gather = algorithmic_flops(nR_run, nA_run, spec.n_hidden, spec.n_types)
+    main_ms = ms[0] / max(launches[0], 1)
+    achieved = f_main / (main_ms * 1e-3) / 1e12
+    traffic = load_traffic(system.n)
+    F_alg_bead = (f_main + f_gather) / system.n
+    roofline = {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+        "kernel": "k_efv_main<1> (fused descriptor + network + angular pair forces)",
+        "flops_per_launch": f_main, "avg_launch_ms": round(main_ms, 4),
+    }
+    kernels = {name: {"avg_ms": round(ms[c] / max(launches[c], 1), 4), "launches": launches[c]}
+               for c, name in enumerate(["efv_main", "efv_gather", "neighbor_build", "kick_drift"])}
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "bead-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "config1 CG water-like MD, 216,000 beads, NEP H=30 rc 0.8/0.5 nm, dt 2 fs, "
+                               "rebuild every 10 steps, skin 0.1 nm",
+                   "beads": system.n, "ns_per_day": round(K / elapsed * dt * 86400 * 1e-6, 2),
+                   "mean_neighbours_radial_start": round(float(nR.mean()), 3),
+                   "mean_neighbours_angular_start": round(float(nA.mean()), 3),
+                   "mean_neighbours_radial_run": round(tot_R / (K * system.n), 3),
+                   "mean_neighbours_angular_run": round(tot_A / (K * system.n), 3),
+                   "row_capacity": [rep.cap, rep.cap_A],
+                   "rebuilds_in_timed_steps": rebuilds,
+                   "F_alg_per_bead_step": round(F_alg_bead, 1),
+                   "path_tflops_alg": round(value * F_alg_bead / 1e12, 3)},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    if args.copy_calibration:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, params, system, rep.positions().astype(np.float64))
+    model.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

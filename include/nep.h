@@ -166,29 +166,61 @@ int nep_compute_efv(nep_model model, const nep_system *sys, const nep_neighbors 
 typedef struct {
     float dt_fs;              /* time step */
     int n_steps;              /* steps in this call */
-    int rebuild_every;        /* lists are rebuilt when (step+1) % rebuild_every == 0 */
+    int rebuild_every;        /* lists are rebuilt at the end of step s when (s+1) % rebuild_every == 0,
+                                 and earlier whenever a bead could otherwise move more than skin/2 */
     float mass[4];            /* amu per type */
     double strain_rate[3];    /* engineering strain per step: L_d(s) = box0_d (1 + rate_d s) */
     double box0[3];           /* reference box of the strain */
-    int64_t step;             /* global step counter s; advanced by n_steps (in/out) */
-    int check_status;         /* 1: synchronise at the end and report status errors */
+    int64_t step;             /* global step counter s; advanced per completed step (in/out) */
+    int n_rebuilds;           /* out: list rebuilds done by this call */
+    double *pair_counts;      /* device double[2] or NULL: += sum_i N_R(i), sum_i N_A(i) over every
+                                 force evaluation (pairs inside the interaction cutoffs) */
 } nep_md_params;
 
 /* Advances sys by n_steps:  v += dt/2 a(F);  x += dt v;  affine strain;
- * [wrap + rebuild];  F = F(x);  v += dt/2 a(F),  with a = 9.648533212e-5 F/m
+ * F = F(x);  v += dt/2 a(F);  [wrap + rebuild],  with a = 9.648533212e-5 F/m
  * (nm/fs^2 from eV/nm and amu).  On entry F (device [3][n]) must hold the
- * forces at the current positions and the lists must be valid; on exit both
- * hold for the final positions.  v: device [3][n] nm/fs.  U: device [n] or
- * NULL (site energies at the last step).  E_pot / E_kin: device double
- * [n_steps] traces or NULL.  sys->box and params->step are updated on the
- * host.  A bead that moves more than skin/2 between rebuilds sets
- * NEP_FLAG_SKIN (reported as NEP_ERR_SKIN_VIOLATION when check_status). */
+ * forces at the current positions and the lists must be valid for them; on
+ * exit both hold for the final positions.  v: device [3][n] nm/fs.  U: device
+ * [n] or NULL (site energies at the last step).  E_pot / E_kin: device double
+ * [n_steps] traces or NULL.
+ *
+ * Rebuild decisions need no per-step synchronisation: after each step the
+ * gather kernel computes, exactly, how far every bead will be from its
+ * build position after the next drift; the reduction writes the maximum
+ * into pinned host memory, and the host (one step behind the device) adds a
+ * bound for one further drift and schedules a rebuild before the displacement
+ * can reach skin/2.  A real violation is still checked per bead and reported
+ * as NEP_ERR_SKIN_VIOLATION.
+ *
+ * A rebuild that overflows (or finds a bad position) freezes the device state
+ * at the end of the last good step: x, v and F are then consistent, the call
+ * returns the error with params->step advanced by the completed steps, and the
+ * caller regrows the lists (status[1], status[2]), rebuilds and repeats the
+ * call for the remaining steps.  sys->box follows the strain of the completed
+ * steps.  The call synchronises the stream before it returns. */
 int nep_md_step(nep_model model, nep_system *sys, float *v, nep_md_params *params,
                 nep_neighbors *nbrs, float *F, float *U, double *E_pot, double *E_kin,
                 void *ws, size_t ws_bytes, void *stream);
 
 /* Reads the status word (synchronises the stream) and maps it to a status. */
 int nep_check_status(const nep_neighbors *nbrs, int32_t host_status_out[4], void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* kernel timing (benchmark support)                                         */
+/* ------------------------------------------------------------------------ */
+/* While enabled, the library records a HIP event pair on the launching stream
+ * around every launch of its kernels, by class: 0 = fused descriptor /
+ * network / angular-force kernel, 1 = gather (forces, virial, half-kick),
+ * 2 = neighbour build (all of its kernels), 3 = first half-kick + drift.
+ * nep_timing_begin(max_launches) creates the event pool (host-side objects
+ * only) and enables recording for the calling process; launches beyond the
+ * pool are not timed.  nep_timing_end synchronises on the recorded events,
+ * writes the summed milliseconds and launch counts per class into ms[4] and
+ * launches[4] (host), destroys the pool and disables recording.  Not
+ * thread-safe: meant for a single benchmarking thread. */
+int nep_timing_begin(int max_launches);
+int nep_timing_end(double ms[4], int launches[4]);
 
 const char *nep_last_error(void);
 

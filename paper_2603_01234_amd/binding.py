@@ -31,7 +31,7 @@ FLAG_NONFINITE, FLAG_OUTSIDE_BOX, FLAG_OVERLAP, FLAG_IMAGE_RANGE = 8, 16, 32, 64
 
 EXPORTS = ["nep_param_count", "nep_model_create", "nep_model_destroy", "nep_workspace_bytes",
            "nep_build_neighbors", "nep_compute_efv", "nep_md_step", "nep_check_status",
-           "nep_last_error"]
+           "nep_last_error", "nep_timing_begin", "nep_timing_end"]
 
 
 class NepError(RuntimeError):
@@ -59,7 +59,7 @@ class Neighbors(ctypes.Structure):
 class MdParams(ctypes.Structure):
     _fields_ = [("dt_fs", c_float), ("n_steps", c_int), ("rebuild_every", c_int), ("mass", c_float * 4),
                 ("strain_rate", c_double * 3), ("box0", c_double * 3), ("step", c_int64),
-                ("check_status", c_int)]
+                ("n_rebuilds", c_int), ("pair_counts", c_void_p)]
 
 
 _lib = None
@@ -90,6 +90,10 @@ def lib():
         L.nep_md_step.restype = c_int
         L.nep_check_status.argtypes = [POINTER(Neighbors), POINTER(c_int32), c_void_p]
         L.nep_check_status.restype = c_int
+        L.nep_timing_begin.argtypes = [c_int]
+        L.nep_timing_begin.restype = c_int
+        L.nep_timing_end.argtypes = [POINTER(c_double), POINTER(c_int)]
+        L.nep_timing_end.restype = c_int
         L.nep_last_error.argtypes = []
         L.nep_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -153,3 +157,15 @@ def nep_check_status(nb: Neighbors, stream):
     out = (c_int32 * 4)()
     code = lib().nep_check_status(ctypes.byref(nb), out, stream)
     return code, list(out)
+
+
+def nep_timing_begin(max_launches: int) -> None:
+    check(lib().nep_timing_begin(int(max_launches)))
+
+
+def nep_timing_end():
+    """Returns (ms[4], launches[4]) per kernel class (main, gather, build, kick-drift)."""
+    ms = (c_double * 4)()
+    cnt = (c_int * 4)()
+    check(lib().nep_timing_end(ms, cnt))
+    return list(ms), list(cnt)

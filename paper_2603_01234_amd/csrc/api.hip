@@ -31,6 +31,65 @@ int fail(int code, const std::string &msg) {
             return fail(NEP_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
+// optional event timing of kernel classes
+struct Timing {
+    bool on = false;
+    int cap = 0, used = 0;
+    std::vector<hipEvent_t> ev;  // 2 per launch
+    std::vector<int> cls;
+};
+Timing g_timing;
+
+struct TimedLaunch {
+    int k = -1;
+    hipStream_t s;
+    TimedLaunch(int cls, hipStream_t st) : s(st) {
+        if (g_timing.on && g_timing.used < g_timing.cap) {
+            k = g_timing.used++;
+            g_timing.cls[k] = cls;
+            (void)hipEventRecord(g_timing.ev[2 * k], s);
+        }
+    }
+    ~TimedLaunch() {
+        if (k >= 0) (void)hipEventRecord(g_timing.ev[2 * k + 1], s);
+    }
+};
+
+// Per-thread pinned ring of per-step info records and their events (the MD
+// loop reads the record of step k-1 while the device runs step k).
+constexpr int NSLOT = 8;
+struct MdCtx {
+    double *host = nullptr;  // [NSLOT + 1][8], mapped pinned memory
+    double *dev = nullptr;
+    hipEvent_t ev[NSLOT + 1] = {};
+    int device = -1;
+    ~MdCtx() {
+        if (host) (void)hipHostFree(host);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+thread_local MdCtx g_md;
+
+int md_ctx(MdCtx *&c) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (!g_md.host || g_md.device != dev) {
+        if (g_md.host) {
+            (void)hipHostFree(g_md.host);
+            for (auto &e : g_md.ev)
+                if (e) (void)hipEventDestroy(e);
+            g_md = MdCtx();
+        }
+        HIPCHK(hipHostMalloc((void **)&g_md.host, (NSLOT + 1) * 8 * sizeof(double), hipHostMallocMapped));
+        HIPCHK(hipHostGetDevicePointer((void **)&g_md.dev, g_md.host, 0));
+        for (auto &e : g_md.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        g_md.device = dev;
+    }
+    c = &g_md;
+    return NEP_OK;
+}
+
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
         cell_list, scan_tmp, total;
@@ -192,7 +251,7 @@ int read_status(const nep_neighbors *nb, int32_t out[4], hipStream_t s) {
 }
 
 int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, const WsLayout &L,
-            int clear_status, NbArgs &a) {
+            int clear_status, int wrap, NbArgs &a) {
     a = NbArgs{};
     int rc = make_grid(M, s, nb->skin, L.ncell_max, a);
     if (rc) return rc;
@@ -216,6 +275,10 @@ int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, co
     a.ref = nb->ref;
     a.status = nb->status;
     a.clear_status = clear_status;
+    a.wrap = wrap;
+    a.x_mut = s->x;
+    a.y_mut = s->y;
+    a.z_mut = s->z;
     return NEP_OK;
 }
 
@@ -237,8 +300,12 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     a.bvec = at<float4>(ws, L.bvec);
     a.angbuf = at<float4>(ws, L.angbuf);
     a.fown = at<float4>(ws, L.fown);
+    a.freeze = md ? nb->status : nullptr;
     size_t lds = ((size_t)M.T * M.H * (ND + 2) + 1 + (size_t)M.T * M.T * TAB_PER_PAIR) * sizeof(float);
-    HIPCHK(launch_efv_main(M.T, a, lds, st));
+    {
+        TimedLaunch tl(0, st);
+        HIPCHK(launch_efv_main(M.T, a, lds, st));
+    }
     GatherArgs g{};
     g.n = n;
     for (int d = 0; d < 3; ++d) g.box[d] = s->box[d];
@@ -256,19 +323,60 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     g.partial = at<double>(ws, L.partial);
     if (md) {
         g.v = v;
+        g.freeze = nb->status;
+        g.ref = nb->ref;
+        g.dt = mp->dt_fs;
         g.half_dt_accel = 0.5f * mp->dt_fs * ACCEL;
         for (int t = 0; t < M.T; ++t) {
             g.inv_mass[t] = 1.0f / mp->mass[t];
             g.mass[t] = mp->mass[t];
         }
     }
-    HIPCHK(launch_efv_gather(M.T, W != nullptr || want_total_virial, md, g, st));
+    {
+        TimedLaunch tl(1, st);
+        HIPCHK(launch_efv_gather(M.T, W != nullptr || want_total_virial, md, g, st));
+    }
     return NEP_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+int nep_timing_begin(int max_launches) {
+    if (g_timing.on) return fail(NEP_ERR_ARG, "timing already enabled");
+    if (max_launches < 1 || max_launches > (1 << 20)) return fail(NEP_ERR_ARG, "max_launches out of range");
+    g_timing.ev.assign(2 * (size_t)max_launches, nullptr);
+    g_timing.cls.assign(max_launches, 0);
+    for (auto &e : g_timing.ev) HIPCHK(hipEventCreate(&e));
+    g_timing.cap = max_launches;
+    g_timing.used = 0;
+    g_timing.on = true;
+    return NEP_OK;
+}
+
+int nep_timing_end(double ms[4], int launches[4]) {
+    if (!g_timing.on) return fail(NEP_ERR_ARG, "timing not enabled");
+    double acc[4] = {0, 0, 0, 0};
+    int cnt[4] = {0, 0, 0, 0};
+    int rc = NEP_OK;
+    for (int k = 0; k < g_timing.used; ++k) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(g_timing.ev[2 * k + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, g_timing.ev[2 * k], g_timing.ev[2 * k + 1]);
+        if (e != hipSuccess) { rc = fail(NEP_ERR_HIP, hipGetErrorString(e)); break; }
+        acc[g_timing.cls[k]] += t;
+        cnt[g_timing.cls[k]] += 1;
+    }
+    for (auto &e : g_timing.ev) (void)hipEventDestroy(e);
+    g_timing = Timing();
+    for (int c = 0; c < 4; ++c) {
+        if (ms) ms[c] = acc[c];
+        if (launches) launches[c] = cnt[c];
+    }
+    return rc;
+}
+
 
 const char *nep_last_error(void) { return g_err.c_str(); }
 
@@ -383,8 +491,11 @@ int nep_build_neighbors(nep_model model, const nep_system *s, nep_neighbors *nb,
     if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
     hipStream_t st = (hipStream_t)stream;
     NbArgs a;
-    if ((rc = fill_nb(M, s, nb, ws, L, 1, a))) return rc;
-    HIPCHK(launch_build(a, st));
+    if ((rc = fill_nb(M, s, nb, ws, L, 1, 0, a))) return rc;
+    {
+        TimedLaunch tl(2, st);
+        HIPCHK(launch_build(a, st));
+    }
     return read_status(nb, nullptr, st);
 }
 
@@ -406,7 +517,7 @@ int nep_compute_efv(nep_model model, const nep_system *s, const nep_neighbors *n
     // an empty system reduces zero blocks, so the totals come out as zero
     if (E_tot || W_tot)
         HIPCHK(launch_reduce(at<double>(ws, L.partial), s->n > 0 ? L.nblocks : 0, E_tot, W_tot, nullptr, nullptr,
-                             nullptr, st));
+                             nullptr, nullptr, nullptr, nullptr, st));
     return NEP_OK;
 }
 
@@ -431,9 +542,58 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         mp->step += mp->n_steps;
         return NEP_OK;
     }
-    if (mp->check_status) HIPCHK(launch_clear_status(nb->status, st));
-    for (int k = 0; k < mp->n_steps; ++k) {
-        const int64_t step = mp->step;
+    MdCtx *C = nullptr;
+    if ((rc = md_ctx(C))) return rc;
+    const int64_t step0 = mp->step;
+    const int n_steps = mp->n_steps;
+    const double half_skin = 0.5 * (double)nb->skin;
+    mp->n_rebuilds = 0;
+    auto box_at = [&](int64_t stp, int d) -> float {
+        return mp->strain_rate[d] != 0.0 ? (float)(mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)stp))
+                                         : s->box[d];
+    };
+    auto enqueue_build = [&]() -> int {
+        NbArgs a;
+        int r = fill_nb(M, s, nb, ws, L, 0, 1, a);
+        if (r) return r;
+        TimedLaunch tl(2, st);
+        HIPCHK(launch_build(a, st));
+        ++mp->n_rebuilds;
+        return NEP_OK;
+    };
+    HIPCHK(launch_clear_status(nb->status, st));
+    // how far the first drift takes every bead from its build position
+    PredictArgs pa{};
+    pa.n = n;
+    pa.T = M.T;
+    pa.x = s->x;
+    pa.y = s->y;
+    pa.z = s->z;
+    pa.v = v;
+    pa.F = F;
+    pa.ref = nb->ref;
+    pa.type = s->type;
+    pa.dt = mp->dt_fs;
+    pa.half_dt_accel = 0.5f * mp->dt_fs * ACCEL;
+    for (int t = 0; t < M.T; ++t) pa.inv_mass[t] = 1.0f / mp->mass[t];
+    pa.partial = at<double>(ws, L.partial);
+    HIPCHK(launch_predict(pa, st));
+    HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr, nullptr, nullptr,
+                         nullptr, nb->status, C->dev + 8 * NSLOT, st));
+    HIPCHK(hipEventRecord(C->ev[NSLOT], st));
+    HIPCHK(hipEventSynchronize(C->ev[NSLOT]));
+    double prev[8];
+    std::memcpy(prev, C->host + 8 * NSLOT, sizeof prev);
+    bool rebuilt_prev = false;
+    if (prev[2] > 0.95 * half_skin) {
+        if ((rc = enqueue_build())) return rc;
+        rebuilt_prev = true;
+    }
+    std::vector<char> rebuilt((size_t)n_steps + 1, 0);
+    int completed = n_steps;
+    bool frozen = false;
+    for (int k = 0; k < n_steps; ++k) {
+        const int64_t step = step0 + k;
         KickDriftArgs kd{};
         kd.n = n;
         kd.x = s->x;
@@ -459,23 +619,48 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
             kd.box[d] = s->box[d];
             kd.pbc[d] = s->pbc[d] ? 1 : 0;
         }
-        const bool rebuild = ((step + 1) % mp->rebuild_every) == 0;
-        kd.wrap = rebuild ? 1 : 0;
         kd.half_skin2 = 0.25f * nb->skin * nb->skin;
         kd.status = nb->status;
-        HIPCHK(launch_kick_drift(kd, st));
-        if (rebuild) {
-            NbArgs a;
-            if ((rc = fill_nb(M, s, nb, ws, L, 0, a))) return rc;
-            HIPCHK(launch_build(a, st));
+        {
+            TimedLaunch tl(3, st);
+            HIPCHK(launch_kick_drift(kd, st));
         }
         if ((rc = launch_efv(M, s, nb, U, F, nullptr, false, ws, L, st, true, v, mp))) return rc;
         HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
-                             E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr, st));
-        mp->step = step + 1;
+                             E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr, mp->pair_counts,
+                             nb->status, C->dev + 8 * (k % NSLOT), st));
+        HIPCHK(hipEventRecord(C->ev[k % NSLOT], st));
+        if (k >= 1) {
+            // the record of step k-1 (the device is busy with step k meanwhile)
+            HIPCHK(hipEventSynchronize(C->ev[(k - 1) % NSLOT]));
+            std::memcpy(prev, C->host + 8 * ((k - 1) % NSLOT), sizeof prev);
+            rebuilt_prev = rebuilt[k - 1] != 0;
+            if ((int)prev[5] & FREEZE_MASK) {  // a build after step k-2 failed
+                completed = k - 1;
+                frozen = true;
+                break;
+            }
+        }
+        // displacement from the build position at the force evaluation of
+        // step k+1, bounded from the exact prediction one step back:
+        //   no rebuild since:  |x_{k+1} + d_k - ref| + |d_{k+1}|
+        //   rebuilt after k-1: |d_k| + |d_{k+1}|,   |d_{k+1}| <= |d_k| + dt^2 |a|
+        double bound = (rebuilt_prev ? 0.0 : prev[2]) + (rebuilt_prev ? 2.0 : 1.0) * prev[3] + 2.0 * prev[4];
+        const bool scheduled = ((step + 1) % mp->rebuild_every) == 0;
+        if (scheduled || bound > 0.95 * half_skin) {
+            if ((rc = enqueue_build())) return rc;
+            rebuilt[k] = 1;
+        }
     }
-    if (mp->check_status) return read_status(nb, nullptr, st);
-    return NEP_OK;
+    if (!frozen && n_steps > 0) {
+        HIPCHK(hipEventSynchronize(C->ev[(n_steps - 1) % NSLOT]));
+        std::memcpy(prev, C->host + 8 * ((n_steps - 1) % NSLOT), sizeof prev);
+        if ((int)prev[5] & FREEZE_MASK) completed = n_steps - 1;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    mp->step = step0 + completed;
+    for (int d = 0; d < 3; ++d) s->box[d] = box_at(mp->step, d);
+    return read_status(nb, nullptr, st);
 }
 
 int nep_check_status(const nep_neighbors *nb, int32_t out[4], void *stream) {

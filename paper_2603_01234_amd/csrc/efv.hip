@@ -88,6 +88,7 @@ __global__ __launch_bounds__(BLOCK) void k_efv_main(EfvArgs a) {
         P = a.params;
         TB = a.tab;
     }
+    if (a.freeze && (a.freeze[0] & FREEZE_MASK)) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int i = tile * BLOCK + threadIdx.x;
     if (i >= a.n) return;
@@ -290,13 +291,17 @@ __global__ __launch_bounds__(BLOCK) void k_efv_main(EfvArgs a) {
 
 template <int NT, bool VIR, bool MD>
 __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
-    __shared__ double red[11][BLOCK];
+    __shared__ double red[NPART][BLOCK];
+    __shared__ float redm[NMAX][BLOCK];
+    if (MD && a.freeze && (a.freeze[0] & FREEZE_MASK)) return;  // uniform over the grid
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int i = tile * BLOCK + threadIdx.x;
     const int n = a.n;
-    double acc[11];
+    double acc[NPART];
+    float mx[NMAX] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int c = 0; c < 11; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
+    int nR_in = 0, nA_in = 0;  // pairs inside the interaction cutoffs (work accounting)
     if (i < n) {
         const float4 pi = a.pos4[i];
         const int ti = (NT == 1) ? 0 : (int)pi.w;
@@ -321,6 +326,8 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
             const int tj = (NT == 1) ? 0 : g.tj;
             const int tp = ti * NT + tj;
             if (g.d2 < a.cut.rcR2[tp]) {
+                ++nR_in;
+                nA_in += (p < cA && g.d2 < a.cut.rcA2[tp]) ? 1 : 0;
                 float r = sqrtf(g.d2);
                 float ir = 1.0f / r;
                 float inv = a.cut.inv_rcR[tp];
@@ -390,6 +397,8 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
         a.F[n + i] = Fy;
         a.F[2 * n + i] = Fz;
         acc[0] = (double)a.U[i];
+        acc[11] = (double)nR_in;
+        acc[12] = (double)nA_in;
         if (VIR) {
             if (a.W) {
 #pragma unroll
@@ -408,52 +417,134 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
             a.v[2 * n + i] = vz;
             acc[10] = 0.5 * (double)a.mass[ti] * ((double)vx * vx + (double)vy * vy + (double)vz * vz) /
                       (double)ACCEL;
+            // next drift d = dt (v + dt/2 a): displacement from the build
+            // reference after it, |d|, and dt^2 |a| (rebuild prediction)
+            float ddx = a.dt * (vx + k * Fx), ddy = a.dt * (vy + k * Fy), ddz = a.dt * (vz + k * Fz);
+            float px = pi.x + ddx - a.ref[i], py = pi.y + ddy - a.ref[n + i], pz = pi.z + ddz - a.ref[2 * n + i];
+            mx[0] = px * px + py * py + pz * pz;
+            mx[1] = ddx * ddx + ddy * ddy + ddz * ddz;
+            mx[2] = 2.0f * a.dt * k * sqrtf(Fx * Fx + Fy * Fy + Fz * Fz);
         }
+    }
+    if (MD) {
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) redm[c][threadIdx.x] = mx[c];
     }
     // fixed-order block reduction
 #pragma unroll
-    for (int c = 0; c < 11; ++c) red[c][threadIdx.x] = acc[c];
+    for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
     __syncthreads();
     for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
+        if (threadIdx.x < s) {
 #pragma unroll
-            for (int c = 0; c < 11; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+            for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+            if (MD)
+#pragma unroll
+                for (int c = 0; c < NMAX; ++c) redm[c][threadIdx.x] = fmaxf(redm[c][threadIdx.x], redm[c][threadIdx.x + s]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x < 11) a.partial[(size_t)tile * 16 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < NPART) a.partial[(size_t)tile * 16 + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < NMAX) a.partial[(size_t)tile * 16 + NPART + threadIdx.x] = MD ? (double)redm[threadIdx.x][0] : 0.0;
 }
 
-__global__ void k_reduce(const double *__restrict__ partial, int nblocks, double *E_tot,
-                         double *W_tot, double *K_tot, double *E_slot, double *K_slot) {
-    __shared__ double red[11][BLOCK];
-    double acc[11];
+__global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
+    __shared__ double red[NPART][BLOCK];
+    __shared__ float redm[NMAX][BLOCK];
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    const int n = a.n;
+    float mx[NMAX] = {0.0f, 0.0f, 0.0f};
+    if (i < n) {
+        int t = min((int)a.type[i], a.T - 1);
+        float k = a.half_dt_accel * a.inv_mass[t];
+        float Fx = a.F[i], Fy = a.F[n + i], Fz = a.F[2 * n + i];
+        float ddx = a.dt * (a.v[i] + k * Fx), ddy = a.dt * (a.v[n + i] + k * Fy), ddz = a.dt * (a.v[2 * n + i] + k * Fz);
+        float px = a.x[i] + ddx - a.ref[i], py = a.y[i] + ddy - a.ref[n + i], pz = a.z[i] + ddz - a.ref[2 * n + i];
+        mx[0] = px * px + py * py + pz * pz;
+        mx[1] = ddx * ddx + ddy * ddy + ddz * ddz;
+        mx[2] = 2.0f * a.dt * k * sqrtf(Fx * Fx + Fy * Fy + Fz * Fz);
+    }
 #pragma unroll
-    for (int c = 0; c < 11; ++c) acc[c] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += BLOCK)
+    for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = 0.0;
 #pragma unroll
-        for (int c = 0; c < 11; ++c) acc[c] += partial[(size_t)b * 16 + c];
-#pragma unroll
-    for (int c = 0; c < 11; ++c) red[c][threadIdx.x] = acc[c];
+    for (int c = 0; c < NMAX; ++c) redm[c][threadIdx.x] = mx[c];
     __syncthreads();
     for (int s = BLOCK / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s)
 #pragma unroll
-            for (int c = 0; c < 11; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+            for (int c = 0; c < NMAX; ++c) redm[c][threadIdx.x] = fmaxf(redm[c][threadIdx.x], redm[c][threadIdx.x + s]);
         __syncthreads();
     }
+    if (threadIdx.x < NPART) a.partial[(size_t)blockIdx.x * 16 + threadIdx.x] = 0.0;
+    if (threadIdx.x < NMAX) a.partial[(size_t)blockIdx.x * 16 + NPART + threadIdx.x] = (double)redm[threadIdx.x][0];
+}
+
+hipError_t launch_predict(const PredictArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_predict, dim3((a.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+// Fixed-order FP64 reduction of the block partials.  In MD mode (status and
+// info given) it also takes the maxima of the rebuild prediction and writes
+// one info record straight into pinned host memory:
+//   info = {E, K, max|x + d - ref|, max|d|, max dt^2|a|, status[0..2]}
+// Once the status carries a freeze flag the energy outputs are left alone.
+__global__ void k_reduce(const double *__restrict__ partial, int nblocks, double *E_tot,
+                         double *W_tot, double *K_tot, double *E_slot, double *K_slot, double *counts,
+                         const int32_t *status, double *info) {
+    __shared__ double red[NPART + NMAX][BLOCK];
+    double acc[NPART + NMAX];
+#pragma unroll
+    for (int c = 0; c < NPART + NMAX; ++c) acc[c] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
+#pragma unroll
+        for (int c = 0; c < NPART; ++c) acc[c] += partial[(size_t)b * 16 + c];
+#pragma unroll
+        for (int c = NPART; c < NPART + NMAX; ++c) acc[c] = fmax(acc[c], partial[(size_t)b * 16 + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NPART + NMAX; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+#pragma unroll
+            for (int c = NPART; c < NPART + NMAX; ++c) red[c][threadIdx.x] = fmax(red[c][threadIdx.x], red[c][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    const int st0 = status ? status[0] : 0;
+    if (threadIdx.x == 0 && info) {
+        info[0] = red[0][0];
+        info[1] = red[10][0];
+        info[2] = sqrt(red[NPART][0]);
+        info[3] = sqrt(red[NPART + 1][0]);
+        info[4] = red[NPART + 2][0];
+        info[5] = (double)st0;
+        info[6] = (double)status[1];
+        info[7] = (double)status[2];
+    }
+    if (st0 & FREEZE_MASK) return;
     if (threadIdx.x == 0) {
         if (E_tot) *E_tot = red[0][0];
         if (E_slot) *E_slot = red[0][0];
         if (K_tot) *K_tot = red[10][0];
         if (K_slot) *K_slot = red[10][0];
+        if (counts) {
+            counts[0] += red[11][0];
+            counts[1] += red[12][0];
+        }
     }
     if (W_tot && threadIdx.x < 9) W_tot[threadIdx.x] = red[1 + threadIdx.x][0];
 }
 
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
-                         double *K_tot, double *E_slot, double *K_slot, hipStream_t s) {
+                         double *K_tot, double *E_slot, double *K_slot, double *counts,
+                         const int32_t *status, double *info, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(BLOCK), 0, s, partial, nblocks, E_tot, W_tot, K_tot,
-                       E_slot, K_slot);
+                       E_slot, K_slot, counts, status, info);
     return hipGetLastError();
 }
 

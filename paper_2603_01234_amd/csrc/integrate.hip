@@ -8,15 +8,9 @@ namespace nep {
 
 
 
-__device__ __forceinline__ float wrap_coord(float x, float L) {
-    float w = x - L * floorf(x / L);
-    if (w >= L) w -= L;
-    if (w < 0.0f) w += L;
-    if (!(w >= 0.0f && w < L)) w = 0.0f;
-    return w;
-}
 
 __global__ void k_kick_drift(KickDriftArgs a) {
+    if (a.status[0] & FREEZE_MASK) return;  // lists invalid: leave the state untouched
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const int n = a.n;
@@ -37,11 +31,6 @@ __global__ void k_kick_drift(KickDriftArgs a) {
     a.ref[2 * n + i] = rz;
     float ddx = x - rx, ddy = y - ry, ddz = z - rz;
     if (ddx * ddx + ddy * ddy + ddz * ddz > a.half_skin2) atomicOr(&a.status[0], NEP_FLAG_SKIN);
-    if (a.wrap) {
-        if (a.pbc[0]) x = wrap_coord(x, a.box[0]);
-        if (a.pbc[1]) y = wrap_coord(y, a.box[1]);
-        if (a.pbc[2]) z = wrap_coord(z, a.box[2]);
-    }
     a.x[i] = x;
     a.y[i] = y;
     a.z[i] = z;

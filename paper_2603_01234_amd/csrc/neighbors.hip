@@ -34,10 +34,28 @@ __device__ __forceinline__ int cell_coord(float x, float inv_cs, int nc) {
     return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
 }
 
+// periodic wrap into [0, L) in float32; a result that rounds to L becomes 0
+__device__ __forceinline__ float wrap_coord(float x, float L) {
+    float w = x - L * floorf(x / L);
+    if (w >= L) w -= L;
+    if (w < 0.0f) w += L;
+    if (!(w >= 0.0f && w < L)) w = 0.0f;
+    return w;
+}
+
 __global__ void k_nb_bin(NbArgs a) {
+    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     float p[3] = {a.x[i], a.y[i], a.z[i]};
+    if (a.wrap) {
+        float *dst[3] = {a.x_mut, a.y_mut, a.z_mut};
+        for (int d = 0; d < 3; ++d)
+            if (a.pbc[d] && isfinite(p[d])) {
+                p[d] = wrap_coord(p[d], a.box[d]);
+                dst[d][i] = p[d];
+            }
+    }
     int flags = 0;
     int c[3];
     for (int d = 0; d < 3; ++d) {
@@ -103,6 +121,7 @@ __global__ void k_scan_add(int32_t *out, int32_t *cursor, const int32_t *block_s
 }
 
 __global__ void k_nb_fill(NbArgs a) {
+    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     int slot = atomicAdd(&a.cell_cursor[a.cell_id[i]], 1);
@@ -110,6 +129,7 @@ __global__ void k_nb_fill(NbArgs a) {
 }
 
 __global__ void k_nb_sort_cells(NbArgs a) {
+    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.ncell) return;
     int s = a.cell_start[c], e = s + a.cell_count[c];
@@ -125,6 +145,7 @@ __global__ void k_nb_sort_cells(NbArgs a) {
 }
 
 __global__ __launch_bounds__(BLOCK) void k_nb_rows(NbArgs a) {
+    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const int n = a.n;
@@ -204,6 +225,7 @@ __global__ __launch_bounds__(BLOCK) void k_nb_rows(NbArgs a) {
 }
 
 __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
+    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const int n = a.n;

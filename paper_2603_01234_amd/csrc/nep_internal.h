@@ -22,6 +22,13 @@ constexpr int TAB_PER_PAIR = NR * KB + NA * KB + NA * (KB - 1);  // 81 + 63 + 56
 constexpr uint32_t J_MASK = 0x1FFFFFFu;
 constexpr int CODE_SHIFT = 25;
 constexpr float ACCEL = 9.648533212e-5f;  // nm/fs^2 per (eV/nm)/amu
+// per-block partial sums: U, W (9), kinetic energy, radial pairs, angular pairs;
+// slots 13..15 of each block hold maxima for the rebuild prediction
+constexpr int NPART = 13;
+constexpr int NMAX = 3;
+// status flags after which the MD kernels do nothing (the lists are invalid)
+constexpr int FREEZE_MASK = NEP_FLAG_OVERFLOW_R | NEP_FLAG_OVERFLOW_A | NEP_FLAG_NONFINITE |
+                            NEP_FLAG_OUTSIDE_BOX | NEP_FLAG_IMAGE_RANGE | NEP_FLAG_BAD_TYPE;
 
 // Model as held by the library: device copies of the flat parameters and of
 // the derived coefficient tables the kernels read.
@@ -54,6 +61,7 @@ struct EfvArgs {
     float4 *bvec;           // [n][T][3] radial back-propagation coefficients
     float4 *angbuf;         // [cap_A][n] dU_i/dr_ij angular part
     float4 *fown;           // [n] sum_j dU_i/dr_ij (angular)
+    const int32_t *freeze;  // MD: status word; the kernel does nothing once FREEZE_MASK is set
 };
 
 struct GatherArgs {
@@ -70,12 +78,15 @@ struct GatherArgs {
     const float *U;         // site energies (for the energy sum)
     float *F;               // [3][n]
     float *W;               // [9][n] or null
-    double *partial;        // [nblocks][16]: U, W(9), K
+    double *partial;        // [nblocks][16]: U, W(9), K, pairs within r_c^R, pairs within r_c^A
     // fused second half-kick (MD)
     float *v;               // [3][n] or null
     float half_dt_accel;    // dt/2 * ACCEL
+    float dt;
     float inv_mass[MAXT];
     float mass[MAXT];
+    const float *ref;       // [3][n] positions at the last build (rebuild prediction)
+    const int32_t *freeze;  // MD: status word (see EfvArgs)
 };
 
 // XCD-aware tile index: consecutive logical tiles are kept on one XCD (the
@@ -177,7 +188,19 @@ hipError_t launch_pack(int n, int T, const float *x, const float *y, const float
 hipError_t launch_efv_main(int T, const EfvArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_efv_gather(int T, bool virial, bool md, const GatherArgs &a, hipStream_t s);
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
-                         double *K_tot, double *E_slot, double *K_slot, hipStream_t s);
+                         double *K_tot, double *E_slot, double *K_slot, double *counts,
+                         const int32_t *status, double *info, hipStream_t s);
+// rebuild prediction at the start of an MD call: maxima of |x + d - ref|,
+// |d| and dt^2 |a| with d = dt (v + dt/2 a) the next drift, into the partials
+struct PredictArgs {
+    int n, T;
+    const float *x, *y, *z, *v, *F, *ref;
+    const uint8_t *type;
+    float dt, half_dt_accel;
+    float inv_mass[MAXT];
+    double *partial;
+};
+hipError_t launch_predict(const PredictArgs &a, hipStream_t s);
 
 struct NbArgs {
     int n, cap, cap_A;
@@ -188,6 +211,7 @@ struct NbArgs {
     float list2R[MAXT * MAXT], list2A[MAXT * MAXT];
     int T;
     const float *x, *y, *z;
+    float *x_mut, *y_mut, *z_mut;  // same arrays, written only when wrap is set
     const uint8_t *type;
     float4 *pos4;
     int32_t *cell_id, *cell_count, *cell_start, *cell_cursor, *cell_list, *scan_tmp;
@@ -197,6 +221,7 @@ struct NbArgs {
     int32_t *status;
     int ncell;
     int clear_status;  // 1: a fresh build resets the status word
+    int wrap;          // 1: wrap periodic coordinates into [0, L) and write them back first
 };
 hipError_t launch_build(const NbArgs &a, hipStream_t s);
 hipError_t launch_clear_status(int32_t *status, hipStream_t s);
@@ -215,7 +240,6 @@ struct KickDriftArgs {
     float lam[3];           // affine scale factors of this step
     float box[3];           // box after the strain
     int pbc[3];
-    int wrap;               // wrap periodic coordinates into [0, L) (rebuild steps)
     int T;                  // number of types (type values are clamped below it)
     float half_skin2;       // (skin/2)^2
     int32_t *status;

@@ -105,6 +105,7 @@ class Replica:
             cap_A = cap_A or ca
         self._alloc_lists(cap, cap_A)
         self.step = 0
+        self.n_rebuilds = 0
         self.lists_valid = False
 
     # -- buffers ----------------------------------------------------------------
@@ -163,26 +164,47 @@ class Replica:
 
     def md(self, n_steps: int, dt: float, masses: Sequence[float], rebuild_every: int = 10,
            strain_rate=(0.0, 0.0, 0.0), E_pot: Optional[torch.Tensor] = None,
-           E_kin: Optional[torch.Tensor] = None, check_status: bool = True):
-        mp = B.MdParams()
-        mp.dt_fs = float(dt)
-        mp.n_steps = int(n_steps)
-        mp.rebuild_every = int(rebuild_every)
-        for t in range(4):
-            mp.mass[t] = float(masses[t]) if t < len(masses) else 1.0
-        for d in range(3):
-            mp.strain_rate[d] = float(strain_rate[d])
-            mp.box0[d] = float(self.box0[d])
-        mp.step = int(self.step)
-        mp.check_status = int(check_status)
-        s, nb = self.c_system(), self.c_neighbors()
-        code = B.nep_md_step(self.model.handle, s, _ptr(self.v), mp, nb, _ptr(self.F), _ptr(self.U),
-                             _ptr(E_pot), _ptr(E_kin), self.ws.data_ptr(), self.ws_bytes, _stream())
-        self.step = int(mp.step)
-        for d in range(3):
-            self.box[d] = s.box[d]
-        B.check(code)
-        return self
+           E_kin: Optional[torch.Tensor] = None,
+           pair_counts: Optional[torch.Tensor] = None, regrow: bool = True):
+        """nep_md_step; after a rebuild overflow the rows are regrown, rebuilt and
+        the remaining steps resumed (x, v, F are consistent at that point)."""
+        if not self.lists_valid:
+            self.build()
+        remaining = int(n_steps)
+        done_total = 0
+        while True:
+            mp = B.MdParams()
+            mp.dt_fs = float(dt)
+            mp.n_steps = remaining
+            mp.rebuild_every = int(rebuild_every)
+            for t in range(4):
+                mp.mass[t] = float(masses[t]) if t < len(masses) else 1.0
+            for d in range(3):
+                mp.strain_rate[d] = float(strain_rate[d])
+                mp.box0[d] = float(self.box0[d])
+            mp.step = int(self.step)
+            mp.pair_counts = _ptr(pair_counts)
+            s, nb = self.c_system(), self.c_neighbors()
+            ep = None if E_pot is None else E_pot.data_ptr() + 8 * done_total
+            ek = None if E_kin is None else E_kin.data_ptr() + 8 * done_total
+            code = B.nep_md_step(self.model.handle, s, _ptr(self.v), mp, nb, _ptr(self.F), _ptr(self.U),
+                                 ep, ek, self.ws.data_ptr(), self.ws_bytes, _stream())
+            done = int(mp.step) - self.step
+            self.step = int(mp.step)
+            self.n_rebuilds += int(mp.n_rebuilds)
+            for d in range(3):
+                self.box[d] = s.box[d]
+            done_total += done
+            remaining -= done
+            if code == B.NEP_ERR_NEIGHBOR_OVERFLOW and regrow:
+                st = self.status.cpu().tolist()
+                self._alloc_lists(max(self.cap, int(st[1] * 1.25) + 8), max(self.cap_A, int(st[2] * 1.25) + 8))
+                self.build()
+                if remaining > 0:
+                    continue
+                return self
+            B.check(code)
+            return self
 
     # -- host views ---------------------------------------------------------------
     def positions(self) -> np.ndarray:

@@ -83,7 +83,7 @@ def test_md_strain_updates_box_and_stays_consistent():
     spec = W.aacg_gold_spec(50)
     params = W.draw_params(spec, rng)
     seq = np.random.SeedSequence(99)
-    wire = W.gold_nanowire(seq, n_target=6000, core_radius=0.9)
+    wire = W.gold_nanowire(seq, n_target=6000, core_radius=0.9, au_cells_z=27)
     rep = _rep(spec, params, wire, 0.1)
     rep.efv(per_bead_virial=False)
     rate = 1e-4
@@ -104,3 +104,45 @@ def test_skin_violation_is_reported():
     with pytest.raises(B.NepError) as ei:
         rep.md(3, 2.0, [W.WATER_MASS], rebuild_every=10)
     assert ei.value.code == B.NEP_ERR_SKIN_VIOLATION
+
+
+def test_fast_beads_trigger_early_rebuilds_and_stay_exact():
+    """At 3000 K beads cross skin/2 within a few steps: the predicted rebuilds
+    must keep every pair, so the forces at the end still match the oracle."""
+    spec, params, system, opts = W.config0()
+    system.vel = W.maxwell_velocities(np.random.default_rng(5), np.full(system.n, W.WATER_MASS), 3000.0)
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv()
+    rep.md(60, opts["dt"], [W.WATER_MASS], rebuild_every=10)
+    print("rebuilds:", rep.n_rebuilds)
+    assert rep.n_rebuilds > 6          # more than the scheduled every-10 rebuilds
+    F_md = rep.F.clone()
+    rep.efv()                          # totals at the final positions, on the lists the run left
+    # equal up to rounding: a final rebuild may have wrapped positions by a box length
+    assert float((F_md - rep.F).norm() / rep.F.norm()) < 1e-6
+    ref = oracle.efv(spec, params.astype(np.float32).astype(np.float64), rep.positions().astype(np.float64),
+                     system.types, system.box.astype(np.float32).astype(np.float64), system.pbc)
+    compare_efv(rep, ref, system.n, label="hot")
+
+
+def test_overflow_freezes_then_resumes_bitwise():
+    """Rows too short for the run: the call stops at the overflowing rebuild with a
+    consistent state, the engine regrows and resumes; the trajectory equals the
+    one run with ample capacity from the start."""
+    spec, params, system, opts = W.config0()
+    runs = []
+    for caps in ((None, None), "tight"):
+        rep = _rep(spec, params, system, opts["skin"])
+        rep.efv()
+        if caps == "tight":
+            st = rep.status.cpu().tolist()
+            rep._alloc_lists(st[1], st[2])     # exactly the current maxima
+            rep.build()
+        else:
+            rep._alloc_lists(200, 100)
+            rep.build()
+        rep.md(300, opts["dt"], [W.WATER_MASS], rebuild_every=10)
+        runs.append((rep.xyz.clone(), rep.v.clone(), rep.F.clone(), rep.cap))
+    print("caps after regrow:", runs[1][3])
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        assert torch.equal(a, b)

@@ -261,24 +261,27 @@ def _fcc(a_xy: float, a_z: float, nxy: int, nz: int) -> np.ndarray:
 
 def gold_nanowire(seed_seq: np.random.SeedSequence, n_target: int = 200_000,
                   core_radius: float = 1.5, gap: float = 0.2, jitter: float = 0.02,
-                  temperature: float = 300.0) -> System:
+                  temperature: float = 300.0, au_cells_z: int = 170) -> System:
     """Cylinder along z (periodic, L_z = 170 fcc Au cells); fcc Au core (type 0)
     inside ``core_radius``, fcc CG beads (type 1, lattice 0.65 nm, 107 cells along
     z so the bead lattice is commensurate) outside ``core_radius + gap`` up to the
-    radius that brings the total to ``n_target`` sites.  x and y are open."""
+    radius that brings the total to ``n_target`` sites.  x and y are open.
+    ``au_cells_z`` shortens the wire for small test systems (bead cells along z
+    are scaled by 107/170 and rounded)."""
     s_pos, s_vel = seed_seq.spawn(2)
     rng = np.random.default_rng(s_pos)
-    Lz = 170 * AU_LATTICE
-    au = _fcc(AU_LATTICE, AU_LATTICE, int(core_radius / AU_LATTICE) + 2, 170)
+    Lz = au_cells_z * AU_LATTICE
+    bead_cells_z = max(1, int(round(au_cells_z * 107 / 170)))
+    au = _fcc(AU_LATTICE, AU_LATTICE, int(core_radius / AU_LATTICE) + 2, au_cells_z)
     rho_au = np.hypot(au[:, 0], au[:, 1])
     au = au[rho_au < core_radius]
-    a_bz = Lz / 107
+    a_bz = Lz / bead_cells_z
     n_beads_target = n_target - au.shape[0]
     # outer radius from the bead density 4 / (a^2 a_z)
     dens = 4.0 / (BEAD_LATTICE ** 2 * a_bz)
     r_in = core_radius + gap
     r_out = math.sqrt(n_beads_target / (dens * math.pi * Lz) + r_in ** 2)
-    beads = _fcc(BEAD_LATTICE, a_bz, int(r_out / BEAD_LATTICE) + 2, 107)
+    beads = _fcc(BEAD_LATTICE, a_bz, int(r_out / BEAD_LATTICE) + 2, bead_cells_z)
     rho_b = np.hypot(beads[:, 0], beads[:, 1])
     order = np.argsort(rho_b, kind="stable")
     beads, rho_b = beads[order], rho_b[order]
