@@ -139,13 +139,17 @@ typedef struct {
 size_t nep_workspace_bytes(nep_model model, int n, int cap, int cap_A);
 
 /* Builds the lists for the current positions (cell lists with cells no smaller
- * than r_c + skin; images enumerated for boxes smaller than two cells).
+ * than half of r_c + skin; images enumerated for boxes smaller than a few
+ * cells).  wrap = 1 first wraps every periodic coordinate into [0, L) in place
+ * (the lists then refer to the wrapped positions); wrap = 0 requires them to be
+ * there already and reports NEP_ERR_OUTSIDE_BOX otherwise.
  * Synchronises the stream to read the status word: returns
  * NEP_ERR_NEIGHBOR_OVERFLOW when a row did not fit (status[1], status[2] hold
  * the required cap and cap_A; grow the buffers and call again),
- * NEP_ERR_NONFINITE, NEP_ERR_OUTSIDE_BOX, NEP_ERR_OVERLAP, or
- * NEP_ERR_UNSUPPORTED when an image beyond +-2 boxes would be needed. */
-int nep_build_neighbors(nep_model model, const nep_system *sys, nep_neighbors *nbrs,
+ * NEP_ERR_NONFINITE, NEP_ERR_OUTSIDE_BOX, NEP_ERR_OVERLAP, NEP_ERR_ARG for a
+ * type value >= n_types, or NEP_ERR_UNSUPPORTED when an image beyond +-2 boxes
+ * would be needed. */
+int nep_build_neighbors(nep_model model, nep_system *sys, nep_neighbors *nbrs, int wrap,
                         void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
@@ -185,13 +189,15 @@ typedef struct {
  * [n] or NULL (site energies at the last step).  E_pot / E_kin: device double
  * [n_steps] traces or NULL.
  *
- * Rebuild decisions need no per-step synchronisation: after each step the
- * gather kernel computes, exactly, how far every bead will be from its
- * build position after the next drift; the reduction writes the maximum
- * into pinned host memory, and the host (one step behind the device) adds a
- * bound for one further drift and schedules a rebuild before the displacement
- * can reach skin/2.  A real violation is still checked per bead and reported
- * as NEP_ERR_SKIN_VIOLATION.
+ * Rebuild decisions are taken on the device, with no host synchronisation
+ * inside the call: after each step the gather kernel computes, exactly, where
+ * the next drift will take every bead; the reduction sets a gate word when
+ * some bead would end up 0.98 skin/2 or farther from its build position, or
+ * when a scheduled rebuild ((step + 1) % rebuild_every == 0) is due, and the
+ * build kernels queued after every step do nothing while the gate is off.
+ * params->n_rebuilds returns the number of rebuilds that ran.  A bead that
+ * still moves more than skin/2 (one drift longer than skin/2) is reported as
+ * NEP_ERR_SKIN_VIOLATION.
  *
  * A rebuild that overflows (or finds a bad position) freezes the device state
  * at the end of the last good step: x, v and F are then consistent, the call

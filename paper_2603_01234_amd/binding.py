@@ -80,7 +80,8 @@ def lib():
         L.nep_model_destroy.restype = c_int
         L.nep_workspace_bytes.argtypes = [c_void_p, c_int, c_int, c_int]
         L.nep_workspace_bytes.restype = c_size_t
-        L.nep_build_neighbors.argtypes = [c_void_p, POINTER(System), POINTER(Neighbors), c_void_p, c_size_t, c_void_p]
+        L.nep_build_neighbors.argtypes = [c_void_p, POINTER(System), POINTER(Neighbors), c_int, c_void_p, c_size_t,
+                                          c_void_p]
         L.nep_build_neighbors.restype = c_int
         L.nep_compute_efv.argtypes = [c_void_p, POINTER(System), POINTER(Neighbors), c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
@@ -138,8 +139,8 @@ def nep_workspace_bytes(model: int, n: int, cap: int, cap_A: int) -> int:
     return int(lib().nep_workspace_bytes(model, n, cap, cap_A))
 
 
-def nep_build_neighbors(model, sys: System, nb: Neighbors, ws_ptr, ws_bytes, stream) -> int:
-    return lib().nep_build_neighbors(model, ctypes.byref(sys), ctypes.byref(nb), ws_ptr, ws_bytes, stream)
+def nep_build_neighbors(model, sys: System, nb: Neighbors, wrap: int, ws_ptr, ws_bytes, stream) -> int:
+    return lib().nep_build_neighbors(model, ctypes.byref(sys), ctypes.byref(nb), int(wrap), ws_ptr, ws_bytes, stream)
 
 
 def nep_compute_efv(model, sys: System, nb: Neighbors, U, F, W, E_tot, W_tot, ws_ptr, ws_bytes, stream) -> int:

@@ -57,42 +57,11 @@ struct TimedLaunch {
 
 // Per-thread pinned ring of per-step info records and their events (the MD
 // loop reads the record of step k-1 while the device runs step k).
-constexpr int NSLOT = 8;
-struct MdCtx {
-    double *host = nullptr;  // [NSLOT + 1][8], mapped pinned memory
-    double *dev = nullptr;
-    hipEvent_t ev[NSLOT + 1] = {};
-    int device = -1;
-    ~MdCtx() {
-        if (host) (void)hipHostFree(host);
-        for (auto &e : ev)
-            if (e) (void)hipEventDestroy(e);
-    }
-};
-thread_local MdCtx g_md;
-
-int md_ctx(MdCtx *&c) {
-    int dev = -1;
-    HIPCHK(hipGetDevice(&dev));
-    if (!g_md.host || g_md.device != dev) {
-        if (g_md.host) {
-            (void)hipHostFree(g_md.host);
-            for (auto &e : g_md.ev)
-                if (e) (void)hipEventDestroy(e);
-            g_md = MdCtx();
-        }
-        HIPCHK(hipHostMalloc((void **)&g_md.host, (NSLOT + 1) * 8 * sizeof(double), hipHostMallocMapped));
-        HIPCHK(hipHostGetDevicePointer((void **)&g_md.dev, g_md.host, 0));
-        for (auto &e : g_md.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        g_md.device = dev;
-    }
-    c = &g_md;
-    return NEP_OK;
-}
+constexpr int MAX_OFF = 125;  // (2m+1)^3 cell offsets with m <= 2
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
-        cell_list, scan_tmp, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, segA, rowbuf, ctrl, total;
     int ncell_max, nblocks;
 };
 
@@ -119,6 +88,11 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.cell_cursor = take((size_t)L.ncell_max * 4);
     L.cell_list = take(nn * 4);
     L.scan_tmp = take((size_t)(L.ncell_max / 1024 + 2) * 4);
+    L.cell_tmp = take(nn * 4);
+    L.pos_sorted = take(nn * 16);
+    L.segA = take(nn * (size_t)(MAX_OFF + 1));
+    L.rowbuf = take(nn * (size_t)std::max(cap, 1) * 4);
+    L.ctrl = take(4 * sizeof(int32_t));
     L.total = off;
     return L;
 }
@@ -147,8 +121,8 @@ int check_system(const Model &M, const nep_system *s) {
 
 int check_nbrs(const nep_system *s, const nep_neighbors *nb) {
     if (!nb) return fail(NEP_ERR_ARG, "neighbour struct is null");
-    if (nb->cap < 1 || nb->cap_A < 1 || nb->cap_A > nb->cap || nb->cap > 4096)
-        return fail(NEP_ERR_ARG, "need 1 <= cap_A <= cap <= 4096");
+    if (nb->cap < 1 || nb->cap_A < 1 || nb->cap_A > nb->cap || nb->cap > 4096 || nb->cap_A > 255)
+        return fail(NEP_ERR_ARG, "need 1 <= cap_A <= cap <= 4096 and cap_A <= 255");
     if ((size_t)nb->cap * (size_t)(s->n > 0 ? s->n : 1) >= (1ull << 31))
         return fail(NEP_ERR_ARG, "cap * n must stay below 2^31");
     if (s->n > 0 && (!nb->nbr || !nb->rev || !nb->cnt || !nb->ref || !nb->status))
@@ -181,9 +155,11 @@ Cut make_cut(const Model &M) {
     return c;
 }
 
-// Cell grid: cells no smaller than (r_c + skin)(1 + 1e-3), so a pair within
-// reach differs by at most one cell index even after float rounding of the
-// cell coordinate; coarsened until the cell count fits the workspace.
+// Cell grid: cells no smaller than half of (r_c + skin)(1 + 1e-3), searched
+// +-2 cells around the bead's own, so a pair within reach differs by at most
+// two cell indices even after float rounding of the cell coordinate.  Fewer,
+// larger cells (searched +-1) when the box is small or the cell count must fit
+// the workspace.
 int make_grid(const Model &M, const nep_system *s, float skin, int ncell_max, NbArgs &a) {
     double reach = 0.0;
     for (int k = 0; k < M.T * M.T; ++k) reach = std::max(reach, (double)M.rcR[k]);
@@ -192,7 +168,8 @@ int make_grid(const Model &M, const nep_system *s, float skin, int ncell_max, Nb
     long nc[3];
     for (int d = 0; d < 3; ++d) {
         double ext = s->box[d];
-        long c = (long)std::floor(ext / target);
+        long c = (long)std::floor(ext / (0.5 * target));
+        if (c < 5) c = (long)std::floor(ext / target);  // too few half cells: whole cells
         nc[d] = std::min(std::max(c, 1L), 4096L);
     }
     while (nc[0] * nc[1] * nc[2] > ncell_max) {
@@ -205,8 +182,8 @@ int make_grid(const Model &M, const nep_system *s, float skin, int ncell_max, Nb
         double cs = (double)s->box[d] / (double)nc[d];
         long m = (long)std::ceil(target / cs);
         if (m < 1) m = 1;
-        if (!s->pbc[d]) m = std::min(m, nc[d]);
-        if (s->pbc[d] && m > 2)
+        if (!s->pbc[d]) m = std::min(m, std::max(nc[d] - 1, 1L));
+        if (m > 2)
             return fail(NEP_ERR_UNSUPPORTED,
                         "periodic box length below half of r_c + skin needs images beyond +-2");
         a.nc[d] = (int)nc[d];
@@ -216,6 +193,12 @@ int make_grid(const Model &M, const nep_system *s, float skin, int ncell_max, Nb
         a.pbc[d] = s->pbc[d] ? 1 : 0;
     }
     a.ncell = (int)(nc[0] * nc[1] * nc[2]);
+    a.n_off = (2 * a.m[0] + 1) * (2 * a.m[1] + 1) * (2 * a.m[2] + 1);
+    // margin far above the float rounding of the cell coordinates, whose
+    // absolute error grows with the box length (about 1.2e-7 L)
+    const double lmax = std::max((double)s->box[0], std::max((double)s->box[1], (double)s->box[2]));
+    const double cull = reach * (1.0 + 1e-4) + 1e-6 * lmax + 1e-5;
+    a.cull2 = (float)(cull * cull);
     for (int k = 0; k < M.T * M.T; ++k) {
         double r = (double)M.rcR[k] + (double)skin;
         double ra = (double)M.rcA[k] + (double)skin;
@@ -269,6 +252,10 @@ int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, co
     a.cell_cursor = at<int32_t>(ws, L.cell_cursor);
     a.cell_list = at<int32_t>(ws, L.cell_list);
     a.scan_tmp = at<int32_t>(ws, L.scan_tmp);
+    a.cell_tmp = at<int32_t>(ws, L.cell_tmp);
+    a.pos_sorted = at<float4>(ws, L.pos_sorted);
+    a.segA = at<uint8_t>(ws, L.segA);
+    a.rowbuf = at<uint32_t>(ws, L.rowbuf);
     a.nbr = nb->nbr;
     a.rev = nb->rev;
     a.cnt = nb->cnt;
@@ -292,19 +279,21 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     for (int d = 0; d < 3; ++d) a.box[d] = s->box[d];
     a.pos4 = at<float4>(ws, L.pos4);
     a.nbr = nb->nbr;
+    a.rev = nb->rev;
     a.cnt = nb->cnt;
     a.params = M.d_params;
     a.tab = M.d_tab;
+    a.ann = M.d_ann;
     a.cut = make_cut(M);
     a.U = U ? U : at<float>(ws, L.U);
     a.bvec = at<float4>(ws, L.bvec);
     a.angbuf = at<float4>(ws, L.angbuf);
     a.fown = at<float4>(ws, L.fown);
     a.freeze = md ? nb->status : nullptr;
-    size_t lds = ((size_t)M.T * M.H * (ND + 2) + 1 + (size_t)M.T * M.T * TAB_PER_PAIR) * sizeof(float);
+    size_t lds = (size_t)M.T * M.T * TAB_PER_PAIR * sizeof(float);
     {
         TimedLaunch tl(0, st);
-        HIPCHK(launch_efv_main(M.T, a, lds, st));
+        HIPCHK(launch_efv_main(M.T, M.HP, a, lds, st));
     }
     GatherArgs g{};
     g.n = n;
@@ -444,9 +433,29 @@ int nep_model_create(const nep_hyper *h, const float *params, size_t n_params, n
             }
         }
     }
+    // network table per centre type: w0 transposed to [nu][mu], b0, w1, zero-padded
+    // to the built hidden width HP (padded neurons have zero weights and add nothing)
+    const int HP = H <= 8 ? 8 : H <= 16 ? 16 : H <= 32 ? 32 : 64;
+    std::vector<float> ann((size_t)T * (ND + 2) * HP + 1, 0.0f);
+    {
+        const float *w0 = params;
+        const float *b0 = params + (size_t)T * H * D;
+        const float *w1 = b0 + (size_t)T * H;
+        const float b1 = w1[(size_t)T * H];
+        for (int t = 0; t < T; ++t) {
+            float *o = ann.data() + (size_t)t * (ND + 2) * HP;
+            for (int mu = 0; mu < H; ++mu) {
+                for (int nu = 0; nu < ND; ++nu) o[(size_t)nu * HP + mu] = w0[((size_t)t * H + mu) * D + nu];
+                o[(size_t)ND * HP + mu] = b0[(size_t)t * H + mu];
+                o[(size_t)(ND + 1) * HP + mu] = w1[(size_t)t * H + mu];
+            }
+        }
+        ann[(size_t)T * (ND + 2) * HP] = b1;
+    }
     nep_model_t *m = new nep_model_t();
     m->m.T = T;
     m->m.H = H;
+    m->m.HP = HP;
     for (int k = 0; k < T * T; ++k) {
         m->m.rcR[k] = h->rc_R[k];
         m->m.rcA[k] = h->rc_A[k];
@@ -455,11 +464,14 @@ int nep_model_create(const nep_hyper *h, const float *params, size_t n_params, n
     hipError_t e = hipGetDevice(&m->m.device);
     if (e == hipSuccess) e = hipMalloc(&m->m.d_params, n_params * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&m->m.d_tab, tab.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&m->m.d_ann, ann.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(m->m.d_ann, ann.data(), ann.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->m.d_params, params, n_params * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->m.d_tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (m->m.d_params) (void)hipFree(m->m.d_params);
         if (m->m.d_tab) (void)hipFree(m->m.d_tab);
+        if (m->m.d_ann) (void)hipFree(m->m.d_ann);
         delete m;
         return fail(NEP_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
     }
@@ -471,6 +483,7 @@ int nep_model_destroy(nep_model m) {
     if (!m) return NEP_OK;
     if (m->m.d_params) (void)hipFree(m->m.d_params);
     if (m->m.d_tab) (void)hipFree(m->m.d_tab);
+    if (m->m.d_ann) (void)hipFree(m->m.d_ann);
     delete m;
     return NEP_OK;
 }
@@ -480,8 +493,8 @@ size_t nep_workspace_bytes(nep_model m, int n, int cap, int cap_A) {
     return ws_layout(m->m.T, n, cap, cap_A).total;
 }
 
-int nep_build_neighbors(nep_model model, const nep_system *s, nep_neighbors *nb, void *ws, size_t ws_bytes,
-                        void *stream) {
+int nep_build_neighbors(nep_model model, nep_system *s, nep_neighbors *nb, int wrap, void *ws,
+                        size_t ws_bytes, void *stream) {
     int rc;
     if ((rc = check_model(model))) return rc;
     const Model &M = model->m;
@@ -491,7 +504,7 @@ int nep_build_neighbors(nep_model model, const nep_system *s, nep_neighbors *nb,
     if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
     hipStream_t st = (hipStream_t)stream;
     NbArgs a;
-    if ((rc = fill_nb(M, s, nb, ws, L, 1, 0, a))) return rc;
+    if ((rc = fill_nb(M, s, nb, ws, L, 1, wrap ? 1 : 0, a))) return rc;
     {
         TimedLaunch tl(2, st);
         HIPCHK(launch_build(a, st));
@@ -517,7 +530,7 @@ int nep_compute_efv(nep_model model, const nep_system *s, const nep_neighbors *n
     // an empty system reduces zero blocks, so the totals come out as zero
     if (E_tot || W_tot)
         HIPCHK(launch_reduce(at<double>(ws, L.partial), s->n > 0 ? L.nblocks : 0, E_tot, W_tot, nullptr, nullptr,
-                             nullptr, nullptr, nullptr, nullptr, st));
+                             nullptr, nullptr, nullptr, nullptr, 0, 0, 0.0f, st));
     return NEP_OK;
 }
 
@@ -540,29 +553,43 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     const int n = s->n;
     if (n == 0) {
         mp->step += mp->n_steps;
+        mp->n_rebuilds = 0;
         return NEP_OK;
     }
-    MdCtx *C = nullptr;
-    if ((rc = md_ctx(C))) return rc;
     const int64_t step0 = mp->step;
     const int n_steps = mp->n_steps;
-    const double half_skin = 0.5 * (double)nb->skin;
-    mp->n_rebuilds = 0;
+    const float half_skin = 0.5f * nb->skin;
+    int32_t *ctrl = at<int32_t>(ws, L.ctrl);
     auto box_at = [&](int64_t stp, int d) -> float {
         return mp->strain_rate[d] != 0.0 ? (float)(mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)stp))
                                          : s->box[d];
     };
-    auto enqueue_build = [&]() -> int {
+    // box scale factor of the drift of step stp
+    auto lam_at = [&](int64_t stp, int d) -> double {
+        return mp->strain_rate[d] != 0.0 ? (1.0 + mp->strain_rate[d] * (double)(stp + 1)) /
+                                               (1.0 + mp->strain_rate[d] * (double)stp)
+                                         : 1.0;
+    };
+    // squared threshold on the unscaled predicted displacement for the drift of
+    // step stp: 2% below skin/2 covers rounding between the prediction and the
+    // drift itself; a strained box scales the displacement by lambda
+    auto gate_thr2 = [&](int64_t stp) -> float {
+        double lmax = std::max(lam_at(stp, 0), std::max(lam_at(stp, 1), lam_at(stp, 2)));
+        double t = 0.98 * (double)half_skin / std::max(lmax, 1.0);
+        return (float)(t * t);
+    };
+    // a build gated by ctrl[0], which the reduction just before it has set
+    auto enqueue_gated_build = [&]() -> int {
         NbArgs a;
         int r = fill_nb(M, s, nb, ws, L, 0, 1, a);
         if (r) return r;
+        a.ctrl = ctrl;
         TimedLaunch tl(2, st);
         HIPCHK(launch_build(a, st));
-        ++mp->n_rebuilds;
         return NEP_OK;
     };
-    HIPCHK(launch_clear_status(nb->status, st));
-    // how far the first drift takes every bead from its build position
+    HIPCHK(launch_clear_status(nb->status, ctrl, st));
+    // the first drift: does it take any bead beyond skin/2 of its build position?
     PredictArgs pa{};
     pa.n = n;
     pa.T = M.T;
@@ -579,19 +606,11 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     pa.partial = at<double>(ws, L.partial);
     HIPCHK(launch_predict(pa, st));
     HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr, nullptr, nullptr,
-                         nullptr, nb->status, C->dev + 8 * NSLOT, st));
-    HIPCHK(hipEventRecord(C->ev[NSLOT], st));
-    HIPCHK(hipEventSynchronize(C->ev[NSLOT]));
-    double prev[8];
-    std::memcpy(prev, C->host + 8 * NSLOT, sizeof prev);
-    bool rebuilt_prev = false;
-    if (prev[2] > 0.95 * half_skin) {
-        if ((rc = enqueue_build())) return rc;
-        rebuilt_prev = true;
-    }
-    std::vector<char> rebuilt((size_t)n_steps + 1, 0);
-    int completed = n_steps;
-    bool frozen = false;
+                         nullptr, nb->status, ctrl, 0, 0, gate_thr2(step0), st));
+    if ((rc = enqueue_gated_build())) return rc;
+    // Steps are queued without waiting for the device: the rebuild after each
+    // step is decided on the device from the exact position the next drift
+    // produces, and a failed rebuild freezes the remaining queued steps.
     for (int k = 0; k < n_steps; ++k) {
         const int64_t step = step0 + k;
         KickDriftArgs kd{};
@@ -611,54 +630,30 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         for (int d = 0; d < 3; ++d) {
             kd.lam[d] = 1.0f;
             if (mp->strain_rate[d] != 0.0) {
-                double Lo = mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)step);
-                double Ln = mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)(step + 1));
-                kd.lam[d] = (float)(Ln / Lo);
-                s->box[d] = (float)Ln;
+                kd.lam[d] = (float)lam_at(step, d);
+                s->box[d] = box_at(step + 1, d);
             }
             kd.box[d] = s->box[d];
             kd.pbc[d] = s->pbc[d] ? 1 : 0;
         }
-        kd.half_skin2 = 0.25f * nb->skin * nb->skin;
+        kd.half_skin2 = half_skin * half_skin;
         kd.status = nb->status;
         {
             TimedLaunch tl(3, st);
             HIPCHK(launch_kick_drift(kd, st));
         }
         if ((rc = launch_efv(M, s, nb, U, F, nullptr, false, ws, L, st, true, v, mp))) return rc;
+        const int scheduled = ((step + 1) % mp->rebuild_every) == 0;
         HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
                              E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr, mp->pair_counts,
-                             nb->status, C->dev + 8 * (k % NSLOT), st));
-        HIPCHK(hipEventRecord(C->ev[k % NSLOT], st));
-        if (k >= 1) {
-            // the record of step k-1 (the device is busy with step k meanwhile)
-            HIPCHK(hipEventSynchronize(C->ev[(k - 1) % NSLOT]));
-            std::memcpy(prev, C->host + 8 * ((k - 1) % NSLOT), sizeof prev);
-            rebuilt_prev = rebuilt[k - 1] != 0;
-            if ((int)prev[5] & FREEZE_MASK) {  // a build after step k-2 failed
-                completed = k - 1;
-                frozen = true;
-                break;
-            }
-        }
-        // displacement from the build position at the force evaluation of
-        // step k+1, bounded from the exact prediction one step back:
-        //   no rebuild since:  |x_{k+1} + d_k - ref| + |d_{k+1}|
-        //   rebuilt after k-1: |d_k| + |d_{k+1}|,   |d_{k+1}| <= |d_k| + dt^2 |a|
-        double bound = (rebuilt_prev ? 0.0 : prev[2]) + (rebuilt_prev ? 2.0 : 1.0) * prev[3] + 2.0 * prev[4];
-        const bool scheduled = ((step + 1) % mp->rebuild_every) == 0;
-        if (scheduled || bound > 0.95 * half_skin) {
-            if ((rc = enqueue_build())) return rc;
-            rebuilt[k] = 1;
-        }
+                             nb->status, ctrl, 1, scheduled, gate_thr2(step + 1), st));
+        if ((rc = enqueue_gated_build())) return rc;
     }
-    if (!frozen && n_steps > 0) {
-        HIPCHK(hipEventSynchronize(C->ev[(n_steps - 1) % NSLOT]));
-        std::memcpy(prev, C->host + 8 * ((n_steps - 1) % NSLOT), sizeof prev);
-        if ((int)prev[5] & FREEZE_MASK) completed = n_steps - 1;
-    }
+    int32_t c[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(c, ctrl, sizeof c, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    mp->step = step0 + completed;
+    mp->n_rebuilds = c[1];
+    mp->step = step0 + c[2];
     for (int d = 0; d < 3; ++d) s->box[d] = box_at(mp->step, d);
     return read_status(nb, nullptr, st);
 }

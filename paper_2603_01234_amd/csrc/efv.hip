@@ -20,6 +20,8 @@
 //               W_i = sum_j r_ij (x) dU_j/dr_ji; fixed-order block sums of U,
 //               W and (for MD) the kinetic energy; optional second half-kick.
 // k_reduce      fixed-order FP64 reduction of the block sums.
+#include <type_traits>
+
 #include "nep_internal.h"
 
 namespace nep {
@@ -54,12 +56,12 @@ struct PairGeom {
     float dx, dy, dz, d2;
 };
 
-__device__ __forceinline__ PairGeom pair_geom(const float4 *__restrict__ pos4, uint32_t e,
-                                              const float4 &pi, const float box[3]) {
+
+__device__ __forceinline__ PairGeom geom_of(uint32_t e, const float4 &pj, const float4 &pi,
+                                            const float box[3]) {
     PairGeom g;
     int nx, ny, nz;
     decode(e, g.j, nx, ny, nz);
-    float4 pj = pos4[g.j];
     g.dx = (pj.x + (float)nx * box[0]) - pi.x;
     g.dy = (pj.y + (float)ny * box[1]) - pi.y;
     g.dz = (pj.z + (float)nz * box[2]) - pi.z;
@@ -68,25 +70,156 @@ __device__ __forceinline__ PairGeom pair_geom(const float4 *__restrict__ pos4, u
     return g;
 }
 
+// Neighbour stream of one row with software prefetch: the entry two slots
+// ahead and the position one slot ahead are in flight while the current pair
+// is processed.
+struct RowStream {
+    const uint32_t *__restrict__ nbr;
+    const float4 *__restrict__ pos4;
+    int n, i, cnt;
+    uint32_t e_cur, e_nxt;
+    float4 p_cur;
+    __device__ __forceinline__ void start(const uint32_t *nb, const float4 *pp, int n_, int i_, int c) {
+        nbr = nb;
+        pos4 = pp;
+        n = n_;
+        i = i_;
+        cnt = c;
+        e_cur = c > 0 ? nbr[i] : 0u;
+        e_nxt = c > 1 ? nbr[(size_t)n + i] : 0u;
+        p_cur = c > 0 ? pos4[e_cur & J_MASK] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    __device__ __forceinline__ void next(int p, uint32_t &e, float4 &pj) {
+        e = e_cur;
+        pj = p_cur;
+        e_cur = e_nxt;
+        if (p + 2 < cnt) e_nxt = nbr[(size_t)(p + 2) * n + i];
+        if (p + 1 < cnt) p_cur = pos4[e_cur & J_MASK];
+    }
+};
+
+
+// Tables read through the constant address space: with wave-uniform addresses
+// (one type) these become scalar loads whose values feed the FMAs as SGPR
+// operands, so the weights never occupy vector registers.
+typedef const __attribute__((address_space(4))) float *const_fp;
+
 template <int NT>
-__global__ __launch_bounds__(BLOCK) void k_efv_main(EfvArgs a) {
+using table_ptr = typename std::conditional<NT == 1, const_fp, const float *>::type;
+
+// Descriptor from the pair sums, the network (Eq. 2) with its gradient, the
+// radial back-propagation coefficients (written to bvec_out), and the angular
+// gradient folded into A (D_{n,lm} = dU/dq_nl 2 N2_lm A_{n,lm}).  ti is
+// wave-uniform, so every table read is a scalar load.
+template <int NT, int HP>
+__device__ __forceinline__ void network(const int ti, const const_fp TB, const const_fp AN,
+                                        const float S[NT][KB], float A[NA][LM], float *U_out,
+                                        float4 *bvec_out) {
+    asm volatile("" ::: "memory");
+    // ---------------- descriptor and network (Eq. 2), nu-outer ----------------
+    const const_fp an = AN + ti * (ND + 2) * HP;  // w0T[ND][HP], b0[HP], w1[HP]
+    float z[HP];
+#pragma unroll
+    for (int m = 0; m < HP; ++m) z[m] = -an[ND * HP + m];
+    // The memory barriers below keep one row of HP weights in flight at a
+    // time; without them the weight loads are hoisted and spill.
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        float qv = 0.0f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const const_fp cRp = TB + (ti * NT + t) * TAB_PER_PAIR;
+#pragma unroll
+            for (int k = 0; k < KB; ++k) qv += cRp[q * KB + k] * S[t][k];
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int m = 0; m < HP; ++m) z[m] += an[q * HP + m] * qv;
+    }
+#pragma unroll
+    for (int L = 1; L <= 4; ++L)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            float qv = 0.0f;
+#pragma unroll
+            for (int l = 0; l < LM; ++l)
+                if (lm_l(l) == L) qv += N2[l] * A[q][l] * A[q][l];
+            const int nu = NR + (L - 1) * NA + q;
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int m = 0; m < HP; ++m) z[m] += an[nu * HP + m] * qv;
+        }
+    float U = -AN[NT * (ND + 2) * HP];
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int m = 0; m < HP; ++m) {
+        const float h = tanh_nobranch(z[m]);
+        const float w1m = an[(ND + 1) * HP + m];
+        U += w1m * h;
+        z[m] = w1m * (1.0f - h * h);  // dU/dz_m
+    }
+    *U_out = U;
+
+    // dU/dq, nu-outer: radial part kept, angular part folded into
+    // D_{n,lm} = dU/dq_nl * 2 N2_lm A_{n,lm}  (in place of A)
+    float dr[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        asm volatile("" ::: "memory");
+        float acc = 0.0f;
+#pragma unroll
+        for (int m = 0; m < HP; ++m) acc += z[m] * an[q * HP + m];
+        dr[q] = acc;
+    }
+#pragma unroll
+    for (int L = 1; L <= 4; ++L)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int nu = NR + (L - 1) * NA + q;
+            asm volatile("" ::: "memory");
+            float acc = 0.0f;
+#pragma unroll
+            for (int m = 0; m < HP; ++m) acc += z[m] * an[nu * HP + m];
+#pragma unroll
+            for (int l = 0; l < LM; ++l)
+                if (lm_l(l) == L) A[q][l] *= 2.0f * N2[l] * acc;
+        }
+    asm volatile("" ::: "memory");
+
+    // radial back-propagation coefficients per neighbour type:
+    //   beta_k = sum_n dU/dq_n c'_nk   (k = 0 uses c'_n0 = c_n0 + sum_k c_nk)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const const_fp cRp = TB + (ti * NT + t) * TAB_PER_PAIR;
+        float be[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc += dr[q] * cRp[q * KB + k];
+            be[k] = acc;
+        }
+        float4 *dst = bvec_out + (size_t)t * 3;
+        dst[0] = make_float4(be[0], be[1], be[2], be[3]);
+        dst[1] = make_float4(be[4], be[5], be[6], be[7]);
+        dst[2] = make_float4(be[8], 0.0f, 0.0f, 0.0f);
+    }
+
+}
+
+template <int NT, int HP>
+__global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
     extern __shared__ float smem[];
-    const int H = a.H;
-    const float *__restrict__ P;
-    const float *__restrict__ TB;
+    table_ptr<NT> TB;
     if constexpr (NT > 1) {
-        // per-lane type indices: stage the network and coefficient tables in LDS
-        int np = NT * H * (ND + 2) + 1;
-        int nt = NT * NT * TAB_PER_PAIR;
-        for (int k = threadIdx.x; k < np; k += BLOCK) smem[k] = a.params[k];
-        for (int k = threadIdx.x; k < nt; k += BLOCK) smem[np + k] = a.tab[k];
+        // per-pair type indices vary across lanes: stage the pair tables in LDS
+        const int nt = NT * NT * TAB_PER_PAIR;
+        for (int k = threadIdx.x; k < nt; k += BLOCK) smem[k] = a.tab[k];
         __syncthreads();
-        P = smem;
-        TB = smem + np;
+        TB = smem;
     } else {
-        // one type: every coefficient address is wave-uniform (scalar loads)
-        P = a.params;
-        TB = a.tab;
+        // one type: every table address is wave-uniform (scalar loads)
+        TB = (const_fp)a.tab;
     }
     if (a.freeze && (a.freeze[0] & FREEZE_MASK)) return;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -110,31 +243,37 @@ __global__ __launch_bounds__(BLOCK) void k_efv_main(EfvArgs a) {
         for (int l = 0; l < LM; ++l) A[q][l] = 0.0f;
 
     // ---------------- pass 1: descriptor sums ----------------
+    RowStream rs;
+    rs.start(a.nbr, a.pos4, n, i, cR);
     for (int p = 0; p < cR; ++p) {
-        PairGeom g = pair_geom(a.pos4, a.nbr[(size_t)p * n + i], pi, a.box);
+        uint32_t e;
+        float4 pj;
+        rs.next(p, e, pj);
+        const PairGeom g = geom_of(e, pj, pi, a.box);
         const int tj = (NT == 1) ? 0 : g.tj;
         const int tp = ti * NT + tj;
         if (g.d2 < a.cut.rcR2[tp]) {
-            float r = sqrtf(g.d2);
-            float t = r * a.cut.inv_rcR[tp];
-            float hfc = 0.25f * (1.0f + cospif(t));
-            float s1 = t - 1.0f;
+            const float ir = __builtin_amdgcn_rsqf(g.d2);
+            const float r = g.d2 * ir;
+            const float t = r * a.cut.inv_rcR[tp];
+            const float hfc = 0.25f * (1.0f + cos_pi(t));
+            const float s1 = t - 1.0f;
             float T[KB];
             cheb_T(2.0f * s1 * s1 - 1.0f, T);
 #pragma unroll
             for (int t2 = 0; t2 < NT; ++t2) {
-                float w = (NT == 1 || tj == t2) ? hfc : 0.0f;
+                const float w = (NT == 1 || tj == t2) ? hfc : 0.0f;
                 S[t2][0] += w;
 #pragma unroll
                 for (int k = 1; k < KB; ++k) S[t2][k] += w * T[k];
             }
             if (p < cA && g.d2 < a.cut.rcA2[tp]) {
-                float tA = r * a.cut.inv_rcA[tp];
-                float hA = 0.25f * (1.0f + cospif(tA));
-                float sA = tA - 1.0f;
+                const float tA = r * a.cut.inv_rcA[tp];
+                const float hA = 0.25f * (1.0f + cos_pi(tA));
+                const float sA = tA - 1.0f;
                 float TA[KB];
                 cheb_T(2.0f * sA * sA - 1.0f, TA);
-                const float *__restrict__ cAp = TB + tp * TAB_PER_PAIR + NR * KB;
+                const table_ptr<NT> cAp = TB + tp * TAB_PER_PAIR + NR * KB;
                 float gv[NA];
 #pragma unroll
                 for (int q = 0; q < NA; ++q) {
@@ -143,111 +282,60 @@ __global__ __launch_bounds__(BLOCK) void k_efv_main(EfvArgs a) {
                     for (int k = 1; k < KB; ++k) G += cAp[q * KB + k] * TA[k];
                     gv[q] = hA * G;
                 }
-                float ir = 1.0f / r;
-                float Pl[LM];
-                harmonics(g.dx * ir, g.dy * ir, g.dz * ir, Pl);
-#pragma unroll
-                for (int q = 0; q < NA; ++q)
-#pragma unroll
-                    for (int l = 0; l < LM; ++l) A[q][l] += gv[q] * Pl[l];
+                accumulate_harmonics(g.dx * ir, g.dy * ir, g.dz * ir, gv, A);
             }
         }
     }
 
-    // ---------------- descriptor ----------------
-    float qd[ND];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const float *__restrict__ cRp = TB + (ti * NT + t) * TAB_PER_PAIR;
-#pragma unroll
-            for (int k = 0; k < KB; ++k) acc += cRp[q * KB + k] * S[t][k];
+    // ---------------- descriptor, network (Eq. 2), back-propagation ----------------
+    // evaluated with a wave-uniform centre type so the weights are scalar loads;
+    // several types in one wave are handled one after the other
+    if constexpr (NT == 1) {
+        network<NT, HP>(0, (const_fp)a.tab, (const_fp)a.ann, S, A, a.U + i, a.bvec + (size_t)i * NT * 3);
+    } else {
+        // the lane test goes through the ballot bit, not ti == tu, so the
+        // compiler cannot substitute the per-lane ti into the table address
+        uint64_t todo = __ballot(1);
+        const int lane = __lane_id();
+        while (todo) {
+            const int lead = __ffsll((unsigned long long)todo) - 1;
+            const int tu = __builtin_amdgcn_readfirstlane(__shfl(ti, lead));
+            const uint64_t mine = __ballot(ti == tu);
+            if ((mine >> lane) & 1ull)
+                network<NT, HP>(tu, (const_fp)a.tab, (const_fp)a.ann, S, A, a.U + i,
+                                a.bvec + (size_t)i * NT * 3);
+            todo &= ~mine;
         }
-        qd[q] = acc;
     }
-#pragma unroll
-    for (int q = 0; q < NA; ++q) {
-        float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int l = 0; l < LM; ++l) s[lm_l(l) - 1] += N2[l] * A[q][l] * A[q][l];
-#pragma unroll
-        for (int L = 0; L < 4; ++L) qd[NR + L * NA + q] = s[L];
-    }
-
-    // ---------------- network (Eq. 2) and dU/dq ----------------
-    const float *__restrict__ w0 = P + ti * H * ND;
-    const float *__restrict__ b0 = P + NT * H * ND + ti * H;
-    const float *__restrict__ w1 = P + NT * H * ND + NT * H + ti * H;
-    const float b1 = P[NT * H * ND + 2 * NT * H];
-    float U = -b1;
-    float dq[ND];
-#pragma unroll
-    for (int v = 0; v < ND; ++v) dq[v] = 0.0f;
-    for (int mu = 0; mu < H; ++mu) {
-        float z = -b0[mu];
-#pragma unroll
-        for (int v = 0; v < ND; ++v) z += w0[mu * ND + v] * qd[v];
-        float h = tanhf(z);
-        float w1m = w1[mu];
-        U += w1m * h;
-        float s = w1m * (1.0f - h * h);
-#pragma unroll
-        for (int v = 0; v < ND; ++v) dq[v] += s * w0[mu * ND + v];
-    }
-    a.U[i] = U;
-
-    // radial back-propagation coefficients per neighbour type
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const float *__restrict__ cRp = TB + (ti * NT + t) * TAB_PER_PAIR;
-        float be[12];
-#pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int q = 0; q < NR; ++q) acc += dq[q] * cRp[q * KB + k];
-            be[k] = acc;
-        }
-        be[9] = be[10] = be[11] = 0.0f;
-        float4 *dst = a.bvec + ((size_t)i * NT + t) * 3;
-        dst[0] = make_float4(be[0], be[1], be[2], be[3]);
-        dst[1] = make_float4(be[4], be[5], be[6], be[7]);
-        dst[2] = make_float4(be[8], 0.0f, 0.0f, 0.0f);
-    }
-
-    // D_{n,lm} = dU/dq_nl * dq_nl/dA_{n,lm} = dU/dq_nl * 2 N2_lm A_{n,lm}
-#pragma unroll
-    for (int q = 0; q < NA; ++q)
-#pragma unroll
-        for (int l = 0; l < LM; ++l) A[q][l] *= 2.0f * N2[l] * dq[NR + (lm_l(l) - 1) * NA + q];
-
+    asm volatile("" ::: "memory");
     // ---------------- pass 2: angular pair partials ----------------
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    rs.start(a.nbr, a.pos4, n, i, cA);
     for (int p = 0; p < cA; ++p) {
-        PairGeom g = pair_geom(a.pos4, a.nbr[(size_t)p * n + i], pi, a.box);
+        uint32_t e;
+        float4 pj;
+        rs.next(p, e, pj);
+        const PairGeom g = geom_of(e, pj, pi, a.box);
         const int tj = (NT == 1) ? 0 : g.tj;
         const int tp = ti * NT + tj;
         float ox = 0.0f, oy = 0.0f, oz = 0.0f;
         if (g.d2 < a.cut.rcA2[tp]) {
-            float r = sqrtf(g.d2);
-            float ir = 1.0f / r;
-            float ux = g.dx * ir, uy = g.dy * ir, uz = g.dz * ir;
-            float inv = a.cut.inv_rcA[tp];
-            float tA = r * inv;
-            float sp, cp;
-            sincospif(tA, &sp, &cp);
-            float hA = 0.25f * (1.0f + cp);
-            float dhA = -0.25f * PI_F * sp * inv;
-            float sA = tA - 1.0f;
-            float xA = 2.0f * sA * sA - 1.0f;
-            float xp = 4.0f * sA * inv;
+            const float ir = __builtin_amdgcn_rsqf(g.d2);
+            const float r = g.d2 * ir;
+            const float ux = g.dx * ir, uy = g.dy * ir, uz = g.dz * ir;
+            const float inv = a.cut.inv_rcA[tp];
+            const float tA = r * inv;
+            const float sp = sin_pi(tA), cp = cos_pi(tA);
+            const float hA = 0.25f * (1.0f + cp);
+            const float dhA = -0.25f * PI_F * sp * inv;
+            const float sA = tA - 1.0f;
+            const float xA = 2.0f * sA * sA - 1.0f;
+            const float xp = 4.0f * sA * inv;
             float TA[KB], UA[KB - 1];
             cheb_T(xA, TA);
             cheb_U(xA, UA);
-            const float *__restrict__ cAp = TB + tp * TAB_PER_PAIR + NR * KB;
-            const float *__restrict__ cAd = cAp + NA * KB;
+            const table_ptr<NT> cAp = TB + tp * TAB_PER_PAIR + NR * KB;
+            const table_ptr<NT> cAd = cAp + NA * KB;
             float gv[NA], gp[NA];
 #pragma unroll
             for (int q = 0; q < NA; ++q) {
@@ -260,28 +348,20 @@ __global__ __launch_bounds__(BLOCK) void k_efv_main(EfvArgs a) {
                 gv[q] = hA * G;
                 gp[q] = dhA * G + hA * xp * Gp;
             }
-            float Pl[LM], Bv[LM];
-            harmonics(ux, uy, uz, Pl);
-            float s = 0.0f;
-#pragma unroll
-            for (int l = 0; l < LM; ++l) {
-                float B = 0.0f, Bp = 0.0f;
-#pragma unroll
-                for (int q = 0; q < NA; ++q) {
-                    B += A[q][l] * gv[q];
-                    Bp += A[q][l] * gp[q];
-                }
-                s += Bp * Pl[l];
-                Bv[l] = B;
-            }
-            float vx = 0.0f, vy = 0.0f, vz = 0.0f;
-            harmonics_grad(ux, uy, uz, Bv, vx, vy, vz);
-            float uv = ux * vx + uy * vy + uz * vz;
+            float s = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
+            force_harmonics(ux, uy, uz, A, gv, gp, s, vx, vy, vz);
+            const float uv = ux * vx + uy * vy + uz * vz;
             ox = s * ux + (vx - uv * ux) * ir;
             oy = s * uy + (vy - uv * uy) * ir;
             oz = s * uz + (vz - uv * uz) * ir;
         }
-        a.angbuf[(size_t)p * n + i] = make_float4(ox, oy, oz, 0.0f);
+        // deliver dU_i/dr_ij to the slot where j lists i; a slot whose mirror
+        // does not exist (rounding at the list edge) is zeroed by its owner
+        const int r = a.rev[(size_t)p * n + i];
+        if (r >= 0)
+            a.angbuf[r] = make_float4(ox, oy, oz, 0.0f);
+        else
+            a.angbuf[(size_t)p * n + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         fx += ox;
         fy += oy;
         fz += oz;
@@ -298,7 +378,7 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
     const int i = tile * BLOCK + threadIdx.x;
     const int n = a.n;
     double acc[NPART];
-    float mx[NMAX] = {0.0f, 0.0f, 0.0f};
+    float mx[NMAX] = {0.0f};
 #pragma unroll
     for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
     int nR_in = 0, nA_in = 0;  // pairs inside the interaction cutoffs (work accounting)
@@ -321,19 +401,23 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
         float W[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) W[c] = 0.0f;
+        RowStream rs;
+        rs.start(a.nbr, a.pos4, n, i, cR);
         for (int p = 0; p < cR; ++p) {
-            PairGeom g = pair_geom(a.pos4, a.nbr[(size_t)p * n + i], pi, a.box);
+            uint32_t e;
+            float4 pj;
+            rs.next(p, e, pj);
+            const PairGeom g = geom_of(e, pj, pi, a.box);
             const int tj = (NT == 1) ? 0 : g.tj;
             const int tp = ti * NT + tj;
             if (g.d2 < a.cut.rcR2[tp]) {
                 ++nR_in;
                 nA_in += (p < cA && g.d2 < a.cut.rcA2[tp]) ? 1 : 0;
-                float r = sqrtf(g.d2);
-                float ir = 1.0f / r;
-                float inv = a.cut.inv_rcR[tp];
-                float t = r * inv;
-                float sp, cp;
-                sincospif(t, &sp, &cp);
+                const float ir = __builtin_amdgcn_rsqf(g.d2);
+                const float r = g.d2 * ir;
+                const float inv = a.cut.inv_rcR[tp];
+                const float t = r * inv;
+                const float sp = sin_pi(t), cp = cos_pi(t);
                 float hfc = 0.25f * (1.0f + cp);
                 float dh = -0.25f * PI_F * sp * inv;
                 float s1 = t - 1.0f;
@@ -353,7 +437,7 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
                 }
                 // neighbour's coefficients for this bead's type
                 const float4 *src = a.bvec + ((size_t)g.j * NT + ti) * 3;
-                float4 v0 = src[0], v1 = src[1], v2 = src[2];
+                const float4 v0 = src[0], v1 = src[1], v2 = src[2];
                 float c[KB] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
                 float Si = b[0], Sj = c[0], Di = 0.0f, Dj = 0.0f;
 #pragma unroll
@@ -379,9 +463,8 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
                 }
             }
             if (p < cA) {
-                int q = a.rev[(size_t)p * n + i];
-                if (q >= 0) {
-                    float4 fj = a.angbuf[q];  // dU_j/dr_ji, angular part
+                {
+                    const float4 fj = a.angbuf[(size_t)p * n + i];  // dU_j/dr_ji, angular part
                     Fx -= fj.x;
                     Fy -= fj.y;
                     Fz -= fj.z;
@@ -417,13 +500,12 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
             a.v[2 * n + i] = vz;
             acc[10] = 0.5 * (double)a.mass[ti] * ((double)vx * vx + (double)vy * vy + (double)vz * vz) /
                       (double)ACCEL;
-            // next drift d = dt (v + dt/2 a): displacement from the build
-            // reference after it, |d|, and dt^2 |a| (rebuild prediction)
+            // where the next drift takes the bead, x + dt (v + dt/2 a), in the
+            // same float operations as the kick-drift kernel: its distance
+            // from the build reference decides the rebuild after this step
             float ddx = a.dt * (vx + k * Fx), ddy = a.dt * (vy + k * Fy), ddz = a.dt * (vz + k * Fz);
-            float px = pi.x + ddx - a.ref[i], py = pi.y + ddy - a.ref[n + i], pz = pi.z + ddz - a.ref[2 * n + i];
+            float px = (pi.x + ddx) - a.ref[i], py = (pi.y + ddy) - a.ref[n + i], pz = (pi.z + ddz) - a.ref[2 * n + i];
             mx[0] = px * px + py * py + pz * pz;
-            mx[1] = ddx * ddx + ddy * ddy + ddz * ddz;
-            mx[2] = 2.0f * a.dt * k * sqrtf(Fx * Fx + Fy * Fy + Fz * Fz);
         }
     }
     if (MD) {
@@ -453,16 +535,14 @@ __global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
     __shared__ float redm[NMAX][BLOCK];
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     const int n = a.n;
-    float mx[NMAX] = {0.0f, 0.0f, 0.0f};
+    float mx[NMAX] = {0.0f};
     if (i < n) {
         int t = min((int)a.type[i], a.T - 1);
         float k = a.half_dt_accel * a.inv_mass[t];
         float Fx = a.F[i], Fy = a.F[n + i], Fz = a.F[2 * n + i];
         float ddx = a.dt * (a.v[i] + k * Fx), ddy = a.dt * (a.v[n + i] + k * Fy), ddz = a.dt * (a.v[2 * n + i] + k * Fz);
-        float px = a.x[i] + ddx - a.ref[i], py = a.y[i] + ddy - a.ref[n + i], pz = a.z[i] + ddz - a.ref[2 * n + i];
+        float px = (a.x[i] + ddx) - a.ref[i], py = (a.y[i] + ddy) - a.ref[n + i], pz = (a.z[i] + ddz) - a.ref[2 * n + i];
         mx[0] = px * px + py * py + pz * pz;
-        mx[1] = ddx * ddx + ddy * ddy + ddz * ddz;
-        mx[2] = 2.0f * a.dt * k * sqrtf(Fx * Fx + Fy * Fy + Fz * Fz);
     }
 #pragma unroll
     for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = 0.0;
@@ -485,14 +565,15 @@ hipError_t launch_predict(const PredictArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Fixed-order FP64 reduction of the block partials.  In MD mode (status and
-// info given) it also takes the maxima of the rebuild prediction and writes
-// one info record straight into pinned host memory:
-//   info = {E, K, max|x + d - ref|, max|d|, max dt^2|a|, status[0..2]}
-// Once the status carries a freeze flag the energy outputs are left alone.
+// Fixed-order FP64 reduction of the block partials.  In MD mode (ctrl given)
+// it also sets the rebuild gate ctrl[0] for the build launched right after it:
+// on when a rebuild is due by schedule, or when the next drift would take some
+// bead farther than sqrt(thr2) from its build reference (the block maxima of
+// the squared distance).  After a step (md_step) it counts the completed steps
+// in ctrl[2].  Once the status carries a freeze flag only the gate is written.
 __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double *E_tot,
                          double *W_tot, double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, double *info) {
+                         const int32_t *status, int32_t *ctrl, int md_step, int force_build, float thr2) {
     __shared__ double red[NPART + NMAX][BLOCK];
     double acc[NPART + NMAX];
 #pragma unroll
@@ -516,15 +597,9 @@ __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double
         __syncthreads();
     }
     const int st0 = status ? status[0] : 0;
-    if (threadIdx.x == 0 && info) {
-        info[0] = red[0][0];
-        info[1] = red[10][0];
-        info[2] = sqrt(red[NPART][0]);
-        info[3] = sqrt(red[NPART + 1][0]);
-        info[4] = red[NPART + 2][0];
-        info[5] = (double)st0;
-        info[6] = (double)status[1];
-        info[7] = (double)status[2];
+    if (threadIdx.x == 0 && ctrl) {
+        ctrl[0] = (force_build || red[NPART][0] > (double)thr2) ? 1 : 0;
+        if (md_step && !(st0 & FREEZE_MASK)) ctrl[2] += 1;
     }
     if (st0 & FREEZE_MASK) return;
     if (threadIdx.x == 0) {
@@ -542,26 +617,38 @@ __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double
 
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
                          double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, double *info, hipStream_t s) {
+                         const int32_t *status, int32_t *ctrl, int md_step, int force_build, float thr2,
+                         hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(BLOCK), 0, s, partial, nblocks, E_tot, W_tot, K_tot,
-                       E_slot, K_slot, counts, status, info);
+                       E_slot, K_slot, counts, status, ctrl, md_step, force_build, thr2);
+    return hipGetLastError();
+}
+
+template <int NT, int HP>
+static hipError_t main_t(const EfvArgs &a, size_t lds, hipStream_t s) {
+    int nb = (a.n + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL((k_efv_main<NT, HP>), dim3(nb), dim3(BLOCK), NT > 1 ? lds : 0, s, a);
     return hipGetLastError();
 }
 
 template <int NT>
-static hipError_t main_t(const EfvArgs &a, size_t lds, hipStream_t s) {
-    int nb = (a.n + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL(k_efv_main<NT>, dim3(nb), dim3(BLOCK), NT > 1 ? lds : 0, s, a);
-    return hipGetLastError();
+static hipError_t main_nt(int HP, const EfvArgs &a, size_t lds, hipStream_t s) {
+    switch (HP) {
+        case 8: return main_t<NT, 8>(a, lds, s);
+        case 16: return main_t<NT, 16>(a, lds, s);
+        case 32: return main_t<NT, 32>(a, lds, s);
+        case 64: return main_t<NT, 64>(a, lds, s);
+    }
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_efv_main(int T, const EfvArgs &a, size_t lds, hipStream_t s) {
+hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     switch (T) {
-        case 1: return main_t<1>(a, lds, s);
-        case 2: return main_t<2>(a, lds, s);
-        case 3: return main_t<3>(a, lds, s);
-        case 4: return main_t<4>(a, lds, s);
+        case 1: return main_nt<1>(HP, a, lds, s);
+        case 2: return main_nt<2>(HP, a, lds, s);
+        case 3: return main_nt<3>(HP, a, lds, s);
+        case 4: return main_nt<4>(HP, a, lds, s);
     }
     return hipErrorInvalidValue;
 }

@@ -6,25 +6,47 @@
 //   1. bin:     cell index per bead, per-cell counts (integer atomics), status
 //               checks (non-finite, periodic coordinate outside [0, L))
 //   2. scan:    exclusive prefix sum of the counts -> cell start offsets
-//   3. fill:    scatter bead indices into their cells, then sort every cell
-//               by index so the cell contents do not depend on atomic order
+//   3. fill:    scatter bead indices into their cells (atomic order), then
+//               give every bead its rank by index within its cell, so cell
+//               contents and a cell-ordered copy of the positions are in one
+//               canonical order whatever the atomics did
 //   4. rows:    one thread per bead walks the (2m+1)^3 neighbour cells in a
-//               fixed order and applies the exact float32 predicate; angular
-//               candidates are written from the front of the row, the others
-//               from the back and then moved behind them
-//   5. reverse: for every angular entry, the slot of the mirrored entry
+//               fixed order over the cell-ordered positions and applies the
+//               exact float32 predicate; angular candidates are written from
+//               the front of the row, the others from the back and then moved
+//               behind them; the angular count before every cell offset is
+//               kept per row
+//   5. reverse: for every angular entry, the mirrored entry is searched only
+//               in the mirrored cell offset's segment of the neighbour's row
 #include "nep_internal.h"
 
 namespace nep {
 
-__global__ void k_nb_clear(int ncell, int32_t *cell_count, int32_t *status, int clear_status) {
+// A build inside an MD run is skipped when the reduction before it found no
+// bead close enough to skin/2 and no rebuild was due (ctrl[0] == 0), and once
+// the run is frozen after a failed build.  The test is uniform over the grid.
+__device__ __forceinline__ bool build_off(const int32_t *ctrl, const int32_t *status, int clear_status) {
+    if (ctrl && ctrl[0] == 0) return true;
+    return !clear_status && (status[0] & FREEZE_MASK);
+}
+__device__ __forceinline__ bool build_off(const NbArgs &a) { return build_off(a.ctrl, a.status, a.clear_status); }
+
+__global__ void k_nb_clear(int ncell, int32_t *cell_count, int32_t *status, int clear_status, int32_t *ctrl) {
+    if (build_off(ctrl, status, clear_status)) return;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     for (int c = t; c < ncell; c += gridDim.x * blockDim.x) cell_count[c] = 0;
     if (clear_status && t < 4) status[t] = 0;
+    if (ctrl && t == 0) ctrl[1] += 1;
 }
 
-hipError_t launch_clear_status(int32_t *status, hipStream_t s) {
-    hipLaunchKernelGGL(k_nb_clear, dim3(1), dim3(64), 0, s, 0, (int32_t *)nullptr, status, 1);
+__global__ void k_md_clear(int32_t *status, int32_t *ctrl) {
+    int t = threadIdx.x;
+    if (t < 4) status[t] = 0;
+    if (ctrl && t < 4) ctrl[t] = 0;
+}
+
+hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(k_md_clear, dim3(1), dim3(64), 0, s, status, ctrl);
     return hipGetLastError();
 }
 
@@ -44,7 +66,7 @@ __device__ __forceinline__ float wrap_coord(float x, float L) {
 }
 
 __global__ void k_nb_bin(NbArgs a) {
-    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
+    if (build_off(a)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     float p[3] = {a.x[i], a.y[i], a.z[i]};
@@ -79,7 +101,8 @@ __global__ void k_nb_bin(NbArgs a) {
 // scans the block totals serially in chunks; a last pass adds the offsets.
 constexpr int SCAN_B = 1024;
 
-__global__ void k_scan_local(const int32_t *in, int32_t *out, int32_t *block_sums, int n) {
+__global__ void k_scan_local(const int32_t *in, int32_t *out, int32_t *block_sums, int n, NbArgs a) {
+    if (build_off(a)) return;
     __shared__ int32_t s[SCAN_B];
     int base = blockIdx.x * SCAN_B;
     int t = threadIdx.x;
@@ -101,7 +124,8 @@ __global__ void k_scan_local(const int32_t *in, int32_t *out, int32_t *block_sum
     if (t == 0) block_sums[blockIdx.x] = s[SCAN_B - 1];
 }
 
-__global__ void k_scan_blocks(int32_t *block_sums, int nb, int32_t *total_out) {
+__global__ void k_scan_blocks(int32_t *block_sums, int nb, int32_t *total_out, NbArgs a) {
+    if (build_off(a)) return;
     if (threadIdx.x != 0) return;
     int32_t run = 0;
     for (int b = 0; b < nb; ++b) {
@@ -112,7 +136,8 @@ __global__ void k_scan_blocks(int32_t *block_sums, int nb, int32_t *total_out) {
     *total_out = run;
 }
 
-__global__ void k_scan_add(int32_t *out, int32_t *cursor, const int32_t *block_sums, int n) {
+__global__ void k_scan_add(int32_t *out, int32_t *cursor, const int32_t *block_sums, int n, NbArgs a) {
+    if (build_off(a)) return;
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     int32_t v = out[k] + block_sums[k / SCAN_B];
@@ -121,143 +146,225 @@ __global__ void k_scan_add(int32_t *out, int32_t *cursor, const int32_t *block_s
 }
 
 __global__ void k_nb_fill(NbArgs a) {
-    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
+    if (build_off(a)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     int slot = atomicAdd(&a.cell_cursor[a.cell_id[i]], 1);
-    a.cell_list[slot] = i;
+    a.cell_tmp[slot] = i;
 }
 
-__global__ void k_nb_sort_cells(NbArgs a) {
-    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.ncell) return;
-    int s = a.cell_start[c], e = s + a.cell_count[c];
-    for (int p = s + 1; p < e; ++p) {  // insertion sort by bead index
-        int v = a.cell_list[p];
-        int q = p - 1;
-        while (q >= s && a.cell_list[q] > v) {
-            a.cell_list[q + 1] = a.cell_list[q];
-            --q;
-        }
-        a.cell_list[q + 1] = v;
+// rank of bead i among the members of its cell, by index
+__global__ void k_nb_rank(NbArgs a) {
+    if (build_off(a)) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int c = a.cell_id[i];
+    const int s = a.cell_start[c], e = a.cell_start[c + 1];
+    int rank = 0;
+    for (int q = s; q < e; ++q) rank += (a.cell_tmp[q] < i) ? 1 : 0;
+    a.cell_list[s + rank] = i;
+    const float4 p = a.pos4[i];
+    const uint32_t tag = (uint32_t)i | ((uint32_t)p.w << CODE_SHIFT);
+    a.pos_sorted[s + rank] = make_float4(p.x, p.y, p.z, __uint_as_float(tag));
+}
+
+// flags (or) and row maxima of the active lanes, one atomic per wave
+__device__ __forceinline__ void wave_status(int32_t *status, int flags, int total, int na) {
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        flags |= __shfl_xor(flags, w);
+        total = max(total, __shfl_xor(total, w));
+        na = max(na, __shfl_xor(na, w));
+    }
+    const uint64_t act = __ballot(1);
+    if (__lane_id() == __ffsll((unsigned long long)act) - 1) {
+        if (flags) atomicOr(&status[0], flags);
+        atomicMax(&status[1], total);
+        atomicMax(&status[2], na);
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_nb_rows(NbArgs a) {
-    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+// wrapped cell index and periodic image of k = c0 + offset (|offset| <= 2,
+// so at most two corrections); false for an open dimension outside the grid
+__device__ __forceinline__ bool wrap_cell(int k, int nc, int pbc, int &kw, int &img) {
+    img = 0;
+    if (!pbc) {
+        kw = k;
+        return k >= 0 && k < nc;
+    }
+    while (k < 0) { k += nc; --img; }
+    while (k >= nc) { k -= nc; ++img; }
+    kw = k;
+    return true;
+}
+
+// lower bound, in cell units, of the distance along one axis from a point at
+// fractional position u in its cell to the cell at the given offset
+__device__ __forceinline__ float cell_gap(int off, float u) {
+    return off > 0 ? (float)off - u : (off < 0 ? (float)(-off - 1) + u : 0.0f);
+}
+
+// the row of bead i; returns its flags, length and angular length
+__device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &flags_out, int &total_out,
+                                          int &na_out) {
     const int n = a.n;
-    float4 pi = a.pos4[i];
-    int ti = (int)pi.w;
+    const float4 pi = a.pos4[i];
+    const int ti = (int)pi.w;
     int c0[3];
-    c0[0] = cell_coord(pi.x, a.inv_cs[0], a.nc[0]);
-    c0[1] = cell_coord(pi.y, a.inv_cs[1], a.nc[1]);
-    c0[2] = cell_coord(pi.z, a.inv_cs[2], a.nc[2]);
+    float u[3];
+    {
+        const float pv[3] = {pi.x, pi.y, pi.z};
+        for (int d = 0; d < 3; ++d) {
+            const float f = __fmul_rn(pv[d], a.inv_cs[d]);
+            c0[d] = cell_coord(pv[d], a.inv_cs[d], a.nc[d]);
+            u[d] = fminf(fmaxf(f - (float)c0[d], 0.0f), 1.0f);
+        }
+    }
+    const float cs[3] = {1.0f / a.inv_cs[0], 1.0f / a.inv_cs[1], 1.0f / a.inv_cs[2]};
     int na = 0, nb = 0;  // angular from the front, radial-only from the back
     int flags = 0;
+    int off = 0;         // cell-offset index in (dz, dy, dx) order
     for (int dz = -a.m[2]; dz <= a.m[2]; ++dz) {
-        int kz = c0[2] + dz, iz = 0;
-        if (a.pbc[2]) { iz = (kz >= 0) ? kz / a.nc[2] : -((-kz + a.nc[2] - 1) / a.nc[2]); kz -= iz * a.nc[2]; }
-        else if (kz < 0 || kz >= a.nc[2]) continue;
+        int kz, iz;
+        const bool vz = wrap_cell(c0[2] + dz, a.nc[2], a.pbc[2], kz, iz);
+        const float gz = cell_gap(dz, u[2]) * cs[2];
         for (int dy = -a.m[1]; dy <= a.m[1]; ++dy) {
-            int ky = c0[1] + dy, iy = 0;
-            if (a.pbc[1]) { iy = (ky >= 0) ? ky / a.nc[1] : -((-ky + a.nc[1] - 1) / a.nc[1]); ky -= iy * a.nc[1]; }
-            else if (ky < 0 || ky >= a.nc[1]) continue;
+            int ky, iy;
+            const bool vy = wrap_cell(c0[1] + dy, a.nc[1], a.pbc[1], ky, iy);
+            const float gy = cell_gap(dy, u[1]) * cs[1];
             for (int dx = -a.m[0]; dx <= a.m[0]; ++dx) {
-                int kx = c0[0] + dx, ix = 0;
-                if (a.pbc[0]) { ix = (kx >= 0) ? kx / a.nc[0] : -((-kx + a.nc[0] - 1) / a.nc[0]); kx -= ix * a.nc[0]; }
-                else if (kx < 0 || kx >= a.nc[0]) continue;
+                a.segA[(size_t)(off++) * n + i] = (uint8_t)(na < 255 ? na : 255);
+                int kx, ix;
+                const bool vx = wrap_cell(c0[0] + dx, a.nc[0], a.pbc[0], kx, ix);
+                if (!(vx && vy && vz)) continue;
+                const float gx = cell_gap(dx, u[0]) * cs[0];
+                // skip cells entirely beyond reach (a lower bound with margin)
+                if (gx * gx + gy * gy + gz * gz > a.cull2) continue;
                 if (ix < -2 || ix > 2 || iy < -2 || iy > 2 || iz < -2 || iz > 2) { flags |= NEP_FLAG_IMAGE_RANGE; continue; }
                 // s = fl(n L), exact predicate with every operation rounded separately
-                float sx = __fmul_rn((float)ix, a.box[0]);
-                float sy = __fmul_rn((float)iy, a.box[1]);
-                float sz = __fmul_rn((float)iz, a.box[2]);
-                bool zero_shift = (ix == 0 && iy == 0 && iz == 0);
-                uint32_t code = (uint32_t)((ix + 2) + 5 * (iy + 2) + 25 * (iz + 2));
-                int cid = (kz * a.nc[1] + ky) * a.nc[0] + kx;
-                int s = a.cell_start[cid], e = s + a.cell_count[cid];
-                for (int q = s; q < e; ++q) {
-                    int j = a.cell_list[q];
+                const float sx = __fmul_rn((float)ix, a.box[0]);
+                const float sy = __fmul_rn((float)iy, a.box[1]);
+                const float sz = __fmul_rn((float)iz, a.box[2]);
+                const bool zero_shift = (ix == 0 && iy == 0 && iz == 0);
+                const uint32_t code = (uint32_t)((ix + 2) + 5 * (iy + 2) + 25 * (iz + 2));
+                const int cid = (kz * a.nc[1] + ky) * a.nc[0] + kx;
+                const int s = a.cell_start[cid], e = a.cell_start[cid + 1];
+                for (int q0 = s; q0 < e; q0 += 4) {
+                    // up to four independent loads in flight before any is used
+                    float4 pb[4];
+#pragma unroll
+                    for (int u4 = 0; u4 < 4; ++u4) pb[u4] = a.pos_sorted[min(q0 + u4, e - 1)];
+#pragma unroll
+                    for (int u4 = 0; u4 < 4; ++u4) {
+                    if (q0 + u4 >= e) break;
+                    const float4 pj = pb[u4];
+                    const uint32_t tag = __float_as_uint(pj.w);
+                    const int j = (int)(tag & J_MASK);
                     if (j == i && zero_shift) continue;
-                    float4 pj = a.pos4[j];
-                    float ddx = __fsub_rn(__fadd_rn(pj.x, sx), pi.x);
-                    float ddy = __fsub_rn(__fadd_rn(pj.y, sy), pi.y);
-                    float ddz = __fsub_rn(__fadd_rn(pj.z, sz), pi.z);
-                    float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ddx, ddx), __fmul_rn(ddy, ddy)),
-                                         __fmul_rn(ddz, ddz));
-                    int tp = ti * a.T + (int)pj.w;
+                    const float ddx = __fsub_rn(__fadd_rn(pj.x, sx), pi.x);
+                    const float ddy = __fsub_rn(__fadd_rn(pj.y, sy), pi.y);
+                    const float ddz = __fsub_rn(__fadd_rn(pj.z, sz), pi.z);
+                    const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ddx, ddx), __fmul_rn(ddy, ddy)),
+                                               __fmul_rn(ddz, ddz));
+                    const int tp = ti * a.T + (int)(tag >> CODE_SHIFT);
                     if (!(d2 < a.list2R[tp])) continue;
                     if (d2 == 0.0f) flags |= NEP_FLAG_OVERLAP;
-                    uint32_t entry = (uint32_t)j | (code << CODE_SHIFT);
+                    const uint32_t entry = (uint32_t)j | (code << CODE_SHIFT);
+                    uint32_t *row = a.rowbuf + (size_t)i * a.cap;
                     if (d2 < a.list2A[tp]) {
-                        if (na < a.cap_A && na + nb < a.cap) a.nbr[(size_t)na * n + i] = entry;
+                        if (na < a.cap_A && na + nb < a.cap) row[na] = entry;
                         ++na;
                     } else {
-                        if (na + nb < a.cap) a.nbr[(size_t)(a.cap - 1 - nb) * n + i] = entry;
+                        if (na + nb < a.cap) row[a.cap - 1 - nb] = entry;
                         ++nb;
+                    }
                     }
                 }
             }
         }
     }
-    int total = na + nb;
+    a.segA[(size_t)off * n + i] = (uint8_t)(na < 255 ? na : 255);
+    const int total = na + nb;
     if (na > a.cap_A) flags |= NEP_FLAG_OVERFLOW_A;
     if (total > a.cap) flags |= NEP_FLAG_OVERFLOW_R;
-    if (flags) atomicOr(&a.status[0], flags);
-    if (flags & (NEP_FLAG_OVERFLOW_A | NEP_FLAG_OVERFLOW_R)) {
-        atomicMax(&a.status[1], total);
-        atomicMax(&a.status[2], na);
-        a.cnt[i] = 0;
-        a.cnt[n + i] = 0;
-        return;
-    }
-    // move the radial-only entries (stored at slots cap-nb .. cap-1) to slots
-    // na .. na+nb-1; the source never lies below the destination, so copying
-    // upwards reads every source before it is overwritten
-    for (int k = 0; k < nb; ++k)
-        a.nbr[(size_t)(na + k) * n + i] = a.nbr[(size_t)(a.cap - nb + k) * n + i];
-    a.cnt[i] = total;
-    a.cnt[n + i] = na;
-    atomicMax(&a.status[1], total);
-    atomicMax(&a.status[2], na);
+    const bool over = (flags & (NEP_FLAG_OVERFLOW_A | NEP_FLAG_OVERFLOW_R)) != 0;
+    a.cnt[i] = over ? 0 : total;
+    a.cnt[n + i] = over ? 0 : na;
+    flags_out = flags;
+    total_out = total;
+    na_out = na;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
-    if (!a.clear_status && (a.status[0] & FREEZE_MASK)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+__global__ __launch_bounds__(BLOCK) void k_nb_rows(NbArgs a) {
+    if (build_off(a)) return;  // uniform over the grid
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    int flags = 0, total = 0, na = 0;
+    if (i < a.n) build_row(a, i, flags, total, na);
+    wave_status(a.status, flags, total, na);  // every lane takes part
+}
+
+// row-major scratch -> slot-major lists: slot p of bead i is scratch entry p for
+// the angular prefix, and the radial-only entries, kept from the back of the
+// scratch row, follow in the order they were found.  Lanes write consecutive
+// beads of one slot (coalesced); each lane reads its own scratch row.
+__global__ __launch_bounds__(BLOCK) void k_nb_transpose(NbArgs a) {
+    if (build_off(a)) return;
     const int n = a.n;
-    int na = a.cnt[n + i];
-    for (int p = 0; p < na; ++p) {
-        uint32_t e = a.nbr[(size_t)p * n + i];
-        int j = (int)(e & J_MASK);
-        uint32_t code = e >> CODE_SHIFT;
-        uint32_t want = (uint32_t)i | ((124u - code) << CODE_SHIFT);
-        int nj = a.cnt[n + j];
-        int found = -1;
-        for (int q = 0; q < nj; ++q)
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int total = a.cnt[i], na = a.cnt[n + i];
+    const uint32_t *row = a.rowbuf + (size_t)i * a.cap;
+    for (int p = 0; p < na; ++p) a.nbr[(size_t)p * n + i] = row[p];
+    for (int p = na; p < total; ++p) a.nbr[(size_t)p * n + i] = row[a.cap - 1 - (p - na)];
+}
+
+// one thread per (bead, angular slot); lanes of a wave read consecutive beads
+__global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
+    if (build_off(a)) return;
+    const int n = a.n;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const int p = blockIdx.y;
+    if (i >= n || p >= a.cnt[n + i]) return;
+    const uint32_t e = a.nbr[(size_t)p * n + i];
+    int j, nx, ny, nz;
+    decode(e, j, nx, ny, nz);
+    // cell offset at which i found j, mirrored for j's row
+    const int ci = a.cell_id[i], cj = a.cell_id[j];
+    const int dx = cj % a.nc[0] + nx * a.nc[0] - ci % a.nc[0];
+    const int dy = (cj / a.nc[0]) % a.nc[1] + ny * a.nc[1] - (ci / a.nc[0]) % a.nc[1];
+    const int dz = cj / (a.nc[0] * a.nc[1]) + nz * a.nc[2] - ci / (a.nc[0] * a.nc[1]);
+    const int wx = 2 * a.m[0] + 1, wy = 2 * a.m[1] + 1;
+    const int o = ((dz + a.m[2]) * wy + (dy + a.m[1])) * wx + (dx + a.m[0]);
+    const uint32_t want = (uint32_t)i | ((124u - (e >> CODE_SHIFT)) << CODE_SHIFT);
+    int found = -1;
+    if (o >= 0 && o < a.n_off) {
+        const int om = a.n_off - 1 - o;
+        // never past the neighbour's valid angular prefix (0 after an overflow)
+        const int naj = a.cnt[n + j];
+        const int qs = min((int)a.segA[(size_t)om * n + j], naj);
+        const int qe = min((int)a.segA[(size_t)(om + 1) * n + j], naj);
+        for (int q = qs; q < qe; ++q)
             if (a.nbr[(size_t)q * n + j] == want) { found = q; break; }
-        a.rev[(size_t)p * n + i] = found < 0 ? -1 : (int32_t)((size_t)found * n + j);
     }
+    a.rev[(size_t)p * n + i] = found < 0 ? -1 : (int32_t)((size_t)found * n + j);
 }
 
 hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     int nbk = (a.n + BLOCK - 1) / BLOCK;
     int cbk = (a.ncell + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL(k_nb_clear, dim3(cbk > 0 ? (cbk < 4096 ? cbk : 4096) : 1), dim3(BLOCK), 0, s,
-                       a.ncell, a.cell_count, a.status, a.clear_status);
+                       a.ncell, a.cell_count, a.status, a.clear_status, a.ctrl);
     if (a.n == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_nb_bin, dim3(nbk), dim3(BLOCK), 0, s, a);
     int sb = (a.ncell + SCAN_B - 1) / SCAN_B;
-    hipLaunchKernelGGL(k_scan_local, dim3(sb), dim3(BLOCK), 0, s, a.cell_count, a.cell_start, a.scan_tmp, a.ncell);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, s, a.scan_tmp, sb, a.cell_start + a.ncell);
-    hipLaunchKernelGGL(k_scan_add, dim3(cbk), dim3(BLOCK), 0, s, a.cell_start, a.cell_cursor, a.scan_tmp, a.ncell);
+    hipLaunchKernelGGL(k_scan_local, dim3(sb), dim3(BLOCK), 0, s, a.cell_count, a.cell_start, a.scan_tmp, a.ncell, a);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, s, a.scan_tmp, sb, a.cell_start + a.ncell, a);
+    hipLaunchKernelGGL(k_scan_add, dim3(cbk), dim3(BLOCK), 0, s, a.cell_start, a.cell_cursor, a.scan_tmp, a.ncell, a);
     hipLaunchKernelGGL(k_nb_fill, dim3(nbk), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_nb_sort_cells, dim3(cbk), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_nb_rank, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_rows, dim3(nbk), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_nb_reverse, dim3(nbk), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_nb_transpose, dim3(nbk), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_nb_reverse, dim3(nbk, a.cap_A), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

@@ -23,9 +23,10 @@ constexpr uint32_t J_MASK = 0x1FFFFFFu;
 constexpr int CODE_SHIFT = 25;
 constexpr float ACCEL = 9.648533212e-5f;  // nm/fs^2 per (eV/nm)/amu
 // per-block partial sums: U, W (9), kinetic energy, radial pairs, angular pairs;
-// slots 13..15 of each block hold maxima for the rebuild prediction
+// slot 13 of each block holds the maximum squared displacement from the build
+// reference that the next drift produces (rebuild gate)
 constexpr int NPART = 13;
-constexpr int NMAX = 3;
+constexpr int NMAX = 1;
 // status flags after which the MD kernels do nothing (the lists are invalid)
 constexpr int FREEZE_MASK = NEP_FLAG_OVERFLOW_R | NEP_FLAG_OVERFLOW_A | NEP_FLAG_NONFINITE |
                             NEP_FLAG_OUTSIDE_BOX | NEP_FLAG_IMAGE_RANGE | NEP_FLAG_BAD_TYPE;
@@ -37,6 +38,8 @@ struct Model {
     float rcR[MAXT * MAXT], rcA[MAXT * MAXT];
     float *d_params;  // flat layout of nep.h
     float *d_tab;     // [T*T][TAB_PER_PAIR] derived coefficients
+    float *d_ann;     // [T][(ND+2)][HP] + 1: w0 transposed, b0, w1 (zero-padded to HP), then b1
+    int HP;           // hidden width padded to a built size (8, 16, 32 or 64)
     size_t n_params;
     int device;
 };
@@ -52,14 +55,17 @@ struct EfvArgs {
     float box[3];
     const float4 *pos4;     // x, y, z, type
     const uint32_t *nbr;
+    const int32_t *rev;
     const int32_t *cnt;
     const float *params;    // flat parameters
-    const float *tab;       // derived tables
+    const float *tab;       // derived pair tables
+    const float *ann;       // derived network table (see Model::d_ann)
     Cut cut;
     // outputs of the main kernel
     float *U;
     float4 *bvec;           // [n][T][3] radial back-propagation coefficients
-    float4 *angbuf;         // [cap_A][n] dU_i/dr_ij angular part
+    float4 *angbuf;         // [cap_A][n]: slot (q, j) receives dU_i/dr_ij (angular part) from
+                            // the neighbour i listed at slot q of row j
     float4 *fown;           // [n] sum_j dU_i/dr_ij (angular)
     const int32_t *freeze;  // MD: status word; the kernel does nothing once FREEZE_MASK is set
 };
@@ -129,55 +135,114 @@ __device__ __forceinline__ void cheb_U(float x, float Uc[KB - 1]) {
     for (int k = 2; k < KB - 1; ++k) Uc[k] = x2 * Uc[k - 1] - Uc[k - 2];
 }
 
-// Real solid-harmonic polynomials P_lm(u) for l = 1..4 on the unit sphere;
-// with the weights N2 below, sum_m N2_lm P_lm(u) P_lm(v) = (2l+1)/(4 pi) P_l(u.v),
-// so sum_m N2 A_lm^2 equals the complex sum of Eq. 4.
-__device__ __forceinline__ void harmonics(float x, float y, float z, float P[LM]) {
-    float x2 = x * x, y2 = y * y, z2 = z * z;
-    P[0] = x; P[1] = y; P[2] = z;
-    P[3] = x * y; P[4] = y * z; P[5] = x * z; P[6] = x2 - y2; P[7] = 3.0f * z2 - 1.0f;
-    float a = 3.0f * x2 - y2, b = 5.0f * z2 - 1.0f, c = x2 - 3.0f * y2, d = x2 - y2;
-    P[8] = y * a; P[9] = x * y * z; P[10] = y * b; P[11] = z * (5.0f * z2 - 3.0f);
-    P[12] = x * b; P[13] = z * d; P[14] = x * c;
-    float e = 7.0f * z2 - 1.0f, f = 7.0f * z2 - 3.0f;
-    P[15] = x * y * d; P[16] = y * z * a; P[17] = x * y * e; P[18] = y * z * f;
-    P[19] = (35.0f * z2 - 30.0f) * z2 + 3.0f; P[20] = x * z * f; P[21] = d * e;
-    P[22] = x * z * c; P[23] = x2 * x2 - 6.0f * x2 * y2 + y2 * y2;
+// Real solid-harmonic polynomials P_lm(u), l = 1..4, on the unit sphere.  With
+// the weights N2_lm, sum_m N2_lm P_lm(u) P_lm(v) = (2l+1)/(4 pi) P_l(u.v), so
+// sum_m N2 A_lm^2 equals the complex sum of Eq. 4.  The visitors below walk the
+// 24 terms one at a time (value, and for the force also grad_u P), so no
+// 24-wide temporaries stay live next to the 168 accumulators.
+template <int IDX>
+__device__ __forceinline__ void acc_lm(float P, const float g[NA], float A[NA][LM]) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) A[q][IDX] += g[q] * P;
 }
 
-// V += sum_lm B_lm grad_u P_lm(u)   (polynomial gradients, unprojected)
-__device__ __forceinline__ void harmonics_grad(float x, float y, float z, const float B[LM],
-                                               float &vx, float &vy, float &vz) {
-    float x2 = x * x, y2 = y * y, z2 = z * z;
-    float xy = x * y, yz = y * z, xz = x * z, xyz = xy * z;
-    vx += B[0]; vy += B[1]; vz += B[2];
-    // l = 2
-    vx += B[3] * y; vy += B[3] * x;
-    vy += B[4] * z; vz += B[4] * y;
-    vx += B[5] * z; vz += B[5] * x;
-    vx += 2.0f * B[6] * x; vy -= 2.0f * B[6] * y;
-    vz += 6.0f * B[7] * z;
-    // l = 3
-    float b51 = 5.0f * z2 - 1.0f, d = x2 - y2;
-    vx += 6.0f * B[8] * xy; vy += 3.0f * B[8] * d;
-    vx += B[9] * yz; vy += B[9] * xz; vz += B[9] * xy;
-    vy += B[10] * b51; vz += 10.0f * B[10] * yz;
-    vz += B[11] * (15.0f * z2 - 3.0f);
-    vx += B[12] * b51; vz += 10.0f * B[12] * xz;
-    vx += 2.0f * B[13] * xz; vy -= 2.0f * B[13] * yz; vz += B[13] * d;
-    vx += 3.0f * B[14] * d; vy -= 6.0f * B[14] * xy;
-    // l = 4
-    float a3 = 3.0f * x2 - y2, c3 = x2 - 3.0f * y2;
-    float e = 7.0f * z2 - 1.0f, f = 7.0f * z2 - 3.0f;
-    vx += B[15] * y * a3; vy += B[15] * x * c3;
-    vx += 6.0f * B[16] * xyz; vy += 3.0f * B[16] * z * d; vz += B[16] * y * a3;
-    vx += B[17] * y * e; vy += B[17] * x * e; vz += 14.0f * B[17] * xyz;
-    vy += B[18] * z * f; vz += B[18] * y * (21.0f * z2 - 3.0f);
-    vz += B[19] * z * (140.0f * z2 - 60.0f);
-    vx += B[20] * z * f; vz += B[20] * x * (21.0f * z2 - 3.0f);
-    vx += 2.0f * B[21] * x * e; vy -= 2.0f * B[21] * y * e; vz += 14.0f * B[21] * z * d;
-    vx += 3.0f * B[22] * z * d; vy -= 6.0f * B[22] * xyz; vz += B[22] * x * c3;
-    vx += 4.0f * B[23] * x * c3; vy += 4.0f * B[23] * y * (y2 - 3.0f * x2);
+// A_{n,lm} += g_n P_lm(u)
+__device__ __forceinline__ void accumulate_harmonics(float x, float y, float z, const float g[NA],
+                                                     float A[NA][LM]) {
+    const float x2 = x * x, y2 = y * y, z2 = z * z;
+    acc_lm<0>(x, g, A);
+    acc_lm<1>(y, g, A);
+    acc_lm<2>(z, g, A);
+    acc_lm<3>(x * y, g, A);
+    acc_lm<4>(y * z, g, A);
+    acc_lm<5>(x * z, g, A);
+    acc_lm<6>(x2 - y2, g, A);
+    acc_lm<7>(3.0f * z2 - 1.0f, g, A);
+    const float a = 3.0f * x2 - y2, b = 5.0f * z2 - 1.0f, c = x2 - 3.0f * y2, d = x2 - y2;
+    acc_lm<8>(y * a, g, A);
+    acc_lm<9>(x * y * z, g, A);
+    acc_lm<10>(y * b, g, A);
+    acc_lm<11>(z * (5.0f * z2 - 3.0f), g, A);
+    acc_lm<12>(x * b, g, A);
+    acc_lm<13>(z * d, g, A);
+    acc_lm<14>(x * c, g, A);
+    const float e = 7.0f * z2 - 1.0f, f = 7.0f * z2 - 3.0f;
+    acc_lm<15>(x * y * d, g, A);
+    acc_lm<16>(y * z * a, g, A);
+    acc_lm<17>(x * y * e, g, A);
+    acc_lm<18>(y * z * f, g, A);
+    acc_lm<19>((35.0f * z2 - 30.0f) * z2 + 3.0f, g, A);
+    acc_lm<20>(x * z * f, g, A);
+    acc_lm<21>(d * e, g, A);
+    acc_lm<22>(x * z * c, g, A);
+    acc_lm<23>(x2 * x2 - 6.0f * x2 * y2 + y2 * y2, g, A);
+}
+
+// one term of the pair partial: B = sum_n D g_n, B' = sum_n D g_n';
+// s += B' P,  V += B grad_u P
+template <int IDX>
+__device__ __forceinline__ void force_lm(float P, float Gx, float Gy, float Gz, const float D[NA][LM],
+                                         const float g[NA], const float gp[NA], float &s, float &vx,
+                                         float &vy, float &vz) {
+    float B = 0.0f, Bp = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        B += D[q][IDX] * g[q];
+        Bp += D[q][IDX] * gp[q];
+    }
+    s += Bp * P;
+    vx += B * Gx;
+    vy += B * Gy;
+    vz += B * Gz;
+}
+
+__device__ __forceinline__ void force_harmonics(float x, float y, float z, const float D[NA][LM],
+                                                const float g[NA], const float gp[NA], float &s,
+                                                float &vx, float &vy, float &vz) {
+    const float x2 = x * x, y2 = y * y, z2 = z * z;
+    const float xy = x * y, yz = y * z, xz = x * z, xyz = xy * z;
+    force_lm<0>(x, 1.0f, 0.0f, 0.0f, D, g, gp, s, vx, vy, vz);
+    force_lm<1>(y, 0.0f, 1.0f, 0.0f, D, g, gp, s, vx, vy, vz);
+    force_lm<2>(z, 0.0f, 0.0f, 1.0f, D, g, gp, s, vx, vy, vz);
+    force_lm<3>(xy, y, x, 0.0f, D, g, gp, s, vx, vy, vz);
+    force_lm<4>(yz, 0.0f, z, y, D, g, gp, s, vx, vy, vz);
+    force_lm<5>(xz, z, 0.0f, x, D, g, gp, s, vx, vy, vz);
+    force_lm<6>(x2 - y2, 2.0f * x, -2.0f * y, 0.0f, D, g, gp, s, vx, vy, vz);
+    force_lm<7>(3.0f * z2 - 1.0f, 0.0f, 0.0f, 6.0f * z, D, g, gp, s, vx, vy, vz);
+    const float d = x2 - y2, b51 = 5.0f * z2 - 1.0f;
+    force_lm<8>(y * (3.0f * x2 - y2), 6.0f * xy, 3.0f * d, 0.0f, D, g, gp, s, vx, vy, vz);
+    force_lm<9>(xyz, yz, xz, xy, D, g, gp, s, vx, vy, vz);
+    force_lm<10>(y * b51, 0.0f, b51, 10.0f * yz, D, g, gp, s, vx, vy, vz);
+    force_lm<11>(z * (5.0f * z2 - 3.0f), 0.0f, 0.0f, 15.0f * z2 - 3.0f, D, g, gp, s, vx, vy, vz);
+    force_lm<12>(x * b51, b51, 0.0f, 10.0f * xz, D, g, gp, s, vx, vy, vz);
+    force_lm<13>(z * d, 2.0f * xz, -2.0f * yz, d, D, g, gp, s, vx, vy, vz);
+    force_lm<14>(x * (x2 - 3.0f * y2), 3.0f * d, -6.0f * xy, 0.0f, D, g, gp, s, vx, vy, vz);
+    const float a3 = 3.0f * x2 - y2, c3 = x2 - 3.0f * y2;
+    const float e = 7.0f * z2 - 1.0f, f = 7.0f * z2 - 3.0f, h = 21.0f * z2 - 3.0f;
+    force_lm<15>(xy * d, y * a3, x * c3, 0.0f, D, g, gp, s, vx, vy, vz);
+    force_lm<16>(yz * a3, 6.0f * xyz, 3.0f * z * d, y * a3, D, g, gp, s, vx, vy, vz);
+    force_lm<17>(xy * e, y * e, x * e, 14.0f * xyz, D, g, gp, s, vx, vy, vz);
+    force_lm<18>(yz * f, 0.0f, z * f, y * h, D, g, gp, s, vx, vy, vz);
+    force_lm<19>((35.0f * z2 - 30.0f) * z2 + 3.0f, 0.0f, 0.0f, z * (140.0f * z2 - 60.0f), D, g, gp, s, vx,
+                 vy, vz);
+    force_lm<20>(xz * f, z * f, 0.0f, x * h, D, g, gp, s, vx, vy, vz);
+    force_lm<21>(d * e, 2.0f * x * e, -2.0f * y * e, 14.0f * z * d, D, g, gp, s, vx, vy, vz);
+    force_lm<22>(xz * c3, 3.0f * z * d, -6.0f * xyz, x * c3, D, g, gp, s, vx, vy, vz);
+    force_lm<23>(x2 * x2 - 6.0f * x2 * y2 + y2 * y2, 4.0f * x * c3, 4.0f * y * (y2 - 3.0f * x2), 0.0f, D, g,
+                 gp, s, vx, vy, vz);
+}
+
+// cos(pi t) and sin(pi t) for 0 <= t <= 1 with the hardware instructions,
+// whose argument is in revolutions (cos(2 pi x))
+__device__ __forceinline__ float cos_pi(float t) { return __builtin_amdgcn_cosf(0.5f * t); }
+__device__ __forceinline__ float sin_pi(float t) { return __builtin_amdgcn_sinf(0.5f * t); }
+
+// branch-free tanh: sign(x) (1 - 2 / (exp(2|x|) + 1)); absolute error ~1e-7,
+// saturates to +-1 without overflow (exp -> inf gives 2/inf = 0)
+__device__ __forceinline__ float tanh_nobranch(float x) {
+    const float e = __expf(2.0f * fabsf(x));
+    const float t = 1.0f - __fdividef(2.0f, e + 1.0f);
+    return copysignf(t, x);
 }
 
 __device__ __forceinline__ int lm_l(int lm) { return lm < 3 ? 1 : lm < 8 ? 2 : lm < 15 ? 3 : 4; }
@@ -185,11 +250,12 @@ __device__ __forceinline__ int lm_l(int lm) { return lm < 3 ? 1 : lm < 8 ? 2 : l
 // launchers (defined in the .hip files)
 hipError_t launch_pack(int n, int T, const float *x, const float *y, const float *z, const uint8_t *type,
                        float4 *pos4, hipStream_t s);
-hipError_t launch_efv_main(int T, const EfvArgs &a, size_t lds_bytes, hipStream_t s);
+hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_efv_gather(int T, bool virial, bool md, const GatherArgs &a, hipStream_t s);
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
                          double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, double *info, hipStream_t s);
+                         const int32_t *status, int32_t *ctrl, int md_step, int force_build, float thr2,
+                         hipStream_t s);
 // rebuild prediction at the start of an MD call: maxima of |x + d - ref|,
 // |d| and dt^2 |a| with d = dt (v + dt/2 a) the next drift, into the partials
 struct PredictArgs {
@@ -215,16 +281,26 @@ struct NbArgs {
     const uint8_t *type;
     float4 *pos4;
     int32_t *cell_id, *cell_count, *cell_start, *cell_cursor, *cell_list, *scan_tmp;
+    int32_t *cell_tmp;   // [n] cell members in atomic (arbitrary) order
+    float4 *pos_sorted;  // [n] positions in cell order; w = bits of (index | type << 25)
+    uint8_t *segA;       // [n_off + 1][n] angular-prefix length before each cell offset
+    int n_off;           // (2 m_x + 1)(2 m_y + 1)(2 m_z + 1)
+    float cull2;         // cells whose gap exceeds this squared distance are skipped
+    uint32_t *rowbuf;    // [n][cap] rows built row-major (angular from the front,
+                         // radial-only from the back), then transposed into nbr
     uint32_t *nbr;
     int32_t *rev, *cnt;
     float *ref;
     int32_t *status;
+    int32_t *ctrl;     // MD: [0] rebuild gate set by the preceding reduction, [1] rebuild
+                       // count; null: build unconditionally
     int ncell;
     int clear_status;  // 1: a fresh build resets the status word
     int wrap;          // 1: wrap periodic coordinates into [0, L) and write them back first
 };
 hipError_t launch_build(const NbArgs &a, hipStream_t s);
-hipError_t launch_clear_status(int32_t *status, hipStream_t s);
+// zeroes the status word and, when given, the MD control words [4]
+hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, hipStream_t s);
 
 struct KickDriftArgs {
     int n;

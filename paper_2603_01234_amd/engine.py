@@ -51,6 +51,10 @@ class Model:
             pass
 
 
+MAX_CAP = 4096      # row capacity limit of the library
+MAX_CAP_A = 255     # angular-prefix capacity limit (segment offsets are bytes)
+
+
 def estimate_caps(n, box, pbc, rc_max, rcA_max, skin, pos=None):
     """Row capacities from the mean density with head-room; overflow grows them."""
     vol = float(np.prod(box))
@@ -62,7 +66,8 @@ def estimate_caps(n, box, pbc, rc_max, rcA_max, skin, pos=None):
     rho = n / max(vol, 1e-9)
     cap = int(1.6 * rho * 4.0 / 3.0 * math.pi * (rc_max + skin) ** 3) + 16
     cap_A = int(1.6 * rho * 4.0 / 3.0 * math.pi * (rcA_max + skin) ** 3) + 16
-    return max(cap, 8), max(min(cap_A, cap), 4)
+    cap = min(max(cap, 8), MAX_CAP)
+    return cap, max(min(cap_A, cap, MAX_CAP_A), 4)
 
 
 class Replica:
@@ -111,7 +116,8 @@ class Replica:
     # -- buffers ----------------------------------------------------------------
     def _alloc_lists(self, cap, cap_A):
         n = max(self.n, 1)
-        self.cap, self.cap_A = int(cap), int(min(cap_A, cap))
+        self.cap = int(min(cap, MAX_CAP))
+        self.cap_A = int(min(cap_A, self.cap, MAX_CAP_A))
         self.nbr = torch.zeros((self.cap, n), dtype=torch.int32, device=self.device)
         self.rev = torch.zeros((self.cap_A, n), dtype=torch.int32, device=self.device)
         self.ws_bytes = B.nep_workspace_bytes(self.model.handle, self.n, self.cap, self.cap_A)
@@ -137,11 +143,13 @@ class Replica:
         return nb
 
     # -- calls ------------------------------------------------------------------
-    def build(self, max_tries: int = 4):
-        """nep_build_neighbors, growing the row capacities after an overflow."""
+    def build(self, max_tries: int = 4, wrap: bool = True):
+        """nep_build_neighbors (periodic coordinates wrapped in place unless
+        wrap=False), growing the row capacities after an overflow."""
         for _ in range(max_tries):
             s, nb = self.c_system(), self.c_neighbors()
-            code = B.nep_build_neighbors(self.model.handle, s, nb, self.ws.data_ptr(), self.ws_bytes, _stream())
+            code = B.nep_build_neighbors(self.model.handle, s, nb, int(wrap), self.ws.data_ptr(), self.ws_bytes,
+                                         _stream())
             if code == B.NEP_ERR_NEIGHBOR_OVERFLOW:
                 st = self.status.cpu().tolist()
                 self._alloc_lists(max(self.cap, int(st[1] * 1.2) + 8), max(self.cap_A, int(st[2] * 1.2) + 8))

@@ -72,7 +72,7 @@ def test_calls_reject_null_model_and_bad_structs():
     from paper_2603_01234_amd import binding as B
     s = B.System()
     nb = B.Neighbors()
-    assert B.nep_build_neighbors(None, s, nb, None, 0, None) == B.NEP_ERR_ARG
+    assert B.nep_build_neighbors(None, s, nb, 0, None, 0, None) == B.NEP_ERR_ARG
     assert B.nep_compute_efv(None, s, nb, None, None, None, None, None, None, 0, None) == B.NEP_ERR_ARG
     mp = B.MdParams()
     assert B.nep_md_step(None, s, None, mp, nb, None, None, None, None, None, 0, None) == B.NEP_ERR_ARG

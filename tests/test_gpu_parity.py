@@ -202,7 +202,7 @@ def test_overflow_is_reported_and_recovered():
     spec, params, system, opts = W.config0()
     rep = _replica(spec, params, system, skin=opts["skin"], cap=20, cap_A=8)
     s, nb = rep.c_system(), rep.c_neighbors()
-    code = B.nep_build_neighbors(rep.model.handle, s, nb, rep.ws.data_ptr(), rep.ws_bytes,
+    code = B.nep_build_neighbors(rep.model.handle, s, nb, 0, rep.ws.data_ptr(), rep.ws_bytes,
                                  torch.cuda.current_stream().cuda_stream)
     assert code == B.NEP_ERR_NEIGHBOR_OVERFLOW
     st = rep.status.cpu().tolist()
@@ -229,8 +229,14 @@ def test_bad_positions_are_reported():
     pos[5, 0] = system.box[0] + 0.3
     rep = E.Replica(model, pos, system.types, system.box, system.pbc)
     with pytest.raises(B.NepError) as ei:
-        rep.build()
+        rep.build(wrap=False)
     assert ei.value.code == B.NEP_ERR_OUTSIDE_BOX
+    rep.build(wrap=True)            # wrapped in place, then the same lists as for wrapped input
+    assert 0.0 <= float(rep.xyz[0, 5]) < system.box[0]
+    rep2 = E.Replica(model, rep.positions(), system.types, system.box, system.pbc)
+    rep2.build(wrap=False)
+    a, b = rep.neighbor_rows(), rep2.neighbor_rows()
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[0], b[0])
     pos = system.pos_f32().copy()
     pos[7] = pos[8]
     rep = E.Replica(model, pos, system.types, system.box, system.pbc)
