@@ -159,7 +159,10 @@ int nep_build_neighbors(nep_model model, nep_system *sys, nep_neighbors *nbrs, i
  * W: device [9][n] per-site virial W_i[a][b] (plane 3a+b) or NULL.
  * E_tot: device double[1] or NULL.  W_tot: device double[9] or NULL.
  * Totals are reduced in a fixed order in FP64.  Lists must come from
- * nep_build_neighbors with the same model and skin.  Asynchronous. */
+ * nep_build_neighbors with the same model and skin.  Asynchronous; a bead
+ * farther than skin/2 from where the lists were built sets NEP_FLAG_SKIN in
+ * the status word (the results are then incomplete), which nep_check_status
+ * reports as NEP_ERR_SKIN_VIOLATION. */
 int nep_compute_efv(nep_model model, const nep_system *sys, const nep_neighbors *nbrs,
                     float *U, float *F, float *W, double *E_tot, double *W_tot,
                     void *ws, size_t ws_bytes, void *stream);
@@ -170,8 +173,11 @@ int nep_compute_efv(nep_model model, const nep_system *sys, const nep_neighbors 
 typedef struct {
     float dt_fs;              /* time step */
     int n_steps;              /* steps in this call */
-    int rebuild_every;        /* lists are rebuilt at the end of step s when (s+1) % rebuild_every == 0,
-                                 and earlier whenever a bead could otherwise move more than skin/2 */
+    int rebuild_every;        /* lists are rebuilt after the drift of step s when (s+1) % rebuild_every == 0,
+                                 and whenever a drift takes a bead 0.99 skin/2 or farther from its build
+                                 position */
+    int force_rebuild;        /* in: rebuild after the first drift whatever the displacement (after the
+                                 caller has regrown the lists of a call stopped by an overflow) */
     float mass[4];            /* amu per type */
     double strain_rate[3];    /* engineering strain per step: L_d(s) = box0_d (1 + rate_d s) */
     double box0[3];           /* reference box of the strain */
@@ -181,30 +187,32 @@ typedef struct {
                                  force evaluation (pairs inside the interaction cutoffs) */
 } nep_md_params;
 
-/* Advances sys by n_steps:  v += dt/2 a(F);  x += dt v;  affine strain;
- * F = F(x);  v += dt/2 a(F);  [wrap + rebuild],  with a = 9.648533212e-5 F/m
- * (nm/fs^2 from eV/nm and amu).  On entry F (device [3][n]) must hold the
- * forces at the current positions and the lists must be valid for them; on
- * exit both hold for the final positions.  v: device [3][n] nm/fs.  U: device
- * [n] or NULL (site energies at the last step).  E_pot / E_kin: device double
- * [n_steps] traces or NULL.
+/* Advances sys by n_steps:  v' = v + dt/2 a(F);  x += dt v';  affine strain;
+ * [wrap + rebuild];  F = F(x);  v = v' + dt/2 a(F),  with a = 9.648533212e-5
+ * F/m (nm/fs^2 from eV/nm and amu).  On entry F (device [3][n]) must hold the
+ * forces at the current positions, and the lists must come from
+ * nep_build_neighbors for this system (built at any earlier positions: the
+ * displacement check rebuilds them when they no longer cover the pairs), or
+ * force_rebuild must be set.  On exit x, v, F and the lists hold for the final
+ * positions.  v: device [3][n] nm/fs.  U: device [n] or NULL (site energies at
+ * the last step).  E_pot / E_kin: device double [n_steps] traces or NULL.
  *
  * Rebuild decisions are taken on the device, with no host synchronisation
- * inside the call: after each step the gather kernel computes, exactly, where
- * the next drift will take every bead; the reduction sets a gate word when
- * some bead would end up 0.98 skin/2 or farther from its build position, or
- * when a scheduled rebuild ((step + 1) % rebuild_every == 0) is due, and the
- * build kernels queued after every step do nothing while the gate is off.
- * params->n_rebuilds returns the number of rebuilds that ran.  A bead that
- * still moves more than skin/2 (one drift longer than skin/2) is reported as
- * NEP_ERR_SKIN_VIOLATION.
+ * inside the call: the drift kernel sets a gate word when a bead ends up
+ * 0.99 skin/2 or farther from its build position, the reduction of the
+ * previous step sets it when the schedule asks for a rebuild, and the build
+ * kernels queued in every step do nothing while it is off.  The lists used by
+ * a force evaluation therefore always hold every pair within the cutoffs.
+ * params->n_rebuilds returns the number of rebuilds that ran.
  *
- * A rebuild that overflows (or finds a bad position) freezes the device state
- * at the end of the last good step: x, v and F are then consistent, the call
- * returns the error with params->step advanced by the completed steps, and the
- * caller regrows the lists (status[1], status[2]), rebuilds and repeats the
- * call for the remaining steps.  sys->box follows the strain of the completed
- * steps.  The call synchronises the stream before it returns. */
+ * The new positions and velocities of a step are written to sys and v only
+ * when its forces are done.  A rebuild that overflows (or finds a bad
+ * position) therefore stops the run with x, v and F of the last completed
+ * step: the call returns the error with params->step advanced by the completed
+ * steps, and the caller regrows the lists (status[1], status[2]) and repeats
+ * the call for the remaining steps with force_rebuild set, which continues the
+ * same trajectory.  sys->box follows the strain of the completed steps.  The
+ * call synchronises the stream before it returns. */
 int nep_md_step(nep_model model, nep_system *sys, float *v, nep_md_params *params,
                 nep_neighbors *nbrs, float *F, float *U, double *E_pot, double *E_kin,
                 void *ws, size_t ws_bytes, void *stream);
@@ -219,13 +227,15 @@ int nep_check_status(const nep_neighbors *nbrs, int32_t host_status_out[4], void
  * around every launch of its kernels, by class: 0 = fused descriptor /
  * network / angular-force kernel, 1 = gather (forces, virial, half-kick),
  * 2 = neighbour build (all of its kernels), 3 = first half-kick + drift.
- * nep_timing_begin(max_launches) creates the event pool (host-side objects
- * only) and enables recording for the calling process; launches beyond the
- * pool are not timed.  nep_timing_end synchronises on the recorded events,
+ * nep_timing_begin(max_launches, class_mask) creates the event pool
+ * (host-side objects only) and enables recording, for the classes whose bit
+ * is set in class_mask (bit c for class c), in the calling process; launches
+ * beyond the pool are not timed.  Every event pair adds a little time on the
+ * device, so a throughput measurement times only the class it needs.  nep_timing_end synchronises on the recorded events,
  * writes the summed milliseconds and launch counts per class into ms[4] and
  * launches[4] (host), destroys the pool and disables recording.  Not
  * thread-safe: meant for a single benchmarking thread. */
-int nep_timing_begin(int max_launches);
+int nep_timing_begin(int max_launches, unsigned class_mask);
 int nep_timing_end(double ms[4], int launches[4]);
 
 const char *nep_last_error(void);

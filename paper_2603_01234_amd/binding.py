@@ -25,6 +25,15 @@ NEP_ERR_NONFINITE = -5
 NEP_ERR_OVERLAP = -6
 NEP_ERR_UNSUPPORTED = -7
 NEP_ERR_OUTSIDE_BOX = -8
+# bits of status[0]
+NEP_FLAG_OVERFLOW_R = 1
+NEP_FLAG_OVERFLOW_A = 2
+NEP_FLAG_SKIN = 4
+NEP_FLAG_NONFINITE = 8
+NEP_FLAG_OUTSIDE_BOX = 16
+NEP_FLAG_OVERLAP = 32
+NEP_FLAG_IMAGE_RANGE = 64
+NEP_FLAG_BAD_TYPE = 128
 
 FLAG_OVERFLOW_R, FLAG_OVERFLOW_A, FLAG_SKIN = 1, 2, 4
 FLAG_NONFINITE, FLAG_OUTSIDE_BOX, FLAG_OVERLAP, FLAG_IMAGE_RANGE = 8, 16, 32, 64
@@ -57,7 +66,8 @@ class Neighbors(ctypes.Structure):
 
 
 class MdParams(ctypes.Structure):
-    _fields_ = [("dt_fs", c_float), ("n_steps", c_int), ("rebuild_every", c_int), ("mass", c_float * 4),
+    _fields_ = [("dt_fs", c_float), ("n_steps", c_int), ("rebuild_every", c_int), ("force_rebuild", c_int),
+                ("mass", c_float * 4),
                 ("strain_rate", c_double * 3), ("box0", c_double * 3), ("step", c_int64),
                 ("n_rebuilds", c_int), ("pair_counts", c_void_p)]
 
@@ -91,7 +101,7 @@ def lib():
         L.nep_md_step.restype = c_int
         L.nep_check_status.argtypes = [POINTER(Neighbors), POINTER(c_int32), c_void_p]
         L.nep_check_status.restype = c_int
-        L.nep_timing_begin.argtypes = [c_int]
+        L.nep_timing_begin.argtypes = [c_int, ctypes.c_uint]
         L.nep_timing_begin.restype = c_int
         L.nep_timing_end.argtypes = [POINTER(c_double), POINTER(c_int)]
         L.nep_timing_end.restype = c_int
@@ -160,8 +170,9 @@ def nep_check_status(nb: Neighbors, stream):
     return code, list(out)
 
 
-def nep_timing_begin(max_launches: int) -> None:
-    check(lib().nep_timing_begin(int(max_launches)))
+def nep_timing_begin(max_launches: int, class_mask: int = 0xF) -> None:
+    """Kernel classes: bit 0 main, 1 gather, 2 build, 3 kick-drift."""
+    check(lib().nep_timing_begin(int(max_launches), int(class_mask)))
 
 
 def nep_timing_end():

@@ -34,6 +34,7 @@ int fail(int code, const std::string &msg) {
 // optional event timing of kernel classes
 struct Timing {
     bool on = false;
+    unsigned mask = 0;
     int cap = 0, used = 0;
     std::vector<hipEvent_t> ev;  // 2 per launch
     std::vector<int> cls;
@@ -44,7 +45,7 @@ struct TimedLaunch {
     int k = -1;
     hipStream_t s;
     TimedLaunch(int cls, hipStream_t st) : s(st) {
-        if (g_timing.on && g_timing.used < g_timing.cap) {
+        if (g_timing.on && ((g_timing.mask >> cls) & 1u) && g_timing.used < g_timing.cap) {
             k = g_timing.used++;
             g_timing.cls[k] = cls;
             (void)hipEventRecord(g_timing.ev[2 * k], s);
@@ -61,7 +62,7 @@ constexpr int MAX_OFF = 125;  // (2m+1)^3 cell offsets with m <= 2
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, segA, rowbuf, ctrl, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, segA, rowbuf, vh, ctrl, total;
     int ncell_max, nblocks;
 };
 
@@ -92,6 +93,7 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.pos_sorted = take(nn * 16);
     L.segA = take(nn * (size_t)(MAX_OFF + 1));
     L.rowbuf = take(nn * (size_t)std::max(cap, 1) * 4);
+    L.vh = take(nn * 12);
     L.ctrl = take(4 * sizeof(int32_t));
     L.total = off;
     return L;
@@ -312,14 +314,21 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     g.partial = at<double>(ws, L.partial);
     if (md) {
         g.v = v;
+        g.vh = at<float>(ws, L.vh);
+        g.x = s->x;
+        g.y = s->y;
+        g.z = s->z;
         g.freeze = nb->status;
-        g.ref = nb->ref;
-        g.dt = mp->dt_fs;
         g.half_dt_accel = 0.5f * mp->dt_fs * ACCEL;
         for (int t = 0; t < M.T; ++t) {
             g.inv_mass[t] = 1.0f / mp->mass[t];
             g.mass[t] = mp->mass[t];
         }
+    }
+    if (!md) {
+        g.ref = nb->ref;
+        g.half_skin2 = 0.25f * nb->skin * nb->skin;
+        g.status = nb->status;
     }
     {
         TimedLaunch tl(1, st);
@@ -332,13 +341,15 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
 
 extern "C" {
 
-int nep_timing_begin(int max_launches) {
+int nep_timing_begin(int max_launches, unsigned class_mask) {
     if (g_timing.on) return fail(NEP_ERR_ARG, "timing already enabled");
     if (max_launches < 1 || max_launches > (1 << 20)) return fail(NEP_ERR_ARG, "max_launches out of range");
+    if ((class_mask & 15u) == 0) return fail(NEP_ERR_ARG, "class_mask selects no kernel class");
     g_timing.ev.assign(2 * (size_t)max_launches, nullptr);
     g_timing.cls.assign(max_launches, 0);
     for (auto &e : g_timing.ev) HIPCHK(hipEventCreate(&e));
     g_timing.cap = max_launches;
+    g_timing.mask = class_mask & 15u;
     g_timing.used = 0;
     g_timing.on = true;
     return NEP_OK;
@@ -530,7 +541,7 @@ int nep_compute_efv(nep_model model, const nep_system *s, const nep_neighbors *n
     // an empty system reduces zero blocks, so the totals come out as zero
     if (E_tot || W_tot)
         HIPCHK(launch_reduce(at<double>(ws, L.partial), s->n > 0 ? L.nblocks : 0, E_tot, W_tot, nullptr, nullptr,
-                             nullptr, nullptr, nullptr, nullptr, 0, 0, 0.0f, st));
+                             nullptr, nullptr, nullptr, nullptr, 0, st));
     return NEP_OK;
 }
 
@@ -564,53 +575,13 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         return mp->strain_rate[d] != 0.0 ? (float)(mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)stp))
                                          : s->box[d];
     };
-    // box scale factor of the drift of step stp
-    auto lam_at = [&](int64_t stp, int d) -> double {
-        return mp->strain_rate[d] != 0.0 ? (1.0 + mp->strain_rate[d] * (double)(stp + 1)) /
-                                               (1.0 + mp->strain_rate[d] * (double)stp)
-                                         : 1.0;
-    };
-    // squared threshold on the unscaled predicted displacement for the drift of
-    // step stp: 2% below skin/2 covers rounding between the prediction and the
-    // drift itself; a strained box scales the displacement by lambda
-    auto gate_thr2 = [&](int64_t stp) -> float {
-        double lmax = std::max(lam_at(stp, 0), std::max(lam_at(stp, 1), lam_at(stp, 2)));
-        double t = 0.98 * (double)half_skin / std::max(lmax, 1.0);
-        return (float)(t * t);
-    };
-    // a build gated by ctrl[0], which the reduction just before it has set
-    auto enqueue_gated_build = [&]() -> int {
-        NbArgs a;
-        int r = fill_nb(M, s, nb, ws, L, 0, 1, a);
-        if (r) return r;
-        a.ctrl = ctrl;
-        TimedLaunch tl(2, st);
-        HIPCHK(launch_build(a, st));
-        return NEP_OK;
-    };
-    HIPCHK(launch_clear_status(nb->status, ctrl, st));
-    // the first drift: does it take any bead beyond skin/2 of its build position?
-    PredictArgs pa{};
-    pa.n = n;
-    pa.T = M.T;
-    pa.x = s->x;
-    pa.y = s->y;
-    pa.z = s->z;
-    pa.v = v;
-    pa.F = F;
-    pa.ref = nb->ref;
-    pa.type = s->type;
-    pa.dt = mp->dt_fs;
-    pa.half_dt_accel = 0.5f * mp->dt_fs * ACCEL;
-    for (int t = 0; t < M.T; ++t) pa.inv_mass[t] = 1.0f / mp->mass[t];
-    pa.partial = at<double>(ws, L.partial);
-    HIPCHK(launch_predict(pa, st));
-    HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr, nullptr, nullptr,
-                         nullptr, nb->status, ctrl, 0, 0, gate_thr2(step0), st));
-    if ((rc = enqueue_gated_build())) return rc;
-    // Steps are queued without waiting for the device: the rebuild after each
-    // step is decided on the device from the exact position the next drift
-    // produces, and a failed rebuild freezes the remaining queued steps.
+    auto scheduled = [&](int64_t stp) -> int { return ((stp + 1) % mp->rebuild_every) == 0 ? 1 : 0; };
+    // the drift of step k sets the gate when a bead ends up farther than
+    // 0.99 skin/2 from its build position (the margin covers the rounding of
+    // the list predicate); the build queued right after it runs only then, or
+    // when the schedule asks for it
+    const float gate = 0.99f * half_skin;
+    HIPCHK(launch_clear_status(nb->status, ctrl, (mp->force_rebuild || scheduled(step0)) ? 1 : 0, st));
     for (int k = 0; k < n_steps; ++k) {
         const int64_t step = step0 + k;
         KickDriftArgs kd{};
@@ -619,6 +590,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         kd.y = s->y;
         kd.z = s->z;
         kd.v = v;
+        kd.vh = at<float>(ws, L.vh);
         kd.F = F;
         kd.type = s->type;
         kd.pos4 = at<float4>(ws, L.pos4);
@@ -630,24 +602,32 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         for (int d = 0; d < 3; ++d) {
             kd.lam[d] = 1.0f;
             if (mp->strain_rate[d] != 0.0) {
-                kd.lam[d] = (float)lam_at(step, d);
+                kd.lam[d] = (float)((1.0 + mp->strain_rate[d] * (double)(step + 1)) /
+                                    (1.0 + mp->strain_rate[d] * (double)step));
                 s->box[d] = box_at(step + 1, d);
             }
             kd.box[d] = s->box[d];
             kd.pbc[d] = s->pbc[d] ? 1 : 0;
         }
-        kd.half_skin2 = half_skin * half_skin;
+        kd.gate2 = gate * gate;
         kd.status = nb->status;
+        kd.ctrl = ctrl;
         {
             TimedLaunch tl(3, st);
             HIPCHK(launch_kick_drift(kd, st));
         }
+        {
+            NbArgs a;
+            if ((rc = fill_nb(M, s, nb, ws, L, 0, 1, a))) return rc;
+            a.ctrl = ctrl;
+            a.from_pos4 = 1;
+            TimedLaunch tl(2, st);
+            HIPCHK(launch_build(a, st));
+        }
         if ((rc = launch_efv(M, s, nb, U, F, nullptr, false, ws, L, st, true, v, mp))) return rc;
-        const int scheduled = ((step + 1) % mp->rebuild_every) == 0;
         HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
                              E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr, mp->pair_counts,
-                             nb->status, ctrl, 1, scheduled, gate_thr2(step + 1), st));
-        if ((rc = enqueue_gated_build())) return rc;
+                             nb->status, ctrl, scheduled(step + 1), st));
     }
     int32_t c[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(c, ctrl, sizeof c, hipMemcpyDeviceToHost, st));

@@ -372,13 +372,11 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
 template <int NT, bool VIR, bool MD>
 __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
     __shared__ double red[NPART][BLOCK];
-    __shared__ float redm[NMAX][BLOCK];
     if (MD && a.freeze && (a.freeze[0] & FREEZE_MASK)) return;  // uniform over the grid
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int i = tile * BLOCK + threadIdx.x;
     const int n = a.n;
     double acc[NPART];
-    float mx[NMAX] = {0.0f};
 #pragma unroll
     for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
     int nR_in = 0, nA_in = 0;  // pairs inside the interaction cutoffs (work accounting)
@@ -491,26 +489,27 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
             for (int c = 0; c < 9; ++c) acc[1 + c] = (double)W[c];
         }
         if (MD) {
+            // second half-kick from the half-step velocity; the step's new
+            // state (x, v) is committed to the caller's arrays only here, so
+            // a step stopped by a failed rebuild leaves the previous one whole
             float k = a.half_dt_accel * a.inv_mass[ti];
-            float vx = a.v[i] + k * Fx;
-            float vy = a.v[n + i] + k * Fy;
-            float vz = a.v[2 * n + i] + k * Fz;
+            float vx = a.vh[i] + k * Fx;
+            float vy = a.vh[n + i] + k * Fy;
+            float vz = a.vh[2 * n + i] + k * Fz;
             a.v[i] = vx;
             a.v[n + i] = vy;
             a.v[2 * n + i] = vz;
+            a.x[i] = pi.x;
+            a.y[i] = pi.y;
+            a.z[i] = pi.z;
             acc[10] = 0.5 * (double)a.mass[ti] * ((double)vx * vx + (double)vy * vy + (double)vz * vz) /
                       (double)ACCEL;
-            // where the next drift takes the bead, x + dt (v + dt/2 a), in the
-            // same float operations as the kick-drift kernel: its distance
-            // from the build reference decides the rebuild after this step
-            float ddx = a.dt * (vx + k * Fx), ddy = a.dt * (vy + k * Fy), ddz = a.dt * (vz + k * Fz);
-            float px = (pi.x + ddx) - a.ref[i], py = (pi.y + ddy) - a.ref[n + i], pz = (pi.z + ddz) - a.ref[2 * n + i];
-            mx[0] = px * px + py * py + pz * pz;
+        } else if (a.ref) {
+            // lists are only valid while every bead stays within skin/2 of
+            // where they were built
+            float dx = pi.x - a.ref[i], dy = pi.y - a.ref[n + i], dz = pi.z - a.ref[2 * n + i];
+            if (dx * dx + dy * dy + dz * dz > a.half_skin2) atomicOr(a.status, NEP_FLAG_SKIN);
         }
-    }
-    if (MD) {
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) redm[c][threadIdx.x] = mx[c];
     }
     // fixed-order block reduction
 #pragma unroll
@@ -520,86 +519,41 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
         if (threadIdx.x < s) {
 #pragma unroll
             for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
-            if (MD)
-#pragma unroll
-                for (int c = 0; c < NMAX; ++c) redm[c][threadIdx.x] = fmaxf(redm[c][threadIdx.x], redm[c][threadIdx.x + s]);
         }
         __syncthreads();
     }
-    if (threadIdx.x < NPART) a.partial[(size_t)tile * 16 + threadIdx.x] = red[threadIdx.x][0];
-    if (threadIdx.x < NMAX) a.partial[(size_t)tile * 16 + NPART + threadIdx.x] = MD ? (double)redm[threadIdx.x][0] : 0.0;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_predict(PredictArgs a) {
-    __shared__ double red[NPART][BLOCK];
-    __shared__ float redm[NMAX][BLOCK];
-    const int i = blockIdx.x * BLOCK + threadIdx.x;
-    const int n = a.n;
-    float mx[NMAX] = {0.0f};
-    if (i < n) {
-        int t = min((int)a.type[i], a.T - 1);
-        float k = a.half_dt_accel * a.inv_mass[t];
-        float Fx = a.F[i], Fy = a.F[n + i], Fz = a.F[2 * n + i];
-        float ddx = a.dt * (a.v[i] + k * Fx), ddy = a.dt * (a.v[n + i] + k * Fy), ddz = a.dt * (a.v[2 * n + i] + k * Fz);
-        float px = (a.x[i] + ddx) - a.ref[i], py = (a.y[i] + ddy) - a.ref[n + i], pz = (a.z[i] + ddz) - a.ref[2 * n + i];
-        mx[0] = px * px + py * py + pz * pz;
-    }
-#pragma unroll
-    for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = 0.0;
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) redm[c][threadIdx.x] = mx[c];
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
-#pragma unroll
-            for (int c = 0; c < NMAX; ++c) redm[c][threadIdx.x] = fmaxf(redm[c][threadIdx.x], redm[c][threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x < NPART) a.partial[(size_t)blockIdx.x * 16 + threadIdx.x] = 0.0;
-    if (threadIdx.x < NMAX) a.partial[(size_t)blockIdx.x * 16 + NPART + threadIdx.x] = (double)redm[threadIdx.x][0];
-}
-
-hipError_t launch_predict(const PredictArgs &a, hipStream_t s) {
-    if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_predict, dim3((a.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a);
-    return hipGetLastError();
+    if (threadIdx.x < NPART) a.partial[(size_t)tile * NPART + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Fixed-order FP64 reduction of the block partials.  In MD mode (ctrl given)
-// it also sets the rebuild gate ctrl[0] for the build launched right after it:
-// on when a rebuild is due by schedule, or when the next drift would take some
-// bead farther than sqrt(thr2) from its build reference (the block maxima of
-// the squared distance).  After a step (md_step) it counts the completed steps
-// in ctrl[2].  Once the status carries a freeze flag only the gate is written.
+// it counts the completed step in ctrl[2] and sets the rebuild gate ctrl[0]
+// for the next step to its schedule (the next drift may still switch it on).
+// Once the status carries a freeze flag nothing but the gate is written.
 __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double *E_tot,
                          double *W_tot, double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, int32_t *ctrl, int md_step, int force_build, float thr2) {
-    __shared__ double red[NPART + NMAX][BLOCK];
-    double acc[NPART + NMAX];
+                         const int32_t *status, int32_t *ctrl, int next_gate) {
+    __shared__ double red[NPART][BLOCK];
+    double acc[NPART];
 #pragma unroll
-    for (int c = 0; c < NPART + NMAX; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
 #pragma unroll
-        for (int c = 0; c < NPART; ++c) acc[c] += partial[(size_t)b * 16 + c];
-#pragma unroll
-        for (int c = NPART; c < NPART + NMAX; ++c) acc[c] = fmax(acc[c], partial[(size_t)b * 16 + c]);
+        for (int c = 0; c < NPART; ++c) acc[c] += partial[(size_t)b * NPART + c];
     }
 #pragma unroll
-    for (int c = 0; c < NPART + NMAX; ++c) red[c][threadIdx.x] = acc[c];
+    for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
     __syncthreads();
     for (int s = BLOCK / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
 #pragma unroll
             for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
-#pragma unroll
-            for (int c = NPART; c < NPART + NMAX; ++c) red[c][threadIdx.x] = fmax(red[c][threadIdx.x], red[c][threadIdx.x + s]);
         }
         __syncthreads();
     }
     const int st0 = status ? status[0] : 0;
     if (threadIdx.x == 0 && ctrl) {
-        ctrl[0] = (force_build || red[NPART][0] > (double)thr2) ? 1 : 0;
-        if (md_step && !(st0 & FREEZE_MASK)) ctrl[2] += 1;
+        ctrl[0] = next_gate;
+        if (!(st0 & FREEZE_MASK)) ctrl[2] += 1;
     }
     if (st0 & FREEZE_MASK) return;
     if (threadIdx.x == 0) {
@@ -617,10 +571,9 @@ __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double
 
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
                          double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, int32_t *ctrl, int md_step, int force_build, float thr2,
-                         hipStream_t s) {
+                         const int32_t *status, int32_t *ctrl, int next_gate, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(BLOCK), 0, s, partial, nblocks, E_tot, W_tot, K_tot,
-                       E_slot, K_slot, counts, status, ctrl, md_step, force_build, thr2);
+                       E_slot, K_slot, counts, status, ctrl, next_gate);
     return hipGetLastError();
 }
 

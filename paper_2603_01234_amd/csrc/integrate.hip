@@ -19,9 +19,9 @@ __global__ void k_kick_drift(KickDriftArgs a) {
     float vx = a.v[i] + k * a.F[i];
     float vy = a.v[n + i] + k * a.F[n + i];
     float vz = a.v[2 * n + i] + k * a.F[2 * n + i];
-    a.v[i] = vx;
-    a.v[n + i] = vy;
-    a.v[2 * n + i] = vz;
+    a.vh[i] = vx;
+    a.vh[n + i] = vy;
+    a.vh[2 * n + i] = vz;
     float x = (a.x[i] + a.dt * vx) * a.lam[0];
     float y = (a.y[i] + a.dt * vy) * a.lam[1];
     float z = (a.z[i] + a.dt * vz) * a.lam[2];
@@ -30,10 +30,8 @@ __global__ void k_kick_drift(KickDriftArgs a) {
     a.ref[n + i] = ry;
     a.ref[2 * n + i] = rz;
     float ddx = x - rx, ddy = y - ry, ddz = z - rz;
-    if (ddx * ddx + ddy * ddy + ddz * ddz > a.half_skin2) atomicOr(&a.status[0], NEP_FLAG_SKIN);
-    a.x[i] = x;
-    a.y[i] = y;
-    a.z[i] = z;
+    // every lane that sees a bead too far writes the same value
+    if (ddx * ddx + ddy * ddy + ddz * ddz > a.gate2) a.ctrl[0] = 1;
     a.pos4[i] = make_float4(x, y, z, (float)t);
 }
 

@@ -39,14 +39,14 @@ __global__ void k_nb_clear(int ncell, int32_t *cell_count, int32_t *status, int 
     if (ctrl && t == 0) ctrl[1] += 1;
 }
 
-__global__ void k_md_clear(int32_t *status, int32_t *ctrl) {
+__global__ void k_md_clear(int32_t *status, int32_t *ctrl, int gate0) {
     int t = threadIdx.x;
     if (t < 4) status[t] = 0;
-    if (ctrl && t < 4) ctrl[t] = 0;
+    if (ctrl && t < 4) ctrl[t] = t == 0 ? gate0 : 0;
 }
 
-hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, hipStream_t s) {
-    hipLaunchKernelGGL(k_md_clear, dim3(1), dim3(64), 0, s, status, ctrl);
+hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, int gate0, hipStream_t s) {
+    hipLaunchKernelGGL(k_md_clear, dim3(1), dim3(64), 0, s, status, ctrl, gate0);
     return hipGetLastError();
 }
 
@@ -69,13 +69,19 @@ __global__ void k_nb_bin(NbArgs a) {
     if (build_off(a)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    float p[3] = {a.x[i], a.y[i], a.z[i]};
+    float p[3];
+    if (a.from_pos4) {
+        const float4 q = a.pos4[i];
+        p[0] = q.x; p[1] = q.y; p[2] = q.z;
+    } else {
+        p[0] = a.x[i]; p[1] = a.y[i]; p[2] = a.z[i];
+    }
     if (a.wrap) {
         float *dst[3] = {a.x_mut, a.y_mut, a.z_mut};
         for (int d = 0; d < 3; ++d)
             if (a.pbc[d] && isfinite(p[d])) {
                 p[d] = wrap_coord(p[d], a.box[d]);
-                dst[d][i] = p[d];
+                if (!a.from_pos4) dst[d][i] = p[d];
             }
     }
     int flags = 0;
@@ -314,17 +320,15 @@ __global__ __launch_bounds__(BLOCK) void k_nb_transpose(NbArgs a) {
     if (i >= n) return;
     const int total = a.cnt[i], na = a.cnt[n + i];
     const uint32_t *row = a.rowbuf + (size_t)i * a.cap;
-    for (int p = 0; p < na; ++p) a.nbr[(size_t)p * n + i] = row[p];
-    for (int p = na; p < total; ++p) a.nbr[(size_t)p * n + i] = row[a.cap - 1 - (p - na)];
+    // one slot per iteration for every lane, so each store covers consecutive beads
+    for (int p = 0; p < total; ++p) a.nbr[(size_t)p * n + i] = row[p < na ? p : a.cap - 1 - (p - na)];
 }
 
-// one thread per (bead, angular slot); lanes of a wave read consecutive beads
-__global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
-    if (build_off(a)) return;
+constexpr int REV_SLOTS = 4;  // angular slots per thread: p = blockIdx.y + k gridDim.y
+
+// reverse entry of angular slot p of bead i: where j's row holds i
+__device__ __forceinline__ void reverse_one(const NbArgs &a, int i, int p) {
     const int n = a.n;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
-    const int p = blockIdx.y;
-    if (i >= n || p >= a.cnt[n + i]) return;
     const uint32_t e = a.nbr[(size_t)p * n + i];
     int j, nx, ny, nz;
     decode(e, j, nx, ny, nz);
@@ -349,6 +353,20 @@ __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
     a.rev[(size_t)p * n + i] = found < 0 ? -1 : (int32_t)((size_t)found * n + j);
 }
 
+// one thread per (bead, group of angular slots); lanes of a wave read
+// consecutive beads at the same slot
+__global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
+    if (build_off(a)) return;
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    if (i >= a.n) return;
+    const int na = a.cnt[a.n + i];
+    for (int k = 0; k < REV_SLOTS; ++k) {
+        const int p = blockIdx.y + k * gridDim.y;
+        if (p >= na) break;
+        reverse_one(a, i, p);
+    }
+}
+
 hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     int nbk = (a.n + BLOCK - 1) / BLOCK;
     int cbk = (a.ncell + BLOCK - 1) / BLOCK;
@@ -364,7 +382,7 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_nb_rank, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_rows, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_transpose, dim3(nbk), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_nb_reverse, dim3(nbk, a.cap_A), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_nb_reverse, dim3(nbk, (a.cap_A + REV_SLOTS - 1) / REV_SLOTS), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

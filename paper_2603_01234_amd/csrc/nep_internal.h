@@ -22,11 +22,8 @@ constexpr int TAB_PER_PAIR = NR * KB + NA * KB + NA * (KB - 1);  // 81 + 63 + 56
 constexpr uint32_t J_MASK = 0x1FFFFFFu;
 constexpr int CODE_SHIFT = 25;
 constexpr float ACCEL = 9.648533212e-5f;  // nm/fs^2 per (eV/nm)/amu
-// per-block partial sums: U, W (9), kinetic energy, radial pairs, angular pairs;
-// slot 13 of each block holds the maximum squared displacement from the build
-// reference that the next drift produces (rebuild gate)
+// per-block partial sums: U, W (9), kinetic energy, radial pairs, angular pairs
 constexpr int NPART = 13;
-constexpr int NMAX = 1;
 // status flags after which the MD kernels do nothing (the lists are invalid)
 constexpr int FREEZE_MASK = NEP_FLAG_OVERFLOW_R | NEP_FLAG_OVERFLOW_A | NEP_FLAG_NONFINITE |
                             NEP_FLAG_OUTSIDE_BOX | NEP_FLAG_IMAGE_RANGE | NEP_FLAG_BAD_TYPE;
@@ -85,14 +82,19 @@ struct GatherArgs {
     float *F;               // [3][n]
     float *W;               // [9][n] or null
     double *partial;        // [nblocks][16]: U, W(9), K, pairs within r_c^R, pairs within r_c^A
-    // fused second half-kick (MD)
+    // fused second half-kick (MD): v = vh + dt/2 a, and the drifted positions
+    // (pos4) are written back to x, y, z
     float *v;               // [3][n] or null
+    const float *vh;        // [3][n] half-step velocities from the kick-drift kernel
+    float *x, *y, *z;
     float half_dt_accel;    // dt/2 * ACCEL
-    float dt;
     float inv_mass[MAXT];
     float mass[MAXT];
-    const float *ref;       // [3][n] positions at the last build (rebuild prediction)
     const int32_t *freeze;  // MD: status word (see EfvArgs)
+    // outside MD: flag beads farther than skin/2 from their build position
+    const float *ref;       // [3][n] or null
+    float half_skin2;
+    int32_t *status;
 };
 
 // XCD-aware tile index: consecutive logical tiles are kept on one XCD (the
@@ -254,20 +256,9 @@ hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds_bytes, hi
 hipError_t launch_efv_gather(int T, bool virial, bool md, const GatherArgs &a, hipStream_t s);
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
                          double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, int32_t *ctrl, int md_step, int force_build, float thr2,
-                         hipStream_t s);
+                         const int32_t *status, int32_t *ctrl, int next_gate, hipStream_t s);
 // rebuild prediction at the start of an MD call: maxima of |x + d - ref|,
 // |d| and dt^2 |a| with d = dt (v + dt/2 a) the next drift, into the partials
-struct PredictArgs {
-    int n, T;
-    const float *x, *y, *z, *v, *F, *ref;
-    const uint8_t *type;
-    float dt, half_dt_accel;
-    float inv_mass[MAXT];
-    double *partial;
-};
-hipError_t launch_predict(const PredictArgs &a, hipStream_t s);
-
 struct NbArgs {
     int n, cap, cap_A;
     float box[3];
@@ -297,19 +288,26 @@ struct NbArgs {
     int ncell;
     int clear_status;  // 1: a fresh build resets the status word
     int wrap;          // 1: wrap periodic coordinates into [0, L) and write them back first
+    int from_pos4;     // 1 (MD): positions come from pos4 and are wrapped there, x/y/z are untouched
 };
 hipError_t launch_build(const NbArgs &a, hipStream_t s);
-// zeroes the status word and, when given, the MD control words [4]
-hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, hipStream_t s);
+// zeroes the status word and, when given, the MD control words [4] (the
+// rebuild gate ctrl[0] is set to gate0)
+hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, int gate0, hipStream_t s);
 
+// First half of a velocity-Verlet step.  Reads x, v, F; writes the half-step
+// velocities to vh and the drifted (and strained) positions to pos4, leaving
+// x and v to the gather kernel that completes the step.  Switches the rebuild
+// gate on when a bead ends up farther than sqrt(gate2) from its build position.
 struct KickDriftArgs {
     int n;
-    float *x, *y, *z;
-    float *v;               // [3][n]
+    const float *x, *y, *z;
+    const float *v;         // [3][n]
+    float *vh;              // [3][n]
     const float *F;         // [3][n]
     const uint8_t *type;
     float4 *pos4;
-    float *ref;             // [3][n] positions at the last build
+    float *ref;             // [3][n] positions at the last build (strained in place)
     float half_dt_accel;    // dt/2 * ACCEL
     float dt;
     float inv_mass[MAXT];
@@ -317,8 +315,9 @@ struct KickDriftArgs {
     float box[3];           // box after the strain
     int pbc[3];
     int T;                  // number of types (type values are clamped below it)
-    float half_skin2;       // (skin/2)^2
-    int32_t *status;
+    float gate2;            // squared displacement that calls for a rebuild
+    const int32_t *status;
+    int32_t *ctrl;          // ctrl[0]: rebuild gate
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s);
 

@@ -174,17 +174,20 @@ class Replica:
            strain_rate=(0.0, 0.0, 0.0), E_pot: Optional[torch.Tensor] = None,
            E_kin: Optional[torch.Tensor] = None,
            pair_counts: Optional[torch.Tensor] = None, regrow: bool = True):
-        """nep_md_step; after a rebuild overflow the rows are regrown, rebuilt and
-        the remaining steps resumed (x, v, F are consistent at that point)."""
+        """nep_md_step; after a rebuild overflow the rows are regrown and the
+        remaining steps resumed with a forced rebuild (x, v, F are those of the
+        last completed step, so the trajectory continues unchanged)."""
         if not self.lists_valid:
             self.build()
         remaining = int(n_steps)
         done_total = 0
+        force = False
         while True:
             mp = B.MdParams()
             mp.dt_fs = float(dt)
             mp.n_steps = remaining
             mp.rebuild_every = int(rebuild_every)
+            mp.force_rebuild = int(force)
             for t in range(4):
                 mp.mass[t] = float(masses[t]) if t < len(masses) else 1.0
             for d in range(3):
@@ -207,9 +210,10 @@ class Replica:
             if code == B.NEP_ERR_NEIGHBOR_OVERFLOW and regrow:
                 st = self.status.cpu().tolist()
                 self._alloc_lists(max(self.cap, int(st[1] * 1.25) + 8), max(self.cap_A, int(st[2] * 1.25) + 8))
-                self.build()
                 if remaining > 0:
+                    force = True
                     continue
+                self.build()
                 return self
             B.check(code)
             return self

@@ -79,3 +79,24 @@ def test_calls_reject_null_model_and_bad_structs():
     code, _ = B.nep_check_status(nb, None)
     assert code == B.NEP_ERR_ARG
     assert B.lib().nep_workspace_bytes(None, 10, 8, 4) == 0
+
+
+def test_binding_constants_match_header():
+    """Status codes and flag bits in the binding equal the header's values."""
+    from paper_2603_01234_amd import binding as B
+    txt = open(HEADER).read()
+    flags = dict((k, int(v)) for k, v in re.findall(r"#define\s+(NEP_FLAG_[A-Z_]+)\s+(\d+)", txt))
+    codes = dict((k, int(v)) for k, v in re.findall(r"\b(NEP_(?:OK|ERR_[A-Z_]+))\s*=\s*(-?\d+)", txt))
+    assert len(flags) == 8 and len(codes) >= 9
+    for k, v in list(flags.items()) + list(codes.items()):
+        assert getattr(B, k) == v, k
+
+
+def test_md_params_layout_matches_header():
+    """Field order of nep_md_params in the binding follows the header."""
+    from paper_2603_01234_amd import binding as B
+    txt = open(HEADER).read()
+    body = txt[txt.index("typedef struct {\n    float dt_fs;"):txt.index("} nep_md_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b([a-z_0-9]+)(?:\[\d+\])?;", body)
+    assert names == [f[0] for f in B.MdParams._fields_]

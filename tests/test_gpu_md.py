@@ -95,15 +95,35 @@ def test_md_strain_updates_box_and_stays_consistent():
     compare_efv(rep, ref, wire.n, check_virial=False, targets=targets, label="wire-strained")
 
 
-def test_skin_violation_is_reported():
-    from paper_2603_01234_amd import binding as B
+def test_drift_beyond_half_skin_rebuilds_before_the_forces():
+    """A bead drifting 0.1 nm in one 2 fs step (twice skin/2): the displacement
+    check after the drift rebuilds the lists before the force evaluation, every
+    step, so the forces stay exact."""
     spec, params, system, opts = W.config0()
     rep = _rep(spec, params, system, opts["skin"])
     rep.efv()
-    rep.v[0, 5] = 0.05          # 0.1 nm per 2 fs step: beyond skin/2 after one step
-    with pytest.raises(B.NepError) as ei:
-        rep.md(3, 2.0, [W.WATER_MASS], rebuild_every=10)
-    assert ei.value.code == B.NEP_ERR_SKIN_VIOLATION
+    rep.v[0, 5] = 0.05
+    rep.md(3, 2.0, [W.WATER_MASS], rebuild_every=10)
+    assert rep.n_rebuilds == 3
+    rep.efv()                          # totals (E_tot) at the final positions
+    ref = oracle.efv(spec, params.astype(np.float32).astype(np.float64), rep.positions().astype(np.float64),
+                     system.types, system.box.astype(np.float32).astype(np.float64), system.pbc)
+    compare_efv(rep, ref, system.n, check_virial=False, label="fast-drift")
+
+
+def test_efv_on_stale_lists_is_reported():
+    from paper_2603_01234_amd import binding as B
+    spec, params, system, opts = W.config0()
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.build()
+    rep.xyz[0, 7] += 0.6 * opts["skin"]
+    rep.efv()
+    code, st = B.nep_check_status(rep.c_neighbors(), torch.cuda.current_stream().cuda_stream)
+    assert code == B.NEP_ERR_SKIN_VIOLATION and st[0] & B.NEP_FLAG_SKIN
+    rep.build()
+    rep.efv()
+    code, _ = B.nep_check_status(rep.c_neighbors(), torch.cuda.current_stream().cuda_stream)
+    assert code == B.NEP_OK
 
 
 def test_fast_beads_trigger_early_rebuilds_and_stay_exact():
