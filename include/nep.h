@@ -221,6 +221,58 @@ int nep_md_step(nep_model model, nep_system *sys, float *v, nep_md_params *param
 int nep_check_status(const nep_neighbors *nbrs, int32_t host_status_out[4], void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* batched evaluation for the fitness loop (Sec. II.A: candidates of the      */
+/* evolution strategy scored by the RMSE of energies and virials per bead and */
+/* of forces per component)                                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int block;       /* threads per workgroup: 64, 128 or 256 (0 = 256) */
+    int order;       /* 0: items in the given order; 1: largest structures first */
+    int wg_per_cu;   /* resident workgroups per compute unit (0 = as many as fit) */
+} nep_batch_config;
+
+typedef struct {
+    const double *E; /* device [n_systems]: reference energy of each structure (eV) */
+    const double *F; /* device [sum_s n_s][3]: reference forces, structures in order (eV/nm) */
+    const double *W; /* device [n_systems][9]: reference total virial W[a][b] at 3a+b (eV) */
+} nep_labels;
+
+/* Workspace for nep_compute_efv_batch with this configuration (cfg NULL: the
+ * largest over every configuration nep_batch_autotune tries).  0 on bad
+ * arguments (nep_last_error). */
+size_t nep_batch_workspace_bytes(const nep_model *models, int n_models, const nep_system *systems,
+                                 const nep_neighbors *lists, int n_systems, int n_items,
+                                 const nep_batch_config *cfg);
+
+/* Evaluates n_items (candidate, structure) pairs in one persistent launch.
+ * models: host array of n_models handles that share n_types, n_hidden and
+ * cutoffs (the candidates of one model family).  systems / lists: host arrays
+ * of n_systems structures and their lists from nep_build_neighbors (skin 0 is
+ * fine for a single evaluation; positions must not have moved since).  work:
+ * host [n_items][2] = (model index, system index).  Workgroups take items from
+ * a device work queue, each item being evaluated whole by one workgroup; every
+ * reduction has a fixed order, so results do not depend on the schedule.
+ * Outputs (device, each may be NULL):
+ *   rmse     [n_models][3]: RMSE_E (eV/bead), RMSE_F (eV/nm per component),
+ *            RMSE_W (eV/bead over xx yy zz xy yz xz) over the model's items,
+ *            against labels (labels required when rmse is given);
+ *   item_out [n_items][10]: E and total W[9] of every item, in work order;
+ *   F_out    [sum over items of n][3]: forces of every item, in work order.
+ * cfg NULL: defaults.  Synchronises the stream before it returns. */
+int nep_compute_efv_batch(const nep_model *models, int n_models, const nep_system *systems,
+                          const nep_neighbors *lists, int n_systems, const int32_t *work, int n_items,
+                          const nep_labels *labels, double *rmse, double *item_out, float *F_out,
+                          const nep_batch_config *cfg, void *ws, size_t ws_bytes, void *stream);
+
+/* Times every configuration it knows (block 64 / 128 / 256 x order 0 / 1) on
+ * the given work, one warm-up and one timed run each, and returns the fastest
+ * in best.  ms: host [6] or NULL, the measured times in that order.  The
+ * workspace must hold nep_batch_workspace_bytes(..., NULL). */
+int nep_batch_autotune(const nep_model *models, int n_models, const nep_system *systems,
+                       const nep_neighbors *lists, int n_systems, const int32_t *work, int n_items,
+                       void *ws, size_t ws_bytes, void *stream, nep_batch_config *best, float *ms);
+
+/* ------------------------------------------------------------------------ */
 /* kernel timing (benchmark support)                                         */
 /* ------------------------------------------------------------------------ */
 /* While enabled, the library records a HIP event pair on the launching stream

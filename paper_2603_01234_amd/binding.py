@@ -40,7 +40,8 @@ FLAG_NONFINITE, FLAG_OUTSIDE_BOX, FLAG_OVERLAP, FLAG_IMAGE_RANGE = 8, 16, 32, 64
 
 EXPORTS = ["nep_param_count", "nep_model_create", "nep_model_destroy", "nep_workspace_bytes",
            "nep_build_neighbors", "nep_compute_efv", "nep_md_step", "nep_check_status",
-           "nep_last_error", "nep_timing_begin", "nep_timing_end"]
+           "nep_last_error", "nep_timing_begin", "nep_timing_end", "nep_batch_workspace_bytes",
+           "nep_compute_efv_batch", "nep_batch_autotune"]
 
 
 class NepError(RuntimeError):
@@ -63,6 +64,14 @@ class System(ctypes.Structure):
 class Neighbors(ctypes.Structure):
     _fields_ = [("cap", c_int), ("cap_A", c_int), ("nbr", c_void_p), ("rev", c_void_p),
                 ("cnt", c_void_p), ("ref", c_void_p), ("skin", c_float), ("status", c_void_p)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("block", c_int), ("order", c_int), ("wg_per_cu", c_int)]
+
+
+class Labels(ctypes.Structure):
+    _fields_ = [("E", c_void_p), ("F", c_void_p), ("W", c_void_p)]
 
 
 class MdParams(ctypes.Structure):
@@ -105,6 +114,16 @@ def lib():
         L.nep_timing_begin.restype = c_int
         L.nep_timing_end.argtypes = [POINTER(c_double), POINTER(c_int)]
         L.nep_timing_end.restype = c_int
+        L.nep_batch_workspace_bytes.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, c_int,
+                                                POINTER(BatchConfig)]
+        L.nep_batch_workspace_bytes.restype = c_size_t
+        L.nep_compute_efv_batch.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p, c_int,
+                                            POINTER(Labels), c_void_p, c_void_p, c_void_p, POINTER(BatchConfig),
+                                            c_void_p, c_size_t, c_void_p]
+        L.nep_compute_efv_batch.restype = c_int
+        L.nep_batch_autotune.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p,
+                                         c_size_t, c_void_p, POINTER(BatchConfig), POINTER(c_float)]
+        L.nep_batch_autotune.restype = c_int
         L.nep_last_error.argtypes = []
         L.nep_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -181,3 +200,40 @@ def nep_timing_end():
     cnt = (c_int * 4)()
     check(lib().nep_timing_end(ms, cnt))
     return list(ms), list(cnt)
+
+
+def _batch_arrays(models, systems, lists, work):
+    """Host arrays for the batched calls (kept alive by the caller)."""
+    m = (c_void_p * len(models))(*models)
+    sy = (System * max(len(systems), 1))(*systems)
+    li = (Neighbors * max(len(lists), 1))(*lists)
+    w = np.ascontiguousarray(np.asarray(work, dtype=np.int32).reshape(-1, 2))
+    return m, sy, li, w
+
+
+def nep_batch_workspace_bytes(models, systems, lists, n_items: int, cfg: Optional[BatchConfig]) -> int:
+    m, sy, li, _ = _batch_arrays(models, systems, lists, np.zeros((0, 2)))
+    n = lib().nep_batch_workspace_bytes(m, len(models), sy, li, len(systems), int(n_items),
+                                        ctypes.byref(cfg) if cfg is not None else None)
+    if n == 0:
+        raise NepError(NEP_ERR_ARG, last_error())
+    return int(n)
+
+
+def nep_compute_efv_batch(models, systems, lists, work, labels: Optional[Labels], rmse, item_out, F_out,
+                          cfg: Optional[BatchConfig], ws_ptr, ws_bytes, stream) -> int:
+    m, sy, li, w = _batch_arrays(models, systems, lists, work)
+    return lib().nep_compute_efv_batch(m, len(models), sy, li, len(systems), w.ctypes.data, w.shape[0],
+                                       ctypes.byref(labels) if labels is not None else None, rmse, item_out,
+                                       F_out, ctypes.byref(cfg) if cfg is not None else None, ws_ptr, ws_bytes,
+                                       stream)
+
+
+def nep_batch_autotune(models, systems, lists, work, ws_ptr, ws_bytes, stream):
+    """Returns (best BatchConfig, [ms] per tried configuration)."""
+    m, sy, li, w = _batch_arrays(models, systems, lists, work)
+    best = BatchConfig()
+    ms = (c_float * 6)()
+    check(lib().nep_batch_autotune(m, len(models), sy, li, len(systems), w.ctypes.data, w.shape[0], ws_ptr,
+                                   ws_bytes, stream, ctypes.byref(best), ms))
+    return best, list(ms)

@@ -337,6 +337,169 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     return NEP_OK;
 }
 
+
+// ---- batched evaluation: validation, layout, upload, launch ----
+struct BatchPlan {
+    int T = 0, HP = 0, BS = 256, order = 0, grid = 1, nmax = 1, capAmax = 1;
+    size_t stride = 0;
+    // workspace offsets
+    size_t sys = 0, mod = 0, items = 0, list = 0, F_off = 0, records = 0, counter = 0, scratch = 0, total = 0;
+};
+
+int batch_check(const nep_model *models, int n_models, const nep_system *systems, const nep_neighbors *lists,
+                int n_systems, int n_items, const Model *&M0) {
+    if (n_models < 1 || !models) return fail(NEP_ERR_ARG, "need at least one model");
+    if (n_systems < 0 || n_items < 0) return fail(NEP_ERR_ARG, "negative counts");
+    if (n_systems > 0 && (!systems || !lists)) return fail(NEP_ERR_ARG, "systems or lists are null");
+    int rc;
+    for (int m = 0; m < n_models; ++m)
+        if ((rc = check_model(models[m]))) return rc;
+    M0 = &models[0]->m;
+    for (int m = 1; m < n_models; ++m) {
+        const Model &M = models[m]->m;
+        if (M.T != M0->T || M.H != M0->H || M.HP != M0->HP)
+            return fail(NEP_ERR_ARG, "batched models must share n_types and n_hidden");
+        for (int k = 0; k < M.T * M.T; ++k)
+            if (M.rcR[k] != M0->rcR[k] || M.rcA[k] != M0->rcA[k])
+                return fail(NEP_ERR_ARG, "batched models must share the cutoffs (the lists are shared)");
+    }
+    for (int k = 0; k < n_systems; ++k) {
+        if ((rc = check_system(*M0, &systems[k]))) return rc;
+        if ((rc = check_nbrs(&systems[k], &lists[k]))) return rc;
+    }
+    return NEP_OK;
+}
+
+int batch_plan(const Model &M0, const nep_system *systems, const nep_neighbors *lists, int n_systems,
+               int n_models, int n_items, int block, int order, int wg_per_cu, BatchPlan &P) {
+    if (!(block == 64 || block == 128 || block == 256)) return fail(NEP_ERR_ARG, "block must be 64, 128 or 256");
+    if (order < 0 || order > 1) return fail(NEP_ERR_ARG, "order must be 0 or 1");
+    if (wg_per_cu < 0) return fail(NEP_ERR_ARG, "wg_per_cu must be >= 0");
+    P.T = M0.T;
+    P.HP = M0.HP;
+    P.BS = block;
+    P.order = order;
+    P.nmax = 1;
+    P.capAmax = 1;
+    for (int k = 0; k < n_systems; ++k) {
+        P.nmax = std::max(P.nmax, systems[k].n);
+        P.capAmax = std::max(P.capAmax, lists[k].cap_A);
+    }
+    P.stride = ((size_t)16 * P.nmax * (2 + 3 * (size_t)P.T + P.capAmax) + 4 * (size_t)P.nmax + 255) & ~(size_t)255;
+    int occ = batch_occupancy(P.T, P.HP, P.BS);
+    if (occ < 1) return fail(NEP_ERR_HIP, "batched kernel does not fit on a compute unit");
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int wg = wg_per_cu > 0 ? std::min(wg_per_cu, occ) : occ;
+    P.grid = std::max(1, std::min(wg * std::max(cus, 1), std::max(n_items, 1)));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    P.sys = take(sizeof(SysDesc) * (size_t)std::max(n_systems, 1));
+    P.mod = take(sizeof(ModelDesc) * (size_t)n_models);
+    P.items = take(sizeof(int4) * (size_t)std::max(n_items, 1));
+    P.list = take(sizeof(int4) * (size_t)std::max(n_items, 1));
+    P.F_off = take(sizeof(int64_t) * (size_t)std::max(n_items, 1));
+    P.records = take(sizeof(double) * 12 * (size_t)std::max(n_items, 1));
+    P.counter = take(sizeof(int));
+    P.scratch = take(P.stride * (size_t)P.grid);
+    P.total = off;
+    return NEP_OK;
+}
+
+// Uploads the descriptor tables and queues the persistent kernel (between the
+// two events when given) and the per-candidate sums.
+int batch_run(const nep_model *models, int n_models, const nep_system *systems, const nep_neighbors *lists,
+              int n_systems, const int32_t *work, int n_items, const nep_labels *labels, double *rmse,
+              double *item_out, float *F_out, const BatchPlan &P, void *ws, size_t ws_bytes, hipStream_t st,
+              hipEvent_t ev0, hipEvent_t ev1) {
+    if (!ws || ((uintptr_t)ws) % 256) return fail(NEP_ERR_ARG, "workspace must be non-null and 256-byte aligned");
+    if (ws_bytes < P.total)
+        return fail(NEP_ERR_ARG, "workspace too small: need " + std::to_string(P.total) + " bytes");
+    if (n_items > 0 && !work) return fail(NEP_ERR_ARG, "work list is null");
+    if (rmse && (!labels || !labels->E || !labels->F || !labels->W))
+        return fail(NEP_ERR_ARG, "rmse needs energy, force and virial labels");
+    std::vector<SysDesc> sd((size_t)std::max(n_systems, 1));
+    int64_t label_off = 0;
+    for (int k = 0; k < n_systems; ++k) {
+        const nep_system &S = systems[k];
+        const nep_neighbors &N = lists[k];
+        SysDesc &d = sd[k];
+        d.n = S.n;
+        d.label_off = (int)label_off;
+        for (int q = 0; q < 3; ++q) {
+            d.box[q] = S.box[q];
+            // the images in the lists carry the periodicity; open dimensions
+            // never produce an image code other than zero
+        }
+        d.x = S.x;
+        d.y = S.y;
+        d.z = S.z;
+        d.type = S.type;
+        d.nbr = N.nbr;
+        d.rev = N.rev;
+        d.cnt = N.cnt;
+        label_off += S.n;
+    }
+    if (label_off >= (1ll << 31)) return fail(NEP_ERR_ARG, "too many beads in the batch");
+    std::vector<ModelDesc> md((size_t)n_models);
+    for (int m = 0; m < n_models; ++m) {
+        md[m].tab = models[m]->m.d_tab;
+        md[m].ann = models[m]->m.d_ann;
+    }
+    std::vector<int4> list((size_t)std::max(n_items, 1));
+    std::vector<int64_t> foff((size_t)std::max(n_items, 1));
+    int64_t rows = 0;
+    for (int it = 0; it < n_items; ++it) {
+        const int m = work[2 * it], k = work[2 * it + 1];
+        if (m < 0 || m >= n_models || k < 0 || k >= n_systems)
+            return fail(NEP_ERR_ARG, "work item " + std::to_string(it) + " out of range");
+        list[it] = make_int4(m, k, it, 0);
+        foff[it] = rows;
+        rows += systems[k].n;
+    }
+    std::vector<int4> items(list);
+    if (P.order == 1)
+        std::stable_sort(items.begin(), items.begin() + n_items,
+                         [&](const int4 &a, const int4 &b) { return systems[a.y].n > systems[b.y].n; });
+    HIPCHK(hipMemcpyAsync(at<char>(ws, P.sys), sd.data(), sizeof(SysDesc) * sd.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<char>(ws, P.mod), md.data(), sizeof(ModelDesc) * md.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<char>(ws, P.items), items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<char>(ws, P.list), list.data(), sizeof(int4) * list.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<char>(ws, P.F_off), foff.data(), sizeof(int64_t) * foff.size(), hipMemcpyHostToDevice, st));
+    BatchArgs b{};
+    b.n_items = n_items;
+    b.items = at<int4>(ws, P.items);
+    b.sys = at<SysDesc>(ws, P.sys);
+    b.mod = at<ModelDesc>(ws, P.mod);
+    b.cut = make_cut(models[0]->m);
+    b.counter = at<int>(ws, P.counter);
+    b.scratch = at<char>(ws, P.scratch);
+    b.scratch_stride = P.stride;
+    b.nmax = P.nmax;
+    b.capAmax = P.capAmax;
+    b.F_ref = (labels && rmse) ? labels->F : nullptr;
+    b.records = at<double>(ws, P.records);
+    b.F_out = F_out;
+    b.F_off = at<int64_t>(ws, P.F_off);
+    if (ev0) HIPCHK(hipEventRecord(ev0, st));
+    HIPCHK(launch_efv_batch(P.T, P.HP, P.BS, b, P.grid, st));
+    if (ev1) HIPCHK(hipEventRecord(ev1, st));
+    HIPCHK(launch_batch_rmse(n_models, n_items, at<int4>(ws, P.list), at<SysDesc>(ws, P.sys),
+                             at<double>(ws, P.records), labels ? labels->E : nullptr,
+                             labels ? labels->W : nullptr, rmse, item_out, st));
+    // the host tables above must outlive the copies
+    HIPCHK(hipStreamSynchronize(st));
+    return NEP_OK;
+}
+
+constexpr int N_TUNE = 6;
+const int TUNE_BLOCK[N_TUNE] = {64, 128, 256, 64, 128, 256};
+const int TUNE_ORDER[N_TUNE] = {0, 0, 0, 1, 1, 1};
 }  // namespace
 
 extern "C" {
@@ -636,6 +799,72 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     mp->step = step0 + c[2];
     for (int d = 0; d < 3; ++d) s->box[d] = box_at(mp->step, d);
     return read_status(nb, nullptr, st);
+}
+
+size_t nep_batch_workspace_bytes(const nep_model *models, int n_models, const nep_system *systems,
+                                 const nep_neighbors *lists, int n_systems, int n_items,
+                                 const nep_batch_config *cfg) {
+    const Model *M0 = nullptr;
+    if (batch_check(models, n_models, systems, lists, n_systems, n_items, M0)) return 0;
+    size_t best = 0;
+    for (int c = 0; c < (cfg ? 1 : N_TUNE); ++c) {
+        BatchPlan P;
+        const int block = cfg ? (cfg->block ? cfg->block : 256) : TUNE_BLOCK[c];
+        const int order = cfg ? cfg->order : TUNE_ORDER[c];
+        const int wg = cfg ? cfg->wg_per_cu : 0;
+        if (batch_plan(*M0, systems, lists, n_systems, n_models, n_items, block, order, wg, P)) return 0;
+        best = std::max(best, P.total);
+    }
+    return best;
+}
+
+int nep_compute_efv_batch(const nep_model *models, int n_models, const nep_system *systems,
+                          const nep_neighbors *lists, int n_systems, const int32_t *work, int n_items,
+                          const nep_labels *labels, double *rmse, double *item_out, float *F_out,
+                          const nep_batch_config *cfg, void *ws, size_t ws_bytes, void *stream) {
+    const Model *M0 = nullptr;
+    int rc;
+    if ((rc = batch_check(models, n_models, systems, lists, n_systems, n_items, M0))) return rc;
+    BatchPlan P;
+    if ((rc = batch_plan(*M0, systems, lists, n_systems, n_models, n_items, cfg && cfg->block ? cfg->block : 256,
+                         cfg ? cfg->order : 0, cfg ? cfg->wg_per_cu : 0, P)))
+        return rc;
+    return batch_run(models, n_models, systems, lists, n_systems, work, n_items, labels, rmse, item_out, F_out, P,
+                     ws, ws_bytes, (hipStream_t)stream, nullptr, nullptr);
+}
+
+int nep_batch_autotune(const nep_model *models, int n_models, const nep_system *systems,
+                       const nep_neighbors *lists, int n_systems, const int32_t *work, int n_items,
+                       void *ws, size_t ws_bytes, void *stream, nep_batch_config *best, float *ms) {
+    const Model *M0 = nullptr;
+    int rc;
+    if (!best) return fail(NEP_ERR_ARG, "best is null");
+    if ((rc = batch_check(models, n_models, systems, lists, n_systems, n_items, M0))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = -1.0f;
+    for (int c = 0; c < N_TUNE; ++c) {
+        BatchPlan P;
+        rc = batch_plan(*M0, systems, lists, n_systems, n_models, n_items, TUNE_BLOCK[c], TUNE_ORDER[c], 0, P);
+        float t = 0.0f;
+        for (int rep = 0; rep < 2 && !rc; ++rep)
+            rc = batch_run(models, n_models, systems, lists, n_systems, work, n_items, nullptr, nullptr, nullptr,
+                           nullptr, P, ws, ws_bytes, st, e0, e1);
+        if (!rc && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(NEP_ERR_HIP, "event timing failed");
+        if (rc) break;
+        if (ms) ms[c] = t;
+        if (best_ms < 0.0f || t < best_ms) {
+            best_ms = t;
+            best->block = TUNE_BLOCK[c];
+            best->order = TUNE_ORDER[c];
+            best->wg_per_cu = 0;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int nep_check_status(const nep_neighbors *nb, int32_t out[4], void *stream) {

@@ -20,21 +20,9 @@
 //               W_i = sum_j r_ij (x) dU_j/dr_ji; fixed-order block sums of U,
 //               W and (for MD) the kinetic energy; optional second half-kick.
 // k_reduce      fixed-order FP64 reduction of the block sums.
-#include <type_traits>
-
-#include "nep_internal.h"
+#include "efv_device.h"
 
 namespace nep {
-
-// N2_lm: squared normalisation of the real harmonics P_lm (l = 1..4)
-#define PI_F 3.14159265358979f
-__device__ constexpr float N2[LM] = {
-    3.0f / (4 * PI_F), 3.0f / (4 * PI_F), 3.0f / (4 * PI_F),
-    15.0f / (4 * PI_F), 15.0f / (4 * PI_F), 15.0f / (4 * PI_F), 15.0f / (16 * PI_F), 5.0f / (16 * PI_F),
-    35.0f / (32 * PI_F), 105.0f / (4 * PI_F), 21.0f / (32 * PI_F), 7.0f / (16 * PI_F),
-    21.0f / (32 * PI_F), 105.0f / (16 * PI_F), 35.0f / (32 * PI_F),
-    315.0f / (16 * PI_F), 315.0f / (32 * PI_F), 45.0f / (16 * PI_F), 45.0f / (32 * PI_F),
-    9.0f / (256 * PI_F), 45.0f / (32 * PI_F), 45.0f / (64 * PI_F), 315.0f / (32 * PI_F), 315.0f / (256 * PI_F)};
 
 // positions and (range-clamped) type packed for the neighbour gathers
 __global__ void k_pack(int n, int T, const float *__restrict__ x, const float *__restrict__ y,
@@ -49,162 +37,6 @@ hipError_t launch_pack(int n, int T, const float *x, const float *y, const float
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, n, T, x, y, z, type, pos4);
     return hipGetLastError();
-}
-
-struct PairGeom {
-    int j, tj;
-    float dx, dy, dz, d2;
-};
-
-
-__device__ __forceinline__ PairGeom geom_of(uint32_t e, const float4 &pj, const float4 &pi,
-                                            const float box[3]) {
-    PairGeom g;
-    int nx, ny, nz;
-    decode(e, g.j, nx, ny, nz);
-    g.dx = (pj.x + (float)nx * box[0]) - pi.x;
-    g.dy = (pj.y + (float)ny * box[1]) - pi.y;
-    g.dz = (pj.z + (float)nz * box[2]) - pi.z;
-    g.d2 = g.dx * g.dx + g.dy * g.dy + g.dz * g.dz;
-    g.tj = (int)pj.w;
-    return g;
-}
-
-// Neighbour stream of one row with software prefetch: the entry two slots
-// ahead and the position one slot ahead are in flight while the current pair
-// is processed.
-struct RowStream {
-    const uint32_t *__restrict__ nbr;
-    const float4 *__restrict__ pos4;
-    int n, i, cnt;
-    uint32_t e_cur, e_nxt;
-    float4 p_cur;
-    __device__ __forceinline__ void start(const uint32_t *nb, const float4 *pp, int n_, int i_, int c) {
-        nbr = nb;
-        pos4 = pp;
-        n = n_;
-        i = i_;
-        cnt = c;
-        e_cur = c > 0 ? nbr[i] : 0u;
-        e_nxt = c > 1 ? nbr[(size_t)n + i] : 0u;
-        p_cur = c > 0 ? pos4[e_cur & J_MASK] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-    __device__ __forceinline__ void next(int p, uint32_t &e, float4 &pj) {
-        e = e_cur;
-        pj = p_cur;
-        e_cur = e_nxt;
-        if (p + 2 < cnt) e_nxt = nbr[(size_t)(p + 2) * n + i];
-        if (p + 1 < cnt) p_cur = pos4[e_cur & J_MASK];
-    }
-};
-
-
-// Tables read through the constant address space: with wave-uniform addresses
-// (one type) these become scalar loads whose values feed the FMAs as SGPR
-// operands, so the weights never occupy vector registers.
-typedef const __attribute__((address_space(4))) float *const_fp;
-
-template <int NT>
-using table_ptr = typename std::conditional<NT == 1, const_fp, const float *>::type;
-
-// Descriptor from the pair sums, the network (Eq. 2) with its gradient, the
-// radial back-propagation coefficients (written to bvec_out), and the angular
-// gradient folded into A (D_{n,lm} = dU/dq_nl 2 N2_lm A_{n,lm}).  ti is
-// wave-uniform, so every table read is a scalar load.
-template <int NT, int HP>
-__device__ __forceinline__ void network(const int ti, const const_fp TB, const const_fp AN,
-                                        const float S[NT][KB], float A[NA][LM], float *U_out,
-                                        float4 *bvec_out) {
-    asm volatile("" ::: "memory");
-    // ---------------- descriptor and network (Eq. 2), nu-outer ----------------
-    const const_fp an = AN + ti * (ND + 2) * HP;  // w0T[ND][HP], b0[HP], w1[HP]
-    float z[HP];
-#pragma unroll
-    for (int m = 0; m < HP; ++m) z[m] = -an[ND * HP + m];
-    // The memory barriers below keep one row of HP weights in flight at a
-    // time; without them the weight loads are hoisted and spill.
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        float qv = 0.0f;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const const_fp cRp = TB + (ti * NT + t) * TAB_PER_PAIR;
-#pragma unroll
-            for (int k = 0; k < KB; ++k) qv += cRp[q * KB + k] * S[t][k];
-        }
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int m = 0; m < HP; ++m) z[m] += an[q * HP + m] * qv;
-    }
-#pragma unroll
-    for (int L = 1; L <= 4; ++L)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) {
-            float qv = 0.0f;
-#pragma unroll
-            for (int l = 0; l < LM; ++l)
-                if (lm_l(l) == L) qv += N2[l] * A[q][l] * A[q][l];
-            const int nu = NR + (L - 1) * NA + q;
-            asm volatile("" ::: "memory");
-#pragma unroll
-            for (int m = 0; m < HP; ++m) z[m] += an[nu * HP + m] * qv;
-        }
-    float U = -AN[NT * (ND + 2) * HP];
-    asm volatile("" ::: "memory");
-#pragma unroll
-    for (int m = 0; m < HP; ++m) {
-        const float h = tanh_nobranch(z[m]);
-        const float w1m = an[(ND + 1) * HP + m];
-        U += w1m * h;
-        z[m] = w1m * (1.0f - h * h);  // dU/dz_m
-    }
-    *U_out = U;
-
-    // dU/dq, nu-outer: radial part kept, angular part folded into
-    // D_{n,lm} = dU/dq_nl * 2 N2_lm A_{n,lm}  (in place of A)
-    float dr[NR];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        asm volatile("" ::: "memory");
-        float acc = 0.0f;
-#pragma unroll
-        for (int m = 0; m < HP; ++m) acc += z[m] * an[q * HP + m];
-        dr[q] = acc;
-    }
-#pragma unroll
-    for (int L = 1; L <= 4; ++L)
-#pragma unroll
-        for (int q = 0; q < NA; ++q) {
-            const int nu = NR + (L - 1) * NA + q;
-            asm volatile("" ::: "memory");
-            float acc = 0.0f;
-#pragma unroll
-            for (int m = 0; m < HP; ++m) acc += z[m] * an[nu * HP + m];
-#pragma unroll
-            for (int l = 0; l < LM; ++l)
-                if (lm_l(l) == L) A[q][l] *= 2.0f * N2[l] * acc;
-        }
-    asm volatile("" ::: "memory");
-
-    // radial back-propagation coefficients per neighbour type:
-    //   beta_k = sum_n dU/dq_n c'_nk   (k = 0 uses c'_n0 = c_n0 + sum_k c_nk)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const const_fp cRp = TB + (ti * NT + t) * TAB_PER_PAIR;
-        float be[KB];
-#pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int q = 0; q < NR; ++q) acc += dr[q] * cRp[q * KB + k];
-            be[k] = acc;
-        }
-        float4 *dst = bvec_out + (size_t)t * 3;
-        dst[0] = make_float4(be[0], be[1], be[2], be[3]);
-        dst[1] = make_float4(be[4], be[5], be[6], be[7]);
-        dst[2] = make_float4(be[8], 0.0f, 0.0f, 0.0f);
-    }
-
 }
 
 template <int NT, int HP>
@@ -225,148 +57,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int i = tile * BLOCK + threadIdx.x;
     if (i >= a.n) return;
-    const int n = a.n;
-    const float4 pi = a.pos4[i];
-    const int ti = (NT == 1) ? 0 : (int)pi.w;
-    const int cR = a.cnt[i];
-    const int cA = a.cnt[n + i];
-
-    float S[NT][KB];
-    float A[NA][LM];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int k = 0; k < KB; ++k) S[t][k] = 0.0f;
-#pragma unroll
-    for (int q = 0; q < NA; ++q)
-#pragma unroll
-        for (int l = 0; l < LM; ++l) A[q][l] = 0.0f;
-
-    // ---------------- pass 1: descriptor sums ----------------
-    RowStream rs;
-    rs.start(a.nbr, a.pos4, n, i, cR);
-    for (int p = 0; p < cR; ++p) {
-        uint32_t e;
-        float4 pj;
-        rs.next(p, e, pj);
-        const PairGeom g = geom_of(e, pj, pi, a.box);
-        const int tj = (NT == 1) ? 0 : g.tj;
-        const int tp = ti * NT + tj;
-        if (g.d2 < a.cut.rcR2[tp]) {
-            const float ir = __builtin_amdgcn_rsqf(g.d2);
-            const float r = g.d2 * ir;
-            const float t = r * a.cut.inv_rcR[tp];
-            const float hfc = 0.25f * (1.0f + cos_pi(t));
-            const float s1 = t - 1.0f;
-            float T[KB];
-            cheb_T(2.0f * s1 * s1 - 1.0f, T);
-#pragma unroll
-            for (int t2 = 0; t2 < NT; ++t2) {
-                const float w = (NT == 1 || tj == t2) ? hfc : 0.0f;
-                S[t2][0] += w;
-#pragma unroll
-                for (int k = 1; k < KB; ++k) S[t2][k] += w * T[k];
-            }
-            if (p < cA && g.d2 < a.cut.rcA2[tp]) {
-                const float tA = r * a.cut.inv_rcA[tp];
-                const float hA = 0.25f * (1.0f + cos_pi(tA));
-                const float sA = tA - 1.0f;
-                float TA[KB];
-                cheb_T(2.0f * sA * sA - 1.0f, TA);
-                const table_ptr<NT> cAp = TB + tp * TAB_PER_PAIR + NR * KB;
-                float gv[NA];
-#pragma unroll
-                for (int q = 0; q < NA; ++q) {
-                    float G = cAp[q * KB];
-#pragma unroll
-                    for (int k = 1; k < KB; ++k) G += cAp[q * KB + k] * TA[k];
-                    gv[q] = hA * G;
-                }
-                accumulate_harmonics(g.dx * ir, g.dy * ir, g.dz * ir, gv, A);
-            }
-        }
-    }
-
-    // ---------------- descriptor, network (Eq. 2), back-propagation ----------------
-    // evaluated with a wave-uniform centre type so the weights are scalar loads;
-    // several types in one wave are handled one after the other
-    if constexpr (NT == 1) {
-        network<NT, HP>(0, (const_fp)a.tab, (const_fp)a.ann, S, A, a.U + i, a.bvec + (size_t)i * NT * 3);
-    } else {
-        // the lane test goes through the ballot bit, not ti == tu, so the
-        // compiler cannot substitute the per-lane ti into the table address
-        uint64_t todo = __ballot(1);
-        const int lane = __lane_id();
-        while (todo) {
-            const int lead = __ffsll((unsigned long long)todo) - 1;
-            const int tu = __builtin_amdgcn_readfirstlane(__shfl(ti, lead));
-            const uint64_t mine = __ballot(ti == tu);
-            if ((mine >> lane) & 1ull)
-                network<NT, HP>(tu, (const_fp)a.tab, (const_fp)a.ann, S, A, a.U + i,
-                                a.bvec + (size_t)i * NT * 3);
-            todo &= ~mine;
-        }
-    }
-    asm volatile("" ::: "memory");
-    // ---------------- pass 2: angular pair partials ----------------
-    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    rs.start(a.nbr, a.pos4, n, i, cA);
-    for (int p = 0; p < cA; ++p) {
-        uint32_t e;
-        float4 pj;
-        rs.next(p, e, pj);
-        const PairGeom g = geom_of(e, pj, pi, a.box);
-        const int tj = (NT == 1) ? 0 : g.tj;
-        const int tp = ti * NT + tj;
-        float ox = 0.0f, oy = 0.0f, oz = 0.0f;
-        if (g.d2 < a.cut.rcA2[tp]) {
-            const float ir = __builtin_amdgcn_rsqf(g.d2);
-            const float r = g.d2 * ir;
-            const float ux = g.dx * ir, uy = g.dy * ir, uz = g.dz * ir;
-            const float inv = a.cut.inv_rcA[tp];
-            const float tA = r * inv;
-            const float sp = sin_pi(tA), cp = cos_pi(tA);
-            const float hA = 0.25f * (1.0f + cp);
-            const float dhA = -0.25f * PI_F * sp * inv;
-            const float sA = tA - 1.0f;
-            const float xA = 2.0f * sA * sA - 1.0f;
-            const float xp = 4.0f * sA * inv;
-            float TA[KB], UA[KB - 1];
-            cheb_T(xA, TA);
-            cheb_U(xA, UA);
-            const table_ptr<NT> cAp = TB + tp * TAB_PER_PAIR + NR * KB;
-            const table_ptr<NT> cAd = cAp + NA * KB;
-            float gv[NA], gp[NA];
-#pragma unroll
-            for (int q = 0; q < NA; ++q) {
-                float G = cAp[q * KB], Gp = 0.0f;
-#pragma unroll
-                for (int k = 1; k < KB; ++k) {
-                    G += cAp[q * KB + k] * TA[k];
-                    Gp += cAd[q * (KB - 1) + k - 1] * UA[k - 1];
-                }
-                gv[q] = hA * G;
-                gp[q] = dhA * G + hA * xp * Gp;
-            }
-            float s = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
-            force_harmonics(ux, uy, uz, A, gv, gp, s, vx, vy, vz);
-            const float uv = ux * vx + uy * vy + uz * vz;
-            ox = s * ux + (vx - uv * ux) * ir;
-            oy = s * uy + (vy - uv * uy) * ir;
-            oz = s * uz + (vz - uv * uz) * ir;
-        }
-        // deliver dU_i/dr_ij to the slot where j lists i; a slot whose mirror
-        // does not exist (rounding at the list edge) is zeroed by its owner
-        const int r = a.rev[(size_t)p * n + i];
-        if (r >= 0)
-            a.angbuf[r] = make_float4(ox, oy, oz, 0.0f);
-        else
-            a.angbuf[(size_t)p * n + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        fx += ox;
-        fy += oy;
-        fz += oz;
-    }
-    a.fown[i] = make_float4(fx, fy, fz, 0.0f);
+    main_bead<NT, HP>(a, a.cut, TB, i);
 }
 
 template <int NT, bool VIR, bool MD>
@@ -383,97 +74,8 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
     if (i < n) {
         const float4 pi = a.pos4[i];
         const int ti = (NT == 1) ? 0 : (int)pi.w;
-        const int cR = a.cnt[i];
-        const int cA = a.cnt[n + i];
-        float bi[NT][KB];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const float4 *src = a.bvec + ((size_t)i * NT + t) * 3;
-            float4 v0 = src[0], v1 = src[1], v2 = src[2];
-            bi[t][0] = v0.x; bi[t][1] = v0.y; bi[t][2] = v0.z; bi[t][3] = v0.w;
-            bi[t][4] = v1.x; bi[t][5] = v1.y; bi[t][6] = v1.z; bi[t][7] = v1.w;
-            bi[t][8] = v2.x;
-        }
-        float4 fo = a.fown[i];
-        float Fx = fo.x, Fy = fo.y, Fz = fo.z;
-        float W[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) W[c] = 0.0f;
-        RowStream rs;
-        rs.start(a.nbr, a.pos4, n, i, cR);
-        for (int p = 0; p < cR; ++p) {
-            uint32_t e;
-            float4 pj;
-            rs.next(p, e, pj);
-            const PairGeom g = geom_of(e, pj, pi, a.box);
-            const int tj = (NT == 1) ? 0 : g.tj;
-            const int tp = ti * NT + tj;
-            if (g.d2 < a.cut.rcR2[tp]) {
-                ++nR_in;
-                nA_in += (p < cA && g.d2 < a.cut.rcA2[tp]) ? 1 : 0;
-                const float ir = __builtin_amdgcn_rsqf(g.d2);
-                const float r = g.d2 * ir;
-                const float inv = a.cut.inv_rcR[tp];
-                const float t = r * inv;
-                const float sp = sin_pi(t), cp = cos_pi(t);
-                float hfc = 0.25f * (1.0f + cp);
-                float dh = -0.25f * PI_F * sp * inv;
-                float s1 = t - 1.0f;
-                float x = 2.0f * s1 * s1 - 1.0f;
-                float xp = 4.0f * s1 * inv;
-                float T[KB], Uc[KB - 1];
-                cheb_T(x, T);
-                cheb_U(x, Uc);
-                // own coefficients for the neighbour's type
-                float b[KB];
-#pragma unroll
-                for (int k = 0; k < KB; ++k) {
-                    float v = bi[0][k];
-#pragma unroll
-                    for (int t2 = 1; t2 < NT; ++t2) v = (tj == t2) ? bi[t2][k] : v;
-                    b[k] = v;
-                }
-                // neighbour's coefficients for this bead's type
-                const float4 *src = a.bvec + ((size_t)g.j * NT + ti) * 3;
-                const float4 v0 = src[0], v1 = src[1], v2 = src[2];
-                float c[KB] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x};
-                float Si = b[0], Sj = c[0], Di = 0.0f, Dj = 0.0f;
-#pragma unroll
-                for (int k = 1; k < KB; ++k) {
-                    float dT = (float)k * Uc[k - 1];
-                    Si += b[k] * T[k];
-                    Sj += c[k] * T[k];
-                    Di += b[k] * dT;
-                    Dj += c[k] * dT;
-                }
-                float si = dh * Si + hfc * xp * Di;  // dU_i/dr along r_ij
-                float sj = dh * Sj + hfc * xp * Dj;  // dU_j/dr along r_ji
-                float ux = g.dx * ir, uy = g.dy * ir, uz = g.dz * ir;
-                float st = si + sj;
-                Fx += st * ux;
-                Fy += st * uy;
-                Fz += st * uz;
-                if (VIR) {  // dU_j/dr_ji (radial part) = -sj u
-                    float fx = -sj * ux, fy = -sj * uy, fz = -sj * uz;
-                    W[0] += g.dx * fx; W[1] += g.dx * fy; W[2] += g.dx * fz;
-                    W[3] += g.dy * fx; W[4] += g.dy * fy; W[5] += g.dy * fz;
-                    W[6] += g.dz * fx; W[7] += g.dz * fy; W[8] += g.dz * fz;
-                }
-            }
-            if (p < cA) {
-                {
-                    const float4 fj = a.angbuf[(size_t)p * n + i];  // dU_j/dr_ji, angular part
-                    Fx -= fj.x;
-                    Fy -= fj.y;
-                    Fz -= fj.z;
-                    if (VIR) {
-                        W[0] += g.dx * fj.x; W[1] += g.dx * fj.y; W[2] += g.dx * fj.z;
-                        W[3] += g.dy * fj.x; W[4] += g.dy * fj.y; W[5] += g.dy * fj.z;
-                        W[6] += g.dz * fj.x; W[7] += g.dz * fj.y; W[8] += g.dz * fj.z;
-                    }
-                }
-            }
-        }
+        float Fx, Fy, Fz, W[9];
+        gather_bead<NT, VIR>(a, a.cut, i, pi, ti, Fx, Fy, Fz, W, nR_in, nA_in);
         a.F[i] = Fx;
         a.F[n + i] = Fy;
         a.F[2 * n + i] = Fz;

@@ -321,4 +321,39 @@ struct KickDriftArgs {
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s);
 
+
+// ---- batched evaluation (fitness loop) ----
+struct SysDesc {           // one structure of the batch
+    int n;
+    int label_off;         // first row of the structure in the concatenated force labels
+    float box[3];
+    const float *x, *y, *z;
+    const uint8_t *type;
+    const uint32_t *nbr;
+    const int32_t *rev, *cnt;
+};
+struct ModelDesc {         // one candidate parameter set
+    const float *tab, *ann;
+};
+struct BatchArgs {
+    int n_items;
+    const int4 *items;     // schedule order: (model, system, index in the caller's list, 0)
+    const SysDesc *sys;
+    const ModelDesc *mod;
+    Cut cut;               // shared by every candidate (the lists are shared)
+    int *counter;          // work-queue head, zeroed before the launch
+    char *scratch;         // per-workgroup intermediates, scratch_stride bytes each
+    size_t scratch_stride;
+    int nmax, capAmax;     // largest structure and angular capacity in the batch
+    const double *F_ref;   // [sum_s n_s][3] or null
+    double *records;       // [n_items][12] by list index
+    float *F_out;          // [sum over items of n][3] or null
+    const int64_t *F_off;  // first row of each item in F_out, by list index
+};
+hipError_t launch_efv_batch(int T, int HP, int BS, const BatchArgs &b, int grid, hipStream_t s);
+int batch_occupancy(int T, int HP, int BS);
+hipError_t launch_batch_rmse(int n_models, int n_items, const int4 *list, const SysDesc *sys,
+                             const double *records, const double *E_ref, const double *W_ref, double *rmse,
+                             double *item_out, hipStream_t s);
+
 }  // namespace nep

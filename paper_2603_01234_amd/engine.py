@@ -247,3 +247,80 @@ def decode_row(entries: np.ndarray):
     ny = (code // 5) % 5 - 2
     nz = code // 25 - 2
     return j, nx, ny, nz
+
+
+class FitnessBatch:
+    """Candidates of one model family scored on many structures in one
+    persistent launch (nep_compute_efv_batch).  The structures stay resident
+    with their lists, built once and shared by every candidate."""
+
+    def __init__(self, models: Sequence[Model], replicas: Sequence[Replica]):
+        if not models:
+            raise ValueError("need at least one model")
+        self.models = list(models)
+        self.replicas = list(replicas)
+        for r in self.replicas:
+            if not r.lists_valid:
+                r.build()
+        self.device = self.replicas[0].device if self.replicas else torch.device("cuda")
+        self.labels = None
+        self._ws = None
+        self._ws_key = None
+
+    def _c(self):
+        return ([m.handle for m in self.models], [r.c_system() for r in self.replicas],
+                [r.c_neighbors() for r in self.replicas])
+
+    def all_pairs(self):
+        """Every (candidate, structure) pair, candidate-major."""
+        return [(m, s) for m in range(len(self.models)) for s in range(len(self.replicas))]
+
+    def set_labels(self, E, F, W):
+        """E: [S] eV; F: [sum_s n_s, 3] eV/nm in structure order; W: [S, 9] eV."""
+        dev = self.device
+        self.labels = (torch.as_tensor(np.asarray(E, np.float64), device=dev).contiguous(),
+                       torch.as_tensor(np.asarray(F, np.float64).reshape(-1, 3), device=dev).contiguous(),
+                       torch.as_tensor(np.asarray(W, np.float64).reshape(-1, 9), device=dev).contiguous())
+
+    def _workspace(self, n_items: int):
+        key = n_items
+        if self._ws is None or self._ws_key != key:
+            models, systems, lists = self._c()
+            nbytes = B.nep_batch_workspace_bytes(models, systems, lists, n_items, None)
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self._ws_key = key
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return base + off, self._ws.numel() - off
+
+    def autotune(self, work=None):
+        work = self.all_pairs() if work is None else work
+        ws, nbytes = self._workspace(len(work))
+        models, systems, lists = self._c()
+        return B.nep_batch_autotune(models, systems, lists, work, ws, nbytes, _stream())
+
+    def evaluate(self, work=None, cfg: Optional[B.BatchConfig] = None, rmse: bool = True,
+                 items: bool = False, forces: bool = False):
+        """Returns dict with 'rmse' [n_models, 3] (RMSE_E eV/bead, RMSE_F eV/nm,
+        RMSE_W eV/bead), 'items' [n_items, 10] (E, W) and 'forces' [rows, 3]."""
+        work = self.all_pairs() if work is None else work
+        n_items = len(work)
+        ws, nbytes = self._workspace(n_items)
+        models, systems, lists = self._c()
+        dev = self.device
+        out = {}
+        lab = None
+        if rmse:
+            if self.labels is None:
+                raise ValueError("labels are not set")
+            lab = B.Labels(self.labels[0].data_ptr(), self.labels[1].data_ptr(), self.labels[2].data_ptr())
+            out["rmse"] = torch.zeros((len(self.models), 3), dtype=torch.float64, device=dev)
+        if items:
+            out["items"] = torch.zeros((max(n_items, 1), 10), dtype=torch.float64, device=dev)
+        if forces:
+            rows = sum(self.replicas[s].n for _, s in work)
+            out["forces"] = torch.zeros((max(rows, 1), 3), dtype=torch.float32, device=dev)
+        B.check(B.nep_compute_efv_batch(models, systems, lists, work, lab, _ptr(out.get("rmse")),
+                                        _ptr(out.get("items")), _ptr(out.get("forces")), cfg, ws, nbytes,
+                                        _stream()))
+        return out

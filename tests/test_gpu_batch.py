@@ -1,0 +1,146 @@
+"""Batched fitness evaluation (nep_compute_efv_batch) against the FP64 oracle
+(needs an MI355X).
+
+Two model families as in the fitness workload (water-like, one type; C60-like,
+two types with 2.0 nm cutoffs), a few candidates each (candidate 0 is the base
+set, the others seeded perturbations), a few dozen small periodic structures.
+Labels are the oracle's energies, forces and virials of the base set.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import TOL_E_PER_BEAD, TOL_F_RMS, TOL_U, TOL_W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N_CAND = 3
+
+
+@pytest.fixture(scope="module")
+def families():
+    from paper_2603_01234_amd import engine as E
+    fw = W.config3(n_candidates=N_CAND, n_structures=24, size_range=(32, 200))
+    out = []
+    for f in range(2):
+        spec = fw.specs[f]
+        idx = [k for k in range(len(fw.systems)) if fw.family[k] == f]
+        systems = [fw.systems[k] for k in idx]
+        cands = [c.astype(np.float32) for c in fw.candidates[f]]
+        models = [E.Model.from_spec(spec, c) for c in cands]
+        reps = [E.Replica(models[0], s.pos_f32(), s.types, s.box, s.pbc, skin=0.0) for s in systems]
+        for r in reps:
+            r.build()
+        fb = E.FitnessBatch(models, reps)
+        # oracle E/F/W of every candidate on every structure (FP64, float32 inputs)
+        ref = [[oracle.efv(spec, c.astype(np.float64), r.positions().astype(np.float64), s.types,
+                           np.asarray(r.box, np.float32).astype(np.float64), s.pbc)
+                for r, s in zip(reps, systems)] for c in cands]
+        base = ref[0]
+        fb.set_labels([x.E for x in base], np.concatenate([x.F for x in base]), [x.Wtot.reshape(9) for x in base])
+        out.append((spec, fb, systems, ref))
+    return out
+
+
+def _oracle_rmse(ref, cand):
+    base = ref[0]
+    eE, eF, eW, nF = [], 0.0, [], 0
+    for x, b in zip(ref[cand], base):
+        N = x.F.shape[0]
+        eE.append(((x.E - b.E) / N) ** 2)
+        eF += float(((x.F - b.F) ** 2).sum())
+        nF += 3 * N
+        w, wb = x.Wtot.reshape(9), b.Wtot.reshape(9)
+        eW += [((w[c] - wb[c]) / N) ** 2 for c in (0, 4, 8, 1, 5, 2)]
+    return np.sqrt(np.mean(eE)), np.sqrt(eF / nF), np.sqrt(np.mean(eW))
+
+
+@pytest.mark.parametrize("fam", [0, 1], ids=["water", "c60"])
+def test_batch_items_match_oracle(families, fam):
+    spec, fb, systems, ref = families[fam]
+    work = fb.all_pairs()
+    out = fb.evaluate(work, rmse=False, items=True, forces=True)
+    items = out["items"].cpu().numpy()
+    F = out["forces"].cpu().numpy()
+    row = 0
+    worst = {"E": 0.0, "F": 0.0, "W": 0.0}
+    for it, (m, s) in enumerate(work):
+        x = ref[m][s]
+        N = x.F.shape[0]
+        Fg = F[row:row + N]
+        row += N
+        eE = abs(items[it, 0] - x.E) / N
+        eF = np.sqrt(((Fg - x.F) ** 2).sum() / max((x.F ** 2).sum(), 1e-30))
+        # the total virial is a sum with cancellations: its error is bounded
+        # relative to the size of its summands, the per-bead virials
+        scale = float(np.linalg.norm(x.W.reshape(N, 9), axis=1).sum())
+        eW = float(np.linalg.norm(items[it, 1:] - x.Wtot.reshape(9))) / max(scale, 1e-30)
+        worst = {"E": max(worst["E"], eE), "F": max(worst["F"], eF), "W": max(worst["W"], eW)}
+    print(f"family {fam}: worst E/bead {worst['E']:.2e}, F rel {worst['F']:.2e}, "
+          f"W_tot err / sum |W_i| {worst['W']:.2e}")
+    assert worst["E"] <= TOL_E_PER_BEAD
+    assert worst["F"] <= TOL_F_RMS
+    assert worst["W"] <= TOL_W
+
+
+@pytest.mark.parametrize("fam", [0, 1], ids=["water", "c60"])
+def test_batch_rmse_matches_oracle(families, fam):
+    spec, fb, systems, ref = families[fam]
+    rm = fb.evaluate()["rmse"].cpu().numpy()
+    f_scale = np.sqrt(np.mean(np.concatenate([x.F for x in ref[0]]) ** 2))
+    # candidate 0 is the labelled base set: only FP32 noise remains
+    assert rm[0, 0] <= TOL_U and rm[0, 1] <= TOL_F_RMS * f_scale and rm[0, 2] <= 1e-5
+    for c in range(1, N_CAND):
+        o = _oracle_rmse(ref, c)
+        print(f"family {fam} cand {c}: gpu {rm[c]}, oracle {o}")
+        for k in range(3):
+            assert abs(rm[c, k] - o[k]) <= 1e-4 * o[k] + 1e-7
+
+
+def test_batch_is_independent_of_schedule_and_tiles(families):
+    from paper_2603_01234_amd import binding as B
+    spec, fb, systems, ref = families[1]
+    work = fb.all_pairs()
+    outs = []
+    for block, order in ((256, 0), (64, 1), (128, 0)):
+        cfg = B.BatchConfig(block, order, 0)
+        o = fb.evaluate(work, cfg=cfg, items=True, forces=True)
+        outs.append([o["rmse"].clone(), o["items"].clone(), o["forces"].clone()])
+    for o in outs[1:]:
+        # per-bead values are schedule-free; sums differ only by the block shape
+        assert torch.equal(o[2], outs[0][2])
+        assert torch.allclose(o[1], outs[0][1], rtol=1e-12, atol=1e-12)
+        assert torch.allclose(o[0], outs[0][0], rtol=1e-9, atol=1e-12)
+    # the same configuration twice: bitwise
+    again = fb.evaluate(work, cfg=B.BatchConfig(256, 0, 0), items=True, forces=True)
+    assert torch.equal(again["items"], outs[0][1]) and torch.equal(again["rmse"], outs[0][0])
+
+
+def test_batch_equals_single_structure_path(families):
+    spec, fb, systems, ref = families[0]
+    work = [(1, s) for s in range(len(fb.replicas))]
+    out = fb.evaluate(work, rmse=False, items=True, forces=True)
+    items = out["items"].cpu().numpy()
+    F = out["forces"]
+    row = 0
+    for it, (m, s) in enumerate(work):
+        r = fb.replicas[s]
+        from paper_2603_01234_amd import engine as E
+        r2 = E.Replica(fb.models[m], r.positions(), systems[s].types, r.box, systems[s].pbc, skin=0.0)
+        r2.efv()
+        N = r.n
+        assert torch.equal(F[row:row + N], r2.F[:, :N].T.contiguous())
+        assert abs(items[it, 0] - float(r2.E_tot.cpu()[0])) <= 1e-9 * max(1.0, abs(items[it, 0]))
+        row += N
+
+
+def test_batch_autotune_and_empty_list(families):
+    spec, fb, systems, ref = families[0]
+    best, ms = fb.autotune()
+    print("autotune:", best.block, best.order, ms)
+    assert best.block in (64, 128, 256) and best.order in (0, 1)
+    assert all(t > 0 for t in ms)
+    out = fb.evaluate([], items=False)
+    assert torch.count_nonzero(out["rmse"]) == 0
