@@ -120,12 +120,109 @@ def cpu_baseline(spec, params, system, pos, min_seconds=10.0):
                       f"({el:.1f} s wall); the MD update itself is negligible"}
 
 
+def batched_leg(reps: int = 3, plain_candidates: int = 2):
+    """Fitness workload: 64 candidates x 2000 structures per family pair, one
+    persistent launch per family (autotuned) against the plain loop of one
+    nep_compute_efv call per (candidate, structure).  Labels are the base set's
+    energies, forces and virials from the single-structure GPU path (they only
+    set the residual values, not the work)."""
+    import torch
+    import workloads as W
+    from paper_2603_01234_amd import binding as B
+    from paper_2603_01234_amd import engine
+
+    t_setup = time.perf_counter()
+    fw = W.config3()
+    fams = []
+    for f in range(2):
+        spec = fw.specs[f]
+        idx = [k for k in range(len(fw.systems)) if fw.family[k] == f]
+        models = [engine.Model.from_spec(spec, c.astype(np.float32)) for c in fw.candidates[f]]
+        reps_f = []
+        for k in idx:
+            s = fw.systems[k]
+            r = engine.Replica(models[0], s.pos_f32(), s.types, s.box, s.pbc, skin=0.0)
+            r.build()
+            reps_f.append(r)
+        E_lab, F_lab, W_lab = [], [], []
+        for r in reps_f:
+            r.efv(per_bead_virial=False)
+            E_lab.append(float(r.E_tot.cpu()[0]))
+            F_lab.append(r.forces().astype(np.float64))
+            W_lab.append(r.W_tot.cpu().numpy())
+        fb = engine.FitnessBatch(models, reps_f)
+        fb.set_labels(E_lab, np.concatenate(F_lab), W_lab)
+        fams.append((spec, fb))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+
+    out = {"workload": "config3 fitness: 64 candidates (base + sigma 0.05 perturbations) x 2000 periodic "
+                       "structures, N log-uniform 32-1024; 1000 water-like (1 type, rc 0.8/0.5 nm, density "
+                       "x U(0.8,1.2)), 1000 C60-like monolayers (2 types, rc 2.0 nm); H = 30",
+           "setup_s": round(t_setup, 1)}
+    total_beads = 0
+    t_batch = 0.0
+    fam_out = []
+    for f, (spec, fb) in enumerate(fams):
+        work = fb.all_pairs()
+        beads = sum(fb.replicas[s].n for _, s in work)
+        # autotune on the first 8 candidates (all structures)
+        sample = [(m, s) for (m, s) in work if m < 8]
+        best, ms = fb.autotune(sample)
+        fb.evaluate(work, cfg=best)                      # warm-up at full size
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fb.evaluate(work, cfg=best)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        t = float(np.median(times))
+        rm = res["rmse"].cpu().numpy()
+        # plain form: one nep_compute_efv (pack + fused + gather + reduce) per item
+        pw = [(m, s) for (m, s) in work if m < plain_candidates]
+        ws_plain = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pbeads = 0
+        for m, s in pw:
+            r = fb.replicas[s]
+            sysc, nb = r.c_system(), r.c_neighbors()
+            B.check(B.nep_compute_efv(fb.models[m].handle, sysc, nb, r.U.data_ptr(), r.F.data_ptr(), None,
+                                      r.E_tot.data_ptr(), r.W_tot.data_ptr(), r.ws.data_ptr(), r.ws_bytes,
+                                      torch.cuda.current_stream().cuda_stream))
+            pbeads += r.n
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        fam_out.append({"family": ["water-like", "C60-like"][f], "items": len(work), "bead_evals": beads,
+                        "batched_ms": round(t * 1e3, 2), "batched_bead_evals_per_s": round(beads / t, 1),
+                        "plain_bead_evals_per_s": round(pbeads / t_plain, 1),
+                        "plain_sample_items": len(pw),
+                        "autotune": {"block": best.block, "order": best.order,
+                                     "ms_per_config_on_8_candidates": [round(x, 3) for x in ms]},
+                        "rmse_candidate0": [float(x) for x in rm[0]],
+                        "rmse_candidate1": [float(x) for x in rm[1]]})
+        total_beads += beads
+        t_batch += t
+    # whole-workload rates: both families, total bead-evaluations / total time
+    t_plain_total = sum(x["bead_evals"] / x["plain_bead_evals_per_s"] for x in fam_out)
+    out.update({"bead_evals_per_s": round(total_beads / t_batch, 1),
+                "plain_bead_evals_per_s": round(total_beads / t_plain_total, 1),
+                "speedup_vs_plain": round(t_plain_total / t_batch, 2),
+                "families": fam_out})
+    for _, fb in fams:
+        for m in fb.models:
+            m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched fitness leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -236,6 +333,9 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, params, system, rep.positions().astype(np.float64))
     model.close()
+    if not args.no_batched:
+        print("bench: batched fitness leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg()
     print(json.dumps(out), flush=True)
 
 
