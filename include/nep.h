@@ -221,6 +221,41 @@ int nep_md_step(nep_model model, nep_system *sys, float *v, nep_md_params *param
 int nep_check_status(const nep_neighbors *nbrs, int32_t host_status_out[4], void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* many independent replicas, one MD step each (served form)                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    nep_system *sys;         /* positions (device [n] each), types, box, pbc */
+    float *v;                /* device [3][n] nm/fs */
+    float *F;                /* device [3][n]: forces at the current positions (in/out) */
+    float *U;                /* device [n] or NULL */
+    nep_neighbors *nbrs;     /* the replica's lists, from nep_build_neighbors */
+    void *ws;                /* the replica's own workspace (nep_workspace_bytes) */
+    size_t ws_bytes;
+    int64_t step;            /* in/out: the replica's step counter (advanced when the step completed) */
+    int rebuilt;             /* out: 1 when this step rebuilt the lists */
+    int status;              /* out: NEP_OK, or the error that stopped this replica's step */
+} nep_replica;
+
+/* Workspace of nep_md_step_batch for up to max_active replicas per call. */
+size_t nep_md_batch_workspace_bytes(int max_active);
+
+/* One velocity-Verlet step (as nep_md_step, no strain) for each of n_active
+ * replicas that share one model, batched: one drift launch over the tiles of
+ * every replica, the builds of the replicas whose beads passed 0.99 skin/2 or
+ * whose schedule asks for one ((step + 1) % rebuild_every == 0), one fused-
+ * kernel launch, one gather launch and one launch of per-replica energy sums.
+ * A replica's results depend only on its own state: alone or in any mix they
+ * are the same.  E_pot / E_kin: device double [n_active] or NULL.  A replica
+ * whose rebuild fails keeps x, v and F of its last step (status set, step not
+ * advanced); the others are unaffected.  The call reads the rebuild gates back
+ * to the host once and synchronises the stream before it returns; it returns
+ * NEP_OK unless an argument is invalid or HIP fails (per-replica errors are in
+ * the status fields). */
+int nep_md_step_batch(nep_model model, nep_replica *replicas, int n_active, float dt_fs, const float mass[4],
+                      int rebuild_every, double *E_pot, double *E_kin, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* batched evaluation for the fitness loop (Sec. II.A: candidates of the      */
 /* evolution strategy scored by the RMSE of energies and virials per bead and */
 /* of forces per component)                                                   */

@@ -41,7 +41,7 @@ FLAG_NONFINITE, FLAG_OUTSIDE_BOX, FLAG_OVERLAP, FLAG_IMAGE_RANGE = 8, 16, 32, 64
 EXPORTS = ["nep_param_count", "nep_model_create", "nep_model_destroy", "nep_workspace_bytes",
            "nep_build_neighbors", "nep_compute_efv", "nep_md_step", "nep_check_status",
            "nep_last_error", "nep_timing_begin", "nep_timing_end", "nep_batch_workspace_bytes",
-           "nep_compute_efv_batch", "nep_batch_autotune"]
+           "nep_compute_efv_batch", "nep_batch_autotune", "nep_md_batch_workspace_bytes", "nep_md_step_batch"]
 
 
 class NepError(RuntimeError):
@@ -64,6 +64,12 @@ class System(ctypes.Structure):
 class Neighbors(ctypes.Structure):
     _fields_ = [("cap", c_int), ("cap_A", c_int), ("nbr", c_void_p), ("rev", c_void_p),
                 ("cnt", c_void_p), ("ref", c_void_p), ("skin", c_float), ("status", c_void_p)]
+
+
+class Replica(ctypes.Structure):
+    _fields_ = [("sys", POINTER(System)), ("v", c_void_p), ("F", c_void_p), ("U", c_void_p),
+                ("nbrs", POINTER(Neighbors)), ("ws", c_void_p), ("ws_bytes", c_size_t), ("step", c_int64),
+                ("rebuilt", c_int), ("status", c_int)]
 
 
 class BatchConfig(ctypes.Structure):
@@ -124,6 +130,11 @@ def lib():
         L.nep_batch_autotune.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p,
                                          c_size_t, c_void_p, POINTER(BatchConfig), POINTER(c_float)]
         L.nep_batch_autotune.restype = c_int
+        L.nep_md_batch_workspace_bytes.argtypes = [c_int]
+        L.nep_md_batch_workspace_bytes.restype = c_size_t
+        L.nep_md_step_batch.argtypes = [c_void_p, POINTER(Replica), c_int, c_float, POINTER(c_float), c_int,
+                                        c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+        L.nep_md_step_batch.restype = c_int
         L.nep_last_error.argtypes = []
         L.nep_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -237,3 +248,15 @@ def nep_batch_autotune(models, systems, lists, work, ws_ptr, ws_bytes, stream):
     check(lib().nep_batch_autotune(m, len(models), sy, li, len(systems), w.ctypes.data, w.shape[0], ws_ptr,
                                    ws_bytes, stream, ctypes.byref(best), ms))
     return best, list(ms)
+
+
+def nep_md_batch_workspace_bytes(max_active: int) -> int:
+    return int(lib().nep_md_batch_workspace_bytes(int(max_active)))
+
+
+def nep_md_step_batch(model, reps, dt: float, masses, rebuild_every: int, E_pot, E_kin, ws_ptr, ws_bytes,
+                      stream) -> int:
+    """reps: ctypes array of Replica (its sys / nbrs pointers kept alive by the caller)."""
+    m = (c_float * 4)(*[float(masses[t]) if t < len(masses) else 1.0 for t in range(4)])
+    return lib().nep_md_step_batch(model, reps, len(reps), float(dt), m, int(rebuild_every), E_pot, E_kin,
+                                   ws_ptr, ws_bytes, stream)

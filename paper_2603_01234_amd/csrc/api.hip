@@ -500,6 +500,52 @@ int batch_run(const nep_model *models, int n_models, const nep_system *systems, 
 constexpr int N_TUNE = 6;
 const int TUNE_BLOCK[N_TUNE] = {64, 128, 256, 64, 128, 256};
 const int TUNE_ORDER[N_TUNE] = {0, 0, 0, 1, 1, 1};
+
+// ---- served form: host staging of the replica tables ----
+struct MdBatchCtx {
+    char *host = nullptr;  // pinned staging: descriptors, tile starts, gates; then gates and statuses back
+    size_t bytes = 0;
+    int device = -1;
+    ~MdBatchCtx() {
+        if (host) (void)hipHostFree(host);
+    }
+};
+thread_local MdBatchCtx g_mdb;
+
+int mdb_host(size_t bytes, char *&out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (!g_mdb.host || g_mdb.bytes < bytes || g_mdb.device != dev) {
+        if (g_mdb.host) (void)hipHostFree(g_mdb.host);
+        g_mdb.host = nullptr;
+        g_mdb.bytes = 0;
+        HIPCHK(hipHostMalloc((void **)&g_mdb.host, bytes));
+        g_mdb.bytes = bytes;
+        g_mdb.device = dev;
+    }
+    out = g_mdb.host;
+    return NEP_OK;
+}
+
+struct MdbLayout {
+    size_t desc, tiles, gate, status, total;
+};
+MdbLayout mdb_layout(int n) {
+    MdbLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off += (b + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t nn = (size_t)std::max(n, 1);
+    L.desc = take(sizeof(RepDesc) * nn);
+    L.tiles = take(sizeof(int) * (nn + 1));
+    L.gate = take(sizeof(int) * nn);
+    L.status = take(sizeof(int32_t) * 4 * nn);
+    L.total = off;
+    return L;
+}
 }  // namespace
 
 extern "C" {
@@ -799,6 +845,126 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     mp->step = step0 + c[2];
     for (int d = 0; d < 3; ++d) s->box[d] = box_at(mp->step, d);
     return read_status(nb, nullptr, st);
+}
+
+size_t nep_md_batch_workspace_bytes(int max_active) {
+    if (max_active < 0) return 0;
+    return mdb_layout(max_active).total;
+}
+
+int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt_fs, const float mass[4],
+                      int rebuild_every, double *E_pot, double *E_kin, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_model(model))) return rc;
+    const Model &M = model->m;
+    if (n_active < 0 || (n_active > 0 && !reps)) return fail(NEP_ERR_ARG, "replicas are null");
+    if (!(dt_fs > 0.0f) || rebuild_every < 1 || !mass) return fail(NEP_ERR_ARG, "need dt > 0, rebuild_every >= 1, masses");
+    for (int t = 0; t < M.T; ++t)
+        if (!(mass[t] > 0.0f)) return fail(NEP_ERR_ARG, "masses must be positive");
+    const MdbLayout BL = mdb_layout(n_active);
+    if (!ws || ((uintptr_t)ws) % 256 || ws_bytes < BL.total)
+        return fail(NEP_ERR_ARG, "batch workspace must be 256-byte aligned and hold nep_md_batch_workspace_bytes");
+    if (n_active == 0) return NEP_OK;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<WsLayout> L((size_t)n_active);
+    for (int r = 0; r < n_active; ++r) {
+        nep_replica &R = reps[r];
+        if (!R.sys || !R.nbrs) return fail(NEP_ERR_ARG, "replica " + std::to_string(r) + ": null system or lists");
+        if ((rc = check_system(M, R.sys)) || (rc = check_nbrs(R.sys, R.nbrs)) ||
+            (rc = check_ws(M, R.sys, R.nbrs, R.ws, R.ws_bytes, L[r])))
+            return fail(rc, "replica " + std::to_string(r) + ": " + g_err);
+        if (R.sys->n > 0 && (!R.v || !R.F)) return fail(NEP_ERR_ARG, "replica " + std::to_string(r) + ": null v or F");
+    }
+    char *h = nullptr;
+    if ((rc = mdb_host(BL.total, h))) return rc;
+    RepDesc *hd = reinterpret_cast<RepDesc *>(h + BL.desc);
+    int *ht = reinterpret_cast<int *>(h + BL.tiles);
+    int *hg = reinterpret_cast<int *>(h + BL.gate);
+    int32_t *hs = reinterpret_cast<int32_t *>(h + BL.status);
+    int tiles = 0;
+    for (int r = 0; r < n_active; ++r) {
+        nep_replica &R = reps[r];
+        const nep_system *S = R.sys;
+        RepDesc &d = hd[r];
+        d = RepDesc{};
+        d.n = S->n;
+        // the same threshold as the single-replica step
+        const float gate = 0.99f * (0.5f * R.nbrs->skin);
+        d.gate2 = gate * gate;
+        for (int q = 0; q < 3; ++q) d.box[q] = S->box[q];
+        d.x = S->x;
+        d.y = S->y;
+        d.z = S->z;
+        d.v = R.v;
+        d.F = R.F;
+        d.U = R.U ? R.U : at<float>(R.ws, L[r].U);
+        d.type = S->type;
+        d.nbr = R.nbrs->nbr;
+        d.rev = R.nbrs->rev;
+        d.cnt = R.nbrs->cnt;
+        d.ref = R.nbrs->ref;
+        d.status = R.nbrs->status;
+        d.pos4 = at<float4>(R.ws, L[r].pos4);
+        d.bvec = at<float4>(R.ws, L[r].bvec);
+        d.angbuf = at<float4>(R.ws, L[r].angbuf);
+        d.fown = at<float4>(R.ws, L[r].fown);
+        d.vh = at<float>(R.ws, L[r].vh);
+        d.partial = at<double>(R.ws, L[r].partial);
+        ht[r] = tiles;
+        tiles += (S->n + BLOCK - 1) / BLOCK;
+        hg[r] = ((R.step + 1) % rebuild_every) == 0 ? 1 : 0;
+        R.rebuilt = 0;
+        R.status = NEP_OK;
+    }
+    ht[n_active] = tiles;
+    MdBatchArgs b{};
+    b.n_rep = n_active;
+    b.n_tiles = tiles;
+    b.T = M.T;
+    b.rep = at<RepDesc>(ws, BL.desc);
+    b.tile_start = at<int>(ws, BL.tiles);
+    b.gate = at<int>(ws, BL.gate);
+    b.half_dt_accel = 0.5f * dt_fs * ACCEL;
+    b.dt = dt_fs;
+    for (int t = 0; t < M.T; ++t) {
+        b.inv_mass[t] = 1.0f / mass[t];
+        b.mass[t] = mass[t];
+    }
+    b.cut = make_cut(M);
+    b.tab = M.d_tab;
+    b.ann = M.d_ann;
+    b.E_pot = E_pot;
+    b.E_kin = E_kin;
+    b.status_out = at<int32_t>(ws, BL.status);
+    // descriptors, tile starts and scheduled gates in one copy (they are contiguous)
+    HIPCHK(hipMemcpyAsync(at<char>(ws, BL.desc), h + BL.desc, BL.status - BL.desc, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_kick_drift_batch(b, st));
+    HIPCHK(hipMemcpyAsync(hg, b.gate, sizeof(int) * n_active, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int r = 0; r < n_active; ++r) {
+        if (!hg[r]) continue;
+        nep_replica &R = reps[r];
+        NbArgs a;
+        // a replica left frozen by an earlier failed build is skipped on the device
+        if ((rc = fill_nb(M, R.sys, R.nbrs, R.ws, L[r], 0, 1, a))) return rc;
+        a.from_pos4 = 1;
+        HIPCHK(launch_build(a, st));
+        R.rebuilt = 1;
+    }
+    HIPCHK(launch_efv_md_batch(M.T, M.HP, b, st));
+    // every replica's status word, copied by the reduction, in one transfer
+    HIPCHK(hipMemcpyAsync(hs, b.status_out, 4 * sizeof(int32_t) * n_active, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int r = 0; r < n_active; ++r) {
+        nep_replica &R = reps[r];
+        // a replica frozen by a failed build (now or earlier) did not step
+        if (hs[4 * r] & FREEZE_MASK) {
+            R.status = status_to_code(hs + 4 * r);
+            continue;
+        }
+        R.step += 1;
+    }
+    return NEP_OK;
 }
 
 size_t nep_batch_workspace_bytes(const nep_model *models, int n_models, const nep_system *systems,

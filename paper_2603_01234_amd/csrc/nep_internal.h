@@ -321,6 +321,32 @@ struct KickDriftArgs {
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s);
 
+// First half-kick and drift of bead i (kick k = dt/2 ACCEL / m of its type):
+// half-step velocity to vh, new position (scaled by lam) to pos4, build
+// reference scaled in place.  Returns whether the bead ended up farther than
+// sqrt(gate2) from its build position.
+__device__ __forceinline__ bool kick_drift_bead(int i, int n, int t, float k, float dt, float l0, float l1,
+                                                float l2, const float *x, const float *y, const float *z,
+                                                const float *v, float *vh, const float *F, float4 *pos4,
+                                                float *ref, float gate2) {
+    const float vx = v[i] + k * F[i];
+    const float vy = v[n + i] + k * F[n + i];
+    const float vz = v[2 * n + i] + k * F[2 * n + i];
+    vh[i] = vx;
+    vh[n + i] = vy;
+    vh[2 * n + i] = vz;
+    const float px = (x[i] + dt * vx) * l0;
+    const float py = (y[i] + dt * vy) * l1;
+    const float pz = (z[i] + dt * vz) * l2;
+    const float rx = ref[i] * l0, ry = ref[n + i] * l1, rz = ref[2 * n + i] * l2;
+    ref[i] = rx;
+    ref[n + i] = ry;
+    ref[2 * n + i] = rz;
+    pos4[i] = make_float4(px, py, pz, (float)t);
+    const float dx = px - rx, dy = py - ry, dz = pz - rz;
+    return dx * dx + dy * dy + dz * dz > gate2;
+}
+
 
 // ---- batched evaluation (fitness loop) ----
 struct SysDesc {           // one structure of the batch
@@ -355,5 +381,38 @@ int batch_occupancy(int T, int HP, int BS);
 hipError_t launch_batch_rmse(int n_models, int n_items, const int4 *list, const SysDesc *sys,
                              const double *records, const double *E_ref, const double *W_ref, double *rmse,
                              double *item_out, hipStream_t s);
+
+
+// ---- many replicas, one MD step each (served form) ----
+struct RepDesc {
+    int n;
+    float gate2;           // squared displacement that calls for a rebuild (0.99 skin/2)^2
+    float box[3];
+    float *x, *y, *z, *v, *F, *U;
+    const uint8_t *type;
+    const uint32_t *nbr;
+    const int32_t *rev, *cnt;
+    float *ref;
+    const int32_t *status;
+    // the replica's own workspace
+    float4 *pos4, *bvec, *angbuf, *fown;
+    float *vh;
+    double *partial;       // [tiles][2]: potential and kinetic energy per tile
+};
+struct MdBatchArgs {
+    int n_rep, n_tiles, T;
+    const RepDesc *rep;
+    const int *tile_start; // [n_rep + 1] first tile of every replica
+    int *gate;             // [n_rep] rebuild gate, set by the drift
+    float half_dt_accel, dt;
+    float inv_mass[MAXT], mass[MAXT];
+    Cut cut;
+    const float *tab, *ann;
+    double *E_pot, *E_kin; // [n_rep] or null
+    int32_t *status_out;   // [n_rep][4] copies of the status words after the step
+};
+hipError_t launch_kick_drift_batch(const MdBatchArgs &b, hipStream_t s);
+// fused kernel, gather (second half-kick) and per-replica energy sums
+hipError_t launch_efv_md_batch(int T, int HP, const MdBatchArgs &b, hipStream_t s);
 
 }  // namespace nep

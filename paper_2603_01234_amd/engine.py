@@ -6,6 +6,7 @@ integrator runs in the library's kernels.
 """
 from __future__ import annotations
 
+import ctypes
 import math
 from typing import Optional, Sequence
 
@@ -324,3 +325,175 @@ class FitnessBatch:
                                         _ptr(out.get("items")), _ptr(out.get("forces")), cfg, ws, nbytes,
                                         _stream()))
         return out
+
+
+def replica_footprint(model: Model, n: int, box, pbc, skin: float, pos=None) -> int:
+    """Device bytes a Replica of n beads holds: state, lists and workspace."""
+    cap, cap_A = estimate_caps(n, np.asarray(box, np.float32), pbc, float(model.rc_R.max()),
+                               float(model.rc_A.max()), skin, pos)
+    n1 = max(n, 1)
+    state = n1 * (4 * 3 * 5 + 4 + 1 + 4 * 2)          # xyz, v, F, ref, vh-less state, U, type, cnt
+    lists = 4 * n1 * (cap + cap_A)
+    return state + lists + B.nep_workspace_bytes(model.handle, n, cap, cap_A)
+
+
+class MdStepBatch:
+    """One velocity-Verlet step for many resident replicas per call
+    (nep_md_step_batch)."""
+
+    def __init__(self, model: Model, dt: float, masses: Sequence[float], rebuild_every: int = 10,
+                 max_active: int = 256, device: str = "cuda"):
+        self.model = model
+        self.dt = float(dt)
+        self.masses = list(masses)
+        self.rebuild_every = int(rebuild_every)
+        self.max_active = int(max_active)
+        nbytes = B.nep_md_batch_workspace_bytes(self.max_active)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = base + (-base) % 256
+        self._ws_bytes = self._ws.numel() - (-base) % 256
+        self.E_pot = torch.zeros(self.max_active, dtype=torch.float64, device=device)
+        self.E_kin = torch.zeros(self.max_active, dtype=torch.float64, device=device)
+
+    def step(self, reps: Sequence[Replica]):
+        """Advances every replica by one step; returns the per-replica status
+        codes (a replica whose rebuild overflowed is regrown, rebuilt and left
+        at its last step, its code NEP_ERR_NEIGHBOR_OVERFLOW)."""
+        if len(reps) > self.max_active:
+            raise ValueError("more replicas than max_active")
+        arr = (B.Replica * max(len(reps), 1))()
+        keep = []
+        for k, r in enumerate(reps):
+            if not r.lists_valid:
+                r.build()
+            s, nb = r.c_system(), r.c_neighbors()
+            keep.append((s, nb))
+            arr[k] = B.Replica(ctypes.pointer(s), r.v.data_ptr(), r.F.data_ptr(), r.U.data_ptr(),
+                               ctypes.pointer(nb), r.ws.data_ptr(), r.ws_bytes, r.step, 0, 0)
+        if not reps:
+            return []
+        B.check(B.nep_md_step_batch(self.model.handle, arr, self.dt,
+                                    self.masses, self.rebuild_every, self.E_pot.data_ptr(), self.E_kin.data_ptr(),
+                                    self._ws_ptr, self._ws_bytes, _stream()))
+        codes = []
+        for k, r in enumerate(reps):
+            r.step = int(arr[k].step)
+            r.n_rebuilds += int(arr[k].rebuilt)
+            code = int(arr[k].status)
+            if code == B.NEP_ERR_NEIGHBOR_OVERFLOW:
+                st = r.status.cpu().tolist()
+                r._alloc_lists(max(r.cap, int(st[1] * 1.25) + 8), max(r.cap_A, int(st[2] * 1.25) + 8))
+                r.build()
+            elif code != B.NEP_OK:
+                raise B.NepError(code, f"replica {k}: step failed")
+            codes.append(code)
+        return codes
+
+
+class Server:
+    """Continuous batching of MD requests over independent replicas.
+
+    A request advances one replica by a number of steps; requests for a busy
+    replica wait in order.  Replicas stay on the host until a request needs
+    them, are admitted to the device when their footprint fits the HBM budget
+    (idle resident replicas are evicted least recently used to make room), and
+    then stay resident with their lists.  Every tick advances each replica
+    with an active request by one step in one nep_md_step_batch call; requests
+    that arrived meanwhile join at the next tick and finished ones leave."""
+
+    def __init__(self, model: Model, systems, skin: float, dt: float, masses: Sequence[float],
+                 rebuild_every: int = 10, hbm_budget: Optional[int] = None, max_active: int = 256,
+                 clock=None):
+        import collections
+        import time
+        self.model = model
+        self.skin = float(skin)
+        self.masses = list(masses)
+        self.host = [dict(pos=np.asarray(s.pos_f32()), vel=np.asarray(s.vel, np.float32), types=s.types,
+                          box=np.asarray(s.box, np.float64), pbc=s.pbc, step=0) for s in systems]
+        self.footprint = [replica_footprint(model, h["pos"].shape[0], h["box"], h["pbc"], self.skin, h["pos"])
+                          for h in self.host]
+        self.budget = hbm_budget if hbm_budget is not None else sum(self.footprint)
+        self.stepper = MdStepBatch(model, dt, masses, rebuild_every, max_active)
+        self.max_active = int(max_active)
+        self.resident = collections.OrderedDict()   # replica id -> Replica, least recently used first
+        self.used = 0
+        self.pending = collections.OrderedDict()    # replica id -> deque of [req, steps_left, t_arrival, steps]
+        self.active = collections.OrderedDict()     # replica id -> [req, steps_left, t_arrival, steps]
+        self.done = []                              # (req, replica, t_arrival, t_done, bead-steps)
+        self.ticks = 0
+        self.evictions = 0
+        self.admissions = 0
+        self.clock = clock or time.perf_counter
+
+    # -- residency ------------------------------------------------------------
+    def _admit(self, rid: int) -> bool:
+        need = self.footprint[rid]
+        if need > self.budget:
+            raise ValueError(f"replica {rid} alone exceeds the HBM budget")
+        while self.used + need > self.budget:
+            victim = next((k for k in self.resident if k not in self.active), None)
+            if victim is None:
+                return False
+            self._evict(victim)
+        h = self.host[rid]
+        r = Replica(self.model, h["pos"], h["types"], h["box"], h["pbc"], skin=self.skin, vel=h["vel"])
+        r.step = h["step"]
+        r.efv(per_bead_virial=False)                # lists and forces at the stored positions
+        self.resident[rid] = r
+        self.used += need
+        self.admissions += 1
+        return True
+
+    def _evict(self, rid: int):
+        r = self.resident.pop(rid)
+        h = self.host[rid]
+        h["pos"], h["vel"], h["step"] = r.positions(), r.velocities(), r.step
+        self.used -= self.footprint[rid]
+        self.evictions += 1
+        del r
+
+    def replica(self, rid: int) -> Optional[Replica]:
+        return self.resident.get(rid)
+
+    # -- requests -------------------------------------------------------------
+    def submit(self, req: int, rid: int, n_steps: int, t_arrival: float):
+        import collections
+        self.pending.setdefault(rid, collections.deque()).append([req, int(n_steps), float(t_arrival), int(n_steps)])
+
+    def idle(self) -> bool:
+        return not self.active and not self.pending
+
+    def tick(self) -> int:
+        """Admits waiting requests, runs one batched step; returns requests completed."""
+        for rid in list(self.pending.keys()):
+            if len(self.active) >= self.max_active:
+                break
+            if rid in self.active:
+                continue
+            if rid not in self.resident and not self._admit(rid):
+                continue
+            q = self.pending[rid]
+            self.active[rid] = q.popleft()
+            if not q:
+                del self.pending[rid]
+        if not self.active:
+            return 0
+        rids = list(self.active.keys())
+        reps = [self.resident[k] for k in rids]
+        codes = self.stepper.step(reps)
+        self.ticks += 1
+        t = self.clock()
+        finished = 0
+        for rid, r, code in zip(rids, reps, codes):
+            self.resident.move_to_end(rid)
+            if code != B.NEP_OK:
+                continue                            # lists regrown; the step runs again next tick
+            a = self.active[rid]
+            a[1] -= 1
+            if a[1] == 0:
+                del self.active[rid]
+                self.done.append((a[0], rid, a[2], t, r.n * a[3]))
+                finished += 1
+        return finished

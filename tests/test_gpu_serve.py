@@ -1,0 +1,143 @@
+"""Served form: many replicas advanced together by nep_md_step_batch, and the
+continuous-batching server on top (needs an MI355X).
+
+A replica's result must not depend on the company it keeps: stepped alone,
+in a mix, joining the batch late, or through nep_md_step, its trajectory is
+the same; after serving, its forces still match the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import compare_efv
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def serve_small():
+    return W.config4(n_replicas=6, n_requests=60, rate_hz=2000.0, size_range=(200, 900), warmup_requests=0)
+
+
+def _reps(sw, model, ids):
+    from paper_2603_01234_amd import engine as E
+    out = []
+    for k in ids:
+        s = sw.replicas[k]
+        r = E.Replica(model, s.pos_f32(), s.types, s.box, s.pbc, skin=0.1, vel=s.vel)
+        r.efv(per_bead_virial=False)
+        out.append(r)
+    return out
+
+
+def _state(r):
+    return (r.xyz[:, :r.n].clone(), r.v[:, :r.n].clone(), r.F[:, :r.n].clone())
+
+
+def test_batched_step_equals_single_replica_path(serve_small):
+    """Every replica stepped 25 times in one batch equals, bitwise, the same
+    replica advanced by nep_md_step (same rebuild decisions, same kernels)."""
+    from paper_2603_01234_amd import engine as E
+    sw = serve_small
+    model = E.Model.from_spec(sw.spec, sw.params)
+    ids = list(range(len(sw.replicas)))
+    batch = _reps(sw, model, ids)
+    stepper = E.MdStepBatch(model, 2.0, [W.WATER_MASS], rebuild_every=10, max_active=8)
+    for _ in range(25):
+        assert all(c == 0 for c in stepper.step(batch))
+    single = _reps(sw, model, ids)
+    for r in single:
+        r.md(25, 2.0, [W.WATER_MASS], rebuild_every=10)
+    for a, b in zip(batch, single):
+        assert a.step == b.step == 25 and a.n_rebuilds == b.n_rebuilds
+        for x, y in zip(_state(a), _state(b)):
+            assert torch.equal(x, y)
+
+
+def test_result_is_the_same_alone_and_in_any_mix(serve_small):
+    """Replica 2 alone for 12 steps versus inside batches whose membership
+    changes every few steps (others join late and leave early)."""
+    from paper_2603_01234_amd import engine as E
+    sw = serve_small
+    model = E.Model.from_spec(sw.spec, sw.params)
+    stepper = E.MdStepBatch(model, 2.0, [W.WATER_MASS], rebuild_every=10, max_active=8)
+    alone = _reps(sw, model, [2])[0]
+    for _ in range(12):
+        stepper.step([alone])
+    mix = _reps(sw, model, range(len(sw.replicas)))
+    members = [[2], [0, 2, 5], [2, 1, 3, 4, 5, 0], [4, 2], [2, 3]]
+    k = 0
+    for step in range(12):
+        group = members[(step // 3) % len(members)]
+        stepper.step([mix[j] for j in group])
+        k += 1
+    assert mix[2].step == 12
+    for x, y in zip(_state(alone), _state(mix[2])):
+        assert torch.equal(x, y)
+
+
+def test_served_replicas_match_oracle_after_the_trace(serve_small):
+    """Run the small trace through the server with a budget that holds only
+    three replicas (evictions and re-admissions happen), then compare every
+    replica's forces with the oracle and its step count with its requests."""
+    from paper_2603_01234_amd import engine as E
+    sw = serve_small
+    model = E.Model.from_spec(sw.spec, sw.params)
+    fp = [E.replica_footprint(model, s.n, s.box, s.pbc, 0.1, s.pos_f32()) for s in sw.replicas]
+    budget = sum(sorted(fp)[-3:])
+    srv = E.Server(model, sw.replicas, skin=0.1, dt=2.0, masses=[W.WATER_MASS], hbm_budget=budget)
+    for q in range(len(sw.arrivals_s)):
+        srv.submit(q, int(sw.replica_of[q]), sw.steps_per_request, float(sw.arrivals_s[q]))
+    while not srv.idle():
+        srv.tick()
+    assert len(srv.done) == len(sw.arrivals_s)
+    assert srv.evictions > 0 and srv.used <= budget
+    want = np.bincount(sw.replica_of, minlength=len(sw.replicas)) * sw.steps_per_request
+    for rid, s in enumerate(sw.replicas):
+        r = srv.replica(rid)
+        if r is None:
+            assert srv.host[rid]["step"] == want[rid]
+            continue
+        assert r.step == want[rid]
+        r.efv()
+        ref = oracle.efv(sw.spec, sw.params.astype(np.float32).astype(np.float64),
+                         r.positions().astype(np.float64), s.types,
+                         np.asarray(r.box, np.float32).astype(np.float64), s.pbc)
+        compare_efv(r, ref, s.n, label=f"served replica {rid}")
+
+
+def test_overflow_in_one_replica_leaves_the_others_alone(serve_small):
+    """Replica 1 starts with lists one angular slot too short (its build
+    overflowed): its first batched step is refused and it keeps its state,
+    the engine regrows it, and both replicas then follow the trajectories they
+    have alone."""
+    from paper_2603_01234_amd import binding as B
+    from paper_2603_01234_amd import engine as E
+    sw = serve_small
+    model = E.Model.from_spec(sw.spec, sw.params)
+    stepper = E.MdStepBatch(model, 2.0, [W.WATER_MASS], rebuild_every=10, max_active=8)
+    reps = _reps(sw, model, [0, 1])
+    st = reps[1].status.cpu().tolist()
+    reps[1]._alloc_lists(st[1], st[2] - 1)
+    code = B.nep_build_neighbors(model.handle, reps[1].c_system(), reps[1].c_neighbors(), 1,
+                                 reps[1].ws.data_ptr(), reps[1].ws_bytes, torch.cuda.current_stream().cuda_stream)
+    assert code == B.NEP_ERR_NEIGHBOR_OVERFLOW
+    before = _state(reps[1])
+    codes = stepper.step(reps)
+    assert codes == [B.NEP_OK, B.NEP_ERR_NEIGHBOR_OVERFLOW]
+    assert reps[0].step == 1 and reps[1].step == 0 and reps[1].cap_A >= st[2]
+    for x, y in zip(before, _state(reps[1])):
+        assert torch.equal(x, y)
+    for _ in range(5):
+        assert stepper.step(reps) == [B.NEP_OK, B.NEP_OK]
+    ref = _reps(sw, model, [0, 1])
+    for _ in range(6):
+        stepper.step([ref[0]])
+    for _ in range(5):
+        stepper.step([ref[1]])
+    for a, b in zip(reps, ref):
+        assert a.step == b.step
+        for x, y in zip(_state(a), _state(b)):
+            assert torch.equal(x, y)
