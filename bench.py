@@ -216,6 +216,99 @@ def batched_leg(reps: int = 3, plain_candidates: int = 2):
     return out
 
 
+def served_leg(plain_requests: int = 2000):
+    """Serving workload: 256 resident water-like replicas (500-20,000 beads,
+    density x U(1.00, 1.25), config-0 weights, 300 K) and a Poisson trace of
+    10-step requests at 2,000/s replayed in real time, through the continuous-
+    batching server and through a plain FIFO loop of one nep_md_step call per
+    request (first plain_requests requests of the same trace)."""
+    import torch
+    import workloads as W
+    from paper_2603_01234_amd import engine
+
+    sw = W.config4()
+    model = engine.Model.from_spec(sw.spec, sw.params)
+    n_req = len(sw.arrivals_s)
+    steps = sw.steps_per_request
+    srv = engine.Server(model, sw.replicas, skin=0.1, dt=2.0, masses=[W.WATER_MASS], rebuild_every=10)
+    t_setup = time.perf_counter()
+    for rid in range(len(sw.replicas)):          # everything fits the default budget: admit up front
+        srv._admit(rid)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+
+    def replay(submit, step, idle, n, t_first):
+        t0 = time.perf_counter()
+        i = 0
+        while True:
+            now = time.perf_counter() - t0
+            while i < n and sw.arrivals_s[i] <= now:
+                submit(i, t0 + float(sw.arrivals_s[i]))
+                i += 1
+            if idle():
+                if i >= n:
+                    break
+                time.sleep(max(0.0, min(float(sw.arrivals_s[i]) - now, 1e-3)))
+                continue
+            step()
+        return t0
+
+    active_sizes = []
+
+    def srv_step():
+        active_sizes.append(len(srv.active) + min(len(srv.pending), srv.max_active))
+        srv.tick()
+
+    replay(lambda q, ta: srv.submit(q, int(sw.replica_of[q]), steps, ta), srv_step, srv.idle, n_req, 0)
+    done = sorted(srv.done)
+    warm = sw.warmup_requests
+    lat = np.array([d[3] - d[2] for d in done[warm:]]) * 1e3
+    meas = done[warm:]
+    t_begin = min(d[2] for d in meas)
+    t_end = max(d[3] for d in meas)
+    bead_steps = sum(d[4] for d in meas)
+    served = {"requests": n_req, "warmup_requests": warm, "ticks": srv.ticks,
+              "mean_replicas_per_tick": round(float(np.mean(active_sizes)), 1),
+              "bead_steps_per_s": round(bead_steps / (t_end - t_begin), 1),
+              "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+              "setup_s": round(t_setup, 1)}
+
+    # plain FIFO loop over the first plain_requests requests, same arrival times
+    reps = []
+    for s in sw.replicas:
+        r = engine.Replica(model, s.pos_f32(), s.types, s.box, s.pbc, skin=0.1, vel=s.vel)
+        r.efv(per_bead_virial=False)
+        reps.append(r)
+    torch.cuda.synchronize()
+    queue = []
+    pdone = []
+
+    def p_submit(q, ta):
+        queue.append((q, ta))
+
+    def p_step():
+        q, ta = queue.pop(0)
+        r = reps[int(sw.replica_of[q])]
+        r.md(steps, 2.0, [W.WATER_MASS], rebuild_every=10)       # synchronises at its end
+        pdone.append((q, ta, time.perf_counter(), r.n * steps))
+
+    replay(p_submit, p_step, lambda: not queue, plain_requests, 0)
+    pw = plain_requests // 10
+    plat = np.array([d[2] - d[1] for d in pdone[pw:]]) * 1e3
+    pt0 = min(d[1] for d in pdone[pw:])
+    pt1 = max(d[2] for d in pdone[pw:])
+    plain = {"requests": plain_requests, "warmup_requests": pw,
+             "bead_steps_per_s": round(sum(d[3] for d in pdone[pw:]) / (pt1 - pt0), 1),
+             "p50_ms": round(float(np.percentile(plat, 50)), 3), "p99_ms": round(float(np.percentile(plat, 99)), 3)}
+    offered = float(np.mean([sw.replicas[int(k)].n for k in sw.replica_of])) * steps * n_req / float(sw.arrivals_s[-1])
+    model.close()
+    return {"workload": "config4 serving: 256 water-like replicas, N U{500..20000}, density x U(1.00,1.25), "
+                        "config-0 weights, 300 K, skin 0.1 nm; Poisson 2000 req/s of 10 MD steps, "
+                        "20,000 requests (first 1,000 warm-up)",
+            "offered_bead_steps_per_s": round(offered, 1), "served": served, "plain_fifo": plain,
+            "throughput_ratio": round(served["bead_steps_per_s"] / plain["bead_steps_per_s"], 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +316,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fitness leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -336,6 +430,9 @@ def main():
     if not args.no_batched:
         print("bench: batched fitness leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg()
+    if not args.no_served:
+        print("bench: serving leg", file=sys.stderr, flush=True)
+        out["served"] = served_leg()
     print(json.dumps(out), flush=True)
 
 

@@ -528,7 +528,7 @@ int mdb_host(size_t bytes, char *&out) {
 }
 
 struct MdbLayout {
-    size_t desc, tiles, gate, status, total;
+    size_t desc, tiles, gate, status, nbargs, nbstart, total;
 };
 MdbLayout mdb_layout(int n) {
     MdbLayout L{};
@@ -543,6 +543,8 @@ MdbLayout mdb_layout(int n) {
     L.tiles = take(sizeof(int) * (nn + 1));
     L.gate = take(sizeof(int) * nn);
     L.status = take(sizeof(int32_t) * 4 * nn);
+    L.nbargs = take(sizeof(NbArgs) * nn);
+    L.nbstart = take(sizeof(int) * 6 * (nn + 1));
     L.total = off;
     return L;
 }
@@ -941,15 +943,35 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
     HIPCHK(launch_kick_drift_batch(b, st));
     HIPCHK(hipMemcpyAsync(hg, b.gate, sizeof(int) * n_active, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    // the builds of every replica whose gate is on, one launch per phase
+    NbArgs *hn = reinterpret_cast<NbArgs *>(h + BL.nbargs);
+    int *hstart = reinterpret_cast<int *>(h + BL.nbstart);
+    int nsys = 0;
     for (int r = 0; r < n_active; ++r) {
-        if (!hg[r]) continue;
+        if (!hg[r] || reps[r].sys->n == 0) continue;
         nep_replica &R = reps[r];
-        NbArgs a;
         // a replica left frozen by an earlier failed build is skipped on the device
-        if ((rc = fill_nb(M, R.sys, R.nbrs, R.ws, L[r], 0, 1, a))) return rc;
-        a.from_pos4 = 1;
-        HIPCHK(launch_build(a, st));
+        if ((rc = fill_nb(M, R.sys, R.nbrs, R.ws, L[r], 0, 1, hn[nsys]))) return rc;
+        hn[nsys].from_pos4 = 1;
         R.rebuilt = 1;
+        ++nsys;
+    }
+    if (nsys > 0) {
+        int totals[6] = {0, 0, 0, 0, 0, 0};
+        for (int q = 0; q < nsys; ++q) {
+            int c[6];
+            nb_batch_tiles(hn[q], c);
+            for (int k = 0; k < 6; ++k) {
+                hstart[k * (nsys + 1) + q] = totals[k];
+                totals[k] += c[k];
+            }
+        }
+        for (int k = 0; k < 6; ++k) hstart[k * (nsys + 1) + nsys] = totals[k];
+        HIPCHK(hipMemcpyAsync(at<char>(ws, BL.nbargs), hn, sizeof(NbArgs) * nsys, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(at<char>(ws, BL.nbstart), hstart, sizeof(int) * 6 * (nsys + 1),
+                              hipMemcpyHostToDevice, st));
+        NbBatchArgs nbb{nsys, at<NbArgs>(ws, BL.nbargs), at<int>(ws, BL.nbstart)};
+        HIPCHK(launch_build_batch(nbb, totals, st));
     }
     HIPCHK(launch_efv_md_batch(M.T, M.HP, b, st));
     // every replica's status word, copied by the reduction, in one transfer

@@ -31,12 +31,20 @@ __device__ __forceinline__ bool build_off(const int32_t *ctrl, const int32_t *st
 }
 __device__ __forceinline__ bool build_off(const NbArgs &a) { return build_off(a.ctrl, a.status, a.clear_status); }
 
-__global__ void k_nb_clear(int ncell, int32_t *cell_count, int32_t *status, int clear_status, int32_t *ctrl) {
+// Every phase of the build is a body taking its block index and block count,
+// so that the same code runs as one kernel per system or as one kernel over
+// the blocks of many systems (the served form).
+__device__ __forceinline__ void nb_clear_body(int ncell, int32_t *cell_count, int32_t *status, int clear_status,
+                                              int32_t *ctrl, int bx, int gx) {
     if (build_off(ctrl, status, clear_status)) return;
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int c = t; c < ncell; c += gridDim.x * blockDim.x) cell_count[c] = 0;
+    int t = bx * blockDim.x + threadIdx.x;
+    for (int c = t; c < ncell; c += gx * blockDim.x) cell_count[c] = 0;
     if (clear_status && t < 4) status[t] = 0;
     if (ctrl && t == 0) ctrl[1] += 1;
+}
+
+__global__ void k_nb_clear(int ncell, int32_t *cell_count, int32_t *status, int clear_status, int32_t *ctrl) {
+    nb_clear_body(ncell, cell_count, status, clear_status, ctrl, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_md_clear(int32_t *status, int32_t *ctrl, int gate0) {
@@ -65,9 +73,9 @@ __device__ __forceinline__ float wrap_coord(float x, float L) {
     return w;
 }
 
-__global__ void k_nb_bin(NbArgs a) {
+__device__ __forceinline__ void nb_bin_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     float p[3];
     if (a.from_pos4) {
@@ -103,14 +111,19 @@ __global__ void k_nb_bin(NbArgs a) {
     a.ref[2 * a.n + i] = p[2];
 }
 
+__global__ void k_nb_bin(NbArgs a) { nb_bin_body(a, blockIdx.x); }
+
 // Exclusive scan, three phases.  Block b scans 1024 counts; one block then
 // scans the block totals serially in chunks; a last pass adds the offsets.
 constexpr int SCAN_B = 1024;
 
-__global__ void k_scan_local(const int32_t *in, int32_t *out, int32_t *block_sums, int n, NbArgs a) {
+__device__ __forceinline__ void scan_local_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
+    const int32_t *in = a.cell_count;
+    int32_t *out = a.cell_start, *block_sums = a.scan_tmp;
+    const int n = a.ncell;
     __shared__ int32_t s[SCAN_B];
-    int base = blockIdx.x * SCAN_B;
+    int base = bx * SCAN_B;
     int t = threadIdx.x;
     for (int k = t; k < SCAN_B; k += blockDim.x) s[k] = (base + k < n) ? in[base + k] : 0;
     __syncthreads();
@@ -127,12 +140,17 @@ __global__ void k_scan_local(const int32_t *in, int32_t *out, int32_t *block_sum
     }
     for (int k = t; k < SCAN_B; k += blockDim.x)
         if (base + k < n) out[base + k] = s[k] - ((base + k < n) ? in[base + k] : 0);
-    if (t == 0) block_sums[blockIdx.x] = s[SCAN_B - 1];
+    if (t == 0) block_sums[bx] = s[SCAN_B - 1];
 }
 
-__global__ void k_scan_blocks(int32_t *block_sums, int nb, int32_t *total_out, NbArgs a) {
+__global__ void k_scan_local(NbArgs a) { scan_local_body(a, blockIdx.x); }
+
+__device__ __forceinline__ void scan_blocks_body(const NbArgs &a) {
     if (build_off(a)) return;
     if (threadIdx.x != 0) return;
+    int32_t *block_sums = a.scan_tmp;
+    int32_t *total_out = a.cell_start + a.ncell;
+    const int nb = (a.ncell + SCAN_B - 1) / SCAN_B;
     int32_t run = 0;
     for (int b = 0; b < nb; ++b) {
         int32_t v = block_sums[b];
@@ -142,27 +160,33 @@ __global__ void k_scan_blocks(int32_t *block_sums, int nb, int32_t *total_out, N
     *total_out = run;
 }
 
-__global__ void k_scan_add(int32_t *out, int32_t *cursor, const int32_t *block_sums, int n, NbArgs a) {
+__global__ void k_scan_blocks(NbArgs a) { scan_blocks_body(a); }
+
+__device__ __forceinline__ void scan_add_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    int32_t v = out[k] + block_sums[k / SCAN_B];
-    out[k] = v;
-    cursor[k] = v;
+    int k = bx * blockDim.x + threadIdx.x;
+    if (k >= a.ncell) return;
+    int32_t v = a.cell_start[k] + a.scan_tmp[k / SCAN_B];
+    a.cell_start[k] = v;
+    a.cell_cursor[k] = v;
 }
 
-__global__ void k_nb_fill(NbArgs a) {
+__global__ void k_scan_add(NbArgs a) { scan_add_body(a, blockIdx.x); }
+
+__device__ __forceinline__ void nb_fill_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     int slot = atomicAdd(&a.cell_cursor[a.cell_id[i]], 1);
     a.cell_tmp[slot] = i;
 }
 
+__global__ void k_nb_fill(NbArgs a) { nb_fill_body(a, blockIdx.x); }
+
 // rank of bead i among the members of its cell, by index
-__global__ void k_nb_rank(NbArgs a) {
+__device__ __forceinline__ void nb_rank_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const int c = a.cell_id[i];
     const int s = a.cell_start[c], e = a.cell_start[c + 1];
@@ -173,6 +197,8 @@ __global__ void k_nb_rank(NbArgs a) {
     const uint32_t tag = (uint32_t)i | ((uint32_t)p.w << CODE_SHIFT);
     a.pos_sorted[s + rank] = make_float4(p.x, p.y, p.z, __uint_as_float(tag));
 }
+
+__global__ void k_nb_rank(NbArgs a) { nb_rank_body(a, blockIdx.x); }
 
 // flags (or) and row maxima of the active lanes, one atomic per wave
 __device__ __forceinline__ void wave_status(int32_t *status, int flags, int total, int na) {
@@ -301,28 +327,32 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
     na_out = na;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_nb_rows(NbArgs a) {
+__device__ __forceinline__ void nb_rows_body(const NbArgs &a, int bx, int gx) {
     if (build_off(a)) return;  // uniform over the grid
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
     int flags = 0, total = 0, na = 0;
     if (i < a.n) build_row(a, i, flags, total, na);
     wave_status(a.status, flags, total, na);  // every lane takes part
 }
 
+__global__ __launch_bounds__(BLOCK) void k_nb_rows(NbArgs a) { nb_rows_body(a, blockIdx.x, gridDim.x); }
+
 // row-major scratch -> slot-major lists: slot p of bead i is scratch entry p for
 // the angular prefix, and the radial-only entries, kept from the back of the
 // scratch row, follow in the order they were found.  Lanes write consecutive
 // beads of one slot (coalesced); each lane reads its own scratch row.
-__global__ __launch_bounds__(BLOCK) void k_nb_transpose(NbArgs a) {
+__device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int gx) {
     if (build_off(a)) return;
     const int n = a.n;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int total = a.cnt[i], na = a.cnt[n + i];
     const uint32_t *row = a.rowbuf + (size_t)i * a.cap;
     // one slot per iteration for every lane, so each store covers consecutive beads
     for (int p = 0; p < total; ++p) a.nbr[(size_t)p * n + i] = row[p < na ? p : a.cap - 1 - (p - na)];
 }
+
+__global__ __launch_bounds__(BLOCK) void k_nb_transpose(NbArgs a) { nb_transpose_body(a, blockIdx.x, gridDim.x); }
 
 constexpr int REV_SLOTS = 4;  // angular slots per thread: p = blockIdx.y + k gridDim.y
 
@@ -355,16 +385,20 @@ __device__ __forceinline__ void reverse_one(const NbArgs &a, int i, int p) {
 
 // one thread per (bead, group of angular slots); lanes of a wave read
 // consecutive beads at the same slot
-__global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
+__device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int bx, int gx, int by, int gy) {
     if (build_off(a)) return;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
+    const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
     if (i >= a.n) return;
     const int na = a.cnt[a.n + i];
     for (int k = 0; k < REV_SLOTS; ++k) {
-        const int p = blockIdx.y + k * gridDim.y;
+        const int p = by + k * gy;
         if (p >= na) break;
         reverse_one(a, i, p);
     }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
+    nb_reverse_body(a, blockIdx.x, gridDim.x, blockIdx.y, gridDim.y);
 }
 
 hipError_t launch_build(const NbArgs &a, hipStream_t s) {
@@ -375,14 +409,83 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     if (a.n == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_nb_bin, dim3(nbk), dim3(BLOCK), 0, s, a);
     int sb = (a.ncell + SCAN_B - 1) / SCAN_B;
-    hipLaunchKernelGGL(k_scan_local, dim3(sb), dim3(BLOCK), 0, s, a.cell_count, a.cell_start, a.scan_tmp, a.ncell, a);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, s, a.scan_tmp, sb, a.cell_start + a.ncell, a);
-    hipLaunchKernelGGL(k_scan_add, dim3(cbk), dim3(BLOCK), 0, s, a.cell_start, a.cell_cursor, a.scan_tmp, a.ncell, a);
+    hipLaunchKernelGGL(k_scan_local, dim3(sb), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_scan_add, dim3(cbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_fill, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_rank, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_rows, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_transpose, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_reverse, dim3(nbk, (a.cap_A + REV_SLOTS - 1) / REV_SLOTS), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+
+// ---- one launch per phase over the builds of many systems ----
+// start[ph][r] is the first block of system r in phase ph (tables of
+// n_sys + 1 entries, one per tile kind: cells to clear, beads, scan blocks,
+// the one-block scan, cells to offset, and (bead, slot-group) pairs).
+enum { NB_TILE_CLEAR = 0, NB_TILE_BEAD, NB_TILE_SCANL, NB_TILE_SCANB, NB_TILE_SCANA, NB_TILE_REV, NB_TILES };
+enum { OP_CLEAR, OP_BIN, OP_SCANL, OP_SCANB, OP_SCANA, OP_FILL, OP_RANK, OP_ROWS, OP_TRANSPOSE, OP_REVERSE };
+
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
+    constexpr int TILE = OP == OP_CLEAR ? NB_TILE_CLEAR
+                         : OP == OP_SCANL ? NB_TILE_SCANL
+                         : OP == OP_SCANB ? NB_TILE_SCANB
+                         : OP == OP_SCANA ? NB_TILE_SCANA
+                         : OP == OP_REVERSE ? NB_TILE_REV
+                                            : NB_TILE_BEAD;
+    const int *st = b.start + TILE * (b.n_sys + 1);
+    int lo = 0, hi = b.n_sys - 1;  // last system whose first block is <= blockIdx.x
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const NbArgs &a = b.args[lo];
+    const int bx = blockIdx.x - st[lo], gx = st[lo + 1] - st[lo];
+    if constexpr (OP == OP_CLEAR) nb_clear_body(a.ncell, a.cell_count, a.status, a.clear_status, a.ctrl, bx, gx);
+    if constexpr (OP == OP_BIN) nb_bin_body(a, bx);
+    if constexpr (OP == OP_SCANL) scan_local_body(a, bx);
+    if constexpr (OP == OP_SCANB) scan_blocks_body(a);
+    if constexpr (OP == OP_SCANA) scan_add_body(a, bx);
+    if constexpr (OP == OP_FILL) nb_fill_body(a, bx);
+    if constexpr (OP == OP_RANK) nb_rank_body(a, bx);
+    if constexpr (OP == OP_ROWS) nb_rows_body(a, bx, gx);
+    if constexpr (OP == OP_TRANSPOSE) nb_transpose_body(a, bx, gx);
+    if constexpr (OP == OP_REVERSE) {
+        const int nbk = (a.n + BLOCK - 1) / BLOCK;
+        nb_reverse_body(a, bx % nbk, nbk, bx / nbk, gx / nbk);
+    }
+}
+
+void nb_batch_tiles(const NbArgs &a, int counts[6]) {
+    const int nbk = (a.n + BLOCK - 1) / BLOCK;
+    const int cbk = (a.ncell + BLOCK - 1) / BLOCK;
+    counts[NB_TILE_CLEAR] = cbk > 0 ? (cbk < 4096 ? cbk : 4096) : 1;
+    counts[NB_TILE_BEAD] = nbk;
+    counts[NB_TILE_SCANL] = (a.ncell + SCAN_B - 1) / SCAN_B;
+    counts[NB_TILE_SCANB] = 1;
+    counts[NB_TILE_SCANA] = cbk;
+    counts[NB_TILE_REV] = nbk * ((a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
+}
+
+hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[6], hipStream_t s) {
+    if (b.n_sys == 0) return hipSuccess;
+#define NB_LAUNCH(OPC, TILEK)                                                                     \
+    if (totals[TILEK] > 0) hipLaunchKernelGGL(k_nb_batch<OPC>, dim3(totals[TILEK]), dim3(BLOCK), 0, s, b);
+    NB_LAUNCH(OP_CLEAR, NB_TILE_CLEAR)
+    NB_LAUNCH(OP_BIN, NB_TILE_BEAD)
+    NB_LAUNCH(OP_SCANL, NB_TILE_SCANL)
+    NB_LAUNCH(OP_SCANB, NB_TILE_SCANB)
+    NB_LAUNCH(OP_SCANA, NB_TILE_SCANA)
+    NB_LAUNCH(OP_FILL, NB_TILE_BEAD)
+    NB_LAUNCH(OP_RANK, NB_TILE_BEAD)
+    NB_LAUNCH(OP_ROWS, NB_TILE_BEAD)
+    NB_LAUNCH(OP_TRANSPOSE, NB_TILE_BEAD)
+    NB_LAUNCH(OP_REVERSE, NB_TILE_REV)
+#undef NB_LAUNCH
     return hipGetLastError();
 }
 

@@ -291,6 +291,17 @@ struct NbArgs {
     int from_pos4;     // 1 (MD): positions come from pos4 and are wrapped there, x/y/z are untouched
 };
 hipError_t launch_build(const NbArgs &a, hipStream_t s);
+// Builds of many systems, one launch per phase: args[r] as for launch_build
+// (systems with n > 0); start holds the six tables of first blocks written by
+// the caller from nb_batch_tiles; totals are the last entries of the tables.
+struct NbBatchArgs {
+    int n_sys;
+    const NbArgs *args;
+    const int *start;     // [6][n_sys + 1]
+};
+void nb_batch_tiles(const NbArgs &a, int counts[6]);
+hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[6], hipStream_t s);
+
 // zeroes the status word and, when given, the MD control words [4] (the
 // rebuild gate ctrl[0] is set to gate0)
 hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, int gate0, hipStream_t s);

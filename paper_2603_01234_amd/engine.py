@@ -123,6 +123,7 @@ class Replica:
         self.rev = torch.zeros((self.cap_A, n), dtype=torch.int32, device=self.device)
         self.ws_bytes = B.nep_workspace_bytes(self.model.handle, self.n, self.cap, self.cap_A)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self._cstruct = None
 
     def c_system(self) -> B.System:
         s = B.System()
@@ -133,6 +134,16 @@ class Replica:
             s.box[d] = float(self.box[d])
             s.pbc[d] = self.pbc[d]
         return s
+
+    def c_replica(self) -> B.Replica:
+        """nep_replica view of this system (cached until the lists are reallocated;
+        the box must not change meanwhile)."""
+        if self._cstruct is None:
+            s, nb = self.c_system(), self.c_neighbors()
+            rp = B.Replica(ctypes.pointer(s), self.v.data_ptr(), self.F.data_ptr(), self.U.data_ptr(),
+                           ctypes.pointer(nb), self.ws.data_ptr(), self.ws_bytes, 0, 0, 0)
+            self._cstruct = (rp, s, nb)
+        return self._cstruct[0]
 
     def c_neighbors(self) -> B.Neighbors:
         nb = B.Neighbors()
@@ -362,17 +373,14 @@ class MdStepBatch:
         at its last step, its code NEP_ERR_NEIGHBOR_OVERFLOW)."""
         if len(reps) > self.max_active:
             raise ValueError("more replicas than max_active")
-        arr = (B.Replica * max(len(reps), 1))()
-        keep = []
+        if not reps:
+            return []
+        arr = (B.Replica * len(reps))()
         for k, r in enumerate(reps):
             if not r.lists_valid:
                 r.build()
-            s, nb = r.c_system(), r.c_neighbors()
-            keep.append((s, nb))
-            arr[k] = B.Replica(ctypes.pointer(s), r.v.data_ptr(), r.F.data_ptr(), r.U.data_ptr(),
-                               ctypes.pointer(nb), r.ws.data_ptr(), r.ws_bytes, r.step, 0, 0)
-        if not reps:
-            return []
+            arr[k] = r.c_replica()
+            arr[k].step = r.step
         B.check(B.nep_md_step_batch(self.model.handle, arr, self.dt,
                                     self.masses, self.rebuild_every, self.E_pot.data_ptr(), self.E_kin.data_ptr(),
                                     self._ws_ptr, self._ws_bytes, _stream()))
