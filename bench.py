@@ -83,7 +83,7 @@ def pair_counts(rep, spec):
 
 def kernel_hash() -> str:
     h = hashlib.sha256()
-    for f in ("efv.hip", "nep_internal.h"):
+    for f in ("efv.hip", "efv_device.h", "nep_internal.h"):
         with open(os.path.join(ROOT, "paper_2603_01234_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -419,10 +419,11 @@ def main():
         "kernels": kernels,
     }
     if args.copy_calibration:
-        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        # a plain elementwise kernel of known traffic: reads 256 MiB, writes 256 MiB
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.add(a, 1.0, out=b)
         torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, params, system, rep.positions().astype(np.float64))
