@@ -62,7 +62,7 @@ constexpr int MAX_OFF = 125;  // (2m+1)^3 cell offsets with m <= 2
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, segA, rowbuf, vh, ctrl, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, segA, segS, cls, rowbuf, vh, order, ctrl, total;
     int ncell_max, nblocks;
 };
 
@@ -92,8 +92,11 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.cell_tmp = take(nn * 4);
     L.pos_sorted = take(nn * 16);
     L.segA = take(nn * (size_t)(MAX_OFF + 1));
-    L.rowbuf = take(nn * (size_t)std::max(cap, 1) * 4);
+    L.segS = take(nn * (size_t)(MAX_OFF + 1));
+    L.cls = take(nn * 4);
+    L.rowbuf = take(nn * (size_t)(std::max(cap, 1) + std::max(cap_A, 1)) * 4);
     L.vh = take(nn * 12);
+    L.order = take(nn * 4);
     L.ctrl = take(4 * sizeof(int32_t));
     L.total = off;
     return L;
@@ -206,6 +209,8 @@ int make_grid(const Model &M, const nep_system *s, float skin, int ncell_max, Nb
         double ra = (double)M.rcA[k] + (double)skin;
         a.list2R[k] = (float)(r * r);
         a.list2A[k] = (float)(ra * ra);
+        a.in2R[k] = M.rcR[k] * M.rcR[k];
+        a.in2A[k] = M.rcA[k] * M.rcA[k];
     }
     a.T = M.T;
     return NEP_OK;
@@ -257,7 +262,10 @@ int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, co
     a.cell_tmp = at<int32_t>(ws, L.cell_tmp);
     a.pos_sorted = at<float4>(ws, L.pos_sorted);
     a.segA = at<uint8_t>(ws, L.segA);
+    a.segS = at<uint8_t>(ws, L.segS);
+    a.cls = at<int32_t>(ws, L.cls);
     a.rowbuf = at<uint32_t>(ws, L.rowbuf);
+    a.order = at<int32_t>(ws, L.order);
     a.nbr = nb->nbr;
     a.rev = nb->rev;
     a.cnt = nb->cnt;
@@ -292,6 +300,7 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     a.angbuf = at<float4>(ws, L.angbuf);
     a.fown = at<float4>(ws, L.fown);
     a.freeze = md ? nb->status : nullptr;
+    a.order = at<int32_t>(ws, L.order);
     size_t lds = (size_t)M.T * M.T * TAB_PER_PAIR * sizeof(float);
     {
         TimedLaunch tl(0, st);
@@ -544,7 +553,7 @@ MdbLayout mdb_layout(int n) {
     L.gate = take(sizeof(int) * nn);
     L.status = take(sizeof(int32_t) * 4 * nn);
     L.nbargs = take(sizeof(NbArgs) * nn);
-    L.nbstart = take(sizeof(int) * 6 * (nn + 1));
+    L.nbstart = take(sizeof(int) * NB_BATCH_TILES * (nn + 1));
     L.total = off;
     return L;
 }
@@ -957,18 +966,18 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
         ++nsys;
     }
     if (nsys > 0) {
-        int totals[6] = {0, 0, 0, 0, 0, 0};
+        int totals[NB_BATCH_TILES] = {};
         for (int q = 0; q < nsys; ++q) {
-            int c[6];
+            int c[NB_BATCH_TILES];
             nb_batch_tiles(hn[q], c);
-            for (int k = 0; k < 6; ++k) {
+            for (int k = 0; k < NB_BATCH_TILES; ++k) {
                 hstart[k * (nsys + 1) + q] = totals[k];
                 totals[k] += c[k];
             }
         }
-        for (int k = 0; k < 6; ++k) hstart[k * (nsys + 1) + nsys] = totals[k];
+        for (int k = 0; k < NB_BATCH_TILES; ++k) hstart[k * (nsys + 1) + nsys] = totals[k];
         HIPCHK(hipMemcpyAsync(at<char>(ws, BL.nbargs), hn, sizeof(NbArgs) * nsys, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(at<char>(ws, BL.nbstart), hstart, sizeof(int) * 6 * (nsys + 1),
+        HIPCHK(hipMemcpyAsync(at<char>(ws, BL.nbstart), hstart, sizeof(int) * NB_BATCH_TILES * (nsys + 1),
                               hipMemcpyHostToDevice, st));
         NbBatchArgs nbb{nsys, at<NbArgs>(ws, BL.nbargs), at<int>(ws, BL.nbstart)};
         HIPCHK(launch_build_batch(nbb, totals, st));

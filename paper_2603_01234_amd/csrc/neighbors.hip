@@ -253,7 +253,11 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
         }
     }
     const float cs[3] = {1.0f / a.inv_cs[0], 1.0f / a.inv_cs[1], 1.0f / a.inv_cs[2]};
-    int na = 0, nb = 0;  // angular from the front, radial-only from the back
+    // four stacks in the row: angular inside r_c^A up from 0, angular shell
+    // down from cap_A - 1, radial-only inside r_c^R up from cap_A, radial
+    // shell down from cap_A + cap - 1.  Kept in this class order, the rows let
+    // the lanes of a wave find their in-cutoff pairs in the same slots.
+    int nai = 0, nas = 0, nri = 0, nrs = 0;
     int flags = 0;
     int off = 0;         // cell-offset index in (dz, dy, dx) order
     for (int dz = -a.m[2]; dz <= a.m[2]; ++dz) {
@@ -265,7 +269,8 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
             const bool vy = wrap_cell(c0[1] + dy, a.nc[1], a.pbc[1], ky, iy);
             const float gy = cell_gap(dy, u[1]) * cs[1];
             for (int dx = -a.m[0]; dx <= a.m[0]; ++dx) {
-                a.segA[(size_t)(off++) * n + i] = (uint8_t)(na < 255 ? na : 255);
+                a.segA[(size_t)off * n + i] = (uint8_t)(nai < 255 ? nai : 255);
+                a.segS[(size_t)(off++) * n + i] = (uint8_t)(nas < 255 ? nas : 255);
                 int kx, ix;
                 const bool vx = wrap_cell(c0[0] + dx, a.nc[0], a.pbc[0], kx, ix);
                 if (!(vx && vy && vz)) continue;
@@ -302,26 +307,38 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
                     if (!(d2 < a.list2R[tp])) continue;
                     if (d2 == 0.0f) flags |= NEP_FLAG_OVERLAP;
                     const uint32_t entry = (uint32_t)j | (code << CODE_SHIFT);
-                    uint32_t *row = a.rowbuf + (size_t)i * a.cap;
+                    uint32_t *row = a.rowbuf + (size_t)i * (a.cap_A + a.cap);
+                    const int na = nai + nas, nb = nri + nrs;
                     if (d2 < a.list2A[tp]) {
-                        if (na < a.cap_A && na + nb < a.cap) row[na] = entry;
-                        ++na;
+                        if (na < a.cap_A && na + nb < a.cap) {
+                            if (d2 < a.in2A[tp]) row[nai] = entry;
+                            else row[a.cap_A - 1 - nas] = entry;
+                        }
+                        if (d2 < a.in2A[tp]) ++nai;
+                        else ++nas;
                     } else {
-                        if (na + nb < a.cap) row[a.cap - 1 - nb] = entry;
-                        ++nb;
+                        if (na + nb < a.cap) {
+                            if (d2 < a.in2R[tp]) row[a.cap_A + nri] = entry;
+                            else row[a.cap_A + a.cap - 1 - nrs] = entry;
+                        }
+                        if (d2 < a.in2R[tp]) ++nri;
+                        else ++nrs;
                     }
                     }
                 }
             }
         }
     }
-    a.segA[(size_t)off * n + i] = (uint8_t)(na < 255 ? na : 255);
-    const int total = na + nb;
+    a.segA[(size_t)off * n + i] = (uint8_t)(nai < 255 ? nai : 255);
+    a.segS[(size_t)off * n + i] = (uint8_t)(nas < 255 ? nas : 255);
+    const int na = nai + nas;
+    const int total = na + nri + nrs;
     if (na > a.cap_A) flags |= NEP_FLAG_OVERFLOW_A;
     if (total > a.cap) flags |= NEP_FLAG_OVERFLOW_R;
     const bool over = (flags & (NEP_FLAG_OVERFLOW_A | NEP_FLAG_OVERFLOW_R)) != 0;
     a.cnt[i] = over ? 0 : total;
     a.cnt[n + i] = over ? 0 : na;
+    a.cls[i] = over ? 0 : (min(nai, 255) | (nri << 8));
     flags_out = flags;
     total_out = total;
     na_out = na;
@@ -347,9 +364,17 @@ __device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int g
     const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int total = a.cnt[i], na = a.cnt[n + i];
-    const uint32_t *row = a.rowbuf + (size_t)i * a.cap;
+    const int nai = a.cls[i] & 255, nri = a.cls[i] >> 8;
+    const uint32_t *row = a.rowbuf + (size_t)i * (a.cap_A + a.cap);
     // one slot per iteration for every lane, so each store covers consecutive beads
-    for (int p = 0; p < total; ++p) a.nbr[(size_t)p * n + i] = row[p < na ? p : a.cap - 1 - (p - na)];
+    for (int p = 0; p < total; ++p) {
+        int src;
+        if (p < nai) src = p;                                           // inside r_c^A
+        else if (p < na) src = a.cap_A - 1 - (p - nai);                 // angular shell
+        else if (p < na + nri) src = a.cap_A + (p - na);                // inside r_c^R
+        else src = a.cap_A + a.cap - 1 - (p - na - nri);                // radial shell
+        a.nbr[(size_t)p * n + i] = row[src];
+    }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_nb_transpose(NbArgs a) { nb_transpose_body(a, blockIdx.x, gridDim.x); }
@@ -373,12 +398,20 @@ __device__ __forceinline__ void reverse_one(const NbArgs &a, int i, int p) {
     int found = -1;
     if (o >= 0 && o < a.n_off) {
         const int om = a.n_off - 1 - o;
+        // the mirrored offset's entries inside r_c^A, then its shell entries;
         // never past the neighbour's valid angular prefix (0 after an overflow)
         const int naj = a.cnt[n + j];
-        const int qs = min((int)a.segA[(size_t)om * n + j], naj);
-        const int qe = min((int)a.segA[(size_t)(om + 1) * n + j], naj);
+        const int naij = min(a.cls[j] & 255, naj);
+        int qs = min((int)a.segA[(size_t)om * n + j], naij);
+        int qe = min((int)a.segA[(size_t)(om + 1) * n + j], naij);
         for (int q = qs; q < qe; ++q)
             if (a.nbr[(size_t)q * n + j] == want) { found = q; break; }
+        if (found < 0) {
+            qs = min(naij + (int)a.segS[(size_t)om * n + j], naj);
+            qe = min(naij + (int)a.segS[(size_t)(om + 1) * n + j], naj);
+            for (int q = qs; q < qe; ++q)
+                if (a.nbr[(size_t)q * n + j] == want) { found = q; break; }
+        }
     }
     a.rev[(size_t)p * n + i] = found < 0 ? -1 : (int32_t)((size_t)found * n + j);
 }
@@ -401,6 +434,51 @@ __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
     nb_reverse_body(a, blockIdx.x, gridDim.x, blockIdx.y, gridDim.y);
 }
 
+// Processing order of the fused kernel.  Its cost per bead grows with the
+// row lengths (an angular entry costs several radial ones), and a wave takes
+// as long as its busiest lane, so within every block of ORDER_B consecutive
+// beads (neighbours in space for a spatially ordered system) the beads are
+// ordered by decreasing cost: the lanes of a wave then carry similar work.
+// The order only decides which thread evaluates which bead; every result is
+// the same bit for bit.
+#ifndef NEP_ORDER_B
+#define NEP_ORDER_B 256
+#endif
+constexpr int ORDER_B = NEP_ORDER_B > 0 ? NEP_ORDER_B : 1;
+constexpr int ORDER_T = 1024;  // threads per block of the order kernel
+constexpr int ORDER_KEYS = 1024;
+
+__device__ __forceinline__ int order_key(const NbArgs &a, int i) {
+    const int k = (6 * a.cnt[a.n + i] + a.cnt[i]) >> 2;
+    return ORDER_KEYS - 1 - min(k, ORDER_KEYS - 1);  // ascending key = decreasing cost
+}
+
+__device__ __forceinline__ void nb_order_body(const NbArgs &a, int bx) {
+    if (build_off(a) || !a.order) return;
+    __shared__ int hist[ORDER_KEYS];
+    const int base = bx * ORDER_B;
+    const int len = min(ORDER_B, a.n - base);
+    for (int k = threadIdx.x; k < ORDER_KEYS; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < len; q += blockDim.x) atomicAdd(&hist[order_key(a, base + q)], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {  // exclusive scan of 1024 bins (short, once per block)
+        int run = 0;
+        for (int k = 0; k < ORDER_KEYS; ++k) {
+            const int v = hist[k];
+            hist[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < len; q += blockDim.x) {
+        const int i = base + q;
+        a.order[base + atomicAdd(&hist[order_key(a, i)], 1)] = i;
+    }
+}
+
+__global__ __launch_bounds__(ORDER_T) void k_nb_order(NbArgs a) { nb_order_body(a, blockIdx.x); }
+
 hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     int nbk = (a.n + BLOCK - 1) / BLOCK;
     int cbk = (a.ncell + BLOCK - 1) / BLOCK;
@@ -417,16 +495,20 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_nb_rows, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_transpose, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_reverse, dim3(nbk, (a.cap_A + REV_SLOTS - 1) / REV_SLOTS), dim3(BLOCK), 0, s, a);
+    if (a.order && NEP_ORDER_B > 0)
+        hipLaunchKernelGGL(k_nb_order, dim3((a.n + ORDER_B - 1) / ORDER_B), dim3(ORDER_T), 0, s, a);
     return hipGetLastError();
 }
+
 
 
 // ---- one launch per phase over the builds of many systems ----
 // start[ph][r] is the first block of system r in phase ph (tables of
 // n_sys + 1 entries, one per tile kind: cells to clear, beads, scan blocks,
-// the one-block scan, cells to offset, and (bead, slot-group) pairs).
-enum { NB_TILE_CLEAR = 0, NB_TILE_BEAD, NB_TILE_SCANL, NB_TILE_SCANB, NB_TILE_SCANA, NB_TILE_REV, NB_TILES };
-enum { OP_CLEAR, OP_BIN, OP_SCANL, OP_SCANB, OP_SCANA, OP_FILL, OP_RANK, OP_ROWS, OP_TRANSPOSE, OP_REVERSE };
+// the one-block scan, cells to offset, (bead, slot-group) pairs, and blocks of
+// the processing order).
+enum { NB_TILE_CLEAR = 0, NB_TILE_BEAD, NB_TILE_SCANL, NB_TILE_SCANB, NB_TILE_SCANA, NB_TILE_REV, NB_TILE_ORDER, NB_TILES };
+enum { OP_CLEAR, OP_BIN, OP_SCANL, OP_SCANB, OP_SCANA, OP_FILL, OP_RANK, OP_ROWS, OP_TRANSPOSE, OP_REVERSE, OP_ORDER };
 
 template <int OP>
 __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
@@ -435,6 +517,7 @@ __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
                          : OP == OP_SCANB ? NB_TILE_SCANB
                          : OP == OP_SCANA ? NB_TILE_SCANA
                          : OP == OP_REVERSE ? NB_TILE_REV
+                         : OP == OP_ORDER   ? NB_TILE_ORDER
                                             : NB_TILE_BEAD;
     const int *st = b.start + TILE * (b.n_sys + 1);
     int lo = 0, hi = b.n_sys - 1;  // last system whose first block is <= blockIdx.x
@@ -458,9 +541,10 @@ __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
         const int nbk = (a.n + BLOCK - 1) / BLOCK;
         nb_reverse_body(a, bx % nbk, nbk, bx / nbk, gx / nbk);
     }
+    if constexpr (OP == OP_ORDER) nb_order_body(a, bx);
 }
 
-void nb_batch_tiles(const NbArgs &a, int counts[6]) {
+void nb_batch_tiles(const NbArgs &a, int counts[NB_BATCH_TILES]) {
     const int nbk = (a.n + BLOCK - 1) / BLOCK;
     const int cbk = (a.ncell + BLOCK - 1) / BLOCK;
     counts[NB_TILE_CLEAR] = cbk > 0 ? (cbk < 4096 ? cbk : 4096) : 1;
@@ -469,9 +553,10 @@ void nb_batch_tiles(const NbArgs &a, int counts[6]) {
     counts[NB_TILE_SCANB] = 1;
     counts[NB_TILE_SCANA] = cbk;
     counts[NB_TILE_REV] = nbk * ((a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
+    counts[NB_TILE_ORDER] = a.order ? (a.n + ORDER_B - 1) / ORDER_B : 0;
 }
 
-hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[6], hipStream_t s) {
+hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[NB_BATCH_TILES], hipStream_t s) {
     if (b.n_sys == 0) return hipSuccess;
 #define NB_LAUNCH(OPC, TILEK)                                                                     \
     if (totals[TILEK] > 0) hipLaunchKernelGGL(k_nb_batch<OPC>, dim3(totals[TILEK]), dim3(BLOCK), 0, s, b);
@@ -485,6 +570,7 @@ hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[6], hipStre
     NB_LAUNCH(OP_ROWS, NB_TILE_BEAD)
     NB_LAUNCH(OP_TRANSPOSE, NB_TILE_BEAD)
     NB_LAUNCH(OP_REVERSE, NB_TILE_REV)
+    NB_LAUNCH(OP_ORDER, NB_TILE_ORDER)
 #undef NB_LAUNCH
     return hipGetLastError();
 }

@@ -65,6 +65,7 @@ struct EfvArgs {
                             // the neighbour i listed at slot q of row j
     float4 *fown;           // [n] sum_j dU_i/dr_ij (angular)
     const int32_t *freeze;  // MD: status word; the kernel does nothing once FREEZE_MASK is set
+    const int32_t *order;   // [n] bead of each thread (null: thread i takes bead i)
 };
 
 struct GatherArgs {
@@ -266,6 +267,7 @@ struct NbArgs {
     int nc[3], m[3];
     float inv_cs[3];
     float list2R[MAXT * MAXT], list2A[MAXT * MAXT];
+    float in2R[MAXT * MAXT], in2A[MAXT * MAXT];  // squared interaction cutoffs (row classes)
     int T;
     const float *x, *y, *z;
     float *x_mut, *y_mut, *z_mut;  // same arrays, written only when wrap is set
@@ -274,11 +276,14 @@ struct NbArgs {
     int32_t *cell_id, *cell_count, *cell_start, *cell_cursor, *cell_list, *scan_tmp;
     int32_t *cell_tmp;   // [n] cell members in atomic (arbitrary) order
     float4 *pos_sorted;  // [n] positions in cell order; w = bits of (index | type << 25)
-    uint8_t *segA;       // [n_off + 1][n] angular-prefix length before each cell offset
+    uint8_t *segA;       // [n_off + 1][n] entries inside r_c^A before each cell offset
+    uint8_t *segS;       // [n_off + 1][n] angular skin-shell entries before each cell offset
+    int32_t *cls;        // [n] entries inside r_c^A | entries inside r_c^R (radial-only) << 8
     int n_off;           // (2 m_x + 1)(2 m_y + 1)(2 m_z + 1)
     float cull2;         // cells whose gap exceeds this squared distance are skipped
-    uint32_t *rowbuf;    // [n][cap] rows built row-major (angular from the front,
-                         // radial-only from the back), then transposed into nbr
+    uint32_t *rowbuf;    // [n][cap_A + cap] rows built row-major in four stacks (angular inside
+                         // r_c^A, angular shell, radial inside r_c^R, radial shell), then
+                         // transposed into nbr in that class order
     uint32_t *nbr;
     int32_t *rev, *cnt;
     float *ref;
@@ -288,19 +293,21 @@ struct NbArgs {
     int ncell;
     int clear_status;  // 1: a fresh build resets the status word
     int wrap;          // 1: wrap periodic coordinates into [0, L) and write them back first
+    int32_t *order;    // [n] or null: processing order for the fused kernel, written from the row counts
     int from_pos4;     // 1 (MD): positions come from pos4 and are wrapped there, x/y/z are untouched
 };
 hipError_t launch_build(const NbArgs &a, hipStream_t s);
 // Builds of many systems, one launch per phase: args[r] as for launch_build
-// (systems with n > 0); start holds the six tables of first blocks written by
+// (systems with n > 0); start holds the tables of first blocks written by
 // the caller from nb_batch_tiles; totals are the last entries of the tables.
+constexpr int NB_BATCH_TILES = 7;
 struct NbBatchArgs {
     int n_sys;
     const NbArgs *args;
-    const int *start;     // [6][n_sys + 1]
+    const int *start;     // [NB_BATCH_TILES][n_sys + 1]
 };
-void nb_batch_tiles(const NbArgs &a, int counts[6]);
-hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[6], hipStream_t s);
+void nb_batch_tiles(const NbArgs &a, int counts[NB_BATCH_TILES]);
+hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[NB_BATCH_TILES], hipStream_t s);
 
 // zeroes the status word and, when given, the MD control words [4] (the
 // rebuild gate ctrl[0] is set to gate0)
