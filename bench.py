@@ -59,7 +59,7 @@ def pair_counts(rep, spec):
     """Neighbours within r_c (not r_c + skin) per bead, from the device lists."""
     from paper_2603_01234_amd.engine import decode_row
     nbr, cnt = rep.neighbor_rows()
-    pos = rep.positions().astype(np.float64)
+    pos = rep.positions(internal=True).astype(np.float64)
     box = np.asarray(rep.box, np.float64)
     n = rep.n
     nR = np.zeros(n, np.int64)
@@ -315,6 +315,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sort-every", type=int, default=100,
+                    help="put the beads back into cell order every so many MD steps (0: never)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fitness leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -339,7 +341,7 @@ def main():
     masses = [W.WATER_MASS]
     dt, every = opts["dt"], opts["rebuild_every"]
     if args.warmup:
-        rep.md(args.warmup, dt, masses, rebuild_every=every)
+        rep.md(args.warmup, dt, masses, rebuild_every=every, sort_every=args.sort_every)
     torch.cuda.synchronize()
     nR, nA = pair_counts(rep, spec)          # neighbours within the cutoffs at the start of the timed run
     print(f"bench: N={system.n}, mean neighbours within r_c: radial {nR.mean():.2f}, angular {nA.mean():.2f}",
@@ -359,7 +361,7 @@ def main():
     t0 = time.perf_counter()
     ev0.record()
     rb0 = rep.n_rebuilds
-    rep.md(K, dt, masses, rebuild_every=every, pair_counts=counts)
+    rep.md(K, dt, masses, rebuild_every=every, pair_counts=counts, sort_every=args.sort_every)
     rebuilds = rep.n_rebuilds - rb0
     ev1.record()
     torch.cuda.synchronize()
@@ -373,7 +375,7 @@ def main():
     rb1 = rep.n_rebuilds
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    rep.md(K2, dt, masses, rebuild_every=every)
+    rep.md(K2, dt, masses, rebuild_every=every, sort_every=args.sort_every)
     torch.cuda.synchronize()
     split_ms_step = (time.perf_counter() - t1) * 1e3 / K2
     ms_all, launches_all = B.nep_timing_end()
@@ -412,6 +414,7 @@ def main():
                    "mean_neighbours_radial_run": round(tot_R / (K * system.n), 3),
                    "mean_neighbours_angular_run": round(tot_A / (K * system.n), 3),
                    "row_capacity": [rep.cap, rep.cap_A],
+                   "sort_every": args.sort_every,
                    "rebuilds_in_timed_steps": rebuilds,
                    "F_alg_per_bead_step": round(F_alg_bead, 1),
                    "path_tflops_alg": round(value * F_alg_bead / 1e12, 3)},

@@ -152,6 +152,19 @@ size_t nep_workspace_bytes(nep_model model, int n, int cap, int cap_A);
 int nep_build_neighbors(nep_model model, nep_system *sys, nep_neighbors *nbrs, int wrap,
                         void *ws, size_t ws_bytes, void *stream);
 
+/* Reorders the beads of a system in place into the cell order of the
+ * neighbour build, so that beads near in space are near in memory again after
+ * they have diffused (the lists, the fused kernel and the gather all read
+ * neighbours' data by index).  x, y, z and type are permuted together with v,
+ * F and U (device arrays as in nep_md_step, each may be NULL) and with perm
+ * (device int32 [n] or NULL): new position s receives the bead that was at
+ * position src(s), and perm[s] keeps naming that bead's index in the
+ * caller's original numbering.  sys->type is written (it must be writable).
+ * Periodic coordinates are wrapped first; the lists are rebuilt for the new
+ * order.  Returns like nep_build_neighbors (synchronises the stream). */
+int nep_sort_system(nep_model model, nep_system *sys, float *v, float *F, float *U, int32_t *perm,
+                    nep_neighbors *nbrs, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* energy / force / virial (Eqs. 2-8, 15-16)                                 */
 /* ------------------------------------------------------------------------ */

@@ -41,7 +41,8 @@ FLAG_NONFINITE, FLAG_OUTSIDE_BOX, FLAG_OVERLAP, FLAG_IMAGE_RANGE = 8, 16, 32, 64
 EXPORTS = ["nep_param_count", "nep_model_create", "nep_model_destroy", "nep_workspace_bytes",
            "nep_build_neighbors", "nep_compute_efv", "nep_md_step", "nep_check_status",
            "nep_last_error", "nep_timing_begin", "nep_timing_end", "nep_batch_workspace_bytes",
-           "nep_compute_efv_batch", "nep_batch_autotune", "nep_md_batch_workspace_bytes", "nep_md_step_batch"]
+           "nep_compute_efv_batch", "nep_batch_autotune", "nep_md_batch_workspace_bytes", "nep_md_step_batch",
+           "nep_sort_system"]
 
 
 class NepError(RuntimeError):
@@ -135,6 +136,9 @@ def lib():
         L.nep_md_step_batch.argtypes = [c_void_p, POINTER(Replica), c_int, c_float, POINTER(c_float), c_int,
                                         c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
         L.nep_md_step_batch.restype = c_int
+        L.nep_sort_system.argtypes = [c_void_p, POINTER(System), c_void_p, c_void_p, c_void_p, c_void_p,
+                                      POINTER(Neighbors), c_void_p, c_size_t, c_void_p]
+        L.nep_sort_system.restype = c_int
         L.nep_last_error.argtypes = []
         L.nep_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -260,3 +264,7 @@ def nep_md_step_batch(model, reps, dt: float, masses, rebuild_every: int, E_pot,
     m = (c_float * 4)(*[float(masses[t]) if t < len(masses) else 1.0 for t in range(4)])
     return lib().nep_md_step_batch(model, reps, len(reps), float(dt), m, int(rebuild_every), E_pot, E_kin,
                                    ws_ptr, ws_bytes, stream)
+
+
+def nep_sort_system(model, sys: System, v, F, U, perm, nb: Neighbors, ws_ptr, ws_bytes, stream) -> int:
+    return lib().nep_sort_system(model, ctypes.byref(sys), v, F, U, perm, ctypes.byref(nb), ws_ptr, ws_bytes, stream)

@@ -743,6 +743,41 @@ int nep_build_neighbors(nep_model model, nep_system *s, nep_neighbors *nb, int w
     return read_status(nb, nullptr, st);
 }
 
+int nep_sort_system(nep_model model, nep_system *s, float *v, float *F, float *U, int32_t *perm,
+                    nep_neighbors *nb, void *ws, size_t ws_bytes, void *stream) {
+    int rc;
+    if ((rc = check_model(model))) return rc;
+    const Model &M = model->m;
+    if ((rc = check_system(M, s))) return rc;
+    if ((rc = check_nbrs(s, nb))) return rc;
+    WsLayout L;
+    if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
+    if (s->n == 0) return NEP_OK;
+    if (nb->cap + nb->cap_A < 12) return fail(NEP_ERR_ARG, "cap + cap_A must be at least 12 to stage the reorder");
+    hipStream_t st = (hipStream_t)stream;
+    NbArgs a;
+    // the build's cell order (cells in grid order, beads by index inside a cell)
+    if ((rc = fill_nb(M, s, nb, ws, L, 1, 1, a))) return rc;
+    HIPCHK(launch_build(a, st));
+    PermuteArgs p{};
+    p.n = s->n;
+    p.src = at<int32_t>(ws, L.cell_list);
+    p.x = s->x;
+    p.y = s->y;
+    p.z = s->z;
+    p.type = const_cast<uint8_t *>(s->type);
+    p.v = v;
+    p.F = F;
+    p.U = U;
+    p.perm = perm;
+    p.tmp = at<float>(ws, L.rowbuf);  // free once the build above has run
+    HIPCHK(launch_permute(p, st));
+    // lists for the new order
+    if ((rc = fill_nb(M, s, nb, ws, L, 1, 0, a))) return rc;
+    HIPCHK(launch_build(a, st));
+    return read_status(nb, nullptr, st);
+}
+
 int nep_compute_efv(nep_model model, const nep_system *s, const nep_neighbors *nb, float *U, float *F,
                     float *W, double *E_tot, double *W_tot, void *ws, size_t ws_bytes, void *stream) {
     int rc;

@@ -27,4 +27,51 @@ hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+
+// Gathers every per-bead array into the order given by src through the
+// staging area, then writes it back in place.
+
+__global__ void k_permute_gather(PermuteArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n) return;
+    const int n = a.n;
+    const int i = a.src[s];
+    float *t = a.tmp;
+    t[s] = a.x[i];
+    t[n + s] = a.y[i];
+    t[2 * n + s] = a.z[i];
+    for (int d = 0; d < 3; ++d) {
+        if (a.v) t[(3 + d) * (size_t)n + s] = a.v[(size_t)d * n + i];
+        if (a.F) t[(6 + d) * (size_t)n + s] = a.F[(size_t)d * n + i];
+    }
+    if (a.U) t[9 * (size_t)n + s] = a.U[i];
+    if (a.perm) reinterpret_cast<int32_t *>(t)[10 * (size_t)n + s] = a.perm[i];
+    reinterpret_cast<uint8_t *>(t + 11 * (size_t)n)[s] = a.type[i];
+}
+
+__global__ void k_permute_scatter(PermuteArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n) return;
+    const int n = a.n;
+    const float *t = a.tmp;
+    a.x[s] = t[s];
+    a.y[s] = t[n + s];
+    a.z[s] = t[2 * n + s];
+    for (int d = 0; d < 3; ++d) {
+        if (a.v) a.v[(size_t)d * n + s] = t[(3 + d) * (size_t)n + s];
+        if (a.F) a.F[(size_t)d * n + s] = t[(6 + d) * (size_t)n + s];
+    }
+    if (a.U) a.U[s] = t[9 * (size_t)n + s];
+    if (a.perm) a.perm[s] = reinterpret_cast<const int32_t *>(t)[10 * (size_t)n + s];
+    a.type[s] = reinterpret_cast<const uint8_t *>(t + 11 * (size_t)n)[s];
+}
+
+hipError_t launch_permute(const PermuteArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    const dim3 g((a.n + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_permute_gather, g, dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_permute_scatter, g, dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace nep

@@ -433,4 +433,18 @@ hipError_t launch_kick_drift_batch(const MdBatchArgs &b, hipStream_t s);
 // fused kernel, gather (second half-kick) and per-replica energy sums
 hipError_t launch_efv_md_batch(int T, int HP, const MdBatchArgs &b, hipStream_t s);
 
+
+// In-place reordering of a system's per-bead arrays: new position s takes old
+// bead src[s] for x, y, z, type and, when given, v, F, U and perm.
+struct PermuteArgs {
+    int n;
+    const int32_t *src;
+    float *x, *y, *z;
+    uint8_t *type;
+    float *v, *F, *U;   // [3][n], [3][n], [n] or null
+    int32_t *perm;      // [n] or null
+    float *tmp;         // [12][n] floats and [n] bytes
+};
+hipError_t launch_permute(const PermuteArgs &a, hipStream_t s);
+
 }  // namespace nep

@@ -113,6 +113,7 @@ class Replica:
         self.step = 0
         self.n_rebuilds = 0
         self.lists_valid = False
+        self.perm = None   # after sort(): original index of the bead at each position
 
     # -- buffers ----------------------------------------------------------------
     def _alloc_lists(self, cap, cap_A):
@@ -182,13 +183,47 @@ class Replica:
                                   self.ws.data_ptr(), self.ws_bytes, _stream()))
         return self
 
+    def sort(self):
+        """nep_sort_system: beads back into cell order (with v, F, U and the
+        permutation); the host views below keep the original numbering."""
+        if self.n == 0:
+            return self
+        if self.perm is None:
+            self.perm = torch.arange(self.n, dtype=torch.int32, device=self.device)
+        for _ in range(4):
+            s, nb = self.c_system(), self.c_neighbors()
+            code = B.nep_sort_system(self.model.handle, s, _ptr(self.v), _ptr(self.F), _ptr(self.U),
+                                     _ptr(self.perm), nb, self.ws.data_ptr(), self.ws_bytes, _stream())
+            if code == B.NEP_ERR_NEIGHBOR_OVERFLOW:
+                st = self.status.cpu().tolist()
+                self._alloc_lists(max(self.cap, int(st[1] * 1.2) + 8), max(self.cap_A, int(st[2] * 1.2) + 8))
+                self.build(wrap=False)
+                return self
+            B.check(code)
+            self.lists_valid = True
+            return self
+        return self
+
     def md(self, n_steps: int, dt: float, masses: Sequence[float], rebuild_every: int = 10,
            strain_rate=(0.0, 0.0, 0.0), E_pot: Optional[torch.Tensor] = None,
            E_kin: Optional[torch.Tensor] = None,
-           pair_counts: Optional[torch.Tensor] = None, regrow: bool = True):
+           pair_counts: Optional[torch.Tensor] = None, regrow: bool = True, sort_every: int = 0):
         """nep_md_step; after a rebuild overflow the rows are regrown and the
         remaining steps resumed with a forced rebuild (x, v, F are those of the
-        last completed step, so the trajectory continues unchanged)."""
+        last completed step, so the trajectory continues unchanged).  With
+        sort_every > 0 the beads are put back into cell order (sort()) every
+        sort_every steps."""
+        if sort_every and sort_every > 0:
+            done = 0
+            while done < n_steps:
+                k = min(int(sort_every), n_steps - done)
+                self.md(k, dt, masses, rebuild_every, strain_rate,
+                        None if E_pot is None else E_pot[done:], None if E_kin is None else E_kin[done:],
+                        pair_counts, regrow, 0)
+                done += k
+                if done < n_steps:
+                    self.sort()
+            return self
         if not self.lists_valid:
             self.build()
         remaining = int(n_steps)
@@ -230,21 +265,28 @@ class Replica:
             B.check(code)
             return self
 
-    # -- host views ---------------------------------------------------------------
-    def positions(self) -> np.ndarray:
-        return self.xyz[:, :self.n].T.contiguous().cpu().numpy()
+    # -- host views (original numbering unless internal=True) ---------------------
+    def _unperm(self, a: np.ndarray, internal: bool) -> np.ndarray:
+        if internal or self.perm is None:
+            return a
+        out = np.empty_like(a)
+        out[self.perm.cpu().numpy()] = a
+        return out
 
-    def forces(self) -> np.ndarray:
-        return self.F[:, :self.n].T.contiguous().cpu().numpy()
+    def positions(self, internal: bool = False) -> np.ndarray:
+        return self._unperm(self.xyz[:, :self.n].T.contiguous().cpu().numpy(), internal)
 
-    def velocities(self) -> np.ndarray:
-        return self.v[:, :self.n].T.contiguous().cpu().numpy()
+    def forces(self, internal: bool = False) -> np.ndarray:
+        return self._unperm(self.F[:, :self.n].T.contiguous().cpu().numpy(), internal)
 
-    def site_energies(self) -> np.ndarray:
-        return self.U[:self.n].cpu().numpy()
+    def velocities(self, internal: bool = False) -> np.ndarray:
+        return self._unperm(self.v[:, :self.n].T.contiguous().cpu().numpy(), internal)
 
-    def virials(self) -> np.ndarray:
-        return self.W[:, :self.n].T.contiguous().cpu().numpy().reshape(-1, 3, 3)
+    def site_energies(self, internal: bool = False) -> np.ndarray:
+        return self._unperm(self.U[:self.n].cpu().numpy(), internal)
+
+    def virials(self, internal: bool = False) -> np.ndarray:
+        return self._unperm(self.W[:, :self.n].T.contiguous().cpu().numpy().reshape(-1, 3, 3), internal)
 
     def neighbor_rows(self):
         """Host copy of the lists: (entries [cap, n] uint32, counts [2, n])."""

@@ -166,3 +166,31 @@ def test_overflow_freezes_then_resumes_bitwise():
     print("caps after regrow:", runs[1][3])
     for a, b in zip(runs[0][:3], runs[1][:3]):
         assert torch.equal(a, b)
+
+
+def test_sort_reorders_in_place_and_keeps_the_physics():
+    """nep_sort_system: a permutation of the beads (x, v, F, type and the
+    numbering move together), cell order inside, the same forces after a fresh
+    evaluation, and an MD run that sorts every few steps still matches the
+    oracle in the original numbering."""
+    from gpu_helpers import rel_rms
+    spec, params, system, opts = W.config1()
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv(per_bead_virial=False)
+    x0, v0, F0 = rep.positions(), rep.velocities(), rep.forces()
+    rep.sort()
+    perm = rep.perm.cpu().numpy()
+    assert np.array_equal(np.sort(perm), np.arange(system.n))
+    assert np.array_equal(rep.positions(), x0) and np.array_equal(rep.velocities(), v0)
+    assert np.array_equal(rep.forces(), F0)
+    assert np.array_equal(rep.type[:system.n].cpu().numpy(), system.types[perm])
+    xi = rep.positions(internal=True)
+    step = np.linalg.norm(np.diff(xi, axis=0), axis=1)
+    assert np.median(step) < 0.6, "consecutive beads are not neighbours in space"
+    rep.efv(per_bead_virial=False)
+    assert rel_rms(rep.forces(), F0) < 1e-6
+    rep.md(20, opts["dt"], [W.WATER_MASS], rebuild_every=10, sort_every=7)
+    targets = np.random.default_rng(6).choice(system.n, 150, replace=False)
+    ref = oracle.efv(spec, params.astype(np.float32).astype(np.float64), rep.positions().astype(np.float64),
+                     system.types, system.box.astype(np.float32).astype(np.float64), system.pbc, targets=targets)
+    compare_efv(rep, ref, system.n, check_virial=False, targets=targets, label="sorted-md20")
