@@ -94,7 +94,8 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.segA = take(nn * (size_t)(MAX_OFF + 1));
     L.segS = take(nn * (size_t)(MAX_OFF + 1));
     L.cls = take(nn * 4);
-    L.rowbuf = take(nn * (size_t)(std::max(cap, 1) + std::max(cap_A, 1)) * 4);
+    // row stride: both regions padded to whole 16-byte groups
+    L.rowbuf = take(nn * (size_t)(((std::max(cap, 1) + 3) & ~3) + ((std::max(cap_A, 1) + 3) & ~3)) * 4);
     L.vh = take(nn * 12);
     L.order = take(nn * 4);
     L.ctrl = take(4 * sizeof(int32_t));

@@ -236,6 +236,39 @@ __device__ __forceinline__ float cell_gap(int off, float u) {
     return off > 0 ? (float)off - u : (off < 0 ? (float)(-off - 1) + u : 0.0f);
 }
 
+// One of the four stacks of a row under construction.  Entries are kept in
+// registers four at a time and written as one aligned 16-byte store (the rows
+// of a wave lie far apart, so single 4-byte stores would each take a memory
+// transaction); a stack that grows downwards stores its groups reversed.
+// Groups that would leave the stack's region are dropped: the row then
+// overflows and is discarded anyway.
+struct RowStack {
+    uint32_t b0, b1, b2, b3;  // the last four entries, oldest first
+    int cnt;
+    __device__ __forceinline__ void push(uint32_t e, uint32_t *row, int base, int limit, bool down) {
+        b0 = b1;
+        b1 = b2;
+        b2 = b3;
+        b3 = e;
+        ++cnt;
+        if ((cnt & 3) != 0 || cnt > limit) return;
+        if (!down) *reinterpret_cast<uint4 *>(row + base + cnt - 4) = make_uint4(b0, b1, b2, b3);
+        else *reinterpret_cast<uint4 *>(row + base - cnt + 1) = make_uint4(b3, b2, b1, b0);
+    }
+    // the entries of the last, incomplete group
+    __device__ __forceinline__ void finish(uint32_t *row, int base, int limit, bool down) {
+        const int r = cnt & 3;
+        const uint32_t last[4] = {b0, b1, b2, b3};
+#pragma unroll
+        for (int q = 1; q <= 3; ++q) {
+            if (q > r) break;
+            const int k = cnt - q;  // insertion index of entry last[4 - q]
+            if (k >= limit) continue;
+            row[down ? base - k : base + k] = last[4 - q];
+        }
+    }
+};
+
 // the row of bead i; returns its flags, length and angular length
 __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &flags_out, int &total_out,
                                           int &na_out) {
@@ -257,7 +290,9 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
     // down from cap_A - 1, radial-only inside r_c^R up from cap_A, radial
     // shell down from cap_A + cap - 1.  Kept in this class order, the rows let
     // the lanes of a wave find their in-cutoff pairs in the same slots.
-    int nai = 0, nas = 0, nri = 0, nrs = 0;
+    const int A4 = (a.cap_A + 3) & ~3, R4 = (a.cap + 3) & ~3;
+    uint32_t *row = a.rowbuf + (size_t)i * (A4 + R4);
+    RowStack sai{0u, 0u, 0u, 0u, 0}, sas{0u, 0u, 0u, 0u, 0}, sri{0u, 0u, 0u, 0u, 0}, srs{0u, 0u, 0u, 0u, 0};
     int flags = 0;
     int off = 0;         // cell-offset index in (dz, dy, dx) order
     for (int dz = -a.m[2]; dz <= a.m[2]; ++dz) {
@@ -268,15 +303,40 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
             int ky, iy;
             const bool vy = wrap_cell(c0[1] + dy, a.nc[1], a.pbc[1], ky, iy);
             const float gy = cell_gap(dy, u[1]) * cs[1];
-            for (int dx = -a.m[0]; dx <= a.m[0]; ++dx) {
-                a.segA[(size_t)off * n + i] = (uint8_t)(nai < 255 ? nai : 255);
-                a.segS[(size_t)(off++) * n + i] = (uint8_t)(nas < 255 ? nas : 255);
-                int kx, ix;
-                const bool vx = wrap_cell(c0[0] + dx, a.nc[0], a.pbc[0], kx, ix);
-                if (!(vx && vy && vz)) continue;
-                const float gx = cell_gap(dx, u[0]) * cs[0];
-                // skip cells entirely beyond reach (a lower bound with margin)
-                if (gx * gx + gy * gy + gz * gz > a.cull2) continue;
+            // the (up to five) cells of this row of offsets: indices and cull
+            // tests first, then every candidate range is loaded before any
+            // candidate is read, so the loads overlap instead of queueing
+            const int wx = 2 * a.m[0] + 1;
+            int cid5[5], ix5[5], s5[5], e5[5];
+            bool use5[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                use5[k] = false;
+                cid5[k] = 0;
+                ix5[k] = 0;
+                if (k < wx) {
+                    const int dx = k - a.m[0];
+                    int kx, ix;
+                    const bool vx = wrap_cell(c0[0] + dx, a.nc[0], a.pbc[0], kx, ix);
+                    const float gx = cell_gap(dx, u[0]) * cs[0];
+                    // skip cells entirely beyond reach (a lower bound with margin)
+                    use5[k] = vx && vy && vz && !(gx * gx + gy * gy + gz * gz > a.cull2);
+                    cid5[k] = (kz * a.nc[1] + ky) * a.nc[0] + kx;
+                    ix5[k] = ix;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                s5[k] = use5[k] ? a.cell_start[cid5[k]] : 0;
+                e5[k] = use5[k] ? a.cell_start[cid5[k] + 1] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                if (k >= wx) break;
+                a.segA[(size_t)off * n + i] = (uint8_t)(sai.cnt < 255 ? sai.cnt : 255);
+                a.segS[(size_t)(off++) * n + i] = (uint8_t)(sas.cnt < 255 ? sas.cnt : 255);
+                if (!use5[k]) continue;
+                const int ix = ix5[k];
                 if (ix < -2 || ix > 2 || iy < -2 || iy > 2 || iz < -2 || iz > 2) { flags |= NEP_FLAG_IMAGE_RANGE; continue; }
                 // s = fl(n L), exact predicate with every operation rounded separately
                 const float sx = __fmul_rn((float)ix, a.box[0]);
@@ -284,8 +344,7 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
                 const float sz = __fmul_rn((float)iz, a.box[2]);
                 const bool zero_shift = (ix == 0 && iy == 0 && iz == 0);
                 const uint32_t code = (uint32_t)((ix + 2) + 5 * (iy + 2) + 25 * (iz + 2));
-                const int cid = (kz * a.nc[1] + ky) * a.nc[0] + kx;
-                const int s = a.cell_start[cid], e = a.cell_start[cid + 1];
+                const int s = s5[k], e = e5[k];
                 for (int q0 = s; q0 < e; q0 += 4) {
                     // up to four independent loads in flight before any is used
                     float4 pb[4];
@@ -307,32 +366,27 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
                     if (!(d2 < a.list2R[tp])) continue;
                     if (d2 == 0.0f) flags |= NEP_FLAG_OVERLAP;
                     const uint32_t entry = (uint32_t)j | (code << CODE_SHIFT);
-                    uint32_t *row = a.rowbuf + (size_t)i * (a.cap_A + a.cap);
-                    const int na = nai + nas, nb = nri + nrs;
                     if (d2 < a.list2A[tp]) {
-                        if (na < a.cap_A && na + nb < a.cap) {
-                            if (d2 < a.in2A[tp]) row[nai] = entry;
-                            else row[a.cap_A - 1 - nas] = entry;
-                        }
-                        if (d2 < a.in2A[tp]) ++nai;
-                        else ++nas;
+                        if (d2 < a.in2A[tp]) sai.push(entry, row, 0, A4, false);
+                        else sas.push(entry, row, A4 - 1, A4, true);
                     } else {
-                        if (na + nb < a.cap) {
-                            if (d2 < a.in2R[tp]) row[a.cap_A + nri] = entry;
-                            else row[a.cap_A + a.cap - 1 - nrs] = entry;
-                        }
-                        if (d2 < a.in2R[tp]) ++nri;
-                        else ++nrs;
+                        if (d2 < a.in2R[tp]) sri.push(entry, row, A4, R4, false);
+                        else srs.push(entry, row, A4 + R4 - 1, R4, true);
                     }
                     }
                 }
             }
         }
     }
-    a.segA[(size_t)off * n + i] = (uint8_t)(nai < 255 ? nai : 255);
-    a.segS[(size_t)off * n + i] = (uint8_t)(nas < 255 ? nas : 255);
-    const int na = nai + nas;
-    const int total = na + nri + nrs;
+    a.segA[(size_t)off * n + i] = (uint8_t)(sai.cnt < 255 ? sai.cnt : 255);
+    a.segS[(size_t)off * n + i] = (uint8_t)(sas.cnt < 255 ? sas.cnt : 255);
+    sai.finish(row, 0, A4, false);
+    sas.finish(row, A4 - 1, A4, true);
+    sri.finish(row, A4, R4, false);
+    srs.finish(row, A4 + R4 - 1, R4, true);
+    const int nai = sai.cnt, nri = sri.cnt;
+    const int na = nai + sas.cnt;
+    const int total = na + nri + srs.cnt;
     if (na > a.cap_A) flags |= NEP_FLAG_OVERFLOW_A;
     if (total > a.cap) flags |= NEP_FLAG_OVERFLOW_R;
     const bool over = (flags & (NEP_FLAG_OVERFLOW_A | NEP_FLAG_OVERFLOW_R)) != 0;
@@ -365,14 +419,15 @@ __device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int g
     if (i >= n) return;
     const int total = a.cnt[i], na = a.cnt[n + i];
     const int nai = a.cls[i] & 255, nri = a.cls[i] >> 8;
-    const uint32_t *row = a.rowbuf + (size_t)i * (a.cap_A + a.cap);
+    const int A4 = (a.cap_A + 3) & ~3, R4 = (a.cap + 3) & ~3;
+    const uint32_t *row = a.rowbuf + (size_t)i * (A4 + R4);
     // one slot per iteration for every lane, so each store covers consecutive beads
     for (int p = 0; p < total; ++p) {
         int src;
         if (p < nai) src = p;                                           // inside r_c^A
-        else if (p < na) src = a.cap_A - 1 - (p - nai);                 // angular shell
-        else if (p < na + nri) src = a.cap_A + (p - na);                // inside r_c^R
-        else src = a.cap_A + a.cap - 1 - (p - na - nri);                // radial shell
+        else if (p < na) src = A4 - 1 - (p - nai);                      // angular shell
+        else if (p < na + nri) src = A4 + (p - na);                     // inside r_c^R
+        else src = A4 + R4 - 1 - (p - na - nri);                        // radial shell
         a.nbr[(size_t)p * n + i] = row[src];
     }
 }

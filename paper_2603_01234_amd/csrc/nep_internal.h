@@ -281,7 +281,8 @@ struct NbArgs {
     int32_t *cls;        // [n] entries inside r_c^A | entries inside r_c^R (radial-only) << 8
     int n_off;           // (2 m_x + 1)(2 m_y + 1)(2 m_z + 1)
     float cull2;         // cells whose gap exceeds this squared distance are skipped
-    uint32_t *rowbuf;    // [n][cap_A + cap] rows built row-major in four stacks (angular inside
+    uint32_t *rowbuf;    // [n][A4 + R4] (cap_A, cap rounded up to multiples of 4) rows built
+                         // row-major in four stacks (angular inside
                          // r_c^A, angular shell, radial inside r_c^R, radial shell), then
                          // transposed into nbr in that class order
     uint32_t *nbr;
