@@ -436,52 +436,65 @@ __global__ __launch_bounds__(BLOCK) void k_nb_transpose(NbArgs a) { nb_transpose
 
 constexpr int REV_SLOTS = 4;  // angular slots per thread: p = blockIdx.y + k gridDim.y
 
-// reverse entry of angular slot p of bead i: where j's row holds i
-__device__ __forceinline__ void reverse_one(const NbArgs &a, int i, int p) {
-    const int n = a.n;
-    const uint32_t e = a.nbr[(size_t)p * n + i];
-    int j, nx, ny, nz;
-    decode(e, j, nx, ny, nz);
-    // cell offset at which i found j, mirrored for j's row
-    const int ci = a.cell_id[i], cj = a.cell_id[j];
-    const int dx = cj % a.nc[0] + nx * a.nc[0] - ci % a.nc[0];
-    const int dy = (cj / a.nc[0]) % a.nc[1] + ny * a.nc[1] - (ci / a.nc[0]) % a.nc[1];
-    const int dz = cj / (a.nc[0] * a.nc[1]) + nz * a.nc[2] - ci / (a.nc[0] * a.nc[1]);
-    const int wx = 2 * a.m[0] + 1, wy = 2 * a.m[1] + 1;
-    const int o = ((dz + a.m[2]) * wy + (dy + a.m[1])) * wx + (dx + a.m[0]);
-    const uint32_t want = (uint32_t)i | ((124u - (e >> CODE_SHIFT)) << CODE_SHIFT);
-    int found = -1;
-    if (o >= 0 && o < a.n_off) {
-        const int om = a.n_off - 1 - o;
-        // the mirrored offset's entries inside r_c^A, then its shell entries;
-        // never past the neighbour's valid angular prefix (0 after an overflow)
-        const int naj = a.cnt[n + j];
-        const int naij = min(a.cls[j] & 255, naj);
-        int qs = min((int)a.segA[(size_t)om * n + j], naij);
-        int qe = min((int)a.segA[(size_t)(om + 1) * n + j], naij);
-        for (int q = qs; q < qe; ++q)
-            if (a.nbr[(size_t)q * n + j] == want) { found = q; break; }
-        if (found < 0) {
-            qs = min(naij + (int)a.segS[(size_t)om * n + j], naj);
-            qe = min(naij + (int)a.segS[(size_t)(om + 1) * n + j], naj);
-            for (int q = qs; q < qe; ++q)
-                if (a.nbr[(size_t)q * n + j] == want) { found = q; break; }
-        }
-    }
-    a.rev[(size_t)p * n + i] = found < 0 ? -1 : (int32_t)((size_t)found * n + j);
-}
-
-// one thread per (bead, group of angular slots); lanes of a wave read
-// consecutive beads at the same slot
+// Reverse entries of up to REV_SLOTS angular slots of bead i (slots by,
+// by + gy, ...): where each neighbour j's row holds i.  The mirrored cell
+// offset narrows the search to one segment of j's entries inside r_c^A and
+// one of its shell entries.  The searches go in phases so that the loads of
+// all of them are in flight together.  Lanes of a wave handle consecutive
+// beads at the same slots.
 __device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int bx, int gx, int by, int gy) {
     if (build_off(a)) return;
+    const int n = a.n;
     const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
-    if (i >= a.n) return;
-    const int na = a.cnt[a.n + i];
+    if (i >= n) return;
+    const int na = a.cnt[n + i];
+    const int ci = a.cell_id[i];
+    const int cix = ci % a.nc[0], ciy = (ci / a.nc[0]) % a.nc[1], ciz = ci / (a.nc[0] * a.nc[1]);
+    const int wx = 2 * a.m[0] + 1, wy = 2 * a.m[1] + 1;
+    int p[REV_SLOTS], j[REV_SLOTS], om[REV_SLOTS], naj[REV_SLOTS], naij[REV_SLOTS], found[REV_SLOTS];
+    uint32_t e[REV_SLOTS], want[REV_SLOTS];
+#pragma unroll
     for (int k = 0; k < REV_SLOTS; ++k) {
-        const int p = by + k * gy;
-        if (p >= na) break;
-        reverse_one(a, i, p);
+        p[k] = by + k * gy;
+        e[k] = p[k] < na ? a.nbr[(size_t)p[k] * n + i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < REV_SLOTS; ++k) {
+        int nx, ny, nz;
+        decode(e[k], j[k], nx, ny, nz);
+        const bool v = p[k] < na;
+        const int cj = v ? a.cell_id[j[k]] : 0;
+        naj[k] = v ? a.cnt[n + j[k]] : 0;
+        naij[k] = v ? min(a.cls[j[k]] & 255, naj[k]) : 0;
+        // cell offset at which i found j, mirrored for j's row
+        const int dx = cj % a.nc[0] + nx * a.nc[0] - cix;
+        const int dy = (cj / a.nc[0]) % a.nc[1] + ny * a.nc[1] - ciy;
+        const int dz = cj / (a.nc[0] * a.nc[1]) + nz * a.nc[2] - ciz;
+        const int o = ((dz + a.m[2]) * wy + (dy + a.m[1])) * wx + (dx + a.m[0]);
+        om[k] = (v && o >= 0 && o < a.n_off) ? a.n_off - 1 - o : -1;
+        want[k] = (uint32_t)i | ((124u - (e[k] >> CODE_SHIFT)) << CODE_SHIFT);
+        found[k] = -1;
+    }
+    int qs[REV_SLOTS], qe[REV_SLOTS], ss[REV_SLOTS], se[REV_SLOTS];
+#pragma unroll
+    for (int k = 0; k < REV_SLOTS; ++k) {
+        const bool v = om[k] >= 0;
+        const int o = v ? om[k] : 0;
+        // never past the neighbour's valid angular prefix (0 after an overflow)
+        qs[k] = v ? min((int)a.segA[(size_t)o * n + j[k]], naij[k]) : 0;
+        qe[k] = v ? min((int)a.segA[(size_t)(o + 1) * n + j[k]], naij[k]) : 0;
+        ss[k] = v ? min(naij[k] + (int)a.segS[(size_t)o * n + j[k]], naj[k]) : 0;
+        se[k] = v ? min(naij[k] + (int)a.segS[(size_t)(o + 1) * n + j[k]], naj[k]) : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < REV_SLOTS; ++k) {
+        for (int q = qs[k]; q < qe[k]; ++q)
+            if (a.nbr[(size_t)q * n + j[k]] == want[k]) { found[k] = q; break; }
+        if (found[k] < 0)
+            for (int q = ss[k]; q < se[k]; ++q)
+                if (a.nbr[(size_t)q * n + j[k]] == want[k]) { found[k] = q; break; }
+        if (p[k] < na)
+            a.rev[(size_t)p[k] * n + i] = found[k] < 0 ? -1 : (int32_t)((size_t)found[k] * n + j[k]);
     }
 }
 
@@ -490,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
 }
 
 // Processing order of the fused kernel.  Its cost per bead grows with the
-// row lengths (an angular entry costs several radial ones), and a wave takes
+// row lengths (an angular pair costs many radial entries), and a wave takes
 // as long as its busiest lane, so within every block of ORDER_B consecutive
 // beads (neighbours in space for a spatially ordered system) the beads are
 // ordered by decreasing cost: the lanes of a wave then carry similar work.
@@ -504,7 +517,8 @@ constexpr int ORDER_T = 1024;  // threads per block of the order kernel
 constexpr int ORDER_KEYS = 1024;
 
 __device__ __forceinline__ int order_key(const NbArgs &a, int i) {
-    const int k = (6 * a.cnt[a.n + i] + a.cnt[i]) >> 2;
+    // an angular pair inside r_c^A costs about twenty radial list entries
+    const int k = (20 * (a.cls[i] & 255) + a.cnt[i]) >> 3;
     return ORDER_KEYS - 1 - min(k, ORDER_KEYS - 1);  // ascending key = decreasing cost
 }
 
