@@ -6,9 +6,15 @@ the 216,000-bead CG water-like box (60^3 jittered simple-cubic lattice at
 33.4 beads/nm^3, Maxwell 300 K), NEP with radial/angular cutoffs 0.8/0.5 nm,
 Chebyshev basis 8, n_max 8/6, l_max 4, 30 tanh neurons, random N(0, 0.1^2)
 weights; dt = 2 fs, 18 amu; neighbour lists rebuilt every 10 steps on a
-0.1 nm skin.  Each step: half-kick + drift, [wrap + rebuild], fused
-descriptor/network/angular-force kernel, gather kernel (forces + second
-half-kick + energy sums), FP64 energy reduction.
+0.1 nm skin, and earlier whenever a bead passes 0.99 skin/2; beads put back
+into cell order every 100 steps.  Each step: half-kick + drift, [wrap +
+rebuild], fused descriptor/network/angular-force kernel, gather kernel
+(forces + second half-kick + energy sums), FP64 energy reduction.
+
+Two more legs follow (each skippable): the batched fitness form (64
+candidates x 2000 structures, persistent launch against the plain
+one-structure-per-call loop) and the served form (Poisson trace of MD
+requests through the continuous-batching server against a plain FIFO loop).
 
 Prints ONE JSON line.  `value` is bead-steps/s with every input resident in
 HBM.  The roofline entry prices the dominant kernel's algorithmic FP32 work,

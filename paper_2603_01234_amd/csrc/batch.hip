@@ -41,16 +41,19 @@ __global__ __launch_bounds__(BS, 2) void k_efv_batch(BatchArgs b) {
         const int4 w = b.items[it];  // model, system, index in the caller's list
         const SysDesc &sd = b.sys[w.y];
         const ModelDesc &md = b.mod[w.x];
+        // the candidate's tables, in scalar registers (the item is uniform)
+        const float *tab = uniform_ptr(md.tab);
+        const float *ann = uniform_ptr(md.ann);
         const int n = sd.n;
         table_ptr<NT> TB;
         if constexpr (NT > 1) {
             if (w.x != cur_model) {
-                for (int k = threadIdx.x; k < NT * NT * TAB_PER_PAIR; k += BS) smem[k] = md.tab[k];
+                for (int k = threadIdx.x; k < NT * NT * TAB_PER_PAIR; k += BS) smem[k] = tab[k];
                 cur_model = w.x;
             }
             TB = smem;
         } else {
-            TB = (const_fp)md.tab;
+            TB = (const_fp)tab;
         }
         for (int i = threadIdx.x; i < n; i += BS)
             pos4[i] = make_float4(sd.x[i], sd.y[i], sd.z[i], (float)min((int)sd.type[i], NT - 1));
@@ -65,8 +68,8 @@ __global__ __launch_bounds__(BS, 2) void k_efv_batch(BatchArgs b) {
         a.nbr = sd.nbr;
         a.rev = sd.rev;
         a.cnt = sd.cnt;
-        a.tab = md.tab;
-        a.ann = md.ann;
+        a.tab = tab;
+        a.ann = ann;
         a.U = U;
         a.bvec = bvec;
         a.angbuf = angbuf;
@@ -98,9 +101,16 @@ __global__ __launch_bounds__(BS, 2) void k_efv_batch(BatchArgs b) {
             if (i < n) {
                 const float4 pi = pos4[i];
                 const int ti = (NT == 1) ? 0 : (int)pi.w;
-                float Fx, Fy, Fz, W[9];
+                float Fx, Fy, Fz, W[9], Fx1, Fy1, Fz1, W1[9];
                 int nR = 0, nA = 0;
-                gather_bead<NT, true>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA);
+                // the even and the odd slots, added as the single-system gather does
+                gather_bead<NT, true>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, 0, 2);
+                gather_bead<NT, true>(g, b.cut, i, pi, ti, Fx1, Fy1, Fz1, W1, nR, nA, 1, 2);
+                Fx += Fx1;
+                Fy += Fy1;
+                Fz += Fz1;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) W[c] += W1[c];
                 acc[0] += (double)U[i];
                 if (Fr) {
                     const double dx = (double)Fx - Fr[3 * i], dy = (double)Fy - Fr[3 * i + 1],

@@ -66,22 +66,45 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
     main_bead<NT, HP>(a, a.cut, TB, i);
 }
 
+// Two lanes per bead: the even and the odd slots of its row, combined with
+// one lane exchange (more waves in flight for the neighbour gathers).  The
+// sum is (own angular sum + even slots) + odd slots; the batched kernels,
+// with one lane per bead, add the two parts in the same way.
+constexpr int GATHER_BEADS = BLOCK / 2;
+
 template <int NT, bool VIR, bool MD>
 __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
     __shared__ double red[NPART][BLOCK];
     if (MD && a.freeze && (a.freeze[0] & FREEZE_MASK)) return;  // uniform over the grid
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int i = tile * BLOCK + threadIdx.x;
+    const int half = threadIdx.x & 1;
+    const int i = tile * GATHER_BEADS + (threadIdx.x >> 1);
     const int n = a.n;
     double acc[NPART];
 #pragma unroll
     for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
     int nR_in = 0, nA_in = 0;  // pairs inside the interaction cutoffs (work accounting)
+    float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, W[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) W[c] = 0.0f;
+    float4 pi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    int ti = 0;
     if (i < n) {
-        const float4 pi = a.pos4[i];
-        const int ti = (NT == 1) ? 0 : (int)pi.w;
-        float Fx, Fy, Fz, W[9];
-        gather_bead<NT, VIR>(a, a.cut, i, pi, ti, Fx, Fy, Fz, W, nR_in, nA_in);
+        pi = a.pos4[i];
+        ti = (NT == 1) ? 0 : (int)pi.w;
+        gather_bead<NT, VIR>(a, a.cut, i, pi, ti, Fx, Fy, Fz, W, nR_in, nA_in, half, 2);
+    }
+    // every lane takes part in the exchange
+    Fx += __shfl_xor(Fx, 1);
+    Fy += __shfl_xor(Fy, 1);
+    Fz += __shfl_xor(Fz, 1);
+    if (VIR) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) W[c] += __shfl_xor(W[c], 1);
+    }
+    nR_in += __shfl_xor(nR_in, 1);
+    nA_in += __shfl_xor(nA_in, 1);
+    if (i < n && half == 0) {
         a.F[i] = Fx;
         a.F[n + i] = Fy;
         a.F[2 * n + i] = Fz;
@@ -216,7 +239,7 @@ hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds, hipStrea
 
 template <int NT, bool VIR, bool MD>
 static hipError_t gather_t(const GatherArgs &a, hipStream_t s) {
-    int nb = (a.n + BLOCK - 1) / BLOCK;
+    int nb = (a.n + GATHER_BEADS - 1) / GATHER_BEADS;
     hipLaunchKernelGGL((k_efv_gather<NT, VIR, MD>), dim3(nb), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }

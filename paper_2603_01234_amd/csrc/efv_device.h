@@ -43,25 +43,28 @@ __device__ __forceinline__ PairGeom geom_of(uint32_t e, const float4 &pj, const 
 struct RowStream {
     const uint32_t *__restrict__ nbr;
     const float4 *__restrict__ pos4;
-    int n, i, cnt;
+    int n, i, cnt, step;
     uint32_t e_cur, e_nxt;
     float4 p_cur;
-    __device__ __forceinline__ void start(const uint32_t *nb, const float4 *pp, int n_, int i_, int c) {
+    // slots p0, p0 + step, p0 + 2 step, ... of row i (c entries in the row)
+    __device__ __forceinline__ void start(const uint32_t *nb, const float4 *pp, int n_, int i_, int c,
+                                          int p0 = 0, int step_ = 1) {
         nbr = nb;
         pos4 = pp;
         n = n_;
         i = i_;
         cnt = c;
-        e_cur = c > 0 ? nbr[i] : 0u;
-        e_nxt = c > 1 ? nbr[(size_t)n + i] : 0u;
-        p_cur = c > 0 ? pos4[e_cur & J_MASK] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        step = step_;
+        e_cur = p0 < c ? nbr[(size_t)p0 * n + i] : 0u;
+        e_nxt = p0 + step < c ? nbr[(size_t)(p0 + step) * n + i] : 0u;
+        p_cur = p0 < c ? pos4[e_cur & J_MASK] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     __device__ __forceinline__ void next(int p, uint32_t &e, float4 &pj) {
         e = e_cur;
         pj = p_cur;
         e_cur = e_nxt;
-        if (p + 2 < cnt) e_nxt = nbr[(size_t)(p + 2) * n + i];
-        if (p + 1 < cnt) p_cur = pos4[e_cur & J_MASK];
+        if (p + 2 * step < cnt) e_nxt = nbr[(size_t)(p + 2 * step) * n + i];
+        if (p + step < cnt) p_cur = pos4[e_cur & J_MASK];
     }
 };
 
@@ -70,6 +73,30 @@ struct RowStream {
 // (one type) these become scalar loads whose values feed the FMAs as SGPR
 // operands, so the weights never occupy vector registers.
 typedef const __attribute__((address_space(4))) float *const_fp;
+
+// Loads from the constant address space count as invariant, so the compiler
+// may issue all of them long before use, whatever the memory barriers say,
+// and then spill the scalar registers that hold them.  Passing a row's
+// address through an empty asm makes it unknown until that row is reached,
+// so each row of weights is loaded just before its use.
+// a wave-uniform pointer moved into scalar registers
+__device__ __forceinline__ const float *uniform_ptr(const float *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const float *)(((uint64_t)hi << 32) | lo);
+}
+
+// The address must be wave-uniform (it is for every table read here); it is
+// moved to scalar registers first in case it was loaded into vector ones.
+__device__ __forceinline__ const_fp opaque(const_fp p) {
+    uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    v = ((uint64_t)hi << 32) | lo;
+    asm volatile("" : "+s"(v));
+    return (const_fp)v;
+}
 
 template <int NT>
 using table_ptr = typename std::conditional<NT == 1, const_fp, const float *>::type;
@@ -88,20 +115,19 @@ __device__ __forceinline__ void network(const int ti, const const_fp TB, const c
     float z[HP];
 #pragma unroll
     for (int m = 0; m < HP; ++m) z[m] = -an[ND * HP + m];
-    // The memory barriers below keep one row of HP weights in flight at a
-    // time; without them the weight loads are hoisted and spill.
+    // one row of weights (and of pair coefficients) in flight at a time
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         float qv = 0.0f;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const const_fp cRp = TB + (ti * NT + t) * TAB_PER_PAIR;
+            const const_fp cRq = opaque(TB + (ti * NT + t) * TAB_PER_PAIR + q * KB);
 #pragma unroll
-            for (int k = 0; k < KB; ++k) qv += cRp[q * KB + k] * S[t][k];
+            for (int k = 0; k < KB; ++k) qv += cRq[k] * S[t][k];
         }
-        asm volatile("" ::: "memory");
+        const const_fp w = opaque(an + q * HP);
 #pragma unroll
-        for (int m = 0; m < HP; ++m) z[m] += an[q * HP + m] * qv;
+        for (int m = 0; m < HP; ++m) z[m] += w[m] * qv;
     }
 #pragma unroll
     for (int L = 1; L <= 4; ++L)
@@ -112,30 +138,34 @@ __device__ __forceinline__ void network(const int ti, const const_fp TB, const c
             for (int l = 0; l < LM; ++l)
                 if (lm_l(l) == L) qv += N2[l] * A[q][l] * A[q][l];
             const int nu = NR + (L - 1) * NA + q;
-            asm volatile("" ::: "memory");
+            const const_fp w = opaque(an + nu * HP);
 #pragma unroll
-            for (int m = 0; m < HP; ++m) z[m] += an[nu * HP + m] * qv;
+            for (int m = 0; m < HP; ++m) z[m] += w[m] * qv;
         }
     float U = -AN[NT * (ND + 2) * HP];
-    asm volatile("" ::: "memory");
+    const const_fp w1 = opaque(an + (ND + 1) * HP);
 #pragma unroll
     for (int m = 0; m < HP; ++m) {
         const float h = tanh_nobranch(z[m]);
-        const float w1m = an[(ND + 1) * HP + m];
+        const float w1m = w1[m];
         U += w1m * h;
         z[m] = w1m * (1.0f - h * h);  // dU/dz_m
     }
     *U_out = U;
 
     // dU/dq, nu-outer: radial part kept, angular part folded into
-    // D_{n,lm} = dU/dq_nl * 2 N2_lm A_{n,lm}  (in place of A)
+    // D_{n,lm} = dU/dq_nl * 2 N2_lm A_{n,lm}  (in place of A); the weights
+    // are loaded again row by row rather than kept from the forward pass
     float dr[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-        asm volatile("" ::: "memory");
+        const const_fp w = opaque(an + q * HP);
         float acc = 0.0f;
 #pragma unroll
-        for (int m = 0; m < HP; ++m) acc += z[m] * an[q * HP + m];
+        for (int m = 0; m < HP; ++m) acc += z[m] * w[m];
+        // computed here, next to its weights: left free, the arithmetic is
+        // sunk towards its use and the loaded weights stay live (and spill)
+        asm volatile("" : "+v"(acc));
         dr[q] = acc;
     }
 #pragma unroll
@@ -143,10 +173,11 @@ __device__ __forceinline__ void network(const int ti, const const_fp TB, const c
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             const int nu = NR + (L - 1) * NA + q;
-            asm volatile("" ::: "memory");
+            const const_fp w = opaque(an + nu * HP);
             float acc = 0.0f;
 #pragma unroll
-            for (int m = 0; m < HP; ++m) acc += z[m] * an[nu * HP + m];
+            for (int m = 0; m < HP; ++m) acc += z[m] * w[m];
+            asm volatile("" : "+v"(acc));
 #pragma unroll
             for (int l = 0; l < LM; ++l)
                 if (lm_l(l) == L) A[q][l] *= 2.0f * N2[l] * acc;
@@ -157,14 +188,14 @@ __device__ __forceinline__ void network(const int ti, const const_fp TB, const c
     //   beta_k = sum_n dU/dq_n c'_nk   (k = 0 uses c'_n0 = c_n0 + sum_k c_nk)
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        const const_fp cRp = TB + (ti * NT + t) * TAB_PER_PAIR;
         float be[KB];
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            float acc = 0.0f;
+        for (int k = 0; k < KB; ++k) be[k] = 0.0f;
 #pragma unroll
-            for (int q = 0; q < NR; ++q) acc += dr[q] * cRp[q * KB + k];
-            be[k] = acc;
+        for (int q = 0; q < NR; ++q) {
+            const const_fp cRq = opaque(TB + (ti * NT + t) * TAB_PER_PAIR + q * KB);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) be[k] += dr[q] * cRq[k];
         }
         float4 *dst = bvec_out + (size_t)t * 3;
         dst[0] = make_float4(be[0], be[1], be[2], be[3]);
@@ -328,10 +359,12 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
 // Force and per-site virial of one bead from the pair terms of both beads of
 // every pair (radial from the two beta vectors, angular from the reverse slot).
 // Also counts the pairs inside the interaction cutoffs.
+// Slots p0, p0 + step, ... of the row; the bead's own angular sum (fown) is
+// added by the part that starts at slot 0.
 template <int NT, bool VIR>
 __device__ __forceinline__ void gather_bead(const GatherArgs &a, const Cut &cut, const int i, const float4 &pi,
                                             const int ti, float &Fx, float &Fy, float &Fz,
-                                            float W[9], int &nR_in, int &nA_in) {
+                                            float W[9], int &nR_in, int &nA_in, int p0 = 0, int step = 1) {
     const int n = a.n;
     const int cR = a.cnt[i];
     const int cA = a.cnt[n + i];
@@ -344,15 +377,19 @@ __device__ __forceinline__ void gather_bead(const GatherArgs &a, const Cut &cut,
         bi[t][4] = v1.x; bi[t][5] = v1.y; bi[t][6] = v1.z; bi[t][7] = v1.w;
         bi[t][8] = v2.x;
     }
-    float4 fo = a.fown[i];
-    Fx = fo.x;
-    Fy = fo.y;
-    Fz = fo.z;
+    if (p0 == 0) {
+        float4 fo = a.fown[i];
+        Fx = fo.x;
+        Fy = fo.y;
+        Fz = fo.z;
+    } else {
+        Fx = Fy = Fz = 0.0f;
+    }
 #pragma unroll
     for (int c = 0; c < 9; ++c) W[c] = 0.0f;
     RowStream rs;
-    rs.start(a.nbr, a.pos4, n, i, cR);
-    for (int p = 0; p < cR; ++p) {
+    rs.start(a.nbr, a.pos4, n, i, cR, p0, step);
+    for (int p = p0; p < cR; p += step) {
         uint32_t e;
         float4 pj;
         rs.next(p, e, pj);

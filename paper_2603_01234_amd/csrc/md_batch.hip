@@ -90,9 +90,14 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather_batch(MdBatchArgs b) {
         g.fown = d.fown;
         const float4 pi = d.pos4[i];
         const int ti = (NT == 1) ? 0 : (int)pi.w;
-        float Fx, Fy, Fz, W[9];
+        float Fx, Fy, Fz, W[9], Fx1, Fy1, Fz1;
         int nR = 0, nA = 0;
-        gather_bead<NT, false>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA);
+        // the even and the odd slots, added as the single-system gather does
+        gather_bead<NT, false>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, 0, 2);
+        gather_bead<NT, false>(g, b.cut, i, pi, ti, Fx1, Fy1, Fz1, W, nR, nA, 1, 2);
+        Fx += Fx1;
+        Fy += Fy1;
+        Fz += Fz1;
         d.F[i] = Fx;
         d.F[n + i] = Fy;
         d.F[2 * n + i] = Fz;

@@ -244,7 +244,8 @@ __device__ __forceinline__ float sin_pi(float t) { return __builtin_amdgcn_sinf(
 // saturates to +-1 without overflow (exp -> inf gives 2/inf = 0)
 __device__ __forceinline__ float tanh_nobranch(float x) {
     const float e = __expf(2.0f * fabsf(x));
-    const float t = 1.0f - __fdividef(2.0f, e + 1.0f);
+    // hardware reciprocal (1 ulp); e = inf gives exactly 1
+    const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
     return copysignf(t, x);
 }
 
