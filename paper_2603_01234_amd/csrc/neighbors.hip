@@ -270,11 +270,13 @@ struct RowStack {
 };
 
 // the row of bead i; returns its flags, length and angular length
-__device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &flags_out, int &total_out,
-                                          int &na_out) {
+// thr[ti T + tj] = (list2R, list2A, in2A, in2R) of the type pair, in LDS
+__device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, const int i, int &flags_out,
+                                          int &total_out, int &na_out) {
     const int n = a.n;
     const float4 pi = a.pos4[i];
     const int ti = (int)pi.w;
+    const float4 *thr_i = thr + ti * a.T;
     int c0[3];
     float u[3];
     {
@@ -362,15 +364,15 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
                     const float ddz = __fsub_rn(__fadd_rn(pj.z, sz), pi.z);
                     const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ddx, ddx), __fmul_rn(ddy, ddy)),
                                                __fmul_rn(ddz, ddz));
-                    const int tp = ti * a.T + (int)(tag >> CODE_SHIFT);
-                    if (!(d2 < a.list2R[tp])) continue;
+                    const float4 th = thr_i[tag >> CODE_SHIFT];
+                    if (!(d2 < th.x)) continue;
                     if (d2 == 0.0f) flags |= NEP_FLAG_OVERLAP;
                     const uint32_t entry = (uint32_t)j | (code << CODE_SHIFT);
-                    if (d2 < a.list2A[tp]) {
-                        if (d2 < a.in2A[tp]) sai.push(entry, row, 0, A4, false);
+                    if (d2 < th.y) {
+                        if (d2 < th.z) sai.push(entry, row, 0, A4, false);
                         else sas.push(entry, row, A4 - 1, A4, true);
                     } else {
-                        if (d2 < a.in2R[tp]) sri.push(entry, row, A4, R4, false);
+                        if (d2 < th.w) sri.push(entry, row, A4, R4, false);
                         else srs.push(entry, row, A4 + R4 - 1, R4, true);
                     }
                     }
@@ -400,9 +402,15 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const int i, int &fla
 
 __device__ __forceinline__ void nb_rows_body(const NbArgs &a, int bx, int gx) {
     if (build_off(a)) return;  // uniform over the grid
+    __shared__ float4 thr[MAXT * MAXT];
+    if (threadIdx.x < MAXT * MAXT) {
+        const int k = threadIdx.x;
+        thr[k] = make_float4(a.list2R[k], a.list2A[k], a.in2A[k], a.in2R[k]);
+    }
+    __syncthreads();
     const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
     int flags = 0, total = 0, na = 0;
-    if (i < a.n) build_row(a, i, flags, total, na);
+    if (i < a.n) build_row(a, thr, i, flags, total, na);
     wave_status(a.status, flags, total, na);  // every lane takes part
 }
 
@@ -410,25 +418,57 @@ __global__ __launch_bounds__(BLOCK) void k_nb_rows(NbArgs a) { nb_rows_body(a, b
 
 // row-major scratch -> slot-major lists: slot p of bead i is scratch entry p for
 // the angular prefix, and the radial-only entries, kept from the back of the
-// scratch row, follow in the order they were found.  Lanes write consecutive
-// beads of one slot (coalesced); each lane reads its own scratch row.
+// scratch row, follow in the order they were found.  A workgroup moves its
+// 256 beads through LDS 16 slots at a time: each wave reads 16 consecutive
+// slots of four rows, and writes one slot of 64 consecutive beads.
+constexpr int TR_SLOTS = 16;
+
+__device__ __forceinline__ int row_src(int p, int na, int nai, int nri, int A4, int R4) {
+    if (p < nai) return p;                            // inside r_c^A
+    if (p < na) return A4 - 1 - (p - nai);            // angular shell
+    if (p < na + nri) return A4 + (p - na);           // inside r_c^R
+    return A4 + R4 - 1 - (p - na - nri);              // radial shell
+}
+
 __device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int gx) {
-    if (build_off(a)) return;
+    if (build_off(a)) return;  // uniform over the grid
+    __shared__ uint32_t tile[TR_SLOTS][BLOCK + 4];
+    __shared__ int4 info[BLOCK];  // total, angular, inside r_c^A, inside r_c^R (radial-only)
+    __shared__ int max_total;
     const int n = a.n;
-    const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
-    if (i >= n) return;
-    const int total = a.cnt[i], na = a.cnt[n + i];
-    const int nai = a.cls[i] & 255, nri = a.cls[i] >> 8;
+    const int i0 = xcd_tile(bx, gx) * BLOCK;
     const int A4 = (a.cap_A + 3) & ~3, R4 = (a.cap + 3) & ~3;
-    const uint32_t *row = a.rowbuf + (size_t)i * (A4 + R4);
-    // one slot per iteration for every lane, so each store covers consecutive beads
-    for (int p = 0; p < total; ++p) {
-        int src;
-        if (p < nai) src = p;                                           // inside r_c^A
-        else if (p < na) src = A4 - 1 - (p - nai);                      // angular shell
-        else if (p < na + nri) src = A4 + (p - na);                     // inside r_c^R
-        else src = A4 + R4 - 1 - (p - na - nri);                        // radial shell
-        a.nbr[(size_t)p * n + i] = row[src];
+    int4 f = make_int4(0, 0, 0, 0);
+    if (i0 + (int)threadIdx.x < n) {
+        const int i = i0 + threadIdx.x;
+        const int c = a.cls[i];
+        f = make_int4(a.cnt[i], a.cnt[n + i], c & 255, c >> 8);
+    }
+    info[threadIdx.x] = f;
+    if (threadIdx.x == 0) max_total = 0;
+    __syncthreads();
+    int m = f.x;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) m = max(m, __shfl_xor(m, w));
+    if (__lane_id() == 0) atomicMax(&max_total, m);
+    __syncthreads();
+    const int mt = max_total;
+    constexpr int BEADS_PER_PASS = BLOCK / TR_SLOTS;
+    const int pl = threadIdx.x % TR_SLOTS, bsub = threadIdx.x / TR_SLOTS;
+    for (int p0 = 0; p0 < mt; p0 += TR_SLOTS) {
+#pragma unroll 4
+        for (int k = 0; k < TR_SLOTS; ++k) {
+            const int b = bsub + k * BEADS_PER_PASS;
+            const int4 g = info[b];
+            const int p = p0 + pl;
+            if (p < g.x)
+                tile[pl][b] = a.rowbuf[(size_t)(i0 + b) * (A4 + R4) + row_src(p, g.y, g.z, g.w, A4, R4)];
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < TR_SLOTS; ++q)
+            if (p0 + q < f.x) a.nbr[(size_t)(p0 + q) * n + i0 + threadIdx.x] = tile[q][threadIdx.x];
+        __syncthreads();
     }
 }
 
