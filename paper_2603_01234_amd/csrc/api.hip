@@ -62,7 +62,7 @@ constexpr int MAX_OFF = 125;  // (2m+1)^3 cell offsets with m <= 2
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, segA, segS, cls, rowbuf, vh, order, ctrl, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, seg, cls, rowbuf, vh, order, ctrl, total;
     int ncell_max, nblocks;
 };
 
@@ -92,8 +92,7 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.scan_tmp = take((size_t)(L.ncell_max / 1024 + 2) * 4);
     L.cell_tmp = take(nn * 4);
     L.pos_sorted = take(nn * 16);
-    L.segA = take(nn * (size_t)(MAX_OFF + 1));
-    L.segS = take(nn * (size_t)(MAX_OFF + 1));
+    L.seg = take(nn * (size_t)(MAX_OFF + 1) * sizeof(uint16_t));
     L.cls = take(nn * 4);
     // row stride: both regions padded to whole 16-byte groups
     L.rowbuf = take(nn * (size_t)(((std::max(cap, 1) + 3) & ~3) + ((std::max(cap_A, 1) + 3) & ~3)) * 4);
@@ -263,8 +262,7 @@ int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, co
     a.scan_tmp = at<int32_t>(ws, L.scan_tmp);
     a.cell_tmp = at<int32_t>(ws, L.cell_tmp);
     a.pos_sorted = at<float4>(ws, L.pos_sorted);
-    a.segA = at<uint8_t>(ws, L.segA);
-    a.segS = at<uint8_t>(ws, L.segS);
+    a.seg = at<uint16_t>(ws, L.seg);
     a.cls = at<int32_t>(ws, L.cls);
     a.rowbuf = at<uint32_t>(ws, L.rowbuf);
     a.order = at<int32_t>(ws, L.order);

@@ -270,6 +270,11 @@ struct RowStack {
 };
 
 // the row of bead i; returns its flags, length and angular length
+// angular entries inside r_c^A and in the skin shell so far, one byte each
+__device__ __forceinline__ uint16_t seg_counts(int in_a, int shell_a) {
+    return (uint16_t)(min(in_a, 255) | (min(shell_a, 255) << 8));
+}
+
 // thr[ti T + tj] = (list2R, list2A, in2A, in2R) of the type pair, in LDS
 __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, const int i, int &flags_out,
                                           int &total_out, int &na_out) {
@@ -335,10 +340,10 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 if (k >= wx) break;
-                a.segA[(size_t)off * n + i] = (uint8_t)(sai.cnt < 255 ? sai.cnt : 255);
-                a.segS[(size_t)(off++) * n + i] = (uint8_t)(sas.cnt < 255 ? sas.cnt : 255);
+                a.seg[(size_t)(off++) * n + i] = seg_counts(sai.cnt, sas.cnt);
                 if (!use5[k]) continue;
                 const int ix = ix5[k];
+                const int s = s5[k], e = e5[k];
                 if (ix < -2 || ix > 2 || iy < -2 || iy > 2 || iz < -2 || iz > 2) { flags |= NEP_FLAG_IMAGE_RANGE; continue; }
                 // s = fl(n L), exact predicate with every operation rounded separately
                 const float sx = __fmul_rn((float)ix, a.box[0]);
@@ -346,7 +351,6 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
                 const float sz = __fmul_rn((float)iz, a.box[2]);
                 const bool zero_shift = (ix == 0 && iy == 0 && iz == 0);
                 const uint32_t code = (uint32_t)((ix + 2) + 5 * (iy + 2) + 25 * (iz + 2));
-                const int s = s5[k], e = e5[k];
                 for (int q0 = s; q0 < e; q0 += 4) {
                     // up to four independent loads in flight before any is used
                     float4 pb[4];
@@ -380,8 +384,7 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
             }
         }
     }
-    a.segA[(size_t)off * n + i] = (uint8_t)(sai.cnt < 255 ? sai.cnt : 255);
-    a.segS[(size_t)off * n + i] = (uint8_t)(sas.cnt < 255 ? sas.cnt : 255);
+    a.seg[(size_t)off * n + i] = seg_counts(sai.cnt, sas.cnt);
     sai.finish(row, 0, A4, false);
     sas.finish(row, A4 - 1, A4, true);
     sri.finish(row, A4, R4, false);
@@ -521,10 +524,12 @@ __device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int bx, int gx,
         const bool v = om[k] >= 0;
         const int o = v ? om[k] : 0;
         // never past the neighbour's valid angular prefix (0 after an overflow)
-        qs[k] = v ? min((int)a.segA[(size_t)o * n + j[k]], naij[k]) : 0;
-        qe[k] = v ? min((int)a.segA[(size_t)(o + 1) * n + j[k]], naij[k]) : 0;
-        ss[k] = v ? min(naij[k] + (int)a.segS[(size_t)o * n + j[k]], naj[k]) : 0;
-        se[k] = v ? min(naij[k] + (int)a.segS[(size_t)(o + 1) * n + j[k]], naj[k]) : 0;
+        const int s0 = v ? a.seg[(size_t)o * n + j[k]] : 0;
+        const int s1 = v ? a.seg[(size_t)(o + 1) * n + j[k]] : 0;
+        qs[k] = min(s0 & 255, naij[k]);
+        qe[k] = min(s1 & 255, naij[k]);
+        ss[k] = min(naij[k] + (s0 >> 8), naj[k]);
+        se[k] = min(naij[k] + (s1 >> 8), naj[k]);
     }
 #pragma unroll
     for (int k = 0; k < REV_SLOTS; ++k) {
