@@ -58,11 +58,10 @@ struct TimedLaunch {
 
 // Per-thread pinned ring of per-step info records and their events (the MD
 // loop reads the record of step k-1 while the device runs step k).
-constexpr int MAX_OFF = 125;  // (2m+1)^3 cell offsets with m <= 2
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, seg, cls, rowbuf, vh, order, ctrl, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, rowbuf, vh, order, ctrl, total;
     int ncell_max, nblocks;
 };
 
@@ -92,7 +91,6 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.scan_tmp = take((size_t)(L.ncell_max / 1024 + 2) * 4);
     L.cell_tmp = take(nn * 4);
     L.pos_sorted = take(nn * 16);
-    L.seg = take(nn * (size_t)(MAX_OFF + 1) * sizeof(uint16_t));
     L.cls = take(nn * 4);
     // row stride: both regions padded to whole 16-byte groups
     L.rowbuf = take(nn * (size_t)(((std::max(cap, 1) + 3) & ~3) + ((std::max(cap_A, 1) + 3) & ~3)) * 4);
@@ -199,7 +197,6 @@ int make_grid(const Model &M, const nep_system *s, float skin, int ncell_max, Nb
         a.pbc[d] = s->pbc[d] ? 1 : 0;
     }
     a.ncell = (int)(nc[0] * nc[1] * nc[2]);
-    a.n_off = (2 * a.m[0] + 1) * (2 * a.m[1] + 1) * (2 * a.m[2] + 1);
     // margin far above the float rounding of the cell coordinates, whose
     // absolute error grows with the box length (about 1.2e-7 L)
     const double lmax = std::max((double)s->box[0], std::max((double)s->box[1], (double)s->box[2]));
@@ -262,7 +259,6 @@ int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, co
     a.scan_tmp = at<int32_t>(ws, L.scan_tmp);
     a.cell_tmp = at<int32_t>(ws, L.cell_tmp);
     a.pos_sorted = at<float4>(ws, L.pos_sorted);
-    a.seg = at<uint16_t>(ws, L.seg);
     a.cls = at<int32_t>(ws, L.cls);
     a.rowbuf = at<uint32_t>(ws, L.rowbuf);
     a.order = at<int32_t>(ws, L.order);

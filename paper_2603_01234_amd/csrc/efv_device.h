@@ -56,18 +56,21 @@ struct RowStream {
         cnt = c;
         step = step_;
         e_cur = p0 < c ? nbr[(size_t)p0 * n + i] : 0u;
-        e_nxt = p0 + step < c ? nbr[(size_t)(p0 + step) * n + i] : 0u;
+        e_nxt = p0 < c ? nbr[(size_t)min(p0 + step, c - 1) * n + i] : 0u;
         p_cur = p0 < c ? pos4[e_cur & J_MASK] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
+    // Called only for slots p < cnt.  The look-ahead loads are unconditional
+    // (past the end they read the row's last entry again): a conditional load
+    // makes the compiler wait for every load in flight at the join, which
+    // would take away the look-ahead.
     __device__ __forceinline__ void next(int p, uint32_t &e, float4 &pj) {
         e = e_cur;
         pj = p_cur;
         e_cur = e_nxt;
-        if (p + 2 * step < cnt) e_nxt = nbr[(size_t)(p + 2 * step) * n + i];
-        if (p + step < cnt) p_cur = pos4[e_cur & J_MASK];
+        e_nxt = nbr[(size_t)min(p + 2 * step, cnt - 1) * n + i];
+        p_cur = pos4[e_cur & J_MASK];
     }
 };
-
 
 // Tables read through the constant address space: with wave-uniform addresses
 // (one type) these become scalar loads whose values feed the FMAs as SGPR
@@ -387,6 +390,9 @@ __device__ __forceinline__ void gather_bead(const GatherArgs &a, const Cut &cut,
     }
 #pragma unroll
     for (int c = 0; c < 9; ++c) W[c] = 0.0f;
+    // the neighbour's coefficients and the angular partial are loaded where
+    // they are used: loading them ahead as well costs more registers (and
+    // occupancy) than it hides
     RowStream rs;
     rs.start(a.nbr, a.pos4, n, i, cR, p0, step);
     for (int p = p0; p < cR; p += step) {

@@ -1,6 +1,6 @@
-// Cell-list neighbour build for the NEP path (the paper only asks for the
-// neighbours "within a cutoff distance", Sec. II.A; pair-specific cutoffs as
-// for the mixed-resolution model, Sec. II.C.2).
+// Cell-list neighbour build for the NEP path (the descriptors run over the
+// neighbours inside a cutoff, Sec. II.A; pair-specific cutoffs as for the
+// mixed-resolution model, Sec. II.C.2).
 //
 // Steps, all on the caller's stream:
 //   1. bin:     cell index per bead, per-cell counts (integer atomics), status
@@ -12,12 +12,12 @@
 //               canonical order whatever the atomics did
 //   4. rows:    one thread per bead walks the (2m+1)^3 neighbour cells in a
 //               fixed order over the cell-ordered positions and applies the
-//               exact float32 predicate; angular candidates are written from
-//               the front of the row, the others from the back and then moved
-//               behind them; the angular count before every cell offset is
-//               kept per row
-//   5. reverse: for every angular entry, the mirrored entry is searched only
-//               in the mirrored cell offset's segment of the neighbour's row
+//               exact float32 predicate; entries go to four stacks of a
+//               row-major scratch row by class (angular inside r_c^A, angular
+//               shell, radial-only inside r_c^R, radial shell)
+//   5. transpose: scratch rows -> slot-major lists in that class order
+//   6. reverse: for every angular entry, the mirrored entry is searched among
+//               the neighbour's angular entries in its scratch row
 #include "nep_internal.h"
 
 namespace nep {
@@ -270,11 +270,6 @@ struct RowStack {
 };
 
 // the row of bead i; returns its flags, length and angular length
-// angular entries inside r_c^A and in the skin shell so far, one byte each
-__device__ __forceinline__ uint16_t seg_counts(int in_a, int shell_a) {
-    return (uint16_t)(min(in_a, 255) | (min(shell_a, 255) << 8));
-}
-
 // thr[ti T + tj] = (list2R, list2A, in2A, in2R) of the type pair, in LDS
 __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, const int i, int &flags_out,
                                           int &total_out, int &na_out) {
@@ -301,7 +296,6 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
     uint32_t *row = a.rowbuf + (size_t)i * (A4 + R4);
     RowStack sai{0u, 0u, 0u, 0u, 0}, sas{0u, 0u, 0u, 0u, 0}, sri{0u, 0u, 0u, 0u, 0}, srs{0u, 0u, 0u, 0u, 0};
     int flags = 0;
-    int off = 0;         // cell-offset index in (dz, dy, dx) order
     for (int dz = -a.m[2]; dz <= a.m[2]; ++dz) {
         int kz, iz;
         const bool vz = wrap_cell(c0[2] + dz, a.nc[2], a.pbc[2], kz, iz);
@@ -340,7 +334,6 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 if (k >= wx) break;
-                a.seg[(size_t)(off++) * n + i] = seg_counts(sai.cnt, sas.cnt);
                 if (!use5[k]) continue;
                 const int ix = ix5[k];
                 const int s = s5[k], e = e5[k];
@@ -362,14 +355,15 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
                     const float4 pj = pb[u4];
                     const uint32_t tag = __float_as_uint(pj.w);
                     const int j = (int)(tag & J_MASK);
-                    if (j == i && zero_shift) continue;
+                    // every component is used before any test, so the candidate
+                    // arrives in one 16-byte load
                     const float ddx = __fsub_rn(__fadd_rn(pj.x, sx), pi.x);
                     const float ddy = __fsub_rn(__fadd_rn(pj.y, sy), pi.y);
                     const float ddz = __fsub_rn(__fadd_rn(pj.z, sz), pi.z);
                     const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ddx, ddx), __fmul_rn(ddy, ddy)),
                                                __fmul_rn(ddz, ddz));
                     const float4 th = thr_i[tag >> CODE_SHIFT];
-                    if (!(d2 < th.x)) continue;
+                    if (!(d2 < th.x) || (j == i && zero_shift)) continue;
                     if (d2 == 0.0f) flags |= NEP_FLAG_OVERLAP;
                     const uint32_t entry = (uint32_t)j | (code << CODE_SHIFT);
                     if (d2 < th.y) {
@@ -384,7 +378,6 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
             }
         }
     }
-    a.seg[(size_t)off * n + i] = seg_counts(sai.cnt, sas.cnt);
     sai.finish(row, 0, A4, false);
     sas.finish(row, A4 - 1, A4, true);
     sri.finish(row, A4, R4, false);
@@ -480,67 +473,65 @@ __global__ __launch_bounds__(BLOCK) void k_nb_transpose(NbArgs a) { nb_transpose
 constexpr int REV_SLOTS = 4;  // angular slots per thread: p = blockIdx.y + k gridDim.y
 
 // Reverse entries of up to REV_SLOTS angular slots of bead i (slots by,
-// by + gy, ...): where each neighbour j's row holds i.  The mirrored cell
-// offset narrows the search to one segment of j's entries inside r_c^A and
-// one of its shell entries.  The searches go in phases so that the loads of
-// all of them are in flight together.  Lanes of a wave handle consecutive
-// beads at the same slots.
+// by + gy, ...): where each neighbour j's row holds i with the opposite
+// image.  The search scans j's angular entries in the row-major build rows,
+// where they lie together (the entries inside r_c^A from the front, the
+// angular shell entries from the end of the angular part), 16 bytes at a
+// time; the searches of one thread advance together so their loads overlap.
+// Lanes of a wave handle consecutive beads at the same slots.
 __device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int bx, int gx, int by, int gy) {
     if (build_off(a)) return;
     const int n = a.n;
     const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int na = a.cnt[n + i];
-    const int ci = a.cell_id[i];
-    const int cix = ci % a.nc[0], ciy = (ci / a.nc[0]) % a.nc[1], ciz = ci / (a.nc[0] * a.nc[1]);
-    const int wx = 2 * a.m[0] + 1, wy = 2 * a.m[1] + 1;
-    int p[REV_SLOTS], j[REV_SLOTS], om[REV_SLOTS], naj[REV_SLOTS], naij[REV_SLOTS], found[REV_SLOTS];
-    uint32_t e[REV_SLOTS], want[REV_SLOTS];
+    const int A4 = (a.cap_A + 3) & ~3, R4 = (a.cap + 3) & ~3;
+    int p[REV_SLOTS], j[REV_SLOTS], nin[REV_SLOTS], lo[REV_SLOTS], nch[REV_SLOTS], found[REV_SLOTS];
+    uint32_t want[REV_SLOTS];
 #pragma unroll
     for (int k = 0; k < REV_SLOTS; ++k) {
         p[k] = by + k * gy;
-        e[k] = p[k] < na ? a.nbr[(size_t)p[k] * n + i] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < REV_SLOTS; ++k) {
-        int nx, ny, nz;
-        decode(e[k], j[k], nx, ny, nz);
-        const bool v = p[k] < na;
-        const int cj = v ? a.cell_id[j[k]] : 0;
-        naj[k] = v ? a.cnt[n + j[k]] : 0;
-        naij[k] = v ? min(a.cls[j[k]] & 255, naj[k]) : 0;
-        // cell offset at which i found j, mirrored for j's row
-        const int dx = cj % a.nc[0] + nx * a.nc[0] - cix;
-        const int dy = (cj / a.nc[0]) % a.nc[1] + ny * a.nc[1] - ciy;
-        const int dz = cj / (a.nc[0] * a.nc[1]) + nz * a.nc[2] - ciz;
-        const int o = ((dz + a.m[2]) * wy + (dy + a.m[1])) * wx + (dx + a.m[0]);
-        om[k] = (v && o >= 0 && o < a.n_off) ? a.n_off - 1 - o : -1;
-        want[k] = (uint32_t)i | ((124u - (e[k] >> CODE_SHIFT)) << CODE_SHIFT);
+        const uint32_t e = p[k] < na ? a.nbr[(size_t)p[k] * n + i] : 0u;
+        j[k] = (int)(e & J_MASK);
+        want[k] = (uint32_t)i | ((124u - (e >> CODE_SHIFT)) << CODE_SHIFT);
         found[k] = -1;
     }
-    int qs[REV_SLOTS], qe[REV_SLOTS], ss[REV_SLOTS], se[REV_SLOTS];
 #pragma unroll
     for (int k = 0; k < REV_SLOTS; ++k) {
-        const bool v = om[k] >= 0;
-        const int o = v ? om[k] : 0;
-        // never past the neighbour's valid angular prefix (0 after an overflow)
-        const int s0 = v ? a.seg[(size_t)o * n + j[k]] : 0;
-        const int s1 = v ? a.seg[(size_t)(o + 1) * n + j[k]] : 0;
-        qs[k] = min(s0 & 255, naij[k]);
-        qe[k] = min(s1 & 255, naij[k]);
-        ss[k] = min(naij[k] + (s0 >> 8), naj[k]);
-        se[k] = min(naij[k] + (s1 >> 8), naj[k]);
+        const bool v = p[k] < na;
+        // j's angular entries (0 after an overflow of j's row): nin inside
+        // r_c^A at row positions [0, nin), the shell at [lo, A4)
+        const int naj = v ? a.cnt[n + j[k]] : 0;
+        const int nai = v ? min(a.cls[j[k]] & 255, naj) : 0;
+        nin[k] = nai;
+        lo[k] = A4 - (naj - nai);
+        nch[k] = ((nai + 3) >> 2) + ((A4 - (lo[k] & ~3)) >> 2) * (naj > nai ? 1 : 0);
+    }
+    int most = 0;
+#pragma unroll
+    for (int k = 0; k < REV_SLOTS; ++k) most = max(most, nch[k]);
+    for (int c = 0; c < most; ++c) {
+#pragma unroll
+        for (int k = 0; k < REV_SLOTS; ++k) {
+            if (c >= nch[k] || found[k] >= 0) continue;
+            const int ca = (nin[k] + 3) >> 2;  // chunks inside r_c^A
+            const bool shell = c >= ca;
+            const int q0 = shell ? (lo[k] & ~3) + 4 * (c - ca) : 4 * c;
+            const uint4 w = *reinterpret_cast<const uint4 *>(a.rowbuf + (size_t)j[k] * (A4 + R4) + q0);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u;
+                const bool in_range = shell ? (q >= lo[k] && q < A4) : (q < nin[k]);
+                // slot of row position q: itself inside r_c^A, counted from the
+                // end of the angular part in the shell
+                if (found[k] < 0 && in_range && ws[u] == want[k]) found[k] = shell ? nin[k] + (A4 - 1 - q) : q;
+            }
+        }
     }
 #pragma unroll
-    for (int k = 0; k < REV_SLOTS; ++k) {
-        for (int q = qs[k]; q < qe[k]; ++q)
-            if (a.nbr[(size_t)q * n + j[k]] == want[k]) { found[k] = q; break; }
-        if (found[k] < 0)
-            for (int q = ss[k]; q < se[k]; ++q)
-                if (a.nbr[(size_t)q * n + j[k]] == want[k]) { found[k] = q; break; }
-        if (p[k] < na)
-            a.rev[(size_t)p[k] * n + i] = found[k] < 0 ? -1 : (int32_t)((size_t)found[k] * n + j[k]);
-    }
+    for (int k = 0; k < REV_SLOTS; ++k)
+        if (p[k] < na) a.rev[(size_t)p[k] * n + i] = found[k] < 0 ? -1 : (int32_t)((size_t)found[k] * n + j[k]);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {

@@ -277,10 +277,7 @@ struct NbArgs {
     int32_t *cell_id, *cell_count, *cell_start, *cell_cursor, *cell_list, *scan_tmp;
     int32_t *cell_tmp;   // [n] cell members in atomic (arbitrary) order
     float4 *pos_sorted;  // [n] positions in cell order; w = bits of (index | type << 25)
-    uint16_t *seg;       // [n_off + 1][n] before each cell offset: entries inside r_c^A
-                         // | angular skin-shell entries << 8 (each saturating at 255)
     int32_t *cls;        // [n] entries inside r_c^A | entries inside r_c^R (radial-only) << 8
-    int n_off;           // (2 m_x + 1)(2 m_y + 1)(2 m_z + 1)
     float cull2;         // cells whose gap exceeds this squared distance are skipped
     uint32_t *rowbuf;    // [n][A4 + R4] (cap_A, cap rounded up to multiples of 4) rows built
                          // row-major in four stacks (angular inside
