@@ -6,7 +6,8 @@ the 216,000-bead CG water-like box (60^3 jittered simple-cubic lattice at
 33.4 beads/nm^3, Maxwell 300 K), NEP with radial/angular cutoffs 0.8/0.5 nm,
 Chebyshev basis 8, n_max 8/6, l_max 4, 30 tanh neurons, random N(0, 0.1^2)
 weights; dt = 2 fs, 18 amu; neighbour lists rebuilt every 10 steps on a
-0.1 nm skin, and earlier whenever a bead passes 0.99 skin/2; beads put back
+0.1 nm skin, and earlier whenever the two largest displacements since the
+last build add up to 0.99 skin (no pair can be missing before); beads put back
 into cell order every 100 steps.  Each step: half-kick + drift, [wrap +
 rebuild], fused descriptor/network/angular-force kernel, gather kernel
 (forces + second half-kick + energy sums), FP64 energy reduction.

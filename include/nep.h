@@ -47,7 +47,7 @@ typedef enum {
     NEP_ERR_ARG = -1,                /* invalid argument (message says which) */
     NEP_ERR_HIP = -2,                /* a HIP runtime call failed */
     NEP_ERR_NEIGHBOR_OVERFLOW = -3,  /* list capacity too small; see status */
-    NEP_ERR_SKIN_VIOLATION = -4,     /* a bead moved more than skin/2 since the build */
+    NEP_ERR_SKIN_VIOLATION = -4,     /* beads moved far enough since the build that a pair may be missing */
     NEP_ERR_NONFINITE = -5,          /* NaN/Inf position */
     NEP_ERR_OVERLAP = -6,            /* two beads (or a bead and its image) at distance 0 */
     NEP_ERR_UNSUPPORTED = -7,        /* hyperparameters or box outside what is built */
@@ -129,7 +129,7 @@ typedef struct {
     uint32_t *nbr;       /* device [cap][n] */
     int32_t *rev;        /* device [cap_A][n] */
     int32_t *cnt;        /* device [2][n]: cnt[i] all entries, cnt[n+i] angular prefix */
-    float *ref;          /* device [3][n]: positions at the last build (skin check) */
+    float *ref;          /* device [3][n]: positions at the last build (completeness test) */
     float skin;          /* nm */
     int32_t *status;     /* device [4]: flags, max row length seen, max angular length, spare */
 } nep_neighbors;
@@ -172,10 +172,13 @@ int nep_sort_system(nep_model model, nep_system *sys, float *v, float *F, float 
  * W: device [9][n] per-site virial W_i[a][b] (plane 3a+b) or NULL.
  * E_tot: device double[1] or NULL.  W_tot: device double[9] or NULL.
  * Totals are reduced in a fixed order in FP64.  Lists must come from
- * nep_build_neighbors with the same model and skin.  Asynchronous; a bead
- * farther than skin/2 from where the lists were built sets NEP_FLAG_SKIN in
- * the status word (the results are then incomplete), which nep_check_status
- * reports as NEP_ERR_SKIN_VIOLATION. */
+ * nep_build_neighbors with the same model and skin.  Asynchronous.  A pair's
+ * distance changes by at most the sum of its two beads' displacements since
+ * the build, so the lists hold every pair within the cutoffs while the two
+ * largest displacements of the system add up to less than the skin.  Once they
+ * add up to 0.99 skin or more (the margin covers the rounding of the list
+ * predicate), NEP_FLAG_SKIN is set in the status word (the results may then be
+ * incomplete), which nep_check_status reports as NEP_ERR_SKIN_VIOLATION. */
 int nep_compute_efv(nep_model model, const nep_system *sys, const nep_neighbors *nbrs,
                     float *U, float *F, float *W, double *E_tot, double *W_tot,
                     void *ws, size_t ws_bytes, void *stream);
@@ -187,8 +190,8 @@ typedef struct {
     float dt_fs;              /* time step */
     int n_steps;              /* steps in this call */
     int rebuild_every;        /* lists are rebuilt after the drift of step s when (s+1) % rebuild_every == 0,
-                                 and whenever a drift takes a bead 0.99 skin/2 or farther from its build
-                                 position */
+                                 and whenever after a drift the two largest displacements since the build
+                                 add up to more than 0.99 skin */
     int force_rebuild;        /* in: rebuild after the first drift whatever the displacement (after the
                                  caller has regrown the lists of a call stopped by an overflow) */
     float mass[4];            /* amu per type */
@@ -211,9 +214,10 @@ typedef struct {
  * the last step).  E_pot / E_kin: device double [n_steps] traces or NULL.
  *
  * Rebuild decisions are taken on the device, with no host synchronisation
- * inside the call: the drift kernel sets a gate word when a bead ends up
- * 0.99 skin/2 or farther from its build position, the reduction of the
- * previous step sets it when the schedule asks for a rebuild, and the build
+ * inside the call: the drift kernel sets a gate word when the two largest
+ * displacements since the build add up to more than 0.99 skin (the test of
+ * nep_compute_efv), the reduction of the previous step sets it when the
+ * schedule asks for a rebuild, and the build
  * kernels queued in every step do nothing while it is off.  The lists used by
  * a force evaluation therefore always hold every pair within the cutoffs.
  * params->n_rebuilds returns the number of rebuilds that ran.
@@ -254,7 +258,8 @@ size_t nep_md_batch_workspace_bytes(int max_active);
 
 /* One velocity-Verlet step (as nep_md_step, no strain) for each of n_active
  * replicas that share one model, batched: one drift launch over the tiles of
- * every replica, the builds of the replicas whose beads passed 0.99 skin/2 or
+ * every replica, the builds of the replicas that fail the rebuild test of
+ * nep_md_step (their two largest displacements add up to more than 0.99 skin) or
  * whose schedule asks for one ((step + 1) % rebuild_every == 0), one fused-
  * kernel launch, one gather launch and one launch of per-replica energy sums.
  * A replica's results depend only on its own state: alone or in any mix they

@@ -61,7 +61,7 @@ struct TimedLaunch {
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, rowbuf, vh, order, ctrl, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, rowbuf, vh, order, ctrl, top2, total;
     int ncell_max, nblocks;
 };
 
@@ -97,6 +97,8 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.vh = take(nn * 12);
     L.order = take(nn * 4);
     L.ctrl = take(4 * sizeof(int32_t));
+    // per-workgroup pairs of the rebuild test (gather or drift workgroups)
+    L.top2 = take((size_t)L.nblocks * sizeof(float2));
     L.total = off;
     return L;
 }
@@ -226,7 +228,7 @@ int status_to_code(const int32_t st[4]) {
                                                    ", cap_A >= " + std::to_string(st[2]));
     if (f & NEP_FLAG_OVERLAP) return fail(NEP_ERR_OVERLAP, "two beads at zero distance");
     if (f & NEP_FLAG_SKIN)
-        return fail(NEP_ERR_SKIN_VIOLATION, "a bead moved more than skin/2 between rebuilds");
+        return fail(NEP_ERR_SKIN_VIOLATION, "beads moved far enough since the build that a pair may be missing");
     return NEP_OK;
 }
 
@@ -332,8 +334,8 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     }
     if (!md) {
         g.ref = nb->ref;
-        g.half_skin2 = 0.25f * nb->skin * nb->skin;
-        g.status = nb->status;
+        g.skin_gate = 0.99f * nb->skin;
+        g.top2 = at<float2>(ws, L.top2);
     }
     {
         TimedLaunch tl(1, st);
@@ -533,7 +535,7 @@ int mdb_host(size_t bytes, char *&out) {
 }
 
 struct MdbLayout {
-    size_t desc, tiles, gate, status, nbargs, nbstart, total;
+    size_t desc, tiles, gate, arrivals, status, nbargs, nbstart, total;
 };
 MdbLayout mdb_layout(int n) {
     MdbLayout L{};
@@ -547,6 +549,7 @@ MdbLayout mdb_layout(int n) {
     L.desc = take(sizeof(RepDesc) * nn);
     L.tiles = take(sizeof(int) * (nn + 1));
     L.gate = take(sizeof(int) * nn);
+    L.arrivals = take(sizeof(int) * nn);
     L.status = take(sizeof(int32_t) * 4 * nn);
     L.nbargs = take(sizeof(NbArgs) * nn);
     L.nbstart = take(sizeof(int) * NB_BATCH_TILES * (nn + 1));
@@ -789,10 +792,12 @@ int nep_compute_efv(nep_model model, const nep_system *s, const nep_neighbors *n
         HIPCHK(launch_pack(s->n, M.T, s->x, s->y, s->z, s->type, at<float4>(ws, L.pos4), st));
         if ((rc = launch_efv(M, s, nb, U, F, W, W_tot != nullptr, ws, L, st, false, nullptr, nullptr))) return rc;
     }
-    // an empty system reduces zero blocks, so the totals come out as zero
-    if (E_tot || W_tot)
+    // an empty system reduces zero blocks, so the totals come out as zero;
+    // the reduction also runs the completeness test of the lists
+    if (E_tot || W_tot || s->n > 0)
         HIPCHK(launch_reduce(at<double>(ws, L.partial), s->n > 0 ? L.nblocks : 0, E_tot, W_tot, nullptr, nullptr,
-                             nullptr, nullptr, nullptr, nullptr, 0, st));
+                             nullptr, nullptr, nullptr, nullptr, 0, s->n > 0 ? at<float2>(ws, L.top2) : nullptr,
+                             0.99f * nb->skin, nb->status, st));
     return NEP_OK;
 }
 
@@ -820,18 +825,16 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     }
     const int64_t step0 = mp->step;
     const int n_steps = mp->n_steps;
-    const float half_skin = 0.5f * nb->skin;
     int32_t *ctrl = at<int32_t>(ws, L.ctrl);
     auto box_at = [&](int64_t stp, int d) -> float {
         return mp->strain_rate[d] != 0.0 ? (float)(mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)stp))
                                          : s->box[d];
     };
     auto scheduled = [&](int64_t stp) -> int { return ((stp + 1) % mp->rebuild_every) == 0 ? 1 : 0; };
-    // the drift of step k sets the gate when a bead ends up farther than
-    // 0.99 skin/2 from its build position (the margin covers the rounding of
-    // the list predicate); the build queued right after it runs only then, or
-    // when the schedule asks for it
-    const float gate = 0.99f * half_skin;
+    // the drift of step k sets the gate when the two largest displacements
+    // since the build add up to more than 0.99 skin (the margin covers the
+    // rounding of the list predicate); the build queued right after it runs
+    // only then, or when the schedule asks for it
     HIPCHK(launch_clear_status(nb->status, ctrl, (mp->force_rebuild || scheduled(step0)) ? 1 : 0, st));
     for (int k = 0; k < n_steps; ++k) {
         const int64_t step = step0 + k;
@@ -860,7 +863,8 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
             kd.box[d] = s->box[d];
             kd.pbc[d] = s->pbc[d] ? 1 : 0;
         }
-        kd.gate2 = gate * gate;
+        kd.skin_gate = 0.99f * nb->skin;
+        kd.top2 = at<float2>(ws, L.top2);
         kd.status = nb->status;
         kd.ctrl = ctrl;
         {
@@ -878,7 +882,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         if ((rc = launch_efv(M, s, nb, U, F, nullptr, false, ws, L, st, true, v, mp))) return rc;
         HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
                              E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr, mp->pair_counts,
-                             nb->status, ctrl, scheduled(step + 1), st));
+                             nb->status, ctrl, scheduled(step + 1), nullptr, 0.0f, nullptr, st));
     }
     int32_t c[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(c, ctrl, sizeof c, hipMemcpyDeviceToHost, st));
@@ -922,6 +926,7 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
     RepDesc *hd = reinterpret_cast<RepDesc *>(h + BL.desc);
     int *ht = reinterpret_cast<int *>(h + BL.tiles);
     int *hg = reinterpret_cast<int *>(h + BL.gate);
+    int *harr = reinterpret_cast<int *>(h + BL.arrivals);
     int32_t *hs = reinterpret_cast<int32_t *>(h + BL.status);
     int tiles = 0;
     for (int r = 0; r < n_active; ++r) {
@@ -930,9 +935,9 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
         RepDesc &d = hd[r];
         d = RepDesc{};
         d.n = S->n;
-        // the same threshold as the single-replica step
-        const float gate = 0.99f * (0.5f * R.nbrs->skin);
-        d.gate2 = gate * gate;
+        // the same rebuild test as the single-replica step
+        d.skin_gate = 0.99f * R.nbrs->skin;
+        d.top2 = at<float2>(R.ws, L[r].top2);
         for (int q = 0; q < 3; ++q) d.box[q] = S->box[q];
         d.x = S->x;
         d.y = S->y;
@@ -955,6 +960,7 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
         ht[r] = tiles;
         tiles += (S->n + BLOCK - 1) / BLOCK;
         hg[r] = ((R.step + 1) % rebuild_every) == 0 ? 1 : 0;
+        harr[r] = 0;
         R.rebuilt = 0;
         R.status = NEP_OK;
     }
@@ -966,6 +972,7 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
     b.rep = at<RepDesc>(ws, BL.desc);
     b.tile_start = at<int>(ws, BL.tiles);
     b.gate = at<int>(ws, BL.gate);
+    b.arrivals = at<int>(ws, BL.arrivals);
     b.half_dt_accel = 0.5f * dt_fs * ACCEL;
     b.dt = dt_fs;
     for (int t = 0; t < M.T; ++t) {
@@ -978,7 +985,8 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
     b.E_pot = E_pot;
     b.E_kin = E_kin;
     b.status_out = at<int32_t>(ws, BL.status);
-    // descriptors, tile starts and scheduled gates in one copy (they are contiguous)
+    // descriptors, tile starts, scheduled gates and zeroed arrival counts in
+    // one copy (they are contiguous)
     HIPCHK(hipMemcpyAsync(at<char>(ws, BL.desc), h + BL.desc, BL.status - BL.desc, hipMemcpyHostToDevice, st));
     HIPCHK(launch_kick_drift_batch(b, st));
     HIPCHK(hipMemcpyAsync(hg, b.gate, sizeof(int) * n_active, hipMemcpyDeviceToHost, st));

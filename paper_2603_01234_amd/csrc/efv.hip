@@ -135,12 +135,18 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
             a.z[i] = pi.z;
             acc[10] = 0.5 * (double)a.mass[ti] * ((double)vx * vx + (double)vy * vy + (double)vz * vz) /
                       (double)ACCEL;
-        } else if (a.ref) {
-            // lists are only valid while every bead stays within skin/2 of
-            // where they were built
-            float dx = pi.x - a.ref[i], dy = pi.y - a.ref[n + i], dz = pi.z - a.ref[2 * n + i];
-            if (dx * dx + dy * dy + dz * dz > a.half_skin2) atomicOr(a.status, NEP_FLAG_SKIN);
         }
+    }
+    if (!MD && a.top2) {
+        // displacement since the build, for the completeness test of the lists
+        // (the reduction merges the blocks' pairs)
+        float d2 = 0.0f;
+        if (i < n && half == 0) {
+            const float dx = pi.x - a.ref[i], dy = pi.y - a.ref[n + i], dz = pi.z - a.ref[2 * n + i];
+            d2 = dx * dx + dy * dy + dz * dz;
+        }
+        const float2 t = block_top2(d2, 0.0f);
+        if (threadIdx.x == 0) a.top2[tile] = t;
     }
     // fixed-order block reduction
 #pragma unroll
@@ -162,8 +168,15 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
 // Once the status carries a freeze flag nothing but the gate is written.
 __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double *E_tot,
                          double *W_tot, double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, int32_t *ctrl, int next_gate) {
+                         const int32_t *status, int32_t *ctrl, int next_gate, const float2 *top2,
+                         float skin_gate, int32_t *skin_status) {
     __shared__ double red[NPART][BLOCK];
+    if (top2) {
+        float a = 0.0f, b = 0.0f;
+        for (int k = threadIdx.x; k < nblocks; k += BLOCK) top2_merge(a, b, top2[k].x, top2[k].y);
+        const float2 t = block_top2(a, b);
+        if (threadIdx.x == 0 && past_skin(t, skin_gate)) atomicOr(skin_status, NEP_FLAG_SKIN);
+    }
     double acc[NPART];
 #pragma unroll
     for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
@@ -202,9 +215,10 @@ __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double
 
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
                          double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, int32_t *ctrl, int next_gate, hipStream_t s) {
+                         const int32_t *status, int32_t *ctrl, int next_gate, const float2 *top2,
+                         float skin_gate, int32_t *skin_status, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(BLOCK), 0, s, partial, nblocks, E_tot, W_tot, K_tot,
-                       E_slot, K_slot, counts, status, ctrl, next_gate);
+                       E_slot, K_slot, counts, status, ctrl, next_gate, top2, skin_gate, skin_status);
     return hipGetLastError();
 }
 

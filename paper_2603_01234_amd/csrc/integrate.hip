@@ -9,15 +9,20 @@ namespace nep {
 
 
 
-__global__ void k_kick_drift(KickDriftArgs a) {
-    if (a.status[0] & FREEZE_MASK) return;  // lists invalid: leave the state untouched
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    int t = min((int)a.type[i], a.T - 1);
-    const float k = a.half_dt_accel * a.inv_mass[t];
-    // every lane that sees a bead too far writes the same value
-    if (kick_drift_bead(i, a.n, t, k, a.dt, a.lam[0], a.lam[1], a.lam[2], a.x, a.y, a.z, a.v, a.vh, a.F,
-                        a.pos4, a.ref, a.gate2))
+__global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
+    if (a.status[0] & FREEZE_MASK) return;  // lists invalid: leave the state untouched (uniform)
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    float d2 = 0.0f;
+    if (i < a.n) {
+        const int t = min((int)a.type[i], a.T - 1);
+        const float k = a.half_dt_accel * a.inv_mass[t];
+        d2 = kick_drift_bead(i, a.n, t, k, a.dt, a.lam[0], a.lam[1], a.lam[2], a.x, a.y, a.z, a.v, a.vh, a.F,
+                             a.pos4, a.ref);
+    }
+    // the last workgroup to finish decides on the rebuild for the whole system
+    float2 all;
+    if (group_top2(block_top2(d2, 0.0f), a.top2, gridDim.x, blockIdx.x, &a.ctrl[3], all) &&
+        past_skin(all, a.skin_gate))
         a.ctrl[0] = 1;
 }
 

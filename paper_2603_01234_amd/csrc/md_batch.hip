@@ -20,14 +20,21 @@ __device__ __forceinline__ int replica_of(const MdBatchArgs &b, int tile) {
 __global__ __launch_bounds__(BLOCK) void k_kick_drift_batch(MdBatchArgs b) {
     const int r = replica_of(b, blockIdx.x);
     const RepDesc &d = b.rep[r];
-    if (d.status[0] & FREEZE_MASK) return;  // uniform over the workgroup
-    const int i = (blockIdx.x - b.tile_start[r]) * BLOCK + threadIdx.x;
-    if (i >= d.n) return;
-    const int t = min((int)d.type[i], b.T - 1);
-    const float k = b.half_dt_accel * b.inv_mass[t];
-    if (kick_drift_bead(i, d.n, t, k, b.dt, 1.0f, 1.0f, 1.0f, d.x, d.y, d.z, d.v, d.vh, d.F, d.pos4, d.ref,
-                        d.gate2))
-        b.gate[r] = 1;  // every lane that sees a bead too far writes the same value
+    if (d.status[0] & FREEZE_MASK) return;  // uniform over the replica's workgroups
+    const int tile = blockIdx.x - b.tile_start[r];
+    const int i = tile * BLOCK + threadIdx.x;
+    float d2 = 0.0f;
+    if (i < d.n) {
+        const int t = min((int)d.type[i], b.T - 1);
+        const float k = b.half_dt_accel * b.inv_mass[t];
+        d2 = kick_drift_bead(i, d.n, t, k, b.dt, 1.0f, 1.0f, 1.0f, d.x, d.y, d.z, d.v, d.vh, d.F, d.pos4, d.ref);
+    }
+    // the replica's last tile to finish decides on its rebuild (the same test
+    // over the same beads as the single-replica step)
+    float2 all;
+    if (group_top2(block_top2(d2, 0.0f), d.top2, b.tile_start[r + 1] - b.tile_start[r], tile, &b.arrivals[r], all) &&
+        past_skin(all, d.skin_gate))
+        b.gate[r] = 1;
 }
 
 template <int NT, int HP>

@@ -22,9 +22,9 @@
 
 namespace nep {
 
-// A build inside an MD run is skipped when the reduction before it found no
-// bead close enough to skin/2 and no rebuild was due (ctrl[0] == 0), and once
-// the run is frozen after a failed build.  The test is uniform over the grid.
+// A build inside an MD run is skipped when neither the drift's rebuild test
+// nor the schedule asked for one (ctrl[0] == 0), and once the run is frozen
+// after a failed build.  The test is uniform over the grid.
 __device__ __forceinline__ bool build_off(const int32_t *ctrl, const int32_t *status, int clear_status) {
     if (ctrl && ctrl[0] == 0) return true;
     return !clear_status && (status[0] & FREEZE_MASK);

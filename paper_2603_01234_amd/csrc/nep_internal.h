@@ -92,10 +92,12 @@ struct GatherArgs {
     float inv_mass[MAXT];
     float mass[MAXT];
     const int32_t *freeze;  // MD: status word (see EfvArgs)
-    // outside MD: flag beads farther than skin/2 from their build position
-    const float *ref;       // [3][n] or null
-    float half_skin2;
-    int32_t *status;
+    // outside MD: the completeness test of the lists (the reduction flags
+    // NEP_FLAG_SKIN once the two largest displacements since the build add up
+    // to more than skin_gate)
+    const float *ref;       // [3][n] build positions
+    float skin_gate;        // 0.99 skin
+    float2 *top2;           // [blocks] or null: per-block pairs of that test
 };
 
 // XCD-aware tile index: consecutive logical tiles are kept on one XCD (the
@@ -256,11 +258,12 @@ hipError_t launch_pack(int n, int T, const float *x, const float *y, const float
                        float4 *pos4, hipStream_t s);
 hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_efv_gather(int T, bool virial, bool md, const GatherArgs &a, hipStream_t s);
+// top2 (optional): the gather blocks' pairs of the rebuild test; the reduction
+// sets NEP_FLAG_SKIN in skin_status when they call for a rebuild
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
                          double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, int32_t *ctrl, int next_gate, hipStream_t s);
-// rebuild prediction at the start of an MD call: maxima of |x + d - ref|,
-// |d| and dt^2 |a| with d = dt (v + dt/2 a) the next drift, into the partials
+                         const int32_t *status, int32_t *ctrl, int next_gate, const float2 *top2,
+                         float skin_gate, int32_t *skin_status, hipStream_t s);
 struct NbArgs {
     int n, cap, cap_A;
     float box[3];
@@ -332,20 +335,79 @@ struct KickDriftArgs {
     float box[3];           // box after the strain
     int pbc[3];
     int T;                  // number of types (type values are clamped below it)
-    float gate2;            // squared displacement that calls for a rebuild
+    float skin_gate;        // 0.99 skin: a rebuild is due once the two largest
+                            // displacements since the build add up to more
+    float2 *top2;           // [blocks] per-block largest and second largest squared displacement
     const int32_t *status;
-    int32_t *ctrl;          // ctrl[0]: rebuild gate
+    int32_t *ctrl;          // ctrl[0]: rebuild gate; ctrl[3]: arrival count of the blocks
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s);
 
+// ---- the rebuild test ----
+// A pair's distance changes by at most |d_i| + |d_j| (d: displacements since
+// the build; periodic images move with their bead), which is at most the sum
+// of the two largest displacements of the system.  While that sum stays below
+// the skin no pair can have come from beyond r_c + skin to inside r_c, so the
+// lists are complete.  The 1% margin covers the rounding of the list predicate.
+
+// (a, b) = largest and second largest of a set of values; merged with (a2, b2)
+__device__ __forceinline__ void top2_merge(float &a, float &b, float a2, float b2) {
+    const float hi = fmaxf(a, a2), lo = fminf(a, a2);
+    b = fmaxf(lo, fmaxf(b, b2));
+    a = hi;
+}
+
+// the pair of the whole workgroup (every thread calls it; valid in thread 0)
+__device__ __forceinline__ float2 block_top2(float a, float b) {
+    __shared__ float2 wtop[BLOCK / 64];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) top2_merge(a, b, __shfl_xor(a, o), __shfl_xor(b, o));
+    if (__lane_id() == 0) wtop[threadIdx.x >> 6] = make_float2(a, b);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < BLOCK / 64; ++w) top2_merge(a, b, wtop[w].x, wtop[w].y);
+    return make_float2(a, b);
+}
+
+// Every workgroup of a group of nslot calls this with its pair (valid in
+// thread 0).  The workgroup that arrives last merges the pairs of the group,
+// resets the arrival count and returns true in its thread 0, with the
+// group's pair in all.
+__device__ __forceinline__ bool group_top2(float2 mine, float2 *slots, int nslot, int slot, int *arrivals,
+                                           float2 &all) {
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        slots[slot] = mine;
+        __threadfence();
+        last = atomicAdd(arrivals, 1) == nslot - 1;
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    float a = 0.0f, b = 0.0f;
+    for (int k = threadIdx.x; k < nslot; k += BLOCK) {
+        const unsigned *w = reinterpret_cast<const unsigned *>(slots + k);
+        top2_merge(a, b, __uint_as_float(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
+                   __uint_as_float(__hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+    }
+    all = block_top2(a, b);
+    if (threadIdx.x == 0) *arrivals = 0;
+    return threadIdx.x == 0;
+}
+
+// whether a pair of squared displacements calls for a rebuild
+__device__ __forceinline__ bool past_skin(float2 t, float skin_gate) {
+    return sqrtf(t.x) + sqrtf(t.y) > skin_gate;
+}
+
 // First half-kick and drift of bead i (kick k = dt/2 ACCEL / m of its type):
 // half-step velocity to vh, new position (scaled by lam) to pos4, build
-// reference scaled in place.  Returns whether the bead ended up farther than
-// sqrt(gate2) from its build position.
-__device__ __forceinline__ bool kick_drift_bead(int i, int n, int t, float k, float dt, float l0, float l1,
-                                                float l2, const float *x, const float *y, const float *z,
-                                                const float *v, float *vh, const float *F, float4 *pos4,
-                                                float *ref, float gate2) {
+// reference scaled in place.  Returns the squared distance from the bead's
+// build position.
+__device__ __forceinline__ float kick_drift_bead(int i, int n, int t, float k, float dt, float l0, float l1,
+                                                 float l2, const float *x, const float *y, const float *z,
+                                                 const float *v, float *vh, const float *F, float4 *pos4,
+                                                 float *ref) {
     const float vx = v[i] + k * F[i];
     const float vy = v[n + i] + k * F[n + i];
     const float vz = v[2 * n + i] + k * F[2 * n + i];
@@ -361,7 +423,7 @@ __device__ __forceinline__ bool kick_drift_bead(int i, int n, int t, float k, fl
     ref[2 * n + i] = rz;
     pos4[i] = make_float4(px, py, pz, (float)t);
     const float dx = px - rx, dy = py - ry, dz = pz - rz;
-    return dx * dx + dy * dy + dz * dz > gate2;
+    return dx * dx + dy * dy + dz * dz;
 }
 
 
@@ -403,7 +465,8 @@ hipError_t launch_batch_rmse(int n_models, int n_items, const int4 *list, const 
 // ---- many replicas, one MD step each (served form) ----
 struct RepDesc {
     int n;
-    float gate2;           // squared displacement that calls for a rebuild (0.99 skin/2)^2
+    float skin_gate;       // 0.99 skin (the rebuild test above)
+    float2 *top2;          // [tiles] per-tile pairs of the rebuild test (replica's workspace)
     float box[3];
     float *x, *y, *z, *v, *F, *U;
     const uint8_t *type;
@@ -421,6 +484,7 @@ struct MdBatchArgs {
     const RepDesc *rep;
     const int *tile_start; // [n_rep + 1] first tile of every replica
     int *gate;             // [n_rep] rebuild gate, set by the drift
+    int *arrivals;         // [n_rep] tiles of each replica done with the drift (zero before the launch)
     float half_dt_accel, dt;
     float inv_mass[MAXT], mass[MAXT];
     Cut cut;

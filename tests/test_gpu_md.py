@@ -96,9 +96,9 @@ def test_md_strain_updates_box_and_stays_consistent():
 
 
 def test_drift_beyond_half_skin_rebuilds_before_the_forces():
-    """A bead drifting 0.1 nm in one 2 fs step (twice skin/2): the displacement
-    check after the drift rebuilds the lists before the force evaluation, every
-    step, so the forces stay exact."""
+    """A bead drifting 0.1 nm in one 2 fs step (alone more than 0.99 skin): the
+    rebuild test after the drift rebuilds the lists before the force
+    evaluation, every step, so the forces stay exact."""
     spec, params, system, opts = W.config0()
     rep = _rep(spec, params, system, opts["skin"])
     rep.efv()
@@ -111,12 +111,52 @@ def test_drift_beyond_half_skin_rebuilds_before_the_forces():
     compare_efv(rep, ref, system.n, check_virial=False, label="fast-drift")
 
 
+def _oracle_at(rep, spec, params, system):
+    return oracle.efv(spec, params.astype(np.float32).astype(np.float64), rep.positions().astype(np.float64),
+                      system.types, system.box.astype(np.float32).astype(np.float64), system.pbc)
+
+
+def test_rebuild_test_adds_the_two_largest_displacements():
+    """A pair's distance changes by at most the sum of its beads'
+    displacements.  One bead moved 0.06 nm (past skin/2, short of the skin)
+    leaves every pair in the lists: no rebuild, and the forces are exact.  Two
+    beads moved 0.06 nm each could bring a pair in from beyond the lists: the
+    step rebuilds first."""
+    spec, params, system, opts = W.config0()
+    assert opts["skin"] == 0.1
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv()
+    rep.v[0, 5] = 0.03                 # 0.06 nm in one 2 fs step
+    rep.md(1, 2.0, [W.WATER_MASS], rebuild_every=10)
+    assert rep.n_rebuilds == 0
+    rep.efv()                          # totals at the final positions, on the same lists
+    compare_efv(rep, _oracle_at(rep, spec, params, system), system.n, check_virial=False,
+                label="one bead past skin/2")
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv()
+    rep.v[0, 5] = 0.03
+    rep.v[1, 9] = -0.03
+    rep.md(1, 2.0, [W.WATER_MASS], rebuild_every=10)
+    assert rep.n_rebuilds == 1
+    rep.efv()
+    compare_efv(rep, _oracle_at(rep, spec, params, system), system.n, check_virial=False,
+                label="two beads past skin/2")
+
+
 def test_efv_on_stale_lists_is_reported():
+    """The same test in nep_compute_efv: one bead 0.6 skin from where the lists
+    were built is fine (forces exact), a second one as far is reported."""
     from paper_2603_01234_amd import binding as B
     spec, params, system, opts = W.config0()
     rep = _rep(spec, params, system, opts["skin"])
     rep.build()
     rep.xyz[0, 7] += 0.6 * opts["skin"]
+    rep.efv()
+    code, st = B.nep_check_status(rep.c_neighbors(), torch.cuda.current_stream().cuda_stream)
+    assert code == B.NEP_OK and not st[0] & B.NEP_FLAG_SKIN
+    compare_efv(rep, _oracle_at(rep, spec, params, system), system.n, check_virial=False,
+                label="one bead 0.6 skin from the build")
+    rep.xyz[1, 9] += 0.6 * opts["skin"]
     rep.efv()
     code, st = B.nep_check_status(rep.c_neighbors(), torch.cuda.current_stream().cuda_stream)
     assert code == B.NEP_ERR_SKIN_VIOLATION and st[0] & B.NEP_FLAG_SKIN
