@@ -535,7 +535,7 @@ int mdb_host(size_t bytes, char *&out) {
 }
 
 struct MdbLayout {
-    size_t desc, tiles, gate, arrivals, status, nbargs, nbstart, total;
+    size_t desc, tiles, gate, status, nbargs, nbstart, total;
 };
 MdbLayout mdb_layout(int n) {
     MdbLayout L{};
@@ -549,7 +549,6 @@ MdbLayout mdb_layout(int n) {
     L.desc = take(sizeof(RepDesc) * nn);
     L.tiles = take(sizeof(int) * (nn + 1));
     L.gate = take(sizeof(int) * nn);
-    L.arrivals = take(sizeof(int) * nn);
     L.status = take(sizeof(int32_t) * 4 * nn);
     L.nbargs = take(sizeof(NbArgs) * nn);
     L.nbstart = take(sizeof(int) * NB_BATCH_TILES * (nn + 1));
@@ -926,7 +925,6 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
     RepDesc *hd = reinterpret_cast<RepDesc *>(h + BL.desc);
     int *ht = reinterpret_cast<int *>(h + BL.tiles);
     int *hg = reinterpret_cast<int *>(h + BL.gate);
-    int *harr = reinterpret_cast<int *>(h + BL.arrivals);
     int32_t *hs = reinterpret_cast<int32_t *>(h + BL.status);
     int tiles = 0;
     for (int r = 0; r < n_active; ++r) {
@@ -960,7 +958,6 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
         ht[r] = tiles;
         tiles += (S->n + BLOCK - 1) / BLOCK;
         hg[r] = ((R.step + 1) % rebuild_every) == 0 ? 1 : 0;
-        harr[r] = 0;
         R.rebuilt = 0;
         R.status = NEP_OK;
     }
@@ -972,7 +969,6 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
     b.rep = at<RepDesc>(ws, BL.desc);
     b.tile_start = at<int>(ws, BL.tiles);
     b.gate = at<int>(ws, BL.gate);
-    b.arrivals = at<int>(ws, BL.arrivals);
     b.half_dt_accel = 0.5f * dt_fs * ACCEL;
     b.dt = dt_fs;
     for (int t = 0; t < M.T; ++t) {
@@ -985,8 +981,7 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
     b.E_pot = E_pot;
     b.E_kin = E_kin;
     b.status_out = at<int32_t>(ws, BL.status);
-    // descriptors, tile starts, scheduled gates and zeroed arrival counts in
-    // one copy (they are contiguous)
+    // descriptors, tile starts and scheduled gates in one copy (they are contiguous)
     HIPCHK(hipMemcpyAsync(at<char>(ws, BL.desc), h + BL.desc, BL.status - BL.desc, hipMemcpyHostToDevice, st));
     HIPCHK(launch_kick_drift_batch(b, st));
     HIPCHK(hipMemcpyAsync(hg, b.gate, sizeof(int) * n_active, hipMemcpyDeviceToHost, st));

@@ -172,9 +172,7 @@ __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double
                          float skin_gate, int32_t *skin_status) {
     __shared__ double red[NPART][BLOCK];
     if (top2) {
-        float a = 0.0f, b = 0.0f;
-        for (int k = threadIdx.x; k < nblocks; k += BLOCK) top2_merge(a, b, top2[k].x, top2[k].y);
-        const float2 t = block_top2(a, b);
+        const float2 t = merge_top2(top2, nblocks);
         if (threadIdx.x == 0 && past_skin(t, skin_gate)) atomicOr(skin_status, NEP_FLAG_SKIN);
     }
     double acc[NPART];

@@ -19,16 +19,22 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
         d2 = kick_drift_bead(i, a.n, t, k, a.dt, a.lam[0], a.lam[1], a.lam[2], a.x, a.y, a.z, a.v, a.vh, a.F,
                              a.pos4, a.ref);
     }
-    // the last workgroup to finish decides on the rebuild for the whole system
-    float2 all;
-    if (group_top2(block_top2(d2, 0.0f), a.top2, gridDim.x, blockIdx.x, &a.ctrl[3], all) &&
-        past_skin(all, a.skin_gate))
-        a.ctrl[0] = 1;
+    const float2 t = block_top2(d2, 0.0f);
+    if (threadIdx.x == 0) a.top2[blockIdx.x] = t;
+}
+
+// one workgroup: the rebuild test over the pairs of the drift's workgroups
+__global__ __launch_bounds__(BLOCK) void k_gate(KickDriftArgs a, int nblocks) {
+    if (a.status[0] & FREEZE_MASK) return;
+    const float2 t = merge_top2(a.top2, nblocks);
+    if (threadIdx.x == 0 && past_skin(t, a.skin_gate)) a.ctrl[0] = 1;
 }
 
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_kick_drift, dim3((a.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a);
+    const int nb = (a.n + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(k_kick_drift, dim3(nb), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_gate, dim3(1), dim3(BLOCK), 0, s, a, nb);
     return hipGetLastError();
 }
 

@@ -29,12 +29,18 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift_batch(MdBatchArgs b) {
         const float k = b.half_dt_accel * b.inv_mass[t];
         d2 = kick_drift_bead(i, d.n, t, k, b.dt, 1.0f, 1.0f, 1.0f, d.x, d.y, d.z, d.v, d.vh, d.F, d.pos4, d.ref);
     }
-    // the replica's last tile to finish decides on its rebuild (the same test
-    // over the same beads as the single-replica step)
-    float2 all;
-    if (group_top2(block_top2(d2, 0.0f), d.top2, b.tile_start[r + 1] - b.tile_start[r], tile, &b.arrivals[r], all) &&
-        past_skin(all, d.skin_gate))
-        b.gate[r] = 1;
+    const float2 t = block_top2(d2, 0.0f);
+    if (threadIdx.x == 0) d.top2[tile] = t;
+}
+
+// one workgroup per replica: the rebuild test over its tiles' pairs (the same
+// test over the same beads as the single-replica step)
+__global__ __launch_bounds__(BLOCK) void k_gate_batch(MdBatchArgs b) {
+    const int r = blockIdx.x;
+    const RepDesc &d = b.rep[r];
+    if (d.status[0] & FREEZE_MASK) return;
+    const float2 t = merge_top2(d.top2, b.tile_start[r + 1] - b.tile_start[r]);
+    if (threadIdx.x == 0 && past_skin(t, d.skin_gate)) b.gate[r] = 1;
 }
 
 template <int NT, int HP>
@@ -167,6 +173,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_batch(MdBatchArgs b) {
 hipError_t launch_kick_drift_batch(const MdBatchArgs &b, hipStream_t s) {
     if (b.n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_kick_drift_batch, dim3(b.n_tiles), dim3(BLOCK), 0, s, b);
+    hipLaunchKernelGGL(k_gate_batch, dim3(b.n_rep), dim3(BLOCK), 0, s, b);
     return hipGetLastError();
 }
 

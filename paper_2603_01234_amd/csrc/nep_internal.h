@@ -339,8 +339,10 @@ struct KickDriftArgs {
                             // displacements since the build add up to more
     float2 *top2;           // [blocks] per-block largest and second largest squared displacement
     const int32_t *status;
-    int32_t *ctrl;          // ctrl[0]: rebuild gate; ctrl[3]: arrival count of the blocks
+    int32_t *ctrl;          // ctrl[0]: rebuild gate
 };
+// the drift, then one workgroup that merges the blocks' pairs and switches
+// the rebuild gate on when they call for a rebuild
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s);
 
 // ---- the rebuild test ----
@@ -369,30 +371,11 @@ __device__ __forceinline__ float2 block_top2(float a, float b) {
     return make_float2(a, b);
 }
 
-// Every workgroup of a group of nslot calls this with its pair (valid in
-// thread 0).  The workgroup that arrives last merges the pairs of the group,
-// resets the arrival count and returns true in its thread 0, with the
-// group's pair in all.
-__device__ __forceinline__ bool group_top2(float2 mine, float2 *slots, int nslot, int slot, int *arrivals,
-                                           float2 &all) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        slots[slot] = mine;
-        __threadfence();
-        last = atomicAdd(arrivals, 1) == nslot - 1;
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+// the pair of n per-workgroup pairs, merged by one workgroup (valid in thread 0)
+__device__ __forceinline__ float2 merge_top2(const float2 *top2, int n) {
     float a = 0.0f, b = 0.0f;
-    for (int k = threadIdx.x; k < nslot; k += BLOCK) {
-        const unsigned *w = reinterpret_cast<const unsigned *>(slots + k);
-        top2_merge(a, b, __uint_as_float(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
-                   __uint_as_float(__hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-    }
-    all = block_top2(a, b);
-    if (threadIdx.x == 0) *arrivals = 0;
-    return threadIdx.x == 0;
+    for (int k = threadIdx.x; k < n; k += BLOCK) top2_merge(a, b, top2[k].x, top2[k].y);
+    return block_top2(a, b);
 }
 
 // whether a pair of squared displacements calls for a rebuild
@@ -484,7 +467,6 @@ struct MdBatchArgs {
     const RepDesc *rep;
     const int *tile_start; // [n_rep + 1] first tile of every replica
     int *gate;             // [n_rep] rebuild gate, set by the drift
-    int *arrivals;         // [n_rep] tiles of each replica done with the drift (zero before the launch)
     float half_dt_accel, dt;
     float inv_mass[MAXT], mass[MAXT];
     Cut cut;
