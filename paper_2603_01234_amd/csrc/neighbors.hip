@@ -102,7 +102,7 @@ __device__ __forceinline__ void nb_bin_body(const NbArgs &a, int bx) {
     int t = a.type[i];
     if (t >= a.T) { flags |= NEP_FLAG_BAD_TYPE; t = a.T - 1; }
     if (flags) atomicOr(&a.status[0], flags);
-    int cid = (c[2] * a.nc[1] + c[1]) * a.nc[0] + c[0];
+    const int cid = cell_index(c[0], c[1], c[2], a.nc);
     a.cell_id[i] = cid;
     atomicAdd(&a.cell_count[cid], 1);
     a.pos4[i] = make_float4(p[0], p[1], p[2], (float)t);
@@ -322,7 +322,7 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
                     const float gx = cell_gap(dx, u[0]) * cs[0];
                     // skip cells entirely beyond reach (a lower bound with margin)
                     use5[k] = vx && vy && vz && !(gx * gx + gy * gy + gz * gz > a.cull2);
-                    cid5[k] = (kz * a.nc[1] + ky) * a.nc[0] + kx;
+                    cid5[k] = cell_index(kx, ky, kz, a.nc);
                     ix5[k] = ix;
                 }
             }

@@ -100,6 +100,23 @@ struct GatherArgs {
     float2 *top2;           // [blocks] or null: per-block pairs of that test
 };
 
+// Cells are numbered tile by tile: tiles of CELL_TILE^3 cells in (z, y, x)
+// order, the cells of a tile in (z, y, x) order, the tiles at the upper edges
+// cut to the grid.  This is a bijection of the grid onto [0, nx ny nz) under
+// which consecutive indices stay close in all three directions, so the beads
+// of a workgroup (kept in cell order) lie in a compact block and their
+// neighbourhoods overlap in the caches.
+constexpr int CELL_TILE = 4;
+__device__ __forceinline__ int cell_index(int x, int y, int z, const int nc[3]) {
+    constexpr int B = CELL_TILE;
+    const int tx = x / B, ty = y / B, tz = z / B;
+    const int hx = min(B, nc[0] - tx * B), hy = min(B, nc[1] - ty * B), hz = min(B, nc[2] - tz * B);
+    return tz * B * nc[1] * nc[0]            // whole slabs of tiles before
+           + ty * B * nc[0] * hz             // whole rows of tiles before, in this slab
+           + tx * B * hy * hz                // tiles before, in this row
+           + ((z - tz * B) * hy + (y - ty * B)) * hx + (x - tx * B);
+}
+
 // XCD-aware tile index: consecutive logical tiles are kept on one XCD (the
 // hardware assigns workgroups round-robin over the 8 XCDs, each with its own
 // L2), so neighbouring beads share an L2.
