@@ -955,6 +955,7 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
         d.fown = at<float4>(R.ws, L[r].fown);
         d.vh = at<float>(R.ws, L[r].vh);
         d.partial = at<double>(R.ws, L[r].partial);
+        d.order = at<int32_t>(R.ws, L[r].order);
         ht[r] = tiles;
         tiles += (S->n + BLOCK - 1) / BLOCK;
         hg[r] = ((R.step + 1) % rebuild_every) == 0 ? 1 : 0;

@@ -57,8 +57,11 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main_batch(MdBatchArgs b) {
     const int r = replica_of(b, blockIdx.x);
     const RepDesc &d = b.rep[r];
     if (d.status[0] & FREEZE_MASK) return;
-    const int i = (blockIdx.x - b.tile_start[r]) * BLOCK + threadIdx.x;
-    if (i >= d.n) return;
+    const int t = (blockIdx.x - b.tile_start[r]) * BLOCK + threadIdx.x;
+    if (t >= d.n) return;
+    // the replica's processing order (beads of similar cost side by side)
+    int i = d.order[t];
+    if ((unsigned)i >= (unsigned)d.n) i = t;  // an order never written by a build is not trusted
     EfvArgs a{};
     a.n = d.n;
     a.box[0] = d.box[0];

@@ -478,6 +478,7 @@ struct RepDesc {
     float4 *pos4, *bvec, *angbuf, *fown;
     float *vh;
     double *partial;       // [tiles][2]: potential and kinetic energy per tile
+    const int32_t *order;  // [n] processing order of the fused kernel, written by the builds
 };
 struct MdBatchArgs {
     int n_rep, n_tiles, T;

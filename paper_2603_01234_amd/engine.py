@@ -450,11 +450,14 @@ class Server:
     (idle resident replicas are evicted least recently used to make room), and
     then stay resident with their lists.  Every tick advances each replica
     with an active request by one step in one nep_md_step_batch call; requests
-    that arrived meanwhile join at the next tick and finished ones leave."""
+    that arrived meanwhile join at the next tick and finished ones leave.
+    A replica is put into cell order (Replica.sort) when it is admitted and
+    every sort_every of its steps (0: never), which keeps the neighbour
+    gathers of its workgroups local as the beads diffuse."""
 
     def __init__(self, model: Model, systems, skin: float, dt: float, masses: Sequence[float],
                  rebuild_every: int = 10, hbm_budget: Optional[int] = None, max_active: int = 256,
-                 clock=None):
+                 clock=None, sort_every: int = 100):
         import collections
         import time
         self.model = model
@@ -476,6 +479,7 @@ class Server:
         self.evictions = 0
         self.admissions = 0
         self.clock = clock or time.perf_counter
+        self.sort_every = int(sort_every)
 
     # -- residency ------------------------------------------------------------
     def _admit(self, rid: int) -> bool:
@@ -490,6 +494,8 @@ class Server:
         h = self.host[rid]
         r = Replica(self.model, h["pos"], h["types"], h["box"], h["pbc"], skin=self.skin, vel=h["vel"])
         r.step = h["step"]
+        if self.sort_every > 0:
+            r.sort()                                # cell order, lists built
         r.efv(per_bead_virial=False)                # lists and forces at the stored positions
         self.resident[rid] = r
         self.used += need
@@ -540,6 +546,8 @@ class Server:
             self.resident.move_to_end(rid)
             if code != B.NEP_OK:
                 continue                            # lists regrown; the step runs again next tick
+            if self.sort_every > 0 and r.step % self.sort_every == 0:
+                r.sort()
             a = self.active[rid]
             a[1] -= 1
             if a[1] == 0:
