@@ -81,17 +81,22 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main_batch(MdBatchArgs b) {
 }
 
 // Forces, second half-kick, commit of x and v, and per-tile sums of the
-// potential and kinetic energy into the replica's partial buffer.
+// potential and kinetic energy into the replica's partial buffer.  Two lanes
+// per bead (even and odd slots, combined as in the single-system gather), so
+// a workgroup of 2 BLOCK threads covers one tile of BLOCK beads.
 template <int NT>
-__global__ __launch_bounds__(BLOCK) void k_efv_gather_batch(MdBatchArgs b) {
-    __shared__ double red[2][BLOCK];
+__global__ __launch_bounds__(2 * BLOCK) void k_efv_gather_batch(MdBatchArgs b) {
+    __shared__ double red[2][2 * BLOCK];
     const int r = replica_of(b, blockIdx.x);
     const RepDesc &d = b.rep[r];
-    if (d.status[0] & FREEZE_MASK) return;
+    if (d.status[0] & FREEZE_MASK) return;  // uniform over the workgroup
     const int tile = blockIdx.x - b.tile_start[r];
-    const int i = tile * BLOCK + threadIdx.x;
+    const int half = threadIdx.x & 1;
+    const int i = tile * BLOCK + (threadIdx.x >> 1);
     const int n = d.n;
-    double eU = 0.0, eK = 0.0;
+    float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
+    float4 pi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    int ti = 0;
     if (i < n) {
         GatherArgs g{};
         g.n = n;
@@ -104,16 +109,18 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather_batch(MdBatchArgs b) {
         g.bvec = d.bvec;
         g.angbuf = d.angbuf;
         g.fown = d.fown;
-        const float4 pi = d.pos4[i];
-        const int ti = (NT == 1) ? 0 : (int)pi.w;
-        float Fx, Fy, Fz, W[9], Fx1, Fy1, Fz1;
+        pi = d.pos4[i];
+        ti = (NT == 1) ? 0 : (int)pi.w;
+        float W[9];
         int nR = 0, nA = 0;
-        // the even and the odd slots, added as the single-system gather does
-        gather_bead<NT, false>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, 0, 2);
-        gather_bead<NT, false>(g, b.cut, i, pi, ti, Fx1, Fy1, Fz1, W, nR, nA, 1, 2);
-        Fx += Fx1;
-        Fy += Fy1;
-        Fz += Fz1;
+        gather_bead<NT, false>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, half, 2);
+    }
+    // every lane takes part in the exchange: (own + even slots) + odd slots
+    Fx += __shfl_xor(Fx, 1);
+    Fy += __shfl_xor(Fy, 1);
+    Fz += __shfl_xor(Fz, 1);
+    double eU = 0.0, eK = 0.0;
+    if (i < n && half == 0) {
         d.F[i] = Fx;
         d.F[n + i] = Fy;
         d.F[2 * n + i] = Fz;
@@ -133,7 +140,7 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather_batch(MdBatchArgs b) {
     red[0][threadIdx.x] = eU;
     red[1][threadIdx.x] = eK;
     __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    for (int s = BLOCK; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
             red[0][threadIdx.x] += red[0][threadIdx.x + s];
             red[1][threadIdx.x] += red[1][threadIdx.x + s];
@@ -213,10 +220,10 @@ hipError_t launch_efv_md_batch(int T, int HP, const MdBatchArgs &b, hipStream_t 
     }
     if (e != hipSuccess) return e;
     switch (T) {
-        case 1: hipLaunchKernelGGL(k_efv_gather_batch<1>, dim3(b.n_tiles), dim3(BLOCK), 0, s, b); break;
-        case 2: hipLaunchKernelGGL(k_efv_gather_batch<2>, dim3(b.n_tiles), dim3(BLOCK), 0, s, b); break;
-        case 3: hipLaunchKernelGGL(k_efv_gather_batch<3>, dim3(b.n_tiles), dim3(BLOCK), 0, s, b); break;
-        case 4: hipLaunchKernelGGL(k_efv_gather_batch<4>, dim3(b.n_tiles), dim3(BLOCK), 0, s, b); break;
+        case 1: hipLaunchKernelGGL(k_efv_gather_batch<1>, dim3(b.n_tiles), dim3(2 * BLOCK), 0, s, b); break;
+        case 2: hipLaunchKernelGGL(k_efv_gather_batch<2>, dim3(b.n_tiles), dim3(2 * BLOCK), 0, s, b); break;
+        case 3: hipLaunchKernelGGL(k_efv_gather_batch<3>, dim3(b.n_tiles), dim3(2 * BLOCK), 0, s, b); break;
+        case 4: hipLaunchKernelGGL(k_efv_gather_batch<4>, dim3(b.n_tiles), dim3(2 * BLOCK), 0, s, b); break;
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
