@@ -96,21 +96,28 @@ __global__ __launch_bounds__(BS, 2) void k_efv_batch(BatchArgs b) {
         for (int c = 0; c < REC; ++c) acc[c] = 0.0;
         const double *Fr = b.F_ref ? b.F_ref + (size_t)sd.label_off * 3 : nullptr;
         float *Fo = b.F_out ? b.F_out + (size_t)b.F_off[w.z] * 3 : nullptr;
-        for (int i0 = 0; i0 < n; i0 += BS) {
-            const int i = i0 + threadIdx.x;
+        // two lanes per bead (even and odd slots), combined as the
+        // single-system gather does: (own + even) + odd
+        for (int i0 = 0; i0 < n; i0 += BS / 2) {
+            const int i = i0 + (threadIdx.x >> 1);
+            const int half = threadIdx.x & 1;
+            float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, W[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) W[c] = 0.0f;
+            int nR = 0, nA = 0;
             if (i < n) {
                 const float4 pi = pos4[i];
                 const int ti = (NT == 1) ? 0 : (int)pi.w;
-                float Fx, Fy, Fz, W[9], Fx1, Fy1, Fz1, W1[9];
-                int nR = 0, nA = 0;
-                // the even and the odd slots, added as the single-system gather does
-                gather_bead<NT, true>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, 0, 2);
-                gather_bead<NT, true>(g, b.cut, i, pi, ti, Fx1, Fy1, Fz1, W1, nR, nA, 1, 2);
-                Fx += Fx1;
-                Fy += Fy1;
-                Fz += Fz1;
+                gather_bead<NT, true>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, half, 2);
+            }
+            // every lane takes part in the exchange
+            Fx += __shfl_xor(Fx, 1);
+            Fy += __shfl_xor(Fy, 1);
+            Fz += __shfl_xor(Fz, 1);
 #pragma unroll
-                for (int c = 0; c < 9; ++c) W[c] += W1[c];
+            for (int c = 0; c < 9; ++c) W[c] += __shfl_xor(W[c], 1);
+            nR += __shfl_xor(nR, 1);
+            if (i < n && half == 0) {
                 acc[0] += (double)U[i];
                 if (Fr) {
                     const double dx = (double)Fx - Fr[3 * i], dy = (double)Fy - Fr[3 * i + 1],
