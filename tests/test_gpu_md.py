@@ -234,3 +234,44 @@ def test_sort_reorders_in_place_and_keeps_the_physics():
     ref = oracle.efv(spec, params.astype(np.float32).astype(np.float64), rep.positions().astype(np.float64),
                      system.types, system.box.astype(np.float32).astype(np.float64), system.pbc, targets=targets)
     compare_efv(rep, ref, system.n, check_virial=False, targets=targets, label="sorted-md20")
+
+
+def _sampled_parity(rep, spec, params, system, box, seed, label):
+    """Sampled beads of the current state against the oracle (forces
+    re-evaluated on the lists the run left)."""
+    rep.efv(per_bead_virial=False)
+    targets = np.random.default_rng(seed).choice(system.n, 120, replace=False)
+    ref = oracle.efv(spec, params.astype(np.float32).astype(np.float64), rep.positions().astype(np.float64),
+                     system.types, np.asarray(box, np.float32).astype(np.float64), system.pbc, targets=targets)
+    compare_efv(rep, ref, system.n, check_virial=False, targets=targets, label=label)
+
+
+def test_md_config1_snapshots_at_0_500_1000():
+    """The timed workload in full: 216,000 beads, 1000 steps (rebuild every 10
+    on a 0.1 nm skin plus the rebuild test, cell-order sort every 100), the
+    oracle at sampled beads of the snapshots at steps 0, 500 and 1000."""
+    spec, params, system, opts = W.config1()
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv(per_bead_virial=False)
+    _sampled_parity(rep, spec, params, system, system.box, 10, "config1 step 0")
+    for k in (1, 2):
+        rep.md(500, opts["dt"], [W.WATER_MASS], rebuild_every=opts["rebuild_every"], sort_every=100)
+        assert rep.step == 500 * k
+        _sampled_parity(rep, spec, params, system, system.box, 10 + k, f"config1 step {500 * k}")
+
+
+def test_md_config2_strained_wire_snapshots_at_0_250_500():
+    """The 200,000-site Au/CG nanowire (two types, pair cutoffs, H = 50, open
+    across the axis), 500 steps of 5 fs under 1e-4 engineering strain per step
+    along z: the box follows the strain and the oracle matches sampled beads at
+    steps 0, 250 and 500 in the strained box."""
+    spec, params, system, opts = W.config2()
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv(per_bead_virial=False)
+    _sampled_parity(rep, spec, params, system, system.box, 20, "config2 step 0")
+    rate = opts["strain_per_step"]
+    for k in (1, 2):
+        rep.md(250, opts["dt"], system.masses, rebuild_every=opts["rebuild_every"], strain_rate=rate)
+        assert rep.step == 250 * k
+        assert abs(rep.box[2] - np.float32(system.box[2] * (1 + rate[2] * 250 * k))) <= 1e-5 * system.box[2]
+        _sampled_parity(rep, spec, params, system, rep.box, 20 + k, f"config2 step {250 * k}")
