@@ -20,7 +20,17 @@
 //               the neighbour's angular entries in its scratch row
 #include "nep_internal.h"
 
+// The list predicate is exact only with every float operation rounded on its
+// own.  The operations are written here, where contraction into fused
+// multiply-adds is switched off; the library's __f*_rn helpers are compiled
+// under the default setting and get fused once inlined.
+#pragma clang fp contract(off)
+
 namespace nep {
+
+__device__ __forceinline__ float mul_rn(float a, float b) { return a * b; }
+__device__ __forceinline__ float add_rn(float a, float b) { return a + b; }
+__device__ __forceinline__ float sub_rn(float a, float b) { return a - b; }
 
 // A build inside an MD run is skipped when neither the drift's rebuild test
 // nor the schedule asked for one (ctrl[0] == 0), and once the run is frozen
@@ -59,7 +69,7 @@ hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, int gate0, hipStr
 }
 
 __device__ __forceinline__ int cell_coord(float x, float inv_cs, int nc) {
-    float f = floorf(__fmul_rn(x, inv_cs));
+    float f = floorf(mul_rn(x, inv_cs));
     int k = (int)fminf(fmaxf(f, -1.0f), (float)nc);
     return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
 }
@@ -282,7 +292,7 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
     {
         const float pv[3] = {pi.x, pi.y, pi.z};
         for (int d = 0; d < 3; ++d) {
-            const float f = __fmul_rn(pv[d], a.inv_cs[d]);
+            const float f = mul_rn(pv[d], a.inv_cs[d]);
             c0[d] = cell_coord(pv[d], a.inv_cs[d], a.nc[d]);
             u[d] = fminf(fmaxf(f - (float)c0[d], 0.0f), 1.0f);
         }
@@ -339,9 +349,9 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
                 const int s = s5[k], e = e5[k];
                 if (ix < -2 || ix > 2 || iy < -2 || iy > 2 || iz < -2 || iz > 2) { flags |= NEP_FLAG_IMAGE_RANGE; continue; }
                 // s = fl(n L), exact predicate with every operation rounded separately
-                const float sx = __fmul_rn((float)ix, a.box[0]);
-                const float sy = __fmul_rn((float)iy, a.box[1]);
-                const float sz = __fmul_rn((float)iz, a.box[2]);
+                const float sx = mul_rn((float)ix, a.box[0]);
+                const float sy = mul_rn((float)iy, a.box[1]);
+                const float sz = mul_rn((float)iz, a.box[2]);
                 const bool zero_shift = (ix == 0 && iy == 0 && iz == 0);
                 const uint32_t code = (uint32_t)((ix + 2) + 5 * (iy + 2) + 25 * (iz + 2));
                 for (int q0 = s; q0 < e; q0 += 4) {
@@ -357,11 +367,11 @@ __device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, co
                     const int j = (int)(tag & J_MASK);
                     // every component is used before any test, so the candidate
                     // arrives in one 16-byte load
-                    const float ddx = __fsub_rn(__fadd_rn(pj.x, sx), pi.x);
-                    const float ddy = __fsub_rn(__fadd_rn(pj.y, sy), pi.y);
-                    const float ddz = __fsub_rn(__fadd_rn(pj.z, sz), pi.z);
-                    const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ddx, ddx), __fmul_rn(ddy, ddy)),
-                                               __fmul_rn(ddz, ddz));
+                    const float ddx = sub_rn(add_rn(pj.x, sx), pi.x);
+                    const float ddy = sub_rn(add_rn(pj.y, sy), pi.y);
+                    const float ddz = sub_rn(add_rn(pj.z, sz), pi.z);
+                    const float d2 = add_rn(add_rn(mul_rn(ddx, ddx), mul_rn(ddy, ddy)),
+                                               mul_rn(ddz, ddz));
                     const float4 th = thr_i[tag >> CODE_SHIFT];
                     if (!(d2 < th.x) || (j == i && zero_shift)) continue;
                     if (d2 == 0.0f) flags |= NEP_FLAG_OVERLAP;
