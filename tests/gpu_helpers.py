@@ -59,3 +59,33 @@ def gpu_sets(rep, rows):
         assert len(set(ent)) == len(ent), f"duplicate entries in row {i}"
         out[i] = (set(ent), set(ent[:ca]))
     return out
+
+
+def _fma32(a, b, c):
+    """float32 fused multiply-add, fl(a b + c) rounded once (a b is exact in
+    float64, and for the magnitudes used here so is the sum)."""
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
+
+
+def predicate_edge_pairs(rng, rc2, count, batch=8192, lo=(0.5, 0.5, 0.5)):
+    """float32 position pairs (x_i, x_j), no image, at the list cutoff rc2,
+    chosen where the separately rounded d2 of the list predicate and a
+    multiply-add evaluation of it fall on opposite sides of rc2.  A build that
+    fused the predicate would get each of these pairs wrong.  x_i is drawn in
+    [lo, lo + 1) per coordinate, so a pair is made where it will be used (a
+    later shift would round its coordinates again)."""
+    rc2 = np.float32(rc2)
+    r = float(np.sqrt(np.float64(rc2)))
+    out_i, out_j = [], []
+    while sum(len(x) for x in out_i) < count:
+        v = rng.normal(size=(batch, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        xi = (np.asarray(lo, np.float64) + rng.uniform(0.0, 1.0, size=(batch, 3))).astype(np.float32)
+        xj = (xi.astype(np.float64) + v * r).astype(np.float32)
+        d = xj - xi                                            # float32, rounded once each
+        sep = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        fused = _fma32(d[:, 2], d[:, 2], _fma32(d[:, 1], d[:, 1], d[:, 0] * d[:, 0]))
+        pick = (sep < rc2) != (fused < rc2)
+        out_i.append(xi[pick])
+        out_j.append(xj[pick])
+    return np.concatenate(out_i)[:count], np.concatenate(out_j)[:count]

@@ -79,6 +79,43 @@ def test_neighbor_sets_small_boxes_with_images(box):
     _check_sets(rep, spec, system, 0.05, range(system.n))
 
 
+def test_neighbor_predicate_is_never_fused():
+    """Pairs at the radial and the angular list cutoff where a fused
+    multiply-add and separate rounding of d2 disagree, each far from the others
+    in an open box: the device lists equal the float32 reference on every one
+    (a build that contracted the predicate would miss or add some)."""
+    from gpu_helpers import predicate_edge_pairs
+    from oracle.neighbors_f32 import cutoff_sq_table
+    E = _engine()
+    spec = W.water_spec(8)
+    params = W.draw_params(spec, np.random.default_rng(4))
+    rng = np.random.default_rng(7)
+    pos = []
+    k = 0
+    for rc in (spec.rc_R, spec.rc_A):
+        rc2 = cutoff_sq_table(rc, 0.1)[0, 0]
+        for _ in range(8):
+            lo = (4.0 * (k % 4) + 0.5, 4.0 * ((k // 4) % 2) + 0.5, 4.0 * (k // 8) + 0.5)
+            xi, xj = predicate_edge_pairs(rng, rc2, 1, lo=lo)
+            pos += [xi[0], xj[0]]
+            k += 1
+    pos = np.asarray(pos, np.float32)
+    types = np.zeros(pos.shape[0], np.uint8)
+    box, pbc = (16.0, 8.0, 8.0), [False, False, False]
+    model = E.Model.from_spec(spec, params)
+    rep = E.Replica(model, pos, types, box, pbc, skin=0.1)
+    rep.build()
+    got = gpu_sets(rep, range(rep.n))
+    refR = neighbor_sets(pos, types, box, pbc, spec.rc_R, 0.1)
+    refA = neighbor_sets(pos, types, box, pbc, spec.rc_A, 0.1)
+    kept = 0
+    for i in range(rep.n):
+        assert got[i][0] == refR[i], f"row {i}: radial set differs"
+        assert got[i][1] == refA[i], f"row {i}: angular prefix differs"
+        kept += len(refR[i])
+    assert 0 < kept < 2 * 16             # some edge pairs are in, some out
+
+
 def test_neighbor_sets_open_and_mixed_boundaries():
     spec, params, system = _small_two_type(5, 40, (3.0, 3.0, 3.0), [False, True, False], H=8)
     rep = _replica(spec, params, system, skin=0.1)
