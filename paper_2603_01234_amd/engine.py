@@ -53,7 +53,7 @@ class Model:
 
 
 MAX_CAP = 4096      # row capacity limit of the library
-MAX_CAP_A = 255     # angular-prefix capacity limit (segment offsets are bytes)
+MAX_CAP_A = 255     # angular-prefix capacity limit (the build keeps the in-cutoff angular count in a byte)
 
 
 def estimate_caps(n, box, pbc, rc_max, rcA_max, skin, pos=None):
