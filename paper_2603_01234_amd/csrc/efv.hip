@@ -57,11 +57,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int t = tile * BLOCK + threadIdx.x;
     if (t >= a.n) return;
-#if defined(NEP_ORDER_B) && NEP_ORDER_B == 0
-    int i = t;
-#else
     int i = a.order ? a.order[t] : t;
-#endif
     if ((unsigned)i >= (unsigned)a.n) i = t;  // an order never written by a build is not trusted
     main_bead<NT, HP>(a, a.cut, TB, i);
 }

@@ -427,6 +427,14 @@ __global__ __launch_bounds__(BLOCK) void k_nb_rows(NbArgs a) { nb_rows_body(a, b
 // scratch row, follow in the order they were found.  A workgroup moves its
 // 256 beads through LDS 16 slots at a time: each wave reads 16 consecutive
 // slots of four rows, and writes one slot of 64 consecutive beads.
+//
+// The same workgroup writes the processing order of its beads for the fused
+// kernel.  A bead's cost grows with its row (an angular pair inside r_c^A costs
+// about twenty radial list entries), and a wave takes as long as its busiest
+// lane, so the beads of the block (neighbours in space for a spatially ordered
+// system) are ordered by decreasing cost, ties by index: the lanes of a wave
+// then carry similar work.  The order only decides which thread evaluates
+// which bead; every result is the same bit for bit.
 constexpr int TR_SLOTS = 16;
 
 __device__ __forceinline__ int row_src(int p, int na, int nai, int nri, int A4, int R4) {
@@ -459,6 +467,19 @@ __device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int g
     if (__lane_id() == 0) atomicMax(&max_total, m);
     __syncthreads();
     const int mt = max_total;
+    if (a.order) {
+        // rank of this bead among the block's beads by decreasing cost
+        const int b = threadIdx.x;
+        const int nb = min(BLOCK, n - i0);
+        const int cost = 20 * f.z + f.x;
+        int rank = 0;
+        for (int k = 0; k < nb; ++k) {
+            const int4 g = info[k];
+            const int ck = 20 * g.z + g.x;
+            rank += (ck > cost || (ck == cost && k < b)) ? 1 : 0;
+        }
+        if (b < nb) a.order[i0 + rank] = i0 + b;
+    }
     constexpr int BEADS_PER_PASS = BLOCK / TR_SLOTS;
     const int pl = threadIdx.x % TR_SLOTS, bsub = threadIdx.x / TR_SLOTS;
     for (int p0 = 0; p0 < mt; p0 += TR_SLOTS) {
@@ -548,51 +569,7 @@ __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
     nb_reverse_body(a, blockIdx.x, gridDim.x, blockIdx.y, gridDim.y);
 }
 
-// Processing order of the fused kernel.  Its cost per bead grows with the
-// row lengths (an angular pair costs many radial entries), and a wave takes
-// as long as its busiest lane, so within every block of ORDER_B consecutive
-// beads (neighbours in space for a spatially ordered system) the beads are
-// ordered by decreasing cost: the lanes of a wave then carry similar work.
-// The order only decides which thread evaluates which bead; every result is
-// the same bit for bit.
-#ifndef NEP_ORDER_B
-#define NEP_ORDER_B 256
-#endif
-constexpr int ORDER_B = NEP_ORDER_B > 0 ? NEP_ORDER_B : 1;
-constexpr int ORDER_T = 1024;  // threads per block of the order kernel
-constexpr int ORDER_KEYS = 1024;
 
-__device__ __forceinline__ int order_key(const NbArgs &a, int i) {
-    // an angular pair inside r_c^A costs about twenty radial list entries
-    const int k = (20 * (a.cls[i] & 255) + a.cnt[i]) >> 3;
-    return ORDER_KEYS - 1 - min(k, ORDER_KEYS - 1);  // ascending key = decreasing cost
-}
-
-__device__ __forceinline__ void nb_order_body(const NbArgs &a, int bx) {
-    if (build_off(a) || !a.order) return;
-    __shared__ int hist[ORDER_KEYS];
-    const int base = bx * ORDER_B;
-    const int len = min(ORDER_B, a.n - base);
-    for (int k = threadIdx.x; k < ORDER_KEYS; k += blockDim.x) hist[k] = 0;
-    __syncthreads();
-    for (int q = threadIdx.x; q < len; q += blockDim.x) atomicAdd(&hist[order_key(a, base + q)], 1);
-    __syncthreads();
-    if (threadIdx.x == 0) {  // exclusive scan of 1024 bins (short, once per block)
-        int run = 0;
-        for (int k = 0; k < ORDER_KEYS; ++k) {
-            const int v = hist[k];
-            hist[k] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < len; q += blockDim.x) {
-        const int i = base + q;
-        a.order[base + atomicAdd(&hist[order_key(a, i)], 1)] = i;
-    }
-}
-
-__global__ __launch_bounds__(ORDER_T) void k_nb_order(NbArgs a) { nb_order_body(a, blockIdx.x); }
 
 hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     int nbk = (a.n + BLOCK - 1) / BLOCK;
@@ -610,8 +587,6 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_nb_rows, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_transpose, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_reverse, dim3(nbk, (a.cap_A + REV_SLOTS - 1) / REV_SLOTS), dim3(BLOCK), 0, s, a);
-    if (a.order && NEP_ORDER_B > 0)
-        hipLaunchKernelGGL(k_nb_order, dim3((a.n + ORDER_B - 1) / ORDER_B), dim3(ORDER_T), 0, s, a);
     return hipGetLastError();
 }
 
@@ -620,10 +595,10 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
 // ---- one launch per phase over the builds of many systems ----
 // start[ph][r] is the first block of system r in phase ph (tables of
 // n_sys + 1 entries, one per tile kind: cells to clear, beads, scan blocks,
-// the one-block scan, cells to offset, (bead, slot-group) pairs, and blocks of
-// the processing order).
-enum { NB_TILE_CLEAR = 0, NB_TILE_BEAD, NB_TILE_SCANL, NB_TILE_SCANB, NB_TILE_SCANA, NB_TILE_REV, NB_TILE_ORDER, NB_TILES };
-enum { OP_CLEAR, OP_BIN, OP_SCANL, OP_SCANB, OP_SCANA, OP_FILL, OP_RANK, OP_ROWS, OP_TRANSPOSE, OP_REVERSE, OP_ORDER };
+// the one-block scan, cells to offset, and (bead, slot-group) pairs).
+enum { NB_TILE_CLEAR = 0, NB_TILE_BEAD, NB_TILE_SCANL, NB_TILE_SCANB, NB_TILE_SCANA, NB_TILE_REV, NB_TILES };
+static_assert(NB_TILES == NB_BATCH_TILES, "tile kinds of the batched build");
+enum { OP_CLEAR, OP_BIN, OP_SCANL, OP_SCANB, OP_SCANA, OP_FILL, OP_RANK, OP_ROWS, OP_TRANSPOSE, OP_REVERSE };
 
 template <int OP>
 __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
@@ -632,7 +607,6 @@ __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
                          : OP == OP_SCANB ? NB_TILE_SCANB
                          : OP == OP_SCANA ? NB_TILE_SCANA
                          : OP == OP_REVERSE ? NB_TILE_REV
-                         : OP == OP_ORDER   ? NB_TILE_ORDER
                                             : NB_TILE_BEAD;
     const int *st = b.start + TILE * (b.n_sys + 1);
     int lo = 0, hi = b.n_sys - 1;  // last system whose first block is <= blockIdx.x
@@ -656,7 +630,6 @@ __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
         const int nbk = (a.n + BLOCK - 1) / BLOCK;
         nb_reverse_body(a, bx % nbk, nbk, bx / nbk, gx / nbk);
     }
-    if constexpr (OP == OP_ORDER) nb_order_body(a, bx);
 }
 
 void nb_batch_tiles(const NbArgs &a, int counts[NB_BATCH_TILES]) {
@@ -668,7 +641,6 @@ void nb_batch_tiles(const NbArgs &a, int counts[NB_BATCH_TILES]) {
     counts[NB_TILE_SCANB] = 1;
     counts[NB_TILE_SCANA] = cbk;
     counts[NB_TILE_REV] = nbk * ((a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
-    counts[NB_TILE_ORDER] = a.order ? (a.n + ORDER_B - 1) / ORDER_B : 0;
 }
 
 hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[NB_BATCH_TILES], hipStream_t s) {
@@ -685,7 +657,6 @@ hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[NB_BATCH_TI
     NB_LAUNCH(OP_ROWS, NB_TILE_BEAD)
     NB_LAUNCH(OP_TRANSPOSE, NB_TILE_BEAD)
     NB_LAUNCH(OP_REVERSE, NB_TILE_REV)
-    NB_LAUNCH(OP_ORDER, NB_TILE_ORDER)
 #undef NB_LAUNCH
     return hipGetLastError();
 }
