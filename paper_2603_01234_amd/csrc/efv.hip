@@ -1,7 +1,9 @@
 // NEP energy / force / virial kernels (paper Sec. II.A, Eqs. 2-8; forces from
 // E = sum_i U_i; per-site virial of Eq. 15, total of Eq. 16).
 //
-// One thread per bead ("centre"), 256 beads per workgroup, XCD-aware tile map.
+// k_efv_main: one thread per bead ("centre"), 256 beads per workgroup in a
+// cost order written by the build; k_efv_gather: two lanes per bead.  Both
+// with an XCD-aware tile map.
 //
 // k_efv_main    pass 1: loop over the bead's list; radial sums
 //                 S_0 = sum hfc,  S_k = sum hfc T_k(x)        (hfc = f_c / 2)
@@ -12,11 +14,12 @@
 //               network (Eq. 2) and dU/dq; radial back-propagation
 //               coefficients beta_k = sum_n dU/dq_n c_nk stored per bead;
 //               pass 2 over the angular candidates: angular part of
-//               dU_i/dr_ij into a per-slot buffer, and their sum.
+//               dU_i/dr_ij into the slot where j lists i (reverse index),
+//               and their sum.
 // k_efv_gather  F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji):
 //               radial part of both terms from the pair geometry and the two
 //               beads' beta vectors (no pair buffer); angular dU_j/dr_ji read
-//               through the reverse index; per-site virial
+//               coalesced from the bead's own slots; per-site virial
 //               W_i = sum_j r_ij (x) dU_j/dr_ji; fixed-order block sums of U,
 //               W and (for MD) the kinetic energy; optional second half-kick.
 // k_reduce      fixed-order FP64 reduction of the block sums.
@@ -64,8 +67,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
 
 // Two lanes per bead: the even and the odd slots of its row, combined with
 // one lane exchange (more waves in flight for the neighbour gathers).  The
-// sum is (own angular sum + even slots) + odd slots; the batched kernels,
-// with one lane per bead, add the two parts in the same way.
+// sum is (own angular sum + even slots) + odd slots; the batched and the
+// served gathers split and add the two parts in the same way.
 constexpr int GATHER_BEADS = BLOCK / 2;
 
 template <int NT, bool VIR, bool MD>

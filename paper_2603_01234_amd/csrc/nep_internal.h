@@ -334,8 +334,9 @@ hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, int gate0, hipStr
 
 // First half of a velocity-Verlet step.  Reads x, v, F; writes the half-step
 // velocities to vh and the drifted (and strained) positions to pos4, leaving
-// x and v to the gather kernel that completes the step.  Switches the rebuild
-// gate on when a bead ends up farther than sqrt(gate2) from its build position.
+// x and v to the gather kernel that completes the step.  Each workgroup leaves
+// the largest and second largest displacement of its beads in top2 for the
+// rebuild test below.
 struct KickDriftArgs {
     int n;
     const float *x, *y, *z;
