@@ -336,8 +336,9 @@ int nep_batch_autotune(const nep_model *models, int n_models, const nep_system *
  * (host-side objects only) and enables recording, for the classes whose bit
  * is set in class_mask (bit c for class c), in the calling process; launches
  * beyond the pool are not timed.  Every event pair adds a little time on the
- * device, so a throughput measurement times only the class it needs.  nep_timing_end synchronises on the recorded events,
- * writes the summed milliseconds and launch counts per class into ms[4] and
+ * device, so a throughput measurement times only the class it needs.
+ * nep_timing_end synchronises on the recorded events, writes the summed
+ * milliseconds and launch counts per class into ms[4] and
  * launches[4] (host), destroys the pool and disables recording.  Not
  * thread-safe: meant for a single benchmarking thread. */
 int nep_timing_begin(int max_launches, unsigned class_mask);

@@ -74,8 +74,8 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
         return o;
     };
     size_t nn = (size_t)(n > 0 ? n : 1);
-    // workgroups of the gather kernel (two lanes per bead), one partial record each
-    L.nblocks = (int)((nn + BLOCK / 2 - 1) / (BLOCK / 2));
+    // workgroups of the gather kernel (GATHER_LANES lanes per bead), one partial record each
+    L.nblocks = (int)((nn + BLOCK / GATHER_LANES - 1) / (BLOCK / GATHER_LANES));
     L.ncell_max = std::max(64, 2 * n);
     L.pos4 = take(nn * 16);
     L.bvec = take(nn * (size_t)T * 48);

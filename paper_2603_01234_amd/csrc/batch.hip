@@ -96,11 +96,10 @@ __global__ __launch_bounds__(BS, 2) void k_efv_batch(BatchArgs b) {
         for (int c = 0; c < REC; ++c) acc[c] = 0.0;
         const double *Fr = b.F_ref ? b.F_ref + (size_t)sd.label_off * 3 : nullptr;
         float *Fo = b.F_out ? b.F_out + (size_t)b.F_off[w.z] * 3 : nullptr;
-        // two lanes per bead (even and odd slots), combined as the
-        // single-system gather does: (own + even) + odd
-        for (int i0 = 0; i0 < n; i0 += BS / 2) {
-            const int i = i0 + (threadIdx.x >> 1);
-            const int half = threadIdx.x & 1;
+        // GATHER_LANES lanes per bead, combined as the single-system gather does
+        for (int i0 = 0; i0 < n; i0 += BS / GATHER_LANES) {
+            const int i = i0 + (int)(threadIdx.x / GATHER_LANES);
+            const int q = threadIdx.x % GATHER_LANES;
             float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, W[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) W[c] = 0.0f;
@@ -108,16 +107,19 @@ __global__ __launch_bounds__(BS, 2) void k_efv_batch(BatchArgs b) {
             if (i < n) {
                 const float4 pi = pos4[i];
                 const int ti = (NT == 1) ? 0 : (int)pi.w;
-                gather_bead<NT, true>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, half, 2);
+                gather_bead<NT, true>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, q, GATHER_LANES);
             }
             // every lane takes part in the exchange
-            Fx += __shfl_xor(Fx, 1);
-            Fy += __shfl_xor(Fy, 1);
-            Fz += __shfl_xor(Fz, 1);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) W[c] += __shfl_xor(W[c], 1);
-            nR += __shfl_xor(nR, 1);
-            if (i < n && half == 0) {
+            for (int o = 1; o < GATHER_LANES; o <<= 1) {
+                Fx += __shfl_xor(Fx, o);
+                Fy += __shfl_xor(Fy, o);
+                Fz += __shfl_xor(Fz, o);
+#pragma unroll
+                for (int c = 0; c < 9; ++c) W[c] += __shfl_xor(W[c], o);
+                nR += __shfl_xor(nR, o);
+            }
+            if (i < n && q == 0) {
                 acc[0] += (double)U[i];
                 if (Fr) {
                     const double dx = (double)Fx - Fr[3 * i], dy = (double)Fy - Fr[3 * i + 1],

@@ -2,7 +2,7 @@
 // E = sum_i U_i; per-site virial of Eq. 15, total of Eq. 16).
 //
 // k_efv_main: one thread per bead ("centre"), 256 beads per workgroup in a
-// cost order written by the build; k_efv_gather: two lanes per bead.  Both
+// cost order written by the build; k_efv_gather: four lanes per bead.  Both
 // with an XCD-aware tile map.
 //
 // k_efv_main    pass 1: loop over the bead's list; radial sums
@@ -69,15 +69,15 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
 // one lane exchange (more waves in flight for the neighbour gathers).  The
 // sum is (own angular sum + even slots) + odd slots; the batched and the
 // served gathers split and add the two parts in the same way.
-constexpr int GATHER_BEADS = BLOCK / 2;
+constexpr int GATHER_BEADS = BLOCK / GATHER_LANES;
 
 template <int NT, bool VIR, bool MD>
 __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
-    __shared__ double red[NPART][BLOCK];
+    __shared__ double red[NPART][BLOCK / 64];
     if (MD && a.freeze && (a.freeze[0] & FREEZE_MASK)) return;  // uniform over the grid
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int half = threadIdx.x & 1;
-    const int i = tile * GATHER_BEADS + (threadIdx.x >> 1);
+    const int q = threadIdx.x % GATHER_LANES;
+    const int i = tile * GATHER_BEADS + (int)(threadIdx.x / GATHER_LANES);
     const int n = a.n;
     double acc[NPART];
 #pragma unroll
@@ -91,19 +91,22 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
     if (i < n) {
         pi = a.pos4[i];
         ti = (NT == 1) ? 0 : (int)pi.w;
-        gather_bead<NT, VIR>(a, a.cut, i, pi, ti, Fx, Fy, Fz, W, nR_in, nA_in, half, 2);
+        gather_bead<NT, VIR>(a, a.cut, i, pi, ti, Fx, Fy, Fz, W, nR_in, nA_in, q, GATHER_LANES);
     }
     // every lane takes part in the exchange
-    Fx += __shfl_xor(Fx, 1);
-    Fy += __shfl_xor(Fy, 1);
-    Fz += __shfl_xor(Fz, 1);
-    if (VIR) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) W[c] += __shfl_xor(W[c], 1);
+    for (int o = 1; o < GATHER_LANES; o <<= 1) {
+        Fx += __shfl_xor(Fx, o);
+        Fy += __shfl_xor(Fy, o);
+        Fz += __shfl_xor(Fz, o);
+        if (VIR) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) W[c] += __shfl_xor(W[c], o);
+        }
+        nR_in += __shfl_xor(nR_in, o);
+        nA_in += __shfl_xor(nA_in, o);
     }
-    nR_in += __shfl_xor(nR_in, 1);
-    nA_in += __shfl_xor(nA_in, 1);
-    if (i < n && half == 0) {
+    if (i < n && q == 0) {
         a.F[i] = Fx;
         a.F[n + i] = Fy;
         a.F[2 * n + i] = Fz;
@@ -140,25 +143,29 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
         // displacement since the build, for the completeness test of the lists
         // (the reduction merges the blocks' pairs)
         float d2 = 0.0f;
-        if (i < n && half == 0) {
+        if (i < n && q == 0) {
             const float dx = pi.x - a.ref[i], dy = pi.y - a.ref[n + i], dz = pi.z - a.ref[2 * n + i];
             d2 = dx * dx + dy * dy + dz * dz;
         }
         const float2 t = block_top2(d2, 0.0f);
         if (threadIdx.x == 0) a.top2[tile] = t;
     }
-    // fixed-order block reduction
+    // fixed-order block sums: a butterfly within each wave (lane 0's result),
+    // then the waves in order
 #pragma unroll
-    for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+    for (int c = 0; c < NPART; ++c) {
+        double v = acc[c];
 #pragma unroll
-            for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
-        }
-        __syncthreads();
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        if (__lane_id() == 0) red[c][threadIdx.x >> 6] = v;
     }
-    if (threadIdx.x < NPART) a.partial[(size_t)tile * NPART + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < NPART) {
+        double v = red[threadIdx.x][0];
+#pragma unroll
+        for (int w = 1; w < BLOCK / 64; ++w) v += red[threadIdx.x][w];
+        a.partial[(size_t)tile * NPART + threadIdx.x] = v;
+    }
 }
 
 // Fixed-order FP64 reduction of the block partials.  In MD mode (ctrl given)

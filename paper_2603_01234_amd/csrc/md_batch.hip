@@ -81,18 +81,18 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main_batch(MdBatchArgs b) {
 }
 
 // Forces, second half-kick, commit of x and v, and per-tile sums of the
-// potential and kinetic energy into the replica's partial buffer.  Two lanes
-// per bead (even and odd slots, combined as in the single-system gather), so
-// a workgroup of 2 BLOCK threads covers one tile of BLOCK beads.
+// potential and kinetic energy into the replica's partial buffer.
+// GATHER_LANES lanes per bead (combined as in the single-system gather), so a
+// workgroup of GATHER_LANES * BLOCK threads covers one tile of BLOCK beads.
 template <int NT>
-__global__ __launch_bounds__(2 * BLOCK) void k_efv_gather_batch(MdBatchArgs b) {
-    __shared__ double red[2][2 * BLOCK];
+__global__ __launch_bounds__(GATHER_LANES * BLOCK) void k_efv_gather_batch(MdBatchArgs b) {
+    __shared__ double red[2][GATHER_LANES * BLOCK];
     const int r = replica_of(b, blockIdx.x);
     const RepDesc &d = b.rep[r];
     if (d.status[0] & FREEZE_MASK) return;  // uniform over the workgroup
     const int tile = blockIdx.x - b.tile_start[r];
-    const int half = threadIdx.x & 1;
-    const int i = tile * BLOCK + (threadIdx.x >> 1);
+    const int q = threadIdx.x % GATHER_LANES;
+    const int i = tile * BLOCK + (int)(threadIdx.x / GATHER_LANES);
     const int n = d.n;
     float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
     float4 pi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -113,14 +113,17 @@ __global__ __launch_bounds__(2 * BLOCK) void k_efv_gather_batch(MdBatchArgs b) {
         ti = (NT == 1) ? 0 : (int)pi.w;
         float W[9];
         int nR = 0, nA = 0;
-        gather_bead<NT, false>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, half, 2);
+        gather_bead<NT, false>(g, b.cut, i, pi, ti, Fx, Fy, Fz, W, nR, nA, q, GATHER_LANES);
     }
-    // every lane takes part in the exchange: (own + even slots) + odd slots
-    Fx += __shfl_xor(Fx, 1);
-    Fy += __shfl_xor(Fy, 1);
-    Fz += __shfl_xor(Fz, 1);
+    // every lane takes part in the exchange
+#pragma unroll
+    for (int o = 1; o < GATHER_LANES; o <<= 1) {
+        Fx += __shfl_xor(Fx, o);
+        Fy += __shfl_xor(Fy, o);
+        Fz += __shfl_xor(Fz, o);
+    }
     double eU = 0.0, eK = 0.0;
-    if (i < n && half == 0) {
+    if (i < n && q == 0) {
         d.F[i] = Fx;
         d.F[n + i] = Fy;
         d.F[2 * n + i] = Fz;
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(2 * BLOCK) void k_efv_gather_batch(MdBatchArgs b) {
     red[0][threadIdx.x] = eU;
     red[1][threadIdx.x] = eK;
     __syncthreads();
-    for (int s = BLOCK; s > 0; s >>= 1) {
+    for (int s = GATHER_LANES * BLOCK / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
             red[0][threadIdx.x] += red[0][threadIdx.x + s];
             red[1][threadIdx.x] += red[1][threadIdx.x + s];
@@ -220,10 +223,10 @@ hipError_t launch_efv_md_batch(int T, int HP, const MdBatchArgs &b, hipStream_t 
     }
     if (e != hipSuccess) return e;
     switch (T) {
-        case 1: hipLaunchKernelGGL(k_efv_gather_batch<1>, dim3(b.n_tiles), dim3(2 * BLOCK), 0, s, b); break;
-        case 2: hipLaunchKernelGGL(k_efv_gather_batch<2>, dim3(b.n_tiles), dim3(2 * BLOCK), 0, s, b); break;
-        case 3: hipLaunchKernelGGL(k_efv_gather_batch<3>, dim3(b.n_tiles), dim3(2 * BLOCK), 0, s, b); break;
-        case 4: hipLaunchKernelGGL(k_efv_gather_batch<4>, dim3(b.n_tiles), dim3(2 * BLOCK), 0, s, b); break;
+        case 1: hipLaunchKernelGGL(k_efv_gather_batch<1>, dim3(b.n_tiles), dim3(GATHER_LANES * BLOCK), 0, s, b); break;
+        case 2: hipLaunchKernelGGL(k_efv_gather_batch<2>, dim3(b.n_tiles), dim3(GATHER_LANES * BLOCK), 0, s, b); break;
+        case 3: hipLaunchKernelGGL(k_efv_gather_batch<3>, dim3(b.n_tiles), dim3(GATHER_LANES * BLOCK), 0, s, b); break;
+        case 4: hipLaunchKernelGGL(k_efv_gather_batch<4>, dim3(b.n_tiles), dim3(GATHER_LANES * BLOCK), 0, s, b); break;
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

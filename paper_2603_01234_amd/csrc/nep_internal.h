@@ -24,6 +24,11 @@ constexpr int CODE_SHIFT = 25;
 constexpr float ACCEL = 9.648533212e-5f;  // nm/fs^2 per (eV/nm)/amu
 // per-block partial sums: U, W (9), kinetic energy, radial pairs, angular pairs
 constexpr int NPART = 13;
+// lanes per bead in the gathers: lane q takes slots q, q + 4, ... of the row,
+// and the lane sums are combined by a shuffle butterfly (the same order in the
+// single-system, batched MD and fitness gathers)
+constexpr int GATHER_LANES = 4;
+static_assert(GATHER_LANES * BLOCK <= 1024, "batched MD gather workgroup too large");
 // status flags after which the MD kernels do nothing (the lists are invalid)
 constexpr int FREEZE_MASK = NEP_FLAG_OVERFLOW_R | NEP_FLAG_OVERFLOW_A | NEP_FLAG_NONFINITE |
                             NEP_FLAG_OUTSIDE_BOX | NEP_FLAG_IMAGE_RANGE | NEP_FLAG_BAD_TYPE;
