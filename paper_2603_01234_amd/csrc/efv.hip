@@ -65,10 +65,10 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
     main_bead<NT, HP>(a, a.cut, TB, i);
 }
 
-// Two lanes per bead: the even and the odd slots of its row, combined with
-// one lane exchange (more waves in flight for the neighbour gathers).  The
-// sum is (own angular sum + even slots) + odd slots; the batched and the
-// served gathers split and add the two parts in the same way.
+// GATHER_LANES lanes per bead: lane q takes slots q, q + GATHER_LANES, ... of
+// the row (lane 0 also the bead's own angular sum), and the lane sums are
+// combined by a shuffle butterfly (more waves in flight for the neighbour
+// gathers).  The batched and the served gathers split and add in the same way.
 constexpr int GATHER_BEADS = BLOCK / GATHER_LANES;
 
 template <int NT, bool VIR, bool MD>

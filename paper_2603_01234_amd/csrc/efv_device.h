@@ -59,18 +59,54 @@ struct RowStream {
         e_nxt = p0 < c ? nbr[(size_t)min(p0 + step, c - 1) * n + i] : 0u;
         p_cur = p0 < c ? pos4[e_cur & J_MASK] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-    // Called only for slots p < cnt.  The look-ahead loads are unconditional
-    // (past the end they read the row's last entry again): a conditional load
-    // makes the compiler wait for every load in flight at the join, which
-    // would take away the look-ahead.
-    __device__ __forceinline__ void next(int p, uint32_t &e, float4 &pj) {
-        e = e_cur;
-        pj = p_cur;
+    // The pair geometry of slot p (called only for slots p < cnt), then the
+    // look-ahead loads.  These are unconditional (past the end they read the
+    // row's last entry again): a conditional load makes the compiler wait for
+    // every load in flight at the join, which would take away the look-ahead.
+    __device__ __forceinline__ PairGeom next_geom(int p, const float4 &pi, const float box[3]) {
+        const PairGeom g = geom_of(e_cur, p_cur, pi, box);
         e_cur = e_nxt;
         e_nxt = nbr[(size_t)min(p + 2 * step, cnt - 1) * n + i];
         p_cur = pos4[e_cur & J_MASK];
+        return g;
     }
 };
+
+// Slots p0, p0 + step, ... of row i (c entries) in two interleaved sets (the
+// even and odd positions of that sequence), each with its own registers: a
+// set's position is loaded two slots ahead and its entry four slots ahead.
+// Each load writes the register its previous value was just read from, so
+// the loop carries no register copies: a copy at the back edge waits for the
+// load it copies, which leaves the single-set stream (RowStream) only one
+// slot of look-ahead.  The loads are unconditional and clamped to the row's
+// last entry; body(p, g) runs for slots p < c, in slot order.
+template <class Body>
+__device__ __forceinline__ void for_each_slot2(const uint32_t *__restrict__ nbr, const float4 *__restrict__ pos4,
+                                               int n, int i, int c, int p0, int step, const float4 &pi,
+                                               const float box[3], Body &&body) {
+    if (p0 >= c) return;
+    const int last = c - 1;
+    auto entry = [&](int p) { return nbr[(size_t)min(p, last) * n + i]; };
+    // issued in the loop's own order (position, entry; set A, then B), so the
+    // waits at the loop head are the same from either edge
+    uint32_t eA = entry(p0), eB = entry(p0 + step);
+    float4 PA = pos4[eA & J_MASK];
+    uint32_t aA = entry(p0 + 2 * step);
+    float4 PB = pos4[eB & J_MASK];
+    uint32_t aB = entry(p0 + 3 * step);
+    for (int p = p0; p < c; p += 2 * step) {
+        const PairGeom gA = geom_of(eA, PA, pi, box);
+        eA = aA;
+        PA = pos4[eA & J_MASK];
+        aA = entry(p + 4 * step);
+        body(p, gA);
+        const PairGeom gB = geom_of(eB, PB, pi, box);
+        eB = aB;
+        PB = pos4[eB & J_MASK];
+        aB = entry(p + 5 * step);
+        if (p + step < c) body(p + step, gB);
+    }
+}
 
 // Tables read through the constant address space: with wave-uniform addresses
 // (one type) these become scalar loads whose values feed the FMAs as SGPR
@@ -233,13 +269,9 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
         for (int l = 0; l < LM; ++l) A[q][l] = 0.0f;
 
     // ---------------- pass 1: descriptor sums ----------------
-    RowStream rs;
-    rs.start(a.nbr, a.pos4, n, i, cR);
-    for (int p = 0; p < cR; ++p) {
-        uint32_t e;
-        float4 pj;
-        rs.next(p, e, pj);
-        const PairGeom g = geom_of(e, pj, pi, a.box);
+    // (two-set stream: the radial-only slots are short, so one slot of
+    // look-ahead does not cover the position loads)
+    auto pass1 = [&](const int p, const PairGeom &g) {
         const int tj = (NT == 1) ? 0 : g.tj;
         const int tp = ti * NT + tj;
         if (g.d2 < cut.rcR2[tp]) {
@@ -275,7 +307,8 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
                 accumulate_harmonics(g.dx * ir, g.dy * ir, g.dz * ir, gv, A);
             }
         }
-    }
+    };
+    for_each_slot2(a.nbr, a.pos4, n, i, cR, 0, 1, pi, a.box, pass1);
 
     // ---------------- descriptor, network (Eq. 2), back-propagation ----------------
     // evaluated with a wave-uniform centre type so the weights are scalar loads;
@@ -300,12 +333,13 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
     asm volatile("" ::: "memory");
     // ---------------- pass 2: angular pair partials ----------------
     float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+    RowStream rs;
     rs.start(a.nbr, a.pos4, n, i, cA);
     for (int p = 0; p < cA; ++p) {
-        uint32_t e;
-        float4 pj;
-        rs.next(p, e, pj);
-        const PairGeom g = geom_of(e, pj, pi, a.box);
+        // the reverse slot is read before the look-ahead loads are issued, so
+        // the wait for it at the store leaves them in flight
+        const int r = a.rev[(size_t)p * n + i];
+        const PairGeom g = rs.next_geom(p, pi, a.box);
         const int tj = (NT == 1) ? 0 : g.tj;
         const int tp = ti * NT + tj;
         float ox = 0.0f, oy = 0.0f, oz = 0.0f;
@@ -347,7 +381,6 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
         }
         // deliver dU_i/dr_ij to the slot where j lists i; a slot whose mirror
         // does not exist (rounding at the list edge) is zeroed by its owner
-        const int r = a.rev[(size_t)p * n + i];
         if (r >= 0)
             a.angbuf[r] = make_float4(ox, oy, oz, 0.0f);
         else
@@ -396,10 +429,7 @@ __device__ __forceinline__ void gather_bead(const GatherArgs &a, const Cut &cut,
     RowStream rs;
     rs.start(a.nbr, a.pos4, n, i, cR, p0, step);
     for (int p = p0; p < cR; p += step) {
-        uint32_t e;
-        float4 pj;
-        rs.next(p, e, pj);
-        const PairGeom g = geom_of(e, pj, pi, a.box);
+        const PairGeom g = rs.next_geom(p, pi, a.box);
         const int tj = (NT == 1) ? 0 : g.tj;
         const int tp = ti * NT + tj;
         if (g.d2 < cut.rcR2[tp]) {
@@ -455,16 +485,14 @@ __device__ __forceinline__ void gather_bead(const GatherArgs &a, const Cut &cut,
             }
         }
         if (p < cA) {
-            {
-                const float4 fj = a.angbuf[(size_t)p * n + i];  // dU_j/dr_ji, angular part
-                Fx -= fj.x;
-                Fy -= fj.y;
-                Fz -= fj.z;
-                if (VIR) {
-                    W[0] += g.dx * fj.x; W[1] += g.dx * fj.y; W[2] += g.dx * fj.z;
-                    W[3] += g.dy * fj.x; W[4] += g.dy * fj.y; W[5] += g.dy * fj.z;
-                    W[6] += g.dz * fj.x; W[7] += g.dz * fj.y; W[8] += g.dz * fj.z;
-                }
+            const float4 fj = a.angbuf[(size_t)p * n + i];  // dU_j/dr_ji, angular part
+            Fx -= fj.x;
+            Fy -= fj.y;
+            Fz -= fj.z;
+            if (VIR) {
+                W[0] += g.dx * fj.x; W[1] += g.dx * fj.y; W[2] += g.dx * fj.z;
+                W[3] += g.dy * fj.x; W[4] += g.dy * fj.y; W[5] += g.dy * fj.z;
+                W[6] += g.dz * fj.x; W[7] += g.dz * fj.y; W[8] += g.dz * fj.z;
             }
         }
     }
