@@ -205,19 +205,18 @@ __device__ __forceinline__ void accumulate_harmonics(float x, float y, float z, 
     acc_lm<23>(x2 * x2 - 6.0f * x2 * y2 + y2 * y2, g, A);
 }
 
-// one term of the pair partial: B = sum_n D g_n, B' = sum_n D g_n';
-// s += B' P,  V += B grad_u P
+// one term of the pair partial: B = sum_n D_n g_n, V += B grad_u P, and
+// sig_n += D_n P for the radial part s = sum_n g_n' sig_n (one FMA per term
+// fewer than summing B' = sum_n D_n g_n' per term)
 template <int IDX>
 __device__ __forceinline__ void force_lm(float P, float Gx, float Gy, float Gz, const float D[NA][LM],
-                                         const float g[NA], const float gp[NA], float &s, float &vx,
-                                         float &vy, float &vz) {
-    float B = 0.0f, Bp = 0.0f;
+                                         const float g[NA], float &vx, float &vy, float &vz, float sig[NA]) {
+    float B = 0.0f;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
         B += D[q][IDX] * g[q];
-        Bp += D[q][IDX] * gp[q];
+        sig[q] += D[q][IDX] * P;
     }
-    s += Bp * P;
     vx += B * Gx;
     vy += B * Gy;
     vz += B * Gz;
@@ -226,37 +225,40 @@ __device__ __forceinline__ void force_lm(float P, float Gx, float Gy, float Gz, 
 __device__ __forceinline__ void force_harmonics(float x, float y, float z, const float D[NA][LM],
                                                 const float g[NA], const float gp[NA], float &s,
                                                 float &vx, float &vy, float &vz) {
+    float sig[NA] = {0.0f, 0.0f, 0.0f, 0.0f};
     const float x2 = x * x, y2 = y * y, z2 = z * z;
     const float xy = x * y, yz = y * z, xz = x * z, xyz = xy * z;
-    force_lm<0>(x, 1.0f, 0.0f, 0.0f, D, g, gp, s, vx, vy, vz);
-    force_lm<1>(y, 0.0f, 1.0f, 0.0f, D, g, gp, s, vx, vy, vz);
-    force_lm<2>(z, 0.0f, 0.0f, 1.0f, D, g, gp, s, vx, vy, vz);
-    force_lm<3>(xy, y, x, 0.0f, D, g, gp, s, vx, vy, vz);
-    force_lm<4>(yz, 0.0f, z, y, D, g, gp, s, vx, vy, vz);
-    force_lm<5>(xz, z, 0.0f, x, D, g, gp, s, vx, vy, vz);
-    force_lm<6>(x2 - y2, 2.0f * x, -2.0f * y, 0.0f, D, g, gp, s, vx, vy, vz);
-    force_lm<7>(3.0f * z2 - 1.0f, 0.0f, 0.0f, 6.0f * z, D, g, gp, s, vx, vy, vz);
+    force_lm<0>(x, 1.0f, 0.0f, 0.0f, D, g, vx, vy, vz, sig);
+    force_lm<1>(y, 0.0f, 1.0f, 0.0f, D, g, vx, vy, vz, sig);
+    force_lm<2>(z, 0.0f, 0.0f, 1.0f, D, g, vx, vy, vz, sig);
+    force_lm<3>(xy, y, x, 0.0f, D, g, vx, vy, vz, sig);
+    force_lm<4>(yz, 0.0f, z, y, D, g, vx, vy, vz, sig);
+    force_lm<5>(xz, z, 0.0f, x, D, g, vx, vy, vz, sig);
+    force_lm<6>(x2 - y2, 2.0f * x, -2.0f * y, 0.0f, D, g, vx, vy, vz, sig);
+    force_lm<7>(3.0f * z2 - 1.0f, 0.0f, 0.0f, 6.0f * z, D, g, vx, vy, vz, sig);
     const float d = x2 - y2, b51 = 5.0f * z2 - 1.0f;
-    force_lm<8>(y * (3.0f * x2 - y2), 6.0f * xy, 3.0f * d, 0.0f, D, g, gp, s, vx, vy, vz);
-    force_lm<9>(xyz, yz, xz, xy, D, g, gp, s, vx, vy, vz);
-    force_lm<10>(y * b51, 0.0f, b51, 10.0f * yz, D, g, gp, s, vx, vy, vz);
-    force_lm<11>(z * (5.0f * z2 - 3.0f), 0.0f, 0.0f, 15.0f * z2 - 3.0f, D, g, gp, s, vx, vy, vz);
-    force_lm<12>(x * b51, b51, 0.0f, 10.0f * xz, D, g, gp, s, vx, vy, vz);
-    force_lm<13>(z * d, 2.0f * xz, -2.0f * yz, d, D, g, gp, s, vx, vy, vz);
-    force_lm<14>(x * (x2 - 3.0f * y2), 3.0f * d, -6.0f * xy, 0.0f, D, g, gp, s, vx, vy, vz);
+    force_lm<8>(y * (3.0f * x2 - y2), 6.0f * xy, 3.0f * d, 0.0f, D, g, vx, vy, vz, sig);
+    force_lm<9>(xyz, yz, xz, xy, D, g, vx, vy, vz, sig);
+    force_lm<10>(y * b51, 0.0f, b51, 10.0f * yz, D, g, vx, vy, vz, sig);
+    force_lm<11>(z * (5.0f * z2 - 3.0f), 0.0f, 0.0f, 15.0f * z2 - 3.0f, D, g, vx, vy, vz, sig);
+    force_lm<12>(x * b51, b51, 0.0f, 10.0f * xz, D, g, vx, vy, vz, sig);
+    force_lm<13>(z * d, 2.0f * xz, -2.0f * yz, d, D, g, vx, vy, vz, sig);
+    force_lm<14>(x * (x2 - 3.0f * y2), 3.0f * d, -6.0f * xy, 0.0f, D, g, vx, vy, vz, sig);
     const float a3 = 3.0f * x2 - y2, c3 = x2 - 3.0f * y2;
     const float e = 7.0f * z2 - 1.0f, f = 7.0f * z2 - 3.0f, h = 21.0f * z2 - 3.0f;
-    force_lm<15>(xy * d, y * a3, x * c3, 0.0f, D, g, gp, s, vx, vy, vz);
-    force_lm<16>(yz * a3, 6.0f * xyz, 3.0f * z * d, y * a3, D, g, gp, s, vx, vy, vz);
-    force_lm<17>(xy * e, y * e, x * e, 14.0f * xyz, D, g, gp, s, vx, vy, vz);
-    force_lm<18>(yz * f, 0.0f, z * f, y * h, D, g, gp, s, vx, vy, vz);
-    force_lm<19>((35.0f * z2 - 30.0f) * z2 + 3.0f, 0.0f, 0.0f, z * (140.0f * z2 - 60.0f), D, g, gp, s, vx,
-                 vy, vz);
-    force_lm<20>(xz * f, z * f, 0.0f, x * h, D, g, gp, s, vx, vy, vz);
-    force_lm<21>(d * e, 2.0f * x * e, -2.0f * y * e, 14.0f * z * d, D, g, gp, s, vx, vy, vz);
-    force_lm<22>(xz * c3, 3.0f * z * d, -6.0f * xyz, x * c3, D, g, gp, s, vx, vy, vz);
+    force_lm<15>(xy * d, y * a3, x * c3, 0.0f, D, g, vx, vy, vz, sig);
+    force_lm<16>(yz * a3, 6.0f * xyz, 3.0f * z * d, y * a3, D, g, vx, vy, vz, sig);
+    force_lm<17>(xy * e, y * e, x * e, 14.0f * xyz, D, g, vx, vy, vz, sig);
+    force_lm<18>(yz * f, 0.0f, z * f, y * h, D, g, vx, vy, vz, sig);
+    force_lm<19>((35.0f * z2 - 30.0f) * z2 + 3.0f, 0.0f, 0.0f, z * (140.0f * z2 - 60.0f), D, g, vx, vy, vz,
+                 sig);
+    force_lm<20>(xz * f, z * f, 0.0f, x * h, D, g, vx, vy, vz, sig);
+    force_lm<21>(d * e, 2.0f * x * e, -2.0f * y * e, 14.0f * z * d, D, g, vx, vy, vz, sig);
+    force_lm<22>(xz * c3, 3.0f * z * d, -6.0f * xyz, x * c3, D, g, vx, vy, vz, sig);
     force_lm<23>(x2 * x2 - 6.0f * x2 * y2 + y2 * y2, 4.0f * x * c3, 4.0f * y * (y2 - 3.0f * x2), 0.0f, D, g,
-                 gp, s, vx, vy, vz);
+                 vx, vy, vz, sig);
+#pragma unroll
+    for (int q = 0; q < NA; ++q) s += gp[q] * sig[q];
 }
 
 // cos(pi t) and sin(pi t) for 0 <= t <= 1 with the hardware instructions,
