@@ -518,7 +518,11 @@ __device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int bx, int gx,
     const int na = a.cnt[n + i];
     const int A4 = (a.cap_A + 3) & ~3, R4 = (a.cap + 3) & ~3;
     int p[REV_SLOTS], j[REV_SLOTS], nin[REV_SLOTS], lo[REV_SLOTS], nch[REV_SLOTS], found[REV_SLOTS];
+    int ca[REV_SLOTS], cs[REV_SLOTS];
+    bool sfirst[REV_SLOTS];
     uint32_t want[REV_SLOTS];
+    // this bead's own class split: slots [0, nai_i) inside r_c^A, the rest in the shell
+    const int nai_i = min(a.cls[i] & 255, na);
 #pragma unroll
     for (int k = 0; k < REV_SLOTS; ++k) {
         p[k] = by + k * gy;
@@ -526,6 +530,10 @@ __device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int bx, int gx,
         j[k] = (int)(e & J_MASK);
         want[k] = (uint32_t)i | ((124u - (e >> CODE_SHIFT)) << CODE_SHIFT);
         found[k] = -1;
+        // a pair has the same class in both rows except where rounding puts its
+        // distance on the two sides of r_c^A: search j's part of that class
+        // first, then the other part
+        sfirst[k] = p[k] >= nai_i;
     }
 #pragma unroll
     for (int k = 0; k < REV_SLOTS; ++k) {
@@ -536,18 +544,24 @@ __device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int bx, int gx,
         const int nai = v ? min(a.cls[j[k]] & 255, naj) : 0;
         nin[k] = nai;
         lo[k] = A4 - (naj - nai);
-        nch[k] = ((nai + 3) >> 2) + ((A4 - (lo[k] & ~3)) >> 2) * (naj > nai ? 1 : 0);
+        ca[k] = (nai + 3) >> 2;                                         // chunks inside r_c^A
+        cs[k] = naj > nai ? (A4 - (lo[k] & ~3)) >> 2 : 0;               // chunks of the shell
+        nch[k] = ca[k] + cs[k];
     }
     int most = 0;
 #pragma unroll
     for (int k = 0; k < REV_SLOTS; ++k) most = max(most, nch[k]);
     for (int c = 0; c < most; ++c) {
+        bool done = true;
+#pragma unroll
+        for (int k = 0; k < REV_SLOTS; ++k) done = done && (c >= nch[k] || found[k] >= 0);
+        if (done) break;
 #pragma unroll
         for (int k = 0; k < REV_SLOTS; ++k) {
             if (c >= nch[k] || found[k] >= 0) continue;
-            const int ca = (nin[k] + 3) >> 2;  // chunks inside r_c^A
-            const bool shell = c >= ca;
-            const int q0 = shell ? (lo[k] & ~3) + 4 * (c - ca) : 4 * c;
+            const bool shell = sfirst[k] ? c < cs[k] : c >= ca[k];
+            const int cc = sfirst[k] ? (shell ? c : c - cs[k]) : (shell ? c - ca[k] : c);
+            const int q0 = shell ? (lo[k] & ~3) + 4 * cc : 4 * cc;
             const uint4 w = *reinterpret_cast<const uint4 *>(a.rowbuf + (size_t)j[k] * (A4 + R4) + q0);
             const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
