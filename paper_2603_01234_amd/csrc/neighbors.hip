@@ -123,8 +123,9 @@ __device__ __forceinline__ void nb_bin_body(const NbArgs &a, int bx) {
 
 __global__ void k_nb_bin(NbArgs a) { nb_bin_body(a, blockIdx.x); }
 
-// Exclusive scan, three phases.  Block b scans 1024 counts; one block then
-// scans the block totals serially in chunks; a last pass adds the offsets.
+// Exclusive scan, two phases.  Block b scans 1024 counts and leaves their
+// total; a second pass adds to every count the totals of the blocks before
+// its own (each workgroup sums those itself).
 constexpr int SCAN_B = 1024;
 
 __device__ __forceinline__ void scan_local_body(const NbArgs &a, int bx) {
@@ -155,28 +156,34 @@ __device__ __forceinline__ void scan_local_body(const NbArgs &a, int bx) {
 
 __global__ void k_scan_local(NbArgs a) { scan_local_body(a, blockIdx.x); }
 
-__device__ __forceinline__ void scan_blocks_body(const NbArgs &a) {
-    if (build_off(a)) return;
-    if (threadIdx.x != 0) return;
-    int32_t *block_sums = a.scan_tmp;
-    int32_t *total_out = a.cell_start + a.ncell;
-    const int nb = (a.ncell + SCAN_B - 1) / SCAN_B;
-    int32_t run = 0;
-    for (int b = 0; b < nb; ++b) {
-        int32_t v = block_sums[b];
-        block_sums[b] = run;
-        run += v;
-    }
-    *total_out = run;
-}
-
-__global__ void k_scan_blocks(NbArgs a) { scan_blocks_body(a); }
-
 __device__ __forceinline__ void scan_add_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
-    int k = bx * blockDim.x + threadIdx.x;
+    __shared__ int32_t off_s;
+    const int nb = (a.ncell + SCAN_B - 1) / SCAN_B;
+    const int sb = (bx * (int)blockDim.x) / SCAN_B;  // the scan block of this workgroup's cells
+    if (threadIdx.x < 64) {
+        // the totals of the blocks before it (integer sums: any order gives
+        // the same), and in workgroup 0 the grand total after the last cell
+        int32_t before = 0, all = 0;
+        for (int b = threadIdx.x; b < nb; b += 64) {
+            const int32_t v = a.scan_tmp[b];
+            before += b < sb ? v : 0;
+            all += v;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            before += __shfl_xor(before, o);
+            all += __shfl_xor(all, o);
+        }
+        if (threadIdx.x == 0) {
+            off_s = before;
+            if (bx == 0) a.cell_start[a.ncell] = all;
+        }
+    }
+    __syncthreads();
+    const int k = bx * blockDim.x + threadIdx.x;
     if (k >= a.ncell) return;
-    int32_t v = a.cell_start[k] + a.scan_tmp[k / SCAN_B];
+    const int32_t v = a.cell_start[k] + off_s;
     a.cell_start[k] = v;
     a.cell_cursor[k] = v;
 }
@@ -596,7 +603,6 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_nb_bin, dim3(nbk), dim3(BLOCK), 0, s, a);
     int sb = (a.ncell + SCAN_B - 1) / SCAN_B;
     hipLaunchKernelGGL(k_scan_local, dim3(sb), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_scan_add, dim3(cbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_fill, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_rank, dim3(nbk), dim3(BLOCK), 0, s, a);
@@ -611,16 +617,15 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
 // ---- one launch per phase over the builds of many systems ----
 // start[ph][r] is the first block of system r in phase ph (tables of
 // n_sys + 1 entries, one per tile kind: cells to clear, beads, scan blocks,
-// the one-block scan, cells to offset, and (bead, slot-group) pairs).
-enum { NB_TILE_CLEAR = 0, NB_TILE_BEAD, NB_TILE_SCANL, NB_TILE_SCANB, NB_TILE_SCANA, NB_TILE_REV, NB_TILES };
+// cells to offset, and (bead, slot-group) pairs).
+enum { NB_TILE_CLEAR = 0, NB_TILE_BEAD, NB_TILE_SCANL, NB_TILE_SCANA, NB_TILE_REV, NB_TILES };
 static_assert(NB_TILES == NB_BATCH_TILES, "tile kinds of the batched build");
-enum { OP_CLEAR, OP_BIN, OP_SCANL, OP_SCANB, OP_SCANA, OP_FILL, OP_RANK, OP_ROWS, OP_TRANSPOSE, OP_REVERSE };
+enum { OP_CLEAR, OP_BIN, OP_SCANL, OP_SCANA, OP_FILL, OP_RANK, OP_ROWS, OP_TRANSPOSE, OP_REVERSE };
 
 template <int OP>
 __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
     constexpr int TILE = OP == OP_CLEAR ? NB_TILE_CLEAR
                          : OP == OP_SCANL ? NB_TILE_SCANL
-                         : OP == OP_SCANB ? NB_TILE_SCANB
                          : OP == OP_SCANA ? NB_TILE_SCANA
                          : OP == OP_REVERSE ? NB_TILE_REV
                                             : NB_TILE_BEAD;
@@ -636,7 +641,6 @@ __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
     if constexpr (OP == OP_CLEAR) nb_clear_body(a.ncell, a.cell_count, a.status, a.clear_status, a.ctrl, bx, gx);
     if constexpr (OP == OP_BIN) nb_bin_body(a, bx);
     if constexpr (OP == OP_SCANL) scan_local_body(a, bx);
-    if constexpr (OP == OP_SCANB) scan_blocks_body(a);
     if constexpr (OP == OP_SCANA) scan_add_body(a, bx);
     if constexpr (OP == OP_FILL) nb_fill_body(a, bx);
     if constexpr (OP == OP_RANK) nb_rank_body(a, bx);
@@ -654,7 +658,6 @@ void nb_batch_tiles(const NbArgs &a, int counts[NB_BATCH_TILES]) {
     counts[NB_TILE_CLEAR] = cbk > 0 ? (cbk < 4096 ? cbk : 4096) : 1;
     counts[NB_TILE_BEAD] = nbk;
     counts[NB_TILE_SCANL] = (a.ncell + SCAN_B - 1) / SCAN_B;
-    counts[NB_TILE_SCANB] = 1;
     counts[NB_TILE_SCANA] = cbk;
     counts[NB_TILE_REV] = nbk * ((a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
 }
@@ -666,7 +669,6 @@ hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[NB_BATCH_TI
     NB_LAUNCH(OP_CLEAR, NB_TILE_CLEAR)
     NB_LAUNCH(OP_BIN, NB_TILE_BEAD)
     NB_LAUNCH(OP_SCANL, NB_TILE_SCANL)
-    NB_LAUNCH(OP_SCANB, NB_TILE_SCANB)
     NB_LAUNCH(OP_SCANA, NB_TILE_SCANA)
     NB_LAUNCH(OP_FILL, NB_TILE_BEAD)
     NB_LAUNCH(OP_RANK, NB_TILE_BEAD)

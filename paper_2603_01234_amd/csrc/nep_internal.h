@@ -326,7 +326,7 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s);
 // Builds of many systems, one launch per phase: args[r] as for launch_build
 // (systems with n > 0); start holds the tables of first blocks written by
 // the caller from nb_batch_tiles; totals are the last entries of the tables.
-constexpr int NB_BATCH_TILES = 6;
+constexpr int NB_BATCH_TILES = 5;
 struct NbBatchArgs {
     int n_sys;
     const NbArgs *args;
