@@ -866,15 +866,20 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         kd.top2 = at<float2>(ws, L.top2);
         kd.status = nb->status;
         kd.ctrl = ctrl;
+        // the build's arguments (for the strained box) first: the drift kernel
+        // zeroes its cell counts
+        NbArgs a;
+        if ((rc = fill_nb(M, s, nb, ws, L, 0, 1, a))) return rc;
+        a.ctrl = ctrl;
+        a.from_pos4 = 1;
+        a.skip_clear = 1;
+        kd.cell_count = a.cell_count;
+        kd.ncell = a.ncell;
         {
             TimedLaunch tl(3, st);
             HIPCHK(launch_kick_drift(kd, st));
         }
         {
-            NbArgs a;
-            if ((rc = fill_nb(M, s, nb, ws, L, 0, 1, a))) return rc;
-            a.ctrl = ctrl;
-            a.from_pos4 = 1;
             TimedLaunch tl(2, st);
             HIPCHK(launch_build(a, st));
         }

@@ -12,6 +12,10 @@ namespace nep {
 __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
     if (a.status[0] & FREEZE_MASK) return;  // lists invalid: leave the state untouched (uniform)
     const int i = blockIdx.x * BLOCK + threadIdx.x;
+    // the cell counts of a build later in this step start from zero (cleared
+    // here rather than by a launch of its own, which every step would pay)
+    if (a.cell_count)
+        for (int c = i; c < a.ncell; c += gridDim.x * BLOCK) a.cell_count[c] = 0;
     float d2 = 0.0f;
     if (i < a.n) {
         const int t = min((int)a.type[i], a.T - 1);

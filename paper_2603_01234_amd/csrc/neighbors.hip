@@ -85,6 +85,7 @@ __device__ __forceinline__ float wrap_coord(float x, float L) {
 
 __device__ __forceinline__ void nb_bin_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
+    if (a.skip_clear && a.ctrl && bx == 0 && threadIdx.x == 0) a.ctrl[1] += 1;  // the clear phase's count
     int i = bx * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     float p[3];
@@ -597,8 +598,9 @@ __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
 hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     int nbk = (a.n + BLOCK - 1) / BLOCK;
     int cbk = (a.ncell + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL(k_nb_clear, dim3(cbk > 0 ? (cbk < 4096 ? cbk : 4096) : 1), dim3(BLOCK), 0, s,
-                       a.ncell, a.cell_count, a.status, a.clear_status, a.ctrl);
+    if (!a.skip_clear)
+        hipLaunchKernelGGL(k_nb_clear, dim3(cbk > 0 ? (cbk < 4096 ? cbk : 4096) : 1), dim3(BLOCK), 0, s,
+                           a.ncell, a.cell_count, a.status, a.clear_status, a.ctrl);
     if (a.n == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_nb_bin, dim3(nbk), dim3(BLOCK), 0, s, a);
     int sb = (a.ncell + SCAN_B - 1) / SCAN_B;

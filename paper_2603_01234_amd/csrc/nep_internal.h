@@ -321,6 +321,8 @@ struct NbArgs {
     int wrap;          // 1: wrap periodic coordinates into [0, L) and write them back first
     int32_t *order;    // [n] or null: processing order for the fused kernel, written from the row counts
     int from_pos4;     // 1 (MD): positions come from pos4 and are wrapped there, x/y/z are untouched
+    int skip_clear;    // 1 (MD): the drift kernel of the step already zeroed the cell counts, so no
+                       // clearing launch; the bin phase then counts the rebuild in ctrl[1]
 };
 hipError_t launch_build(const NbArgs &a, hipStream_t s);
 // Builds of many systems, one launch per phase: args[r] as for launch_build
@@ -365,6 +367,8 @@ struct KickDriftArgs {
     float2 *top2;           // [blocks] per-block largest and second largest squared displacement
     const int32_t *status;
     int32_t *ctrl;          // ctrl[0]: rebuild gate
+    int32_t *cell_count;    // or null: cell counts of the step's build, zeroed here
+    int ncell;
 };
 // the drift, then one workgroup that merges the blocks' pairs and switches
 // the rebuild gate on when they call for a rebuild
