@@ -331,7 +331,8 @@ int nep_batch_autotune(const nep_model *models, int n_models, const nep_system *
 /* While enabled, the library records a HIP event pair on the launching stream
  * around every launch of its kernels, by class: 0 = fused descriptor /
  * network / angular-force kernel, 1 = gather (forces, virial, half-kick),
- * 2 = neighbour build (all of its kernels), 3 = first half-kick + drift.
+ * 2 = neighbour build (all of its kernels), 3 = first half-kick + drift
+ * (with the rebuild test and, in MD, the previous step's energy reduction).
  * nep_timing_begin(max_launches, class_mask) creates the event pool
  * (host-side objects only) and enables recording, for the classes whose bit
  * is set in class_mask (bit c for class c), in the calling process; launches

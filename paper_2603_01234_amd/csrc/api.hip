@@ -866,6 +866,15 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         kd.top2 = at<float2>(ws, L.top2);
         kd.status = nb->status;
         kd.ctrl = ctrl;
+        if (k > 0) {
+            // the previous step's reduction runs in the merge kernel
+            kd.prev_partial = at<double>(ws, L.partial);
+            kd.prev_blocks = L.nblocks;
+            kd.prev_E = E_pot ? E_pot + (k - 1) : nullptr;
+            kd.prev_K = E_kin ? E_kin + (k - 1) : nullptr;
+            kd.counts = mp->pair_counts;
+            kd.next_gate = scheduled(step);
+        }
         // the build's arguments (for the strained box) first: the drift kernel
         // zeroes its cell counts
         NbArgs a;
@@ -884,10 +893,13 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
             HIPCHK(launch_build(a, st));
         }
         if ((rc = launch_efv(M, s, nb, U, F, nullptr, false, ws, L, st, true, v, mp))) return rc;
-        HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
-                             E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr, mp->pair_counts,
-                             nb->status, ctrl, scheduled(step + 1), nullptr, 0.0f, nullptr, st));
     }
+    // the last step's reduction (the earlier ones ran in the next step's merge kernel)
+    if (n_steps > 0)
+        HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
+                             E_pot ? E_pot + (n_steps - 1) : nullptr, E_kin ? E_kin + (n_steps - 1) : nullptr,
+                             mp->pair_counts, nb->status, ctrl, scheduled(step0 + n_steps), nullptr, 0.0f,
+                             nullptr, st));
     int32_t c[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(c, ctrl, sizeof c, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

@@ -168,53 +168,18 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
     }
 }
 
-// Fixed-order FP64 reduction of the block partials.  In MD mode (ctrl given)
-// it counts the completed step in ctrl[2] and sets the rebuild gate ctrl[0]
-// for the next step to its schedule (the next drift may still switch it on).
-// Once the status carries a freeze flag nothing but the gate is written.
+// The reduction of the block partials (reduce_partials), after the optional
+// merge of the gather blocks' displacement pairs for the standalone rebuild
+// test.
 __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double *E_tot,
                          double *W_tot, double *K_tot, double *E_slot, double *K_slot, double *counts,
                          const int32_t *status, int32_t *ctrl, int next_gate, const float2 *top2,
                          float skin_gate, int32_t *skin_status) {
-    __shared__ double red[NPART][BLOCK];
     if (top2) {
         const float2 t = merge_top2(top2, nblocks);
         if (threadIdx.x == 0 && past_skin(t, skin_gate)) atomicOr(skin_status, NEP_FLAG_SKIN);
     }
-    double acc[NPART];
-#pragma unroll
-    for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
-#pragma unroll
-        for (int c = 0; c < NPART; ++c) acc[c] += partial[(size_t)b * NPART + c];
-    }
-#pragma unroll
-    for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-#pragma unroll
-            for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    const int st0 = status ? status[0] : 0;
-    if (threadIdx.x == 0 && ctrl) {
-        ctrl[0] = next_gate;
-        if (!(st0 & FREEZE_MASK)) ctrl[2] += 1;
-    }
-    if (st0 & FREEZE_MASK) return;
-    if (threadIdx.x == 0) {
-        if (E_tot) *E_tot = red[0][0];
-        if (E_slot) *E_slot = red[0][0];
-        if (K_tot) *K_tot = red[10][0];
-        if (K_slot) *K_slot = red[10][0];
-        if (counts) {
-            counts[0] += red[11][0];
-            counts[1] += red[12][0];
-        }
-    }
-    if (W_tot && threadIdx.x < 9) W_tot[threadIdx.x] = red[1 + threadIdx.x][0];
+    reduce_partials(partial, nblocks, E_tot, W_tot, K_tot, E_slot, K_slot, counts, status, ctrl, next_gate);
 }
 
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,

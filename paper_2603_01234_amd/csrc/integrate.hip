@@ -27,8 +27,12 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
     if (threadIdx.x == 0) a.top2[blockIdx.x] = t;
 }
 
-// one workgroup: the rebuild test over the pairs of the drift's workgroups
+// one workgroup: the previous step's reduction (which also sets the gate to
+// the schedule), then the rebuild test over the pairs of the drift's workgroups
 __global__ __launch_bounds__(BLOCK) void k_gate(KickDriftArgs a, int nblocks) {
+    if (a.prev_partial)
+        reduce_partials(a.prev_partial, a.prev_blocks, nullptr, nullptr, nullptr, a.prev_E, a.prev_K, a.counts,
+                        a.status, a.ctrl, a.next_gate);
     if (a.status[0] & FREEZE_MASK) return;
     const float2 t = merge_top2(a.top2, nblocks);
     if (threadIdx.x == 0 && past_skin(t, a.skin_gate)) a.ctrl[0] = 1;

@@ -369,6 +369,12 @@ struct KickDriftArgs {
     int32_t *ctrl;          // ctrl[0]: rebuild gate
     int32_t *cell_count;    // or null: cell counts of the step's build, zeroed here
     int ncell;
+    // or null: the previous step's block partials, reduced by the merge kernel
+    // (in place of a reduction launch of their own) into the slots below
+    const double *prev_partial;
+    int prev_blocks;
+    double *prev_E, *prev_K, *counts;
+    int next_gate;          // the schedule's gate for this step's build
 };
 // the drift, then one workgroup that merges the blocks' pairs and switches
 // the rebuild gate on when they call for a rebuild
@@ -405,6 +411,52 @@ __device__ __forceinline__ float2 merge_top2(const float2 *top2, int n) {
     float a = 0.0f, b = 0.0f;
     for (int k = threadIdx.x; k < n; k += BLOCK) top2_merge(a, b, top2[k].x, top2[k].y);
     return block_top2(a, b);
+}
+
+// Fixed-order FP64 reduction of the gather's block partials by one workgroup
+// of BLOCK threads (every thread calls it).  In MD mode (ctrl given) it counts
+// the completed step in ctrl[2] and sets the rebuild gate ctrl[0] to the
+// schedule's next_gate (the next drift may still switch it on).  Once the
+// status carries a freeze flag nothing but the gate is written.
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ partial, int nblocks, double *E_tot,
+                                                double *W_tot, double *K_tot, double *E_slot, double *K_slot,
+                                                double *counts, const int32_t *status, int32_t *ctrl,
+                                                int next_gate) {
+    __shared__ double red[NPART][BLOCK];
+    double acc[NPART];
+#pragma unroll
+    for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
+#pragma unroll
+        for (int c = 0; c < NPART; ++c) acc[c] += partial[(size_t)b * NPART + c];
+    }
+#pragma unroll
+    for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    const int st0 = status ? status[0] : 0;
+    if (threadIdx.x == 0 && ctrl) {
+        ctrl[0] = next_gate;
+        if (!(st0 & FREEZE_MASK)) ctrl[2] += 1;
+    }
+    if (st0 & FREEZE_MASK) return;
+    if (threadIdx.x == 0) {
+        if (E_tot) *E_tot = red[0][0];
+        if (E_slot) *E_slot = red[0][0];
+        if (K_tot) *K_tot = red[10][0];
+        if (K_slot) *K_slot = red[10][0];
+        if (counts) {
+            counts[0] += red[11][0];
+            counts[1] += red[12][0];
+        }
+    }
+    if (W_tot && threadIdx.x < 9) W_tot[threadIdx.x] = red[1 + threadIdx.x][0];
 }
 
 // whether a pair of squared displacements calls for a rebuild
