@@ -835,6 +835,14 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     // rounding of the list predicate); the build queued right after it runs
     // only then, or when the schedule asks for it
     HIPCHK(launch_clear_status(nb->status, ctrl, (mp->force_rebuild || scheduled(step0)) ? 1 : 0, st));
+    // the reduction of step k (energies, pair counts, completed-step count),
+    // launched on its own; within the run it is the next step's merge kernel
+    // that does it
+    auto reduce_step = [&](int k) -> hipError_t {
+        return launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
+                             E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr, mp->pair_counts,
+                             nb->status, ctrl, scheduled(step0 + k + 1), nullptr, 0.0f, nullptr, st);
+    };
     for (int k = 0; k < n_steps; ++k) {
         const int64_t step = step0 + k;
         KickDriftArgs kd{};
@@ -878,7 +886,10 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         // the build's arguments (for the strained box) first: the drift kernel
         // zeroes its cell counts
         NbArgs a;
-        if ((rc = fill_nb(M, s, nb, ws, L, 0, 1, a))) return rc;
+        if ((rc = fill_nb(M, s, nb, ws, L, 0, 1, a))) {
+            if (k > 0) (void)reduce_step(k - 1);  // the previous step stays accounted for
+            return rc;
+        }
         a.ctrl = ctrl;
         a.from_pos4 = 1;
         a.skip_clear = 1;
@@ -895,11 +906,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         if ((rc = launch_efv(M, s, nb, U, F, nullptr, false, ws, L, st, true, v, mp))) return rc;
     }
     // the last step's reduction (the earlier ones ran in the next step's merge kernel)
-    if (n_steps > 0)
-        HIPCHK(launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
-                             E_pot ? E_pot + (n_steps - 1) : nullptr, E_kin ? E_kin + (n_steps - 1) : nullptr,
-                             mp->pair_counts, nb->status, ctrl, scheduled(step0 + n_steps), nullptr, 0.0f,
-                             nullptr, st));
+    if (n_steps > 0) HIPCHK(reduce_step(n_steps - 1));
     int32_t c[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(c, ctrl, sizeof c, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
