@@ -491,14 +491,20 @@ __device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int g
     constexpr int BEADS_PER_PASS = BLOCK / TR_SLOTS;
     const int pl = threadIdx.x % TR_SLOTS, bsub = threadIdx.x / TR_SLOTS;
     for (int p0 = 0; p0 < mt; p0 += TR_SLOTS) {
-#pragma unroll 4
+        // all TR_SLOTS loads are issued before any is used: unconditional, at a
+        // slot clamped into the row (and a bead clamped into the system), so
+        // none waits behind a branch; slots past a row's end are never read
+        uint32_t vals[TR_SLOTS];
+#pragma unroll
         for (int k = 0; k < TR_SLOTS; ++k) {
             const int b = bsub + k * BEADS_PER_PASS;
             const int4 g = info[b];
-            const int p = p0 + pl;
-            if (p < g.x)
-                tile[pl][b] = a.rowbuf[(size_t)(i0 + b) * (A4 + R4) + row_src(p, g.y, g.z, g.w, A4, R4)];
+            const int p = min(p0 + pl, max(g.x - 1, 0));
+            const int bead = min(i0 + b, n - 1);
+            vals[k] = a.rowbuf[(size_t)bead * (A4 + R4) + row_src(p, g.y, g.z, g.w, A4, R4)];
         }
+#pragma unroll
+        for (int k = 0; k < TR_SLOTS; ++k) tile[pl][bsub + k * BEADS_PER_PASS] = vals[k];
         __syncthreads();
 #pragma unroll 4
         for (int q = 0; q < TR_SLOTS; ++q)
