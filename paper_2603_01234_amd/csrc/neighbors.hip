@@ -456,6 +456,7 @@ __device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int g
     if (build_off(a)) return;  // uniform over the grid
     __shared__ uint32_t tile[TR_SLOTS][BLOCK + 4];
     __shared__ int4 info[BLOCK];  // total, angular, inside r_c^A, inside r_c^R (radial-only)
+    __shared__ int4 cost4[BLOCK / 4];  // processing cost of each bead (-1 past the system's end)
     __shared__ int max_total;
     const int n = a.n;
     const int i0 = xcd_tile(bx, gx) * BLOCK;
@@ -467,6 +468,7 @@ __device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int g
         f = make_int4(a.cnt[i], a.cnt[n + i], c & 255, c >> 8);
     }
     info[threadIdx.x] = f;
+    reinterpret_cast<int *>(cost4)[threadIdx.x] = i0 + (int)threadIdx.x < n ? 20 * f.z + f.x : -1;
     if (threadIdx.x == 0) max_total = 0;
     __syncthreads();
     int m = f.x;
@@ -476,15 +478,22 @@ __device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int g
     __syncthreads();
     const int mt = max_total;
     if (a.order) {
-        // rank of this bead among the block's beads by decreasing cost
+        // rank of this bead among the block's beads by decreasing cost (ties
+        // by index; the -1 of missing beads ranks below every cost), four
+        // costs per LDS read
         const int b = threadIdx.x;
         const int nb = min(BLOCK, n - i0);
         const int cost = 20 * f.z + f.x;
         int rank = 0;
-        for (int k = 0; k < nb; ++k) {
-            const int4 g = info[k];
-            const int ck = 20 * g.z + g.x;
-            rank += (ck > cost || (ck == cost && k < b)) ? 1 : 0;
+#pragma unroll 4
+        for (int k4 = 0; k4 < BLOCK / 4; ++k4) {
+            const int4 c = cost4[k4];
+            const int cs[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 4 * k4 + u;
+                rank += (cs[u] > cost || (cs[u] == cost && k < b)) ? 1 : 0;
+            }
         }
         if (b < nb) a.order[i0 + rank] = i0 + b;
     }
