@@ -455,3 +455,118 @@ def test_nve_energy_error_scales_with_dt_squared():
         errs.append(np.abs(E - E[0]).max())
     ratio = errs[0] / errs[1]
     assert 3.0 < ratio < 5.3, (errs, ratio)
+
+
+# --------------------------------------------------------------------------
+# target mode, multi-image pair enumeration, unit constant, strain branch
+# --------------------------------------------------------------------------
+def test_target_mode_equals_full_evaluation_config0():
+    """or_efv with a target subset fills U, F and W of those beads exactly as
+    the full evaluation does (it evaluates every bead within reach of a
+    target, and sums the same pair terms in the same order)."""
+    spec, params, system, _ = W.config0()
+    pos = system.pos_f32().astype(np.float64)
+    full = oracle.efv(spec, params, pos, system.types, system.box, system.pbc)
+    tg = np.random.default_rng(4).choice(system.n, 37, replace=False)
+    part = oracle.efv(spec, params, pos, system.types, system.box, system.pbc, targets=tg)
+    np.testing.assert_array_equal(part.U[tg], full.U[tg])
+    np.testing.assert_array_equal(part.F[tg], full.F[tg])
+    np.testing.assert_array_equal(part.W[tg], full.W[tg])
+    rest = np.setdiff1d(np.arange(system.n), tg)
+    assert np.isnan(part.U[rest]).all() and np.isnan(part.E)
+
+
+def test_target_mode_equals_full_evaluation_two_types_self_images():
+    """The same in a two-type periodic box smaller than twice the cutoff, where
+    a bead interacts with several images of a neighbour and of itself."""
+    spec = W.aacg_gold_spec(12)
+    params = _params(spec, 61)
+    rng = np.random.default_rng(62)
+    box = np.array([1.25, 1.4, 1.15])
+    pos = W.small_cluster(rng, 16, box=1.15, min_dist=0.2) % box
+    types = rng.integers(0, 2, 16)
+    full = oracle.efv(spec, params, pos, types, box, PER)
+    for tg in ([3], [0, 7, 15], list(range(0, 16, 2))):
+        part = oracle.efv(spec, params, pos, types, box, PER, targets=tg)
+        np.testing.assert_array_equal(part.U[tg], full.U[tg])
+        np.testing.assert_array_equal(part.F[tg], full.F[tg])
+        np.testing.assert_array_equal(part.W[tg], full.W[tg])
+
+
+@pytest.mark.parametrize("box", [(0.62, 0.62, 0.62), (0.83, 0.95, 0.7), (1.3, 1.1, 1.25), (0.65, 1.3, 0.9)])
+def test_pairs_within_match_brute_force_on_image_boxes(box):
+    """The oracle's cell enumeration of periodic images against an independent
+    brute force over every image vector in range, on boxes of 0.62-1.3 nm where
+    a bead sees several images of the same neighbour (and of itself) inside
+    r_c = 0.8 nm.  Every row is compared as a set of (j, image).  No box length
+    is a multiple of r_c, where the FP64 and float32 predicates may round a
+    self-image pair at exactly r_c differently."""
+    from oracle.neighbors_f32 import neighbor_sets
+    spec = W.water_spec(8)
+    box = np.array(box)
+    rng = np.random.default_rng(int(box.sum() * 1000))
+    n = 9
+    pos = (rng.uniform(0.0, 1.0, (n, 3)) * box).astype(np.float32)
+    pairs = oracle.pairs_within(pos.astype(np.float64), np.zeros(n, int), 1, spec.rc_R,
+                                box.astype(np.float32).astype(np.float64), PER)
+    sets = neighbor_sets(pos, np.zeros(n, int), box, PER, spec.rc_R, 0.0)
+    multi = 0
+    for i in range(n):
+        ref = {tuple(x[1:]) for x in pairs[pairs[:, 0] == i].tolist()}
+        assert sets[i] == ref, (i, sorted(sets[i] ^ ref))
+        js = [e[0] for e in ref]
+        multi += len(js) - len(set(js))
+    assert multi > 0, "the box should produce several images of one neighbour"
+
+
+def test_accel_constant_from_codata():
+    """1 eV/nm acting on 1 amu, in nm/fs^2.  The constant is the Faraday
+    constant (CODATA 2018, 96485.33212 C/mol) over 1 g/mol, to 1e-12.  From
+    the exact elementary charge and the CODATA 2018 atomic mass constant it
+    differs by 4e-10 relative (the molar mass constant is 1 g/mol only to
+    3.5e-10), far below float32 resolution; a wrong power of ten or an
+    inverted ratio fails both checks."""
+    faraday = 96485.33212        # C/mol
+    a_f = faraday / 1e-3 / 1e-9 * 1e9 / 1e30
+    e = 1.602176634e-19          # J per eV (exact)
+    u = 1.66053906660e-27        # kg per amu (CODATA 2018)
+    a_si = e / 1e-9 / u          # m/s^2
+    a = a_si * 1e9 / 1e30        # nm / fs^2
+    for c in (oracle.ACCEL, W.ACCEL_EV_NM_AMU):
+        assert abs(a_f - c) < 1e-12 * a_f
+        assert abs(a - c) < 1e-9 * a
+
+
+def test_md_strain_branch_with_zero_forces():
+    """With every parameter zero the site energies and forces vanish, so a
+    strained run is pure kinematics: x_{s+1} = (x_s + dt v) L(s+1)/L(s) along
+    the strained axis, the box follows L(s) = L0 (1 + rate s), and velocities
+    stay constant.  From rest the positions scale by L(s)/L0 exactly."""
+    spec = W.water_spec(6)
+    p = np.zeros(spec.n_params)
+    rng = np.random.default_rng(71)
+    box0 = np.array([3.0, 3.2, 2.9])
+    pos0 = rng.uniform(0.1, 2.8, (10, 3))
+    rate = np.array([0.0, -2e-3, 5e-3])
+    dt, steps, step0 = 2.0, 12, 3
+    ty = np.zeros(10, int)
+    # from rest: pure affine scaling about the origin
+    box_s0 = box0 * (1 + rate * step0)
+    pos, vel, F, box, Ep, Ek = oracle.md(spec, p, pos0, np.zeros((10, 3)), ty, [18.0], box_s0, PER, dt, steps,
+                                         step0=step0, strain_rate=rate, box0=box0)
+    L = box0 * (1 + rate * (step0 + steps))
+    np.testing.assert_allclose(box, L, rtol=1e-15)
+    np.testing.assert_allclose(pos, pos0 * (L / box_s0), rtol=1e-13)
+    assert not F.any() and not Ep.any() and not Ek.any()
+    # moving beads: the recurrence in closed form
+    v0 = rng.normal(0, 1e-3, (10, 3))
+    pos, vel, F, box, Ep, Ek = oracle.md(spec, p, pos0, v0, ty, [18.0], box_s0, PER, dt, steps,
+                                         step0=step0, strain_rate=rate, box0=box0)
+    x = pos0.copy()
+    for s in range(step0, step0 + steps):
+        lam = (1 + rate * (s + 1)) / (1 + rate * s)
+        x = (x + dt * v0) * lam
+    np.testing.assert_allclose(pos, x, rtol=1e-12, atol=1e-14)
+    np.testing.assert_array_equal(vel, v0)
+    K = 0.5 * 18.0 * (v0 ** 2).sum() / W.ACCEL_EV_NM_AMU
+    np.testing.assert_allclose(Ek, K, rtol=1e-13)
