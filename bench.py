@@ -17,11 +17,18 @@ candidates x 2000 structures, persistent launch against the plain
 one-structure-per-call loop) and the served form (Poisson trace of MD
 requests through the continuous-batching server against a plain FIFO loop).
 
+The timed window is the central K steps of the workload's 1000-step
+trajectory from the lattice (the steps before it run untimed), so it sees the
+trajectory's typical state: random weights heat the system from 300 K to
+about 1350 K, and rebuilds grow more frequent as it heats.  The whole
+1000-step trajectory is also timed on its own (`config.full_run`).  Every
+step evaluates energies, forces and the per-bead and total virial.
+
 Prints ONE JSON line.  `value` is bead-steps/s with every input resident in
 HBM.  The roofline entry prices the dominant kernel's algorithmic FP32 work,
 timed with HIP events on its own stream inside the timed region.  The CPU
 baseline is the FP64 oracle (the correctness reference, not a tuned CPU code)
-on one full force evaluation of the same snapshot.
+on full force evaluations of the same state, on every host core and on one.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -109,22 +116,42 @@ def load_traffic(n_launch_units: int):
     return c.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(spec, params, system, pos, min_seconds=10.0):
+def cpu_baseline(spec, params, system, pos, min_seconds=10.0, single_core_seconds=8.0):
+    """The FP64 oracle timed on the host: full force evaluations of the timed
+    window's 216,000-bead state on every core of the process, and (the same
+    model and density) of a 4,096-bead box on one core."""
     import oracle
+    import workloads as W
     p64 = params.astype(np.float32).astype(np.float64)
     box = system.box.astype(np.float32).astype(np.float64)
+    cores = oracle.max_threads()
     t0 = time.perf_counter()
     reps = 0
     while True:
-        oracle.efv(spec, p64, pos, system.types, box, system.pbc)
+        oracle.efv(spec, p64, pos, system.types, box, system.pbc, n_threads=cores)
         reps += 1
         el = time.perf_counter() - t0
         if el >= min_seconds or reps >= 3:
             break
-    return {"value": system.n * reps / el, "unit": "bead-steps/s", "cores": oracle.max_threads(),
+    small = W.water_box(np.random.SeedSequence(4096), 16, temperature=300.0)
+    sp = small.pos_f32().astype(np.float64)
+    sb = small.box.astype(np.float32).astype(np.float64)
+    t1 = time.perf_counter()
+    reps1 = 0
+    while True:
+        oracle.efv(spec, p64, sp, small.types, sb, small.pbc, n_threads=1)
+        reps1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= single_core_seconds:
+            break
+    oracle.efv(spec, p64, sp, small.types, sb, small.pbc, n_threads=cores)   # back to every core
+    return {"value": system.n * reps / el, "unit": "bead-steps/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{reps} full FP64 force evaluation(s) of the 216,000-bead snapshot after warm-up "
-                      f"({el:.1f} s wall); the MD update itself is negligible"}
+            "sample": f"{reps} full FP64 force evaluation(s) of the 216,000-bead state at the start of the timed "
+                      f"window ({el:.1f} s wall, {cores} threads); the MD update itself is negligible",
+            "single_core": {"value": small.n * reps1 / el1, "unit": "bead-steps/s", "cores": 1,
+                            "sample": f"{reps1} full FP64 force evaluations of a 4,096-bead box of the same "
+                                      f"density and model on one thread ({el1:.1f} s wall)"}}
 
 
 def batched_leg(reps: int = 3, plain_candidates: int = 2):
@@ -321,6 +348,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--pre-steps", type=int, default=-1,
+                    help="untimed steps from the lattice before the warm-up (default: centre the timed window "
+                         "on the 1000-step trajectory of the workload)")
+    ap.add_argument("--split-steps", type=int, default=100,
+                    help="steps of the run after the timed window that times every kernel class (0: none)")
+    ap.add_argument("--no-full-run", action="store_true",
+                    help="skip the separately timed whole 1000-step trajectory")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort-every", type=int, default=100,
                     help="put the beads back into cell order every so many MD steps (0: never)")
@@ -342,13 +376,39 @@ def main():
     torch.cuda.set_device(0)
     spec, params, system, opts = W.config1()
     model = engine.Model.from_spec(spec, params)
+    masses = [W.WATER_MASS]
+    dt, every = opts["dt"], opts["rebuild_every"]
+    K = args.steps
+    full_run = None
+    if not args.no_full_run:
+        # the whole workload as specified: 1000 steps from the lattice, timed as one
+        fr = engine.Replica(model, system.pos_f32(), system.types, system.box, system.pbc,
+                            skin=opts["skin"], vel=system.vel)
+        fr.efv(per_bead_virial=False)
+        fr.md(5, dt, masses, rebuild_every=every)          # first-launch costs, not part of the run
+        fr = engine.Replica(model, system.pos_f32(), system.types, system.box, system.pbc,
+                            skin=opts["skin"], vel=system.vel)
+        fr.efv(per_bead_virial=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fr.md(opts["steps"], dt, masses, rebuild_every=every, sort_every=args.sort_every)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        full_run = {"steps": opts["steps"], "ms_per_step": round(el * 1e3 / opts["steps"], 4),
+                    "bead_steps_per_s": round(system.n * opts["steps"] / el, 1),
+                    "ns_per_day": round(opts["steps"] / el * dt * 86400 * 1e-6, 2),
+                    "rebuilds": fr.n_rebuilds,
+                    "note": "the whole 1000-step trajectory from the lattice, wall clock, virial every step"}
+        del fr
+    # the timed window: the central K steps of the same trajectory (pre-steps
+    # and warm-up before it are untimed), so the window sees the trajectory's
+    # typical state rather than the cold lattice it starts from
+    pre = args.pre_steps if args.pre_steps >= 0 else max(0, (opts["steps"] - K) // 2 - args.warmup)
     rep = engine.Replica(model, system.pos_f32(), system.types, system.box, system.pbc,
                          skin=opts["skin"], vel=system.vel)
     rep.efv(per_bead_virial=False)          # lists + forces at t = 0
-    masses = [W.WATER_MASS]
-    dt, every = opts["dt"], opts["rebuild_every"]
-    if args.warmup:
-        rep.md(args.warmup, dt, masses, rebuild_every=every, sort_every=args.sort_every)
+    if pre + args.warmup:
+        rep.md(pre + args.warmup, dt, masses, rebuild_every=every, sort_every=args.sort_every)
     torch.cuda.synchronize()
     nR, nA = pair_counts(rep, spec)          # neighbours within the cutoffs at the start of the timed run
     print(f"bench: N={system.n}, mean neighbours within r_c: radial {nR.mean():.2f}, angular {nA.mean():.2f}",
@@ -358,8 +418,16 @@ def main():
     st = rep.status.cpu().tolist()
     rep._alloc_lists(max(rep.cap, int(st[1] * 1.5) + 16), max(rep.cap_A, int(st[2] * 1.5) + 16))
     rep.build()
-    K = args.steps
+    step_first = rep.step
+    # fused-kernel launches before the window: the full run's (one evaluation
+    # and 5 steps, then one evaluation and its steps), then this replica's
+    # first evaluation and its steps so far (a run that overflows a row repeats
+    # launches, so this is exact only for runs that never regrow)
+    before = (0 if args.no_full_run else 1 + 5 + 1 + opts["steps"]) + 1 + step_first
+    print(f"bench: timed window = MD steps {step_first}..{step_first + K - 1} of the trajectory "
+          f"(k_efv_main dispatches {before + 1}..{before + K}, counting from 1)", file=sys.stderr, flush=True)
     counts = torch.zeros(2, dtype=torch.float64, device="cuda")
+    Wtr = torch.zeros((max(K, 1), 9), dtype=torch.float64, device="cuda")
     # inside the timed region only the dominant kernel carries an event pair
     B.nep_timing_begin(2 * K + 64, 0x1)
     torch.cuda.synchronize()
@@ -368,7 +436,7 @@ def main():
     t0 = time.perf_counter()
     ev0.record()
     rb0 = rep.n_rebuilds
-    rep.md(K, dt, masses, rebuild_every=every, pair_counts=counts, sort_every=args.sort_every)
+    rep.md(K, dt, masses, rebuild_every=every, pair_counts=counts, sort_every=args.sort_every, W_trace=Wtr)
     rebuilds = rep.n_rebuilds - rb0
     ev1.record()
     torch.cuda.synchronize()
@@ -377,16 +445,17 @@ def main():
     ms, launches = B.nep_timing_end()
     elapsed = max(wall, gpu_ms / 1e3)
     # per-class split from a separate, shorter run that times every class
-    K2 = min(K, 100)
-    B.nep_timing_begin(8 * K2 + 64, 0xF)
-    rb1 = rep.n_rebuilds
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rep.md(K2, dt, masses, rebuild_every=every, sort_every=args.sort_every)
-    torch.cuda.synchronize()
-    split_ms_step = (time.perf_counter() - t1) * 1e3 / K2
-    ms_all, launches_all = B.nep_timing_end()
-    rebuilds_split = rep.n_rebuilds - rb1
+    K2 = min(K, args.split_steps)
+    if K2 > 0:
+        B.nep_timing_begin(8 * K2 + 64, 0xF)
+        rb1 = rep.n_rebuilds
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rep.md(K2, dt, masses, rebuild_every=every, sort_every=args.sort_every)
+        torch.cuda.synchronize()
+        split_ms_step = (time.perf_counter() - t1) * 1e3 / K2
+        ms_all, launches_all = B.nep_timing_end()
+        rebuilds_split = rep.n_rebuilds - rb1
     value = system.n * K / elapsed
     ms_step = elapsed * 1e3 / K
     # algorithmic work of the timed region from the pairs the kernels evaluated
@@ -404,11 +473,15 @@ def main():
         "kernel": "k_efv_main<1> (fused descriptor + network + angular pair forces)",
         "flops_per_launch": f_main, "avg_launch_ms": round(main_ms, 4),
     }
-    kernels = {name: {"avg_ms": round(ms_all[c] / max(launches_all[c], 1), 4), "launches": launches_all[c]}
-               for c, name in enumerate(["efv_main", "efv_gather", "neighbor_build", "kick_drift"])}
-    kernels["split_run"] = {"steps": K2, "rebuilds": rebuilds_split, "ms_per_step": round(split_ms_step, 4),
-                            "note": "every class timed; neighbor_build launches include the gated ones "
-                                    "that found no rebuild due"}
+    kernels = None
+    if K2 > 0:
+        kernels = {name: {"avg_ms": round(ms_all[c] / max(launches_all[c], 1), 4), "launches": launches_all[c]}
+                   for c, name in enumerate(["efv_main", "efv_gather", "neighbor_build", "kick_drift"])}
+        kernels["split_run"] = {"steps": K2, "rebuilds": rebuilds_split, "ms_per_step": round(split_ms_step, 4),
+                                "note": "every class timed; neighbor_build launches include the gated ones "
+                                        "that found no rebuild due"}
+    W_last = Wtr[K - 1].cpu().numpy().reshape(3, 3) if K > 0 else np.zeros((3, 3))
+    vol = float(np.prod(system.box))
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "bead-steps/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
@@ -422,12 +495,18 @@ def main():
                    "mean_neighbours_angular_run": round(tot_A / (K * system.n), 3),
                    "row_capacity": [rep.cap, rep.cap_A],
                    "sort_every": args.sort_every,
+                   "timed_steps": [step_first, step_first + K - 1],
                    "rebuilds_in_timed_steps": rebuilds,
+                   "virial": "per-bead and total virial every step (Eqs. 15-16)",
+                   "virial_pressure_GPa_last_step": round(float(np.trace(W_last)) / (3 * vol) * 0.1602176634, 4),
                    "F_alg_per_bead_step": round(F_alg_bead, 1),
                    "path_tflops_alg": round(value * F_alg_bead / 1e12, 3)},
         "roofline": roofline,
-        "kernels": kernels,
     }
+    if kernels is not None:
+        out["kernels"] = kernels
+    if full_run is not None:
+        out["config"]["full_run"] = full_run
     if args.copy_calibration:
         # a plain elementwise kernel of known traffic: reads 256 MiB, writes 256 MiB
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")

@@ -119,6 +119,9 @@ typedef struct {
  *                                    the rest the radial-only ones
  *   rev[p*n + i], p < cnt[n+i]      flat index q*n + j of the reverse entry (i in row j),
  *                                    or -1 when rounding left it out of row j
+ *   order[t], t < n                 bead evaluated by thread t of the fused kernel (beads of
+ *                                    similar row cost side by side within blocks of 256); the
+ *                                    build writes it with the rows, so it always belongs to them
  * Rows are in a fixed order (neighbour cells, then index), so every later sum
  * has one canonical order.  The pair predicate is exact in float32:
  * s = fl(n*L); dx = fl(fl(x_j + s) - x_i); d2 = fl(fl(fl(dx dx) + fl(dy dy)) + fl(dz dz));
@@ -131,11 +134,16 @@ typedef struct {
     int32_t *cnt;        /* device [2][n]: cnt[i] all entries, cnt[n+i] angular prefix */
     float *ref;          /* device [3][n]: positions at the last build (completeness test) */
     float skin;          /* nm */
-    int32_t *status;     /* device [4]: flags, max row length seen, max angular length, spare */
+    int32_t *status;     /* device [4]: flags, max row length seen, max angular length, and the
+                            float bits of the compression factor sigma accumulated since the
+                            build (1.0 after a build; see nep_md_step) */
+    int32_t *order;      /* device [n] or NULL: processing order written by the build (NULL: the
+                            build writes none and the kernels take beads in index order) */
 } nep_neighbors;
 
 /* Device workspace needed by the calls below for n beads and capacities cap,
- * cap_A.  Contents are scratch; nothing persists between calls. */
+ * cap_A.  Contents are scratch; nothing persists between calls (a list build
+ * and the evaluations that use its lists may each take a different workspace). */
 size_t nep_workspace_bytes(nep_model model, int n, int cap, int cap_A);
 
 /* Builds the lists for the current positions (cell lists with cells no smaller
@@ -152,7 +160,9 @@ size_t nep_workspace_bytes(nep_model model, int n, int cap, int cap_A);
 int nep_build_neighbors(nep_model model, nep_system *sys, nep_neighbors *nbrs, int wrap,
                         void *ws, size_t ws_bytes, void *stream);
 
-/* Reorders the beads of a system in place into the cell order of the
+/* Data layout only (no quantity of the paper changes: E, F and W are
+ * invariant under a permutation of the beads, Sec. II.A).
+ * Reorders the beads of a system in place into the cell order of the
  * neighbour build, so that beads near in space are near in memory again after
  * they have diffused (the lists, the fused kernel and the gather all read
  * neighbours' data by index).  x, y, z and type are permuted together with v,
@@ -201,26 +211,42 @@ typedef struct {
     int n_rebuilds;           /* out: list rebuilds done by this call */
     double *pair_counts;      /* device double[2] or NULL: += sum_i N_R(i), sum_i N_A(i) over every
                                  force evaluation (pairs inside the interaction cutoffs) */
+    double *W_trace;          /* device double [n_steps][9] or NULL: total virial W = sum_i W_i
+                                 (Eq. 16) at the end of every step, W[a][b] at 9k + 3a + b */
+    float *W;                 /* device [9][n] or NULL: per-bead virial W_i (Eq. 15) at the final
+                                 positions, plane 3a + b */
 } nep_md_params;
 
-/* Advances sys by n_steps:  v' = v + dt/2 a(F);  x += dt v';  affine strain;
- * [wrap + rebuild];  F = F(x);  v = v' + dt/2 a(F),  with a = 9.648533212e-5
- * F/m (nm/fs^2 from eV/nm and amu).  On entry F (device [3][n]) must hold the
- * forces at the current positions, and the lists must come from
- * nep_build_neighbors for this system (built at any earlier positions: the
- * displacement check rebuilds them when they no longer cover the pairs), or
- * force_rebuild must be set.  On exit x, v, F and the lists hold for the final
- * positions.  v: device [3][n] nm/fs.  U: device [n] or NULL (site energies at
- * the last step).  E_pot / E_kin: device double [n_steps] traces or NULL.
+/* Advances sys by n_steps of velocity Verlet (the paper's MD runs in an
+ * external engine and states no integrator; this is plain NVE):
+ *   v' = v + dt/2 a(F);  x += dt v';  affine strain;  [wrap + rebuild];
+ *   F = F(x), U, W (Eqs. 2-8, 15-16);  v = v' + dt/2 a(F),
+ * with a = 9.648533212e-5 F/m (nm/fs^2 from eV/nm and amu).  Every step
+ * evaluates the site energies, the forces and the per-bead and total virial.
+ * On entry F (device [3][n]) must hold the forces at the current positions,
+ * and the lists must come from nep_build_neighbors for this system (built at
+ * any earlier positions: the rebuild test rebuilds them when they no longer
+ * cover the pairs), or force_rebuild must be set.  On exit x, v, F and the
+ * lists hold for the final positions.  v: device [3][n] nm/fs.  U: device [n]
+ * or NULL (site energies at the last step).  E_pot / E_kin: device double
+ * [n_steps] traces or NULL; params->W_trace and params->W as above.
+ *
+ * Strain: the constant engineering strain-rate loading of the nanowire
+ * (Sec. III.C.5), L_d(s) = box0_d (1 + rate_d s) with positions scaled
+ * affinely about the origin each step; rates of either sign are accepted as
+ * long as 1 + rate_d s stays above 0.05 over the call (NEP_ERR_ARG otherwise).
  *
  * Rebuild decisions are taken on the device, with no host synchronisation
- * inside the call: the drift kernel sets a gate word when the two largest
- * displacements since the build add up to more than 0.99 skin (the test of
- * nep_compute_efv), the reduction of the previous step sets it when the
- * schedule asks for a rebuild, and the build
- * kernels queued in every step do nothing while it is off.  The lists used by
- * a force evaluation therefore always hold every pair within the cutoffs.
- * params->n_rebuilds returns the number of rebuilds that ran.
+ * inside the call.  A pair's separation changes since the build by its affine
+ * part, which under compression shrinks it by at most (1 - sigma)(r_c + skin)
+ * (sigma = product over the steps since the build of the smallest per-step
+ * scale factor, capped at 1; kept in status[3]), plus the non-affine
+ * displacements of its two beads.  The lists are rebuilt after a drift when
+ * the two largest non-affine displacements plus (1 - sigma)(r_c + skin) exceed
+ * 0.99 skin, or when the schedule (s + 1) % rebuild_every == 0 asks for one;
+ * the build kernels queued in every step do nothing while the gate is off.
+ * The lists used by a force evaluation therefore always hold every pair
+ * within the cutoffs.  params->n_rebuilds returns the number of rebuilds.
  *
  * The new positions and velocities of a step are written to sys and v only
  * when its forces are done.  A rebuild that overflows (or finds a bad
@@ -256,7 +282,9 @@ typedef struct {
 /* Workspace of nep_md_step_batch for up to max_active replicas per call. */
 size_t nep_md_batch_workspace_bytes(int max_active);
 
-/* One velocity-Verlet step (as nep_md_step, no strain) for each of n_active
+/* The served form of the MD step: continuous batching of independent
+ * replicas, each advanced by the integrator of nep_md_step (Eqs. 2-8 for the
+ * forces).  One velocity-Verlet step (as nep_md_step, no strain) for each of n_active
  * replicas that share one model, batched: one drift launch over the tiles of
  * every replica, the builds of the replicas that fail the rebuild test of
  * nep_md_step (their two largest displacements add up to more than 0.99 skin) or
@@ -298,6 +326,9 @@ size_t nep_batch_workspace_bytes(const nep_model *models, int n_models, const ne
                                  const nep_batch_config *cfg);
 
 /* Evaluates n_items (candidate, structure) pairs in one persistent launch.
+ * The batched kernel is built for n_types <= 2 (the one-type water-like and
+ * the two-type C60-like families); models with more types return
+ * NEP_ERR_UNSUPPORTED here and in the two calls around it.
  * models: host array of n_models handles that share n_types, n_hidden and
  * cutoffs (the candidates of one model family).  systems / lists: host arrays
  * of n_systems structures and their lists from nep_build_neighbors (skin 0 is

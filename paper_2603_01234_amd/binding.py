@@ -64,7 +64,8 @@ class System(ctypes.Structure):
 
 class Neighbors(ctypes.Structure):
     _fields_ = [("cap", c_int), ("cap_A", c_int), ("nbr", c_void_p), ("rev", c_void_p),
-                ("cnt", c_void_p), ("ref", c_void_p), ("skin", c_float), ("status", c_void_p)]
+                ("cnt", c_void_p), ("ref", c_void_p), ("skin", c_float), ("status", c_void_p),
+                ("order", c_void_p)]
 
 
 class Replica(ctypes.Structure):
@@ -85,7 +86,7 @@ class MdParams(ctypes.Structure):
     _fields_ = [("dt_fs", c_float), ("n_steps", c_int), ("rebuild_every", c_int), ("force_rebuild", c_int),
                 ("mass", c_float * 4),
                 ("strain_rate", c_double * 3), ("box0", c_double * 3), ("step", c_int64),
-                ("n_rebuilds", c_int), ("pair_counts", c_void_p)]
+                ("n_rebuilds", c_int), ("pair_counts", c_void_p), ("W_trace", c_void_p), ("W", c_void_p)]
 
 
 _lib = None

@@ -61,7 +61,7 @@ struct TimedLaunch {
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, rowbuf, vh, order, ctrl, top2, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, rowbuf, vh, ctrl, top2, total;
     int ncell_max, nblocks;
 };
 
@@ -95,7 +95,6 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     // row stride: both regions padded to whole 16-byte groups
     L.rowbuf = take(nn * (size_t)(((std::max(cap, 1) + 3) & ~3) + ((std::max(cap_A, 1) + 3) & ~3)) * 4);
     L.vh = take(nn * 12);
-    L.order = take(nn * 4);
     L.ctrl = take(4 * sizeof(int32_t));
     // per-workgroup pairs of the rebuild test (gather or drift workgroups)
     L.top2 = take((size_t)L.nblocks * sizeof(float2));
@@ -159,6 +158,14 @@ Cut make_cut(const Model &M) {
         c.rcA2[k] = M.rcA[k] * M.rcA[k];
     }
     return c;
+}
+
+// largest list reach r_c + skin over the type pairs (the affine-shrink term
+// of the rebuild test)
+float reach_of(const Model &M, float skin) {
+    float r = 0.0f;
+    for (int k = 0; k < M.T * M.T; ++k) r = std::max(r, M.rcR[k]);
+    return r + skin;
 }
 
 // Cell grid: cells no smaller than half of (r_c + skin)(1 + 1e-3), searched
@@ -263,7 +270,7 @@ int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, co
     a.pos_sorted = at<float4>(ws, L.pos_sorted);
     a.cls = at<int32_t>(ws, L.cls);
     a.rowbuf = at<uint32_t>(ws, L.rowbuf);
-    a.order = at<int32_t>(ws, L.order);
+    a.order = nb->order;
     a.nbr = nb->nbr;
     a.rev = nb->rev;
     a.cnt = nb->cnt;
@@ -298,7 +305,7 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     a.angbuf = at<float4>(ws, L.angbuf);
     a.fown = at<float4>(ws, L.fown);
     a.freeze = md ? nb->status : nullptr;
-    a.order = at<int32_t>(ws, L.order);
+    a.order = nb->order;
     size_t lds = (size_t)M.T * M.T * TAB_PER_PAIR * sizeof(float);
     {
         TimedLaunch tl(0, st);
@@ -382,6 +389,7 @@ int batch_plan(const Model &M0, const nep_system *systems, const nep_neighbors *
     if (!(block == 64 || block == 128 || block == 256)) return fail(NEP_ERR_ARG, "block must be 64, 128 or 256");
     if (order < 0 || order > 1) return fail(NEP_ERR_ARG, "order must be 0 or 1");
     if (wg_per_cu < 0) return fail(NEP_ERR_ARG, "wg_per_cu must be >= 0");
+    if (M0.T > 2) return fail(NEP_ERR_UNSUPPORTED, "batched form supports n_types <= 2");
     P.T = M0.T;
     P.HP = M0.HP;
     P.BS = block;
@@ -555,6 +563,8 @@ MdbLayout mdb_layout(int n) {
     L.total = off;
     return L;
 }
+int efv_run(const Model &M, const nep_system *s, const nep_neighbors *nb, float *U, float *F, float *W,
+            double *E_tot, double *W_tot, void *ws, const WsLayout &L, hipStream_t st);
 }  // namespace
 
 extern "C" {
@@ -786,7 +796,15 @@ int nep_compute_efv(nep_model model, const nep_system *s, const nep_neighbors *n
     if (s->n > 0 && !F) return fail(NEP_ERR_ARG, "F is null");
     WsLayout L;
     if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
-    hipStream_t st = (hipStream_t)stream;
+    return efv_run(M, s, nb, U, F, W, E_tot, W_tot, ws, L, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+int efv_run(const Model &M, const nep_system *s, const nep_neighbors *nb, float *U, float *F, float *W,
+            double *E_tot, double *W_tot, void *ws, const WsLayout &L, hipStream_t st) {
+    int rc;
     if (s->n > 0) {
         HIPCHK(launch_pack(s->n, M.T, s->x, s->y, s->z, s->type, at<float4>(ws, L.pos4), st));
         if ((rc = launch_efv(M, s, nb, U, F, W, W_tot != nullptr, ws, L, st, false, nullptr, nullptr))) return rc;
@@ -795,10 +813,14 @@ int nep_compute_efv(nep_model model, const nep_system *s, const nep_neighbors *n
     // the reduction also runs the completeness test of the lists
     if (E_tot || W_tot || s->n > 0)
         HIPCHK(launch_reduce(at<double>(ws, L.partial), s->n > 0 ? L.nblocks : 0, E_tot, W_tot, nullptr, nullptr,
-                             nullptr, nullptr, nullptr, nullptr, 0, s->n > 0 ? at<float2>(ws, L.top2) : nullptr,
-                             0.99f * nb->skin, nb->status, st));
+                             nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                             s->n > 0 ? at<float2>(ws, L.top2) : nullptr, 0.99f * nb->skin,
+                             reach_of(M, nb->skin), nb->status, st));
     return NEP_OK;
 }
+}  // namespace
+
+extern "C" {
 
 int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep_neighbors *nb, float *F,
                 float *U, double *E_pot, double *E_kin, void *ws, size_t ws_bytes, void *stream) {
@@ -813,6 +835,16 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         return fail(NEP_ERR_ARG, "need dt > 0, n_steps >= 0, rebuild_every >= 1");
     for (int t = 0; t < M.T; ++t)
         if (!(mp->mass[t] > 0.0f)) return fail(NEP_ERR_ARG, "masses must be positive");
+    for (int d = 0; d < 3; ++d) {
+        const double r = mp->strain_rate[d];
+        if (r == 0.0) continue;
+        if (!std::isfinite(r) || !(mp->box0[d] > 0.0) || !std::isfinite(mp->box0[d]))
+            return fail(NEP_ERR_ARG, "strain needs a finite rate and a positive reference box");
+        // the box factor 1 + rate s over the steps of this call (linear in s)
+        const double f0 = 1.0 + r * (double)mp->step, f1 = 1.0 + r * (double)(mp->step + mp->n_steps);
+        if (!(std::min(f0, f1) > 0.05))
+            return fail(NEP_ERR_ARG, "strain would shrink the box below 5% of box0 within the call");
+    }
     WsLayout L;
     if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -840,9 +872,11 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     // that does it
     auto reduce_step = [&](int k) -> hipError_t {
         return launch_reduce(at<double>(ws, L.partial), L.nblocks, nullptr, nullptr, nullptr,
-                             E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr, mp->pair_counts,
-                             nb->status, ctrl, scheduled(step0 + k + 1), nullptr, 0.0f, nullptr, st);
+                             E_pot ? E_pot + k : nullptr, E_kin ? E_kin + k : nullptr,
+                             mp->W_trace ? mp->W_trace + 9 * (size_t)k : nullptr, mp->pair_counts, nb->status, ctrl,
+                             scheduled(step0 + k + 1), nullptr, 0.0f, 0.0f, nullptr, st);
     };
+    const float reach = reach_of(M, nb->skin);
     for (int k = 0; k < n_steps; ++k) {
         const int64_t step = step0 + k;
         KickDriftArgs kd{};
@@ -871,6 +905,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
             kd.pbc[d] = s->pbc[d] ? 1 : 0;
         }
         kd.skin_gate = 0.99f * nb->skin;
+        kd.reach = reach;
         kd.top2 = at<float2>(ws, L.top2);
         kd.status = nb->status;
         kd.ctrl = ctrl;
@@ -880,6 +915,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
             kd.prev_blocks = L.nblocks;
             kd.prev_E = E_pot ? E_pot + (k - 1) : nullptr;
             kd.prev_K = E_kin ? E_kin + (k - 1) : nullptr;
+            kd.prev_W = mp->W_trace ? mp->W_trace + 9 * (size_t)(k - 1) : nullptr;
             kd.counts = mp->pair_counts;
             kd.next_gate = scheduled(step);
         }
@@ -903,7 +939,8 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
             TimedLaunch tl(2, st);
             HIPCHK(launch_build(a, st));
         }
-        if ((rc = launch_efv(M, s, nb, U, F, nullptr, false, ws, L, st, true, v, mp))) return rc;
+        // every step evaluates the per-bead and total virial (Eqs. 15-16)
+        if ((rc = launch_efv(M, s, nb, U, F, mp->W, true, ws, L, st, true, v, mp))) return rc;
     }
     // the last step's reduction (the earlier ones ran in the next step's merge kernel)
     if (n_steps > 0) HIPCHK(reduce_step(n_steps - 1));
@@ -979,7 +1016,8 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
         d.fown = at<float4>(R.ws, L[r].fown);
         d.vh = at<float>(R.ws, L[r].vh);
         d.partial = at<double>(R.ws, L[r].partial);
-        d.order = at<int32_t>(R.ws, L[r].order);
+        d.order = R.nbrs->order;
+        d.reach = reach_of(M, R.nbrs->skin);
         ht[r] = tiles;
         tiles += (S->n + BLOCK - 1) / BLOCK;
         hg[r] = ((R.step + 1) % rebuild_every) == 0 ? 1 : 0;

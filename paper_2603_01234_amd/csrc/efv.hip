@@ -60,8 +60,10 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int t = tile * BLOCK + threadIdx.x;
     if (t >= a.n) return;
+    // the lists' own processing order (written by the build with the rows);
+    // an out-of-range entry (a caller's buffer never written) is not trusted
     int i = a.order ? a.order[t] : t;
-    if ((unsigned)i >= (unsigned)a.n) i = t;  // an order never written by a build is not trusted
+    if ((unsigned)i >= (unsigned)a.n) i = t;
     main_bead<NT, HP>(a, a.cut, TB, i);
 }
 
@@ -172,22 +174,25 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
 // merge of the gather blocks' displacement pairs for the standalone rebuild
 // test.
 __global__ void k_reduce(const double *__restrict__ partial, int nblocks, double *E_tot,
-                         double *W_tot, double *K_tot, double *E_slot, double *K_slot, double *counts,
-                         const int32_t *status, int32_t *ctrl, int next_gate, const float2 *top2,
-                         float skin_gate, int32_t *skin_status) {
+                         double *W_tot, double *K_tot, double *E_slot, double *K_slot, double *W_slot,
+                         double *counts, const int32_t *status, int32_t *ctrl, int next_gate,
+                         const float2 *top2, float skin_gate, float reach, int32_t *skin_status) {
     if (top2) {
         const float2 t = merge_top2(top2, nblocks);
-        if (threadIdx.x == 0 && past_skin(t, skin_gate)) atomicOr(skin_status, NEP_FLAG_SKIN);
+        if (threadIdx.x == 0 && past_skin(t, skin_gate, (1.0f - sigma_of(skin_status[3])) * reach))
+            atomicOr(skin_status, NEP_FLAG_SKIN);
     }
-    reduce_partials(partial, nblocks, E_tot, W_tot, K_tot, E_slot, K_slot, counts, status, ctrl, next_gate);
+    reduce_partials(partial, nblocks, E_tot, W_tot, K_tot, E_slot, K_slot, W_slot, counts, status, ctrl,
+                    next_gate);
 }
 
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
-                         double *K_tot, double *E_slot, double *K_slot, double *counts,
+                         double *K_tot, double *E_slot, double *K_slot, double *W_slot, double *counts,
                          const int32_t *status, int32_t *ctrl, int next_gate, const float2 *top2,
-                         float skin_gate, int32_t *skin_status, hipStream_t s) {
+                         float skin_gate, float reach, int32_t *skin_status, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(BLOCK), 0, s, partial, nblocks, E_tot, W_tot, K_tot,
-                       E_slot, K_slot, counts, status, ctrl, next_gate, top2, skin_gate, skin_status);
+                       E_slot, K_slot, W_slot, counts, status, ctrl, next_gate, top2, skin_gate, reach,
+                       skin_status);
     return hipGetLastError();
 }
 

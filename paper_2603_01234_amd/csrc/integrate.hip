@@ -29,13 +29,20 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
 
 // one workgroup: the previous step's reduction (which also sets the gate to
 // the schedule), then the rebuild test over the pairs of the drift's workgroups
+// with the affine shrink of the lists' compression factor sigma, updated by
+// this step's scale factors (and reset to 1 when the step rebuilds)
 __global__ __launch_bounds__(BLOCK) void k_gate(KickDriftArgs a, int nblocks) {
     if (a.prev_partial)
-        reduce_partials(a.prev_partial, a.prev_blocks, nullptr, nullptr, nullptr, a.prev_E, a.prev_K, a.counts,
-                        a.status, a.ctrl, a.next_gate);
+        reduce_partials(a.prev_partial, a.prev_blocks, nullptr, nullptr, nullptr, a.prev_E, a.prev_K, a.prev_W,
+                        a.counts, a.status, a.ctrl, a.next_gate);
     if (a.status[0] & FREEZE_MASK) return;
     const float2 t = merge_top2(a.top2, nblocks);
-    if (threadIdx.x == 0 && past_skin(t, a.skin_gate)) a.ctrl[0] = 1;
+    if (threadIdx.x == 0) {
+        const float lmin = fminf(1.0f, fminf(a.lam[0], fminf(a.lam[1], a.lam[2])));
+        const float sig = sigma_of(a.status[3]) * lmin;
+        if (past_skin(t, a.skin_gate, (1.0f - sig) * a.reach)) a.ctrl[0] = 1;
+        a.status[3] = a.ctrl[0] ? SIGMA_ONE : __float_as_int(sig);
+    }
 }
 
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s) {

@@ -40,7 +40,12 @@ __global__ __launch_bounds__(BLOCK) void k_gate_batch(MdBatchArgs b) {
     const RepDesc &d = b.rep[r];
     if (d.status[0] & FREEZE_MASK) return;
     const float2 t = merge_top2(d.top2, b.tile_start[r + 1] - b.tile_start[r]);
-    if (threadIdx.x == 0 && past_skin(t, d.skin_gate)) b.gate[r] = 1;
+    if (threadIdx.x == 0) {
+        // no strain here: sigma only carries over from a compressive run
+        const float sig = sigma_of(d.status[3]);
+        if (past_skin(t, d.skin_gate, (1.0f - sig) * d.reach)) b.gate[r] = 1;
+        if (b.gate[r]) d.status[3] = SIGMA_ONE;
+    }
 }
 
 template <int NT, int HP>
@@ -59,9 +64,10 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main_batch(MdBatchArgs b) {
     if (d.status[0] & FREEZE_MASK) return;
     const int t = (blockIdx.x - b.tile_start[r]) * BLOCK + threadIdx.x;
     if (t >= d.n) return;
-    // the replica's processing order (beads of similar cost side by side)
-    int i = d.order[t];
-    if ((unsigned)i >= (unsigned)d.n) i = t;  // an order never written by a build is not trusted
+    // the lists' processing order (beads of similar cost side by side); an
+    // out-of-range entry (a buffer never written) is not trusted
+    int i = d.order ? d.order[t] : t;
+    if ((unsigned)i >= (unsigned)d.n) i = t;
     EfvArgs a{};
     a.n = d.n;
     a.box[0] = d.box[0];

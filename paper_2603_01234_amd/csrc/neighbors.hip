@@ -49,7 +49,8 @@ __device__ __forceinline__ void nb_clear_body(int ncell, int32_t *cell_count, in
     if (build_off(ctrl, status, clear_status)) return;
     int t = bx * blockDim.x + threadIdx.x;
     for (int c = t; c < ncell; c += gx * blockDim.x) cell_count[c] = 0;
-    if (clear_status && t < 4) status[t] = 0;
+    // a fresh build: no flags, and the lists start uncompressed (sigma = 1)
+    if (clear_status && t < 4) status[t] = t == 3 ? SIGMA_ONE : 0;
     if (ctrl && t == 0) ctrl[1] += 1;
 }
 
@@ -57,9 +58,11 @@ __global__ void k_nb_clear(int ncell, int32_t *cell_count, int32_t *status, int 
     nb_clear_body(ncell, cell_count, status, clear_status, ctrl, blockIdx.x, gridDim.x);
 }
 
+// start of an MD call: flags and maxima cleared, sigma (status[3]) kept, since
+// it belongs to the lists, which the call continues from
 __global__ void k_md_clear(int32_t *status, int32_t *ctrl, int gate0) {
     int t = threadIdx.x;
-    if (t < 4) status[t] = 0;
+    if (t < 3) status[t] = 0;
     if (ctrl && t < 4) ctrl[t] = t == 0 ? gate0 : 0;
 }
 

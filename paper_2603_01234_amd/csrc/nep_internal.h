@@ -285,9 +285,9 @@ hipError_t launch_efv_gather(int T, bool virial, bool md, const GatherArgs &a, h
 // top2 (optional): the gather blocks' pairs of the rebuild test; the reduction
 // sets NEP_FLAG_SKIN in skin_status when they call for a rebuild
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
-                         double *K_tot, double *E_slot, double *K_slot, double *counts,
+                         double *K_tot, double *E_slot, double *K_slot, double *W_slot, double *counts,
                          const int32_t *status, int32_t *ctrl, int next_gate, const float2 *top2,
-                         float skin_gate, int32_t *skin_status, hipStream_t s);
+                         float skin_gate, float reach, int32_t *skin_status, hipStream_t s);
 struct NbArgs {
     int n, cap, cap_A;
     float box[3];
@@ -364,8 +364,9 @@ struct KickDriftArgs {
     int T;                  // number of types (type values are clamped below it)
     float skin_gate;        // 0.99 skin: a rebuild is due once the two largest
                             // displacements since the build add up to more
+    float reach;            // largest r_c + skin (the affine-shrink term of the test)
     float2 *top2;           // [blocks] per-block largest and second largest squared displacement
-    const int32_t *status;
+    int32_t *status;        // [3] holds sigma (updated by the merge kernel)
     int32_t *ctrl;          // ctrl[0]: rebuild gate
     int32_t *cell_count;    // or null: cell counts of the step's build, zeroed here
     int ncell;
@@ -373,7 +374,7 @@ struct KickDriftArgs {
     // (in place of a reduction launch of their own) into the slots below
     const double *prev_partial;
     int prev_blocks;
-    double *prev_E, *prev_K, *counts;
+    double *prev_E, *prev_K, *prev_W, *counts;
     int next_gate;          // the schedule's gate for this step's build
 };
 // the drift, then one workgroup that merges the blocks' pairs and switches
@@ -420,8 +421,8 @@ __device__ __forceinline__ float2 merge_top2(const float2 *top2, int n) {
 // status carries a freeze flag nothing but the gate is written.
 __device__ __forceinline__ void reduce_partials(const double *__restrict__ partial, int nblocks, double *E_tot,
                                                 double *W_tot, double *K_tot, double *E_slot, double *K_slot,
-                                                double *counts, const int32_t *status, int32_t *ctrl,
-                                                int next_gate) {
+                                                double *W_slot, double *counts, const int32_t *status,
+                                                int32_t *ctrl, int next_gate) {
     __shared__ double red[NPART][BLOCK];
     double acc[NPART];
 #pragma unroll
@@ -457,11 +458,27 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ parti
         }
     }
     if (W_tot && threadIdx.x < 9) W_tot[threadIdx.x] = red[1 + threadIdx.x][0];
+    if (W_slot && threadIdx.x < 9) W_slot[threadIdx.x] = red[1 + threadIdx.x][0];
 }
 
-// whether a pair of squared displacements calls for a rebuild
-__device__ __forceinline__ bool past_skin(float2 t, float skin_gate) {
-    return sqrtf(t.x) + sqrtf(t.y) > skin_gate;
+// The compression factor sigma of the lists (status[3], float bits): the
+// product over the steps since the build of min(1, smallest scale factor of
+// the step).  Each periodic image moves affinely with the box, so a pair at
+// r >= r_c + skin at the build is now at least sigma (r_c + skin) minus the
+// non-affine displacements of its two beads.  A word that is not a factor in
+// (0, 1] (lists from before this convention) counts as 0, which asks for a
+// rebuild.
+__device__ __forceinline__ float sigma_of(int32_t w) {
+    const float s = __int_as_float(w);
+    return (s > 0.0f && s <= 1.0f) ? s : 0.0f;
+}
+constexpr int32_t SIGMA_ONE = 0x3f800000;  // bits of 1.0f
+
+// whether a pair of squared non-affine displacements, together with the
+// affine shrink (1 - sigma) reach (reach = largest r_c + skin), calls for a
+// rebuild
+__device__ __forceinline__ bool past_skin(float2 t, float skin_gate, float shrink = 0.0f) {
+    return sqrtf(t.x) + sqrtf(t.y) + shrink > skin_gate;
 }
 
 // First half-kick and drift of bead i (kick k = dt/2 ACCEL / m of its type):
@@ -537,12 +554,13 @@ struct RepDesc {
     const uint32_t *nbr;
     const int32_t *rev, *cnt;
     float *ref;
-    const int32_t *status;
+    int32_t *status;       // [3]: sigma (reset to 1 when the step rebuilds)
     // the replica's own workspace
     float4 *pos4, *bvec, *angbuf, *fown;
     float *vh;
     double *partial;       // [tiles][2]: potential and kinetic energy per tile
-    const int32_t *order;  // [n] processing order of the fused kernel, written by the builds
+    const int32_t *order;  // [n] or null: processing order of the fused kernel, written by the builds
+    float reach;           // largest r_c + skin (affine-shrink term of the rebuild test)
 };
 struct MdBatchArgs {
     int n_rep, n_tiles, T;

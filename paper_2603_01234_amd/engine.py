@@ -104,6 +104,7 @@ class Replica:
         self.status = torch.zeros(4, dtype=torch.int32, device=dev)
         self.ref = torch.zeros((3, n), dtype=torch.float32, device=dev)
         self.cnt = torch.zeros((2, n), dtype=torch.int32, device=dev)
+        self.order = torch.zeros(n, dtype=torch.int32, device=dev)   # processing order written by the builds
         if cap is None or cap_A is None:
             c, ca = estimate_caps(self.n, self.box, self.pbc, float(model.rc_R.max()), float(model.rc_A.max()),
                                   self.skin, pos)
@@ -153,6 +154,7 @@ class Replica:
                                           self.ref.data_ptr())
         nb.skin = self.skin
         nb.status = self.status.data_ptr()
+        nb.order = self.order.data_ptr()
         return nb
 
     # -- calls ------------------------------------------------------------------
@@ -207,19 +209,23 @@ class Replica:
     def md(self, n_steps: int, dt: float, masses: Sequence[float], rebuild_every: int = 10,
            strain_rate=(0.0, 0.0, 0.0), E_pot: Optional[torch.Tensor] = None,
            E_kin: Optional[torch.Tensor] = None,
-           pair_counts: Optional[torch.Tensor] = None, regrow: bool = True, sort_every: int = 0):
+           pair_counts: Optional[torch.Tensor] = None, regrow: bool = True, sort_every: int = 0,
+           W_trace: Optional[torch.Tensor] = None, per_bead_virial: bool = False):
         """nep_md_step; after a rebuild overflow the rows are regrown and the
         remaining steps resumed with a forced rebuild (x, v, F are those of the
         last completed step, so the trajectory continues unchanged).  With
         sort_every > 0 the beads are put back into cell order (sort()) every
-        sort_every steps."""
+        sort_every steps.  W_trace: float64 [n_steps, 9] total virial per step;
+        per_bead_virial: self.W holds the per-bead virial at the final step."""
+        if per_bead_virial and self.W is None:
+            self.W = torch.zeros((9, max(self.n, 1)), dtype=torch.float32, device=self.device)
         if sort_every and sort_every > 0:
             done = 0
             while done < n_steps:
                 k = min(int(sort_every), n_steps - done)
                 self.md(k, dt, masses, rebuild_every, strain_rate,
                         None if E_pot is None else E_pot[done:], None if E_kin is None else E_kin[done:],
-                        pair_counts, regrow, 0)
+                        pair_counts, regrow, 0, None if W_trace is None else W_trace[done:], per_bead_virial)
                 done += k
                 if done < n_steps:
                     self.sort()
@@ -242,6 +248,8 @@ class Replica:
                 mp.box0[d] = float(self.box0[d])
             mp.step = int(self.step)
             mp.pair_counts = _ptr(pair_counts)
+            mp.W_trace = None if W_trace is None else W_trace.data_ptr() + 72 * done_total
+            mp.W = _ptr(self.W) if per_bead_virial else None
             s, nb = self.c_system(), self.c_neighbors()
             ep = None if E_pot is None else E_pot.data_ptr() + 8 * done_total
             ek = None if E_kin is None else E_kin.data_ptr() + 8 * done_total

@@ -98,5 +98,41 @@ def test_md_params_layout_matches_header():
     txt = open(HEADER).read()
     body = txt[txt.index("typedef struct {\n    float dt_fs;"):txt.index("} nep_md_params;")]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    names = re.findall(r"\b([a-z_0-9]+)(?:\[\d+\])?;", body)
+    names = re.findall(r"\b([A-Za-z_0-9]+)(?:\[\d+\])?;", body)
     assert names == [f[0] for f in B.MdParams._fields_]
+
+
+def _struct_fields(txt, name):
+    """Field names of a typedef struct in the header, in order."""
+    end = txt.index("} " + name + ";")
+    start = txt.rindex("typedef struct {", 0, end)
+    body = re.sub(r"/\*.*?\*/", "", txt[start + len("typedef struct {"):end], flags=re.S)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        # "float *x, *y, *z" declares three fields
+        for part in decl.split(","):
+            m = re.search(r"([A-Za-z_0-9]+)\s*(?:\[[^\]]*\])?\s*$", part.strip())
+            out.append(m.group(1))
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("nep_neighbors", "Neighbors"), ("nep_system", "System"),
+                                          ("nep_replica", "Replica"), ("nep_batch_config", "BatchConfig"),
+                                          ("nep_labels", "Labels"), ("nep_md_params", "MdParams")])
+def test_struct_layouts_match_header(cname, pyname):
+    """Every C-ABI struct of the header and its ctypes mirror in the binding
+    have the same fields in the same order."""
+    from paper_2603_01234_amd import binding as B
+    txt = open(HEADER).read()
+    assert _struct_fields(txt, cname) == [f[0] for f in getattr(B, pyname)._fields_]
+
+
+def test_library_unit_constant_matches_codata():
+    """The library's acceleration unit (1 eV/nm on 1 amu in nm/fs^2) is the
+    Faraday constant over 1 g/mol, the value the oracle is pinned to."""
+    src = open(os.path.join(ROOT, "paper_2603_01234_amd", "csrc", "nep_internal.h")).read()
+    val = float(re.search(r"ACCEL\s*=\s*([0-9.eE+-]+)f", src).group(1))
+    assert abs(val - 96485.33212 / 1e-3 / 1e-9 * 1e9 / 1e30) < 1e-12 * val

@@ -254,10 +254,30 @@ def test_md_config1_snapshots_at_0_500_1000():
     rep = _rep(spec, params, system, opts["skin"])
     rep.efv(per_bead_virial=False)
     _sampled_parity(rep, spec, params, system, system.box, 10, "config1 step 0")
+    Wt = torch.zeros((1000, 9), dtype=torch.float64, device="cuda")
     for k in (1, 2):
-        rep.md(500, opts["dt"], [W.WATER_MASS], rebuild_every=opts["rebuild_every"], sort_every=100)
+        rep.md(500, opts["dt"], [W.WATER_MASS], rebuild_every=opts["rebuild_every"], sort_every=100,
+               W_trace=Wt[500 * (k - 1):])
         assert rep.step == 500 * k
         _sampled_parity(rep, spec, params, system, system.box, 10 + k, f"config1 step {500 * k}")
+    # the MD step's total virial at step 1000 against a full oracle evaluation
+    from gpu_helpers import TOL_W, rel_rms
+    ref = oracle.efv(spec, params.astype(np.float32).astype(np.float64), rep.positions().astype(np.float64),
+                     system.types, system.box.astype(np.float32).astype(np.float64), system.pbc)
+    e = rel_rms(Wt[999].cpu().numpy().reshape(3, 3), ref.Wtot)
+    print(f"config1 step 1000: MD W_tot rel {e:.2e}", flush=True)
+    assert e <= TOL_W
+    # the widest network (H = 64) on the hot state the trajectory reached
+    from paper_2603_01234_amd import engine as E
+    spec64 = W.water_spec(64)
+    p64 = W.draw_params(spec64, np.random.default_rng(64))
+    hot = E.Replica(E.Model.from_spec(spec64, p64), rep.positions(), system.types, system.box, system.pbc,
+                    skin=opts["skin"])
+    hot.efv(per_bead_virial=False)
+    targets = np.random.default_rng(65).choice(system.n, 120, replace=False)
+    ref64 = oracle.efv(spec64, p64.astype(np.float32).astype(np.float64), hot.positions().astype(np.float64),
+                       system.types, system.box.astype(np.float32).astype(np.float64), system.pbc, targets=targets)
+    compare_efv(hot, ref64, system.n, check_virial=False, targets=targets, label="H=64 on the step-1000 state")
 
 
 def test_md_config2_strained_wire_snapshots_at_0_250_500():
