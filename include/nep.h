@@ -193,6 +193,22 @@ int nep_compute_efv(nep_model model, const nep_system *sys, const nep_neighbors 
                     float *U, float *F, float *W, double *E_tot, double *W_tot,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as nep_compute_efv, with the same arguments and results (bit for
+ * bit), but no workspace argument.  Its scratch is a static device array of
+ * NEP_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; the call itself allocates nothing.  An evaluation
+ * needs about n (64 + 48 n_types + 16 cap_A) bytes of it (n = 16,384 beads
+ * with cap_A = 64 fit); a larger one returns NEP_ERR_ARG with the size it
+ * needs.  Nothing in the array must start at zero, and it keeps the last
+ * call's contents.  Every call on one GPU shares its array: calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised
+ * by the caller. */
+#define NEP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int nep_compute_efv_noalloc(nep_model model, const nep_system *sys, const nep_neighbors *nbrs,
+                            float *U, float *F, float *W, double *E_tot, double *W_tot, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* velocity-Verlet MD                                                        */
 /* ------------------------------------------------------------------------ */

@@ -42,7 +42,9 @@ EXPORTS = ["nep_param_count", "nep_model_create", "nep_model_destroy", "nep_work
            "nep_build_neighbors", "nep_compute_efv", "nep_md_step", "nep_check_status",
            "nep_last_error", "nep_timing_begin", "nep_timing_end", "nep_batch_workspace_bytes",
            "nep_compute_efv_batch", "nep_batch_autotune", "nep_md_batch_workspace_bytes", "nep_md_step_batch",
-           "nep_sort_system"]
+           "nep_sort_system", "nep_compute_efv_noalloc"]
+
+NEP_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class NepError(RuntimeError):
@@ -140,6 +142,9 @@ def lib():
         L.nep_sort_system.argtypes = [c_void_p, POINTER(System), c_void_p, c_void_p, c_void_p, c_void_p,
                                       POINTER(Neighbors), c_void_p, c_size_t, c_void_p]
         L.nep_sort_system.restype = c_int
+        L.nep_compute_efv_noalloc.argtypes = [c_void_p, POINTER(System), POINTER(Neighbors), c_void_p, c_void_p,
+                                              c_void_p, c_void_p, c_void_p, c_void_p]
+        L.nep_compute_efv_noalloc.restype = c_int
         L.nep_last_error.argtypes = []
         L.nep_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -191,6 +196,10 @@ def nep_build_neighbors(model, sys: System, nb: Neighbors, wrap: int, ws_ptr, ws
 def nep_compute_efv(model, sys: System, nb: Neighbors, U, F, W, E_tot, W_tot, ws_ptr, ws_bytes, stream) -> int:
     return lib().nep_compute_efv(model, ctypes.byref(sys), ctypes.byref(nb), U, F, W, E_tot, W_tot,
                                  ws_ptr, ws_bytes, stream)
+
+
+def nep_compute_efv_noalloc(model, sys: System, nb: Neighbors, U, F, W, E_tot, W_tot, stream) -> int:
+    return lib().nep_compute_efv_noalloc(model, ctypes.byref(sys), ctypes.byref(nb), U, F, W, E_tot, W_tot, stream)
 
 
 def nep_md_step(model, sys: System, v, mp: MdParams, nb: Neighbors, F, U, E_pot, E_kin, ws_ptr, ws_bytes,

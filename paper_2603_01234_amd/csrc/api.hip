@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -97,6 +98,30 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.vh = take(nn * 12);
     L.ctrl = take(4 * sizeof(int32_t));
     // per-workgroup pairs of the rebuild test (gather or drift workgroups)
+    L.top2 = take((size_t)L.nblocks * sizeof(float2));
+    L.total = off;
+    return L;
+}
+
+// The part of the workspace one evaluation (pack, fused kernel, gather,
+// reduction) uses, packed on its own: the layout of the allocation-free
+// entry point, whose scratch is a fixed static array.
+WsLayout efv_layout(int T, int n, int cap_A) {
+    WsLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    L.nblocks = (int)((nn + BLOCK / GATHER_LANES - 1) / (BLOCK / GATHER_LANES));
+    L.pos4 = take(nn * 16);
+    L.bvec = take(nn * (size_t)T * 48);
+    L.angbuf = take((size_t)std::max(cap_A, 1) * nn * 16);
+    L.fown = take(nn * 16);
+    L.partial = take((size_t)L.nblocks * 16 * sizeof(double));
+    L.U = take(nn * 4);
     L.top2 = take((size_t)L.nblocks * sizeof(float2));
     L.total = off;
     return L;
@@ -567,6 +592,37 @@ int efv_run(const Model &M, const nep_system *s, const nep_neighbors *nb, float 
             double *E_tot, double *W_tot, void *ws, const WsLayout &L, hipStream_t st);
 }  // namespace
 
+// Scratch of the allocation-free evaluation: one fixed array per device,
+// held by the loaded code object until the process ends.  In host code the
+// name stands for a host-side shadow, not the device array: the device
+// address is taken once per device with hipGetSymbolAddress and only that
+// address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[NEP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+// the device address of this device's scratch array (looked up on the first
+// call on the device, with the device current)
+int noalloc_scratch(void **out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(NEP_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(NEP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return NEP_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int nep_timing_begin(int max_launches, unsigned class_mask) {
@@ -796,6 +852,24 @@ int nep_compute_efv(nep_model model, const nep_system *s, const nep_neighbors *n
     if (s->n > 0 && !F) return fail(NEP_ERR_ARG, "F is null");
     WsLayout L;
     if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
+    return efv_run(M, s, nb, U, F, W, E_tot, W_tot, ws, L, (hipStream_t)stream);
+}
+
+int nep_compute_efv_noalloc(nep_model model, const nep_system *s, const nep_neighbors *nb, float *U, float *F,
+                            float *W, double *E_tot, double *W_tot, void *stream) {
+    int rc;
+    if ((rc = check_model(model))) return rc;
+    const Model &M = model->m;
+    if ((rc = check_system(M, s))) return rc;
+    if ((rc = check_nbrs(s, nb))) return rc;
+    if (s->n > 0 && !F) return fail(NEP_ERR_ARG, "F is null");
+    const WsLayout L = efv_layout(M.T, s->n, nb->cap_A);
+    if (L.total > (size_t)NEP_NOALLOC_SCRATCH_BYTES)
+        return fail(NEP_ERR_ARG, "the evaluation needs " + std::to_string(L.total) +
+                                     " bytes of scratch; the static array holds " +
+                                     std::to_string((size_t)NEP_NOALLOC_SCRATCH_BYTES));
+    void *ws = nullptr;
+    if ((rc = noalloc_scratch(&ws))) return rc;
     return efv_run(M, s, nb, U, F, W, E_tot, W_tot, ws, L, (hipStream_t)stream);
 }
 
