@@ -42,6 +42,16 @@ class _Model(ctypes.Structure):
                 ("rc_R", ctypes.c_double * 64), ("rc_A", ctypes.c_double * 64)]
 
 
+class _MdOpts(ctypes.Structure):
+    _fields_ = [("thermostat", ctypes.c_int), ("T_target", ctypes.c_double), ("tau_T", ctypes.c_double),
+                ("noise", ctypes.POINTER(ctypes.c_double)), ("kB", ctypes.c_double),
+                ("barostat", ctypes.c_int), ("P_target", ctypes.c_double * 3), ("tau_P", ctypes.c_double),
+                ("beta", ctypes.c_double), ("P_in", ctypes.c_double * 3), ("Fe", ctypes.c_double * 3)]
+
+
+KB_EV = 8.617333262e-5   # Boltzmann constant, eV/K (CODATA, exact since 2019)
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -62,6 +72,9 @@ def _load():
         lib.or_md.argtypes = [P(_Model), P(d), i, P(d), P(d), P(i), P(d), P(d), P(d), P(i),
                               d, i, ctypes.c_long, P(d), d, P(d), P(d), P(d), i]
         lib.or_md.restype = i
+        lib.or_md_ens.argtypes = [P(_Model), P(d), i, P(d), P(d), P(i), P(d), P(d), P(d), P(i),
+                                  d, i, ctypes.c_long, P(d), d, P(_MdOpts), P(d), P(d), P(d), P(d), P(d), P(d), i]
+        lib.or_md_ens.restype = i
         lib.or_param_count.argtypes = [P(_Model)]
         lib.or_param_count.restype = ctypes.c_long
         lib.or_max_threads.restype = i
@@ -195,3 +208,53 @@ def md(spec, params, pos, vel, types, masses, box, pbc, dt, n_steps, step0=0,
     if rc != 0:
         raise ValueError("oracle md failed")
     return pos, vel, F, box, Ep[:n_steps], Ek[:n_steps]
+
+
+class MDRun:
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def md_ens(spec, params, pos, vel, types, masses, box, pbc, dt, n_steps, step0=0, strain_rate=None, box0=None,
+           thermostat=0, T_target=300.0, tau_T=100.0, noise=None, barostat=0, P_target=(0.0, 0.0, 0.0),
+           tau_P=1000.0, beta=0.0, P_in=(np.nan, np.nan, np.nan), Fe=(0.0, 0.0, 0.0), n_threads: int = 0) -> MDRun:
+    """FP64 velocity Verlet with a thermostat (1 Berendsen, 2 Bussi: noise
+    [n_steps, 2] of (R, S)), a per-call Berendsen barostat (scale factor from
+    P_in, eV/nm^3) and the HNEMD driving force F_e (1/nm).  Returns pos, vel,
+    F, box and per-step E_pot, E_kin, W [n_steps, 3, 3], J [n_steps, 3]
+    and the mean diagonal pressure P_out (eV/nm^3)."""
+    lib = _load()
+    pos = np.array(pos, dtype=np.float64).reshape(-1, 3).copy()
+    vel = np.array(vel, dtype=np.float64).reshape(-1, 3).copy()
+    n = pos.shape[0]
+    types = np.ascontiguousarray(types, dtype=np.int32)
+    masses = np.ascontiguousarray(masses, dtype=np.float64)
+    box = np.array(box, dtype=np.float64).copy()
+    box0 = np.array(box if box0 is None else box0, dtype=np.float64)
+    pbc_a = np.ascontiguousarray(np.asarray(pbc).astype(np.int32))
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    F = np.zeros((n, 3))
+    k = max(n_steps, 1)
+    Ep, Ek, Wt, Jt = np.zeros(k), np.zeros(k), np.zeros((k, 9)), np.zeros((k, 3))
+    Pout = np.zeros(3)
+    sr = None if strain_rate is None else np.ascontiguousarray(strain_rate, dtype=np.float64)
+    o = _MdOpts()
+    o.thermostat, o.T_target, o.tau_T, o.kB = int(thermostat), float(T_target), float(tau_T), KB_EV
+    nz = None
+    if noise is not None:
+        nz = np.ascontiguousarray(noise, dtype=np.float64).reshape(-1)
+        o.noise = nz.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    o.barostat, o.tau_P, o.beta = int(barostat), float(tau_P), float(beta)
+    for d in range(3):
+        o.P_target[d] = float(P_target[d])
+        o.P_in[d] = float(P_in[d])
+        o.Fe[d] = float(Fe[d])
+    m = _model(spec)
+    rc = lib.or_md_ens(ctypes.byref(m), _ptr(params), n, _ptr(pos), _ptr(vel), _ptr(types, ctypes.c_int),
+                       _ptr(masses), _ptr(box), _ptr(box0), _ptr(pbc_a, ctypes.c_int), float(dt), int(n_steps),
+                       int(step0), _ptr(sr) if sr is not None else None, ACCEL, ctypes.byref(o), _ptr(F), _ptr(Ep),
+                       _ptr(Ek), _ptr(Wt), _ptr(Jt), _ptr(Pout), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle md_ens failed")
+    return MDRun(pos=pos, vel=vel, F=F, box=box, E_pot=Ep[:n_steps], E_kin=Ek[:n_steps],
+                 W=Wt[:n_steps].reshape(-1, 3, 3), J=Jt[:n_steps], P_out=Pout)

@@ -693,6 +693,162 @@ int or_md(const or_model *m, const double *params, int n, double *pos, double *v
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* ensembles and the HNEMD driving force, FP64                              */
+/*                                                                          */
+/* The paper equilibrates in NVT/NPT (Sec. III.A.1, III.C.3) and measures   */
+/* thermal conductivity by HNEMD (Sec. III.B.3) inside an external engine,  */
+/* naming no algorithm beyond the HNEMD reference.  Taken here:             */
+/*  - Berendsen velocity rescaling: after the second half-kick of a step,   */
+/*    v *= lam, lam^2 = 1 + (dt/tau_T)(T0/T - 1), T = 2K/(N_f k_B),         */
+/*    N_f = 3N - 3;                                                          */
+/*  - Bussi-Donadio-Parrinello stochastic velocity rescaling (J. Chem.      */
+/*    Phys. 126, 014101): the kinetic energy after the step is drawn from   */
+/*    the exact solution of its stochastic equation over dt, with c =       */
+/*    exp(-dt/tau_T), target Kbar = N_f k_B T0 / 2, a standard normal R and */
+/*    S, a chi-square with N_f - 1 degrees of freedom (both given per step):*/
+/*      K' = c K + (1 - c) Kbar (S + R^2)/N_f + 2 R sqrt(c (1-c) K Kbar/N_f)*/
+/*    and v *= sqrt(K'/K) with the sign of R + sqrt(c N_f K/((1-c) Kbar));  */
+/*  - a Berendsen barostat per periodic axis whose scale factor is set once */
+/*    per call from a given pressure P_in (the previous call's mean):       */
+/*      mu_d = cbrt(1 - beta dt/tau_P (P0_d - P_in_d)), clamped to          */
+/*      [0.99, 1.01], positions and box scaled by mu_d after every drift;   */
+/*    P_dd = (2 K_dd + W_dd)/V with K_dd = sum m v_d^2 / 2;                 */
+/*  - HNEMD (Fan et al., Phys. Rev. B 99, 064308): driving force             */
+/*      F_i^ext = W_i^T F_e - (1/N) sum_k W_k^T F_e                         */
+/*    (the mean removed so that the momentum is conserved), added to the    */
+/*    force of the step's second half-kick; potential heat current          */
+/*      J = sum_i W_i v_i  (after the thermostat).                          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int thermostat;          /* 0 none, 1 Berendsen, 2 Bussi */
+    double T_target, tau_T;  /* K, fs */
+    const double *noise;     /* [n_steps][2]: R, S (Bussi) */
+    double kB;               /* eV/K */
+    int barostat;            /* 0 none, 1 Berendsen (periodic axes) */
+    double P_target[3], tau_P, beta;   /* eV/nm^3, fs, 1/(eV/nm^3) */
+    double P_in[3];          /* sets this call's scale factor (non-finite: none) */
+    double Fe[3];            /* 1/nm */
+} or_md_opts;
+
+int or_md_ens(const or_model *m, const double *params, int n, double *pos, double *vel,
+              const int *types, const double *mass_by_type, double *box, const double *box0,
+              const int *pbc, double dt, int n_steps, long step0, const double *strain_rate,
+              double accel, const or_md_opts *o, double *F, double *E_pot, double *E_kin,
+              double *W_trace /*[n_steps][9]*/, double *J_trace /*[n_steps][3]*/,
+              double *P_out /*[3] mean diagonal pressure*/, int n_threads)
+{
+    int N = n > 0 ? n : 1;
+    double *U = (double *)malloc(sizeof(double) * N);
+    double *Wb = (double *)malloc(sizeof(double) * 9 * N);
+    double E, Wt[9];
+    int hnemd = o && (o->Fe[0] != 0.0 || o->Fe[1] != 0.0 || o->Fe[2] != 0.0);
+    double mu[3] = {1.0, 1.0, 1.0};
+    if (o && o->barostat == 1) {
+        for (int d = 0; d < 3; ++d) {
+            if (!pbc[d] || !isfinite(o->P_in[d])) continue;
+            double f = 1.0 - o->beta * dt / o->tau_P * (o->P_target[d] - o->P_in[d]);
+            double md = cbrt(f);
+            if (md < 0.99) md = 0.99;
+            if (md > 1.01) md = 1.01;
+            mu[d] = md;
+        }
+    }
+    double Psum[3] = {0.0, 0.0, 0.0};
+    /* forces at the starting positions (the plain potential force) */
+    if (or_efv(m, params, n, pos, types, box, pbc, 0, NULL, U, F, NULL, &E, NULL, NULL, n_threads) < 0) {
+        free(U); free(Wb);
+        return -1;
+    }
+    for (int s = 0; s < n_steps; ++s) {
+        for (int i = 0; i < n; ++i) {
+            double a = 0.5 * dt * accel / mass_by_type[types[i]];
+            for (int d = 0; d < 3; ++d) {
+                vel[3 * i + d] += a * F[3 * i + d];
+                pos[3 * i + d] += dt * vel[3 * i + d];
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            double lam = mu[d];
+            if (strain_rate && strain_rate[d] != 0.0) {
+                long st = step0 + s;
+                double L_old = box0[d] * (1.0 + strain_rate[d] * (double)st);
+                double L_new = box0[d] * (1.0 + strain_rate[d] * (double)(st + 1));
+                lam = L_new / L_old;
+                box[d] = L_new;
+            } else if (lam != 1.0) {
+                box[d] *= lam;
+            }
+            if (lam != 1.0)
+                for (int i = 0; i < n; ++i) pos[3 * i + d] *= lam;
+        }
+        if (or_efv(m, params, n, pos, types, box, pbc, 0, NULL, U, F, Wb, &E, Wt, NULL, n_threads) < 0) {
+            free(U); free(Wb);
+            return -1;
+        }
+        if (hnemd) {
+            double mean[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < n; ++i)
+                for (int b = 0; b < 3; ++b)
+                    for (int a = 0; a < 3; ++a) mean[b] += Wb[9 * i + 3 * a + b] * o->Fe[a];
+            for (int b = 0; b < 3; ++b) mean[b] /= (double)n;
+            for (int i = 0; i < n; ++i)
+                for (int b = 0; b < 3; ++b) {
+                    double fe = 0.0;
+                    for (int a = 0; a < 3; ++a) fe += Wb[9 * i + 3 * a + b] * o->Fe[a];
+                    F[3 * i + b] += fe - mean[b];
+                }
+        }
+        double Kd[3] = {0.0, 0.0, 0.0}, J[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < n; ++i) {
+            double mi = mass_by_type[types[i]];
+            double a = 0.5 * dt * accel / mi;
+            for (int d = 0; d < 3; ++d) {
+                vel[3 * i + d] += a * F[3 * i + d];
+                Kd[d] += 0.5 * mi * vel[3 * i + d] * vel[3 * i + d] / accel;
+            }
+            for (int a2 = 0; a2 < 3; ++a2)
+                for (int b = 0; b < 3; ++b) J[a2] += Wb[9 * i + 3 * a2 + b] * vel[3 * i + b];
+        }
+        double K = Kd[0] + Kd[1] + Kd[2];
+        double lam = 1.0;
+        if (o && o->thermostat && n > 1 && K > 0.0) {
+            double Nf = 3.0 * n - 3.0;
+            double Kbar = 0.5 * Nf * o->kB * o->T_target;
+            if (o->thermostat == 1) {
+                double T = 2.0 * K / (Nf * o->kB);
+                double l2 = 1.0 + dt / o->tau_T * (o->T_target / T - 1.0);
+                lam = sqrt(l2 > 0.0 ? l2 : 0.0);
+            } else {
+                double R = o->noise[2 * s], S = o->noise[2 * s + 1];
+                double c = exp(-dt / o->tau_T);
+                double Kn = c * K + (1.0 - c) * Kbar * (S + R * R) / Nf +
+                            2.0 * R * sqrt(c * (1.0 - c) * K * Kbar / Nf);
+                lam = sqrt(Kn / K);
+                if (R + sqrt(c * Nf * K / ((1.0 - c) * Kbar)) < 0.0) lam = -lam;
+            }
+            for (int i = 0; i < 3 * n; ++i) vel[i] *= lam;
+        }
+        double l2 = lam * lam;
+        double V = box[0] * box[1] * box[2];
+        for (int d = 0; d < 3; ++d) {
+            Kd[d] *= l2;
+            Psum[d] += (2.0 * Kd[d] + Wt[4 * d]) / V;
+        }
+        if (E_pot) E_pot[s] = E;
+        if (E_kin) E_kin[s] = K * l2;
+        if (W_trace)
+            for (int a = 0; a < 9; ++a) W_trace[9 * s + a] = Wt[a];
+        if (J_trace)
+            for (int a = 0; a < 3; ++a) J_trace[3 * s + a] = lam * J[a];
+    }
+    if (P_out)
+        for (int d = 0; d < 3; ++d) P_out[d] = n_steps > 0 ? Psum[d] / n_steps : NAN;
+    free(U);
+    free(Wb);
+    return 0;
+}
+
 int or_max_threads(void)
 {
 #ifdef _OPENMP
