@@ -231,6 +231,28 @@ typedef struct {
                                  (Eq. 16) at the end of every step, W[a][b] at 9k + 3a + b */
     float *W;                 /* device [9][n] or NULL: per-bead virial W_i (Eq. 15) at the final
                                  positions, plane 3a + b */
+    /* Ensembles.  The paper equilibrates in NVT and NPT (Sec. III.A.1, III.C.3)
+     * and runs HNEMD (Sec. III.B.3) in an external engine without naming the
+     * algorithms; these are the published methods taken here (all off when zero). */
+    int thermostat;           /* 0 none (NVE), 1 Berendsen, 2 Bussi stochastic velocity rescaling;
+                                 applied after the second half-kick of every step */
+    float T_target;           /* K */
+    float tau_T;              /* coupling time, fs */
+    const double *noise;      /* device [n_steps][2] (thermostat 2): per step a standard normal R and a
+                                 chi-square draw S with 3n - 4 degrees of freedom */
+    int barostat;             /* 0 none, 1 Berendsen per periodic axis: every step of the call scales
+                                 positions and box by mu_d = cbrt(1 - beta dt/tau_P (P_target_d - P_in_d)),
+                                 clamped to [0.99, 1.01]; not with strain on the same axis */
+    double P_target[3];       /* eV/nm^3 (1 GPa = 6.2415 eV/nm^3) */
+    double tau_P;             /* fs */
+    double beta;              /* compressibility, 1/(eV/nm^3) */
+    double P_in[3];           /* pressure that sets this call's factor (the previous call's P_out);
+                                 a non-finite entry leaves that axis unscaled */
+    double P_out[3];          /* out: mean diagonal pressure (2 K_dd + W_dd)/V over the completed steps */
+    float Fe[3];              /* HNEMD driving force parameter, 1/nm (zero: off): the force of every
+                                 step gains W_i^T F_e minus its mean over the beads */
+    double *J_trace;          /* device [n_steps][3] or NULL: potential heat current sum_i W_i v_i
+                                 after every step (eV nm/fs; with a thermostat, after its scaling) */
 } nep_md_params;
 
 /* Advances sys by n_steps of velocity Verlet (the paper's MD runs in an
@@ -246,6 +268,15 @@ typedef struct {
  * lists hold for the final positions.  v: device [3][n] nm/fs.  U: device [n]
  * or NULL (site energies at the last step).  E_pot / E_kin: device double
  * [n_steps] traces or NULL; params->W_trace and params->W as above.
+ *
+ * Ensembles (thermostat, barostat or F_e set): each step runs the gather
+ * without the fused kick, then four small kernels (sums, drive without its
+ * mean and second half-kick, thermostat factor, velocity scaling).  The
+ * force F passed in is used as is for the first half-kick (the plain
+ * potential force from nep_compute_efv, or the previous call's F, which holds
+ * the drive); F on exit holds the total force with the drive.  The barostat
+ * factor is fixed for the call, so the caller runs NPT as a sequence of calls
+ * (of, say, 10 steps) passing P_out back as P_in.
  *
  * Strain: the constant engineering strain-rate loading of the nanowire
  * (Sec. III.C.5), L_d(s) = box0_d (1 + rate_d s) with positions scaled

@@ -88,7 +88,10 @@ class MdParams(ctypes.Structure):
     _fields_ = [("dt_fs", c_float), ("n_steps", c_int), ("rebuild_every", c_int), ("force_rebuild", c_int),
                 ("mass", c_float * 4),
                 ("strain_rate", c_double * 3), ("box0", c_double * 3), ("step", c_int64),
-                ("n_rebuilds", c_int), ("pair_counts", c_void_p), ("W_trace", c_void_p), ("W", c_void_p)]
+                ("n_rebuilds", c_int), ("pair_counts", c_void_p), ("W_trace", c_void_p), ("W", c_void_p),
+                ("thermostat", c_int), ("T_target", c_float), ("tau_T", c_float), ("noise", c_void_p),
+                ("barostat", c_int), ("P_target", c_double * 3), ("tau_P", c_double), ("beta", c_double),
+                ("P_in", c_double * 3), ("P_out", c_double * 3), ("Fe", c_float * 3), ("J_trace", c_void_p)]
 
 
 _lib = None

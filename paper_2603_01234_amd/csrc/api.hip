@@ -62,7 +62,7 @@ struct TimedLaunch {
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, rowbuf, vh, ctrl, top2, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, rowbuf, vh, ctrl, top2, ens, partial2, wbuf, total;
     int ncell_max, nblocks;
 };
 
@@ -82,7 +82,7 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.bvec = take(nn * (size_t)T * 48);
     L.angbuf = take((size_t)std::max(cap_A, 1) * nn * 16);
     L.fown = take(nn * 16);
-    L.partial = take((size_t)L.nblocks * 16 * sizeof(double));
+    L.partial = take((size_t)L.nblocks * NPART * sizeof(double));
     L.U = take(nn * 4);
     L.cell_id = take(nn * 4);
     L.cell_count = take((size_t)L.ncell_max * 4);
@@ -99,6 +99,10 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.ctrl = take(4 * sizeof(int32_t));
     // per-workgroup pairs of the rebuild test (gather or drift workgroups)
     L.top2 = take((size_t)L.nblocks * sizeof(float2));
+    // ensemble steps: sums, finish-block records, per-bead virial of the drive
+    L.ens = take(ENS_DOUBLES * sizeof(double));
+    L.partial2 = take((nn + BLOCK - 1) / BLOCK * 8 * sizeof(double));
+    L.wbuf = take(nn * 9 * sizeof(float));
     L.total = off;
     return L;
 }
@@ -120,7 +124,7 @@ WsLayout efv_layout(int T, int n, int cap_A) {
     L.bvec = take(nn * (size_t)T * 48);
     L.angbuf = take((size_t)std::max(cap_A, 1) * nn * 16);
     L.fown = take(nn * 16);
-    L.partial = take((size_t)L.nblocks * 16 * sizeof(double));
+    L.partial = take((size_t)L.nblocks * NPART * sizeof(double));
     L.U = take(nn * 4);
     L.top2 = take((size_t)L.nblocks * sizeof(float2));
     L.total = off;
@@ -309,8 +313,9 @@ int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, co
     return NEP_OK;
 }
 
+// md: 0 plain evaluation, 1 NVE step, 2 ensemble step (see launch_efv_gather)
 int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, float *U, float *F, float *W,
-               bool want_total_virial, void *ws, const WsLayout &L, hipStream_t st, bool md, float *v,
+               bool want_total_virial, void *ws, const WsLayout &L, hipStream_t st, int md, float *v,
                const nep_md_params *mp) {
     const int n = s->n;
     EfvArgs a{};
@@ -363,6 +368,7 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
             g.inv_mass[t] = 1.0f / mp->mass[t];
             g.mass[t] = mp->mass[t];
         }
+        for (int d = 0; d < 3; ++d) g.Fe[d] = mp->Fe[d];
     }
     if (!md) {
         g.ref = nb->ref;
@@ -371,7 +377,8 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     }
     {
         TimedLaunch tl(1, st);
-        HIPCHK(launch_efv_gather(M.T, W != nullptr || want_total_virial, md, g, st));
+        const bool hn = md == 2 && (mp->Fe[0] != 0.0f || mp->Fe[1] != 0.0f || mp->Fe[2] != 0.0f);
+        HIPCHK(launch_efv_gather(M.T, W != nullptr || want_total_virial, md, hn, g, st));
     }
     return NEP_OK;
 }
@@ -881,7 +888,7 @@ int efv_run(const Model &M, const nep_system *s, const nep_neighbors *nb, float 
     int rc;
     if (s->n > 0) {
         HIPCHK(launch_pack(s->n, M.T, s->x, s->y, s->z, s->type, at<float4>(ws, L.pos4), st));
-        if ((rc = launch_efv(M, s, nb, U, F, W, W_tot != nullptr, ws, L, st, false, nullptr, nullptr))) return rc;
+        if ((rc = launch_efv(M, s, nb, U, F, W, W_tot != nullptr, ws, L, st, 0, nullptr, nullptr))) return rc;
     }
     // an empty system reduces zero blocks, so the totals come out as zero;
     // the reduction also runs the completeness test of the lists
@@ -919,6 +926,29 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         if (!(std::min(f0, f1) > 0.05))
             return fail(NEP_ERR_ARG, "strain would shrink the box below 5% of box0 within the call");
     }
+    if (mp->thermostat < 0 || mp->thermostat > 2) return fail(NEP_ERR_ARG, "thermostat must be 0, 1 or 2");
+    if (mp->thermostat && !(mp->T_target > 0.0f && mp->tau_T > 0.0f))
+        return fail(NEP_ERR_ARG, "a thermostat needs T_target > 0 and tau_T > 0");
+    if (mp->thermostat == 2 && mp->n_steps > 0 && s->n > 0 && !mp->noise)
+        return fail(NEP_ERR_ARG, "the Bussi thermostat needs its per-step random numbers (noise)");
+    if (mp->barostat < 0 || mp->barostat > 1) return fail(NEP_ERR_ARG, "barostat must be 0 or 1");
+    double mu[3] = {1.0, 1.0, 1.0};
+    if (mp->barostat) {
+        if (!(mp->tau_P > 0.0) || !(mp->beta >= 0.0) || !std::isfinite(mp->beta))
+            return fail(NEP_ERR_ARG, "a barostat needs tau_P > 0 and a finite compressibility beta >= 0");
+        for (int d = 0; d < 3; ++d) {
+            if (!s->pbc[d] || !std::isfinite(mp->P_in[d])) continue;
+            if (mp->strain_rate[d] != 0.0) return fail(NEP_ERR_ARG, "barostat and strain on the same axis");
+            if (!std::isfinite(mp->P_target[d])) return fail(NEP_ERR_ARG, "P_target must be finite");
+            const double f = 1.0 - mp->beta * (double)mp->dt_fs / mp->tau_P * (mp->P_target[d] - mp->P_in[d]);
+            mu[d] = std::min(1.01, std::max(0.99, std::cbrt(f)));
+        }
+    }
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(mp->Fe[d])) return fail(NEP_ERR_ARG, "F_e must be finite");
+    const bool hn = mp->Fe[0] != 0.0f || mp->Fe[1] != 0.0f || mp->Fe[2] != 0.0f;
+    const bool ens = mp->thermostat != 0 || mp->barostat != 0 || hn;
+    for (int d = 0; d < 3; ++d) mp->P_out[d] = NAN;
     WsLayout L;
     if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -931,9 +961,15 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     const int64_t step0 = mp->step;
     const int n_steps = mp->n_steps;
     int32_t *ctrl = at<int32_t>(ws, L.ctrl);
-    auto box_at = [&](int64_t stp, int d) -> float {
-        return mp->strain_rate[d] != 0.0 ? (float)(mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)stp))
-                                         : s->box[d];
+    double *ensbuf = at<double>(ws, L.ens);
+    // box after each completed step: the strain's L0 (1 + rate s), or the
+    // barostat's factor once per step (in double, as the box is kept)
+    const float box_start[3] = {s->box[0], s->box[1], s->box[2]};
+    auto box_at = [&](int64_t stp, int d) -> double {
+        if (mp->strain_rate[d] != 0.0) return mp->box0[d] * (1.0 + mp->strain_rate[d] * (double)stp);
+        double b = (double)box_start[d];
+        for (int64_t q = step0; q < stp; ++q) b *= mu[d];
+        return b;
     };
     auto scheduled = [&](int64_t stp) -> int { return ((stp + 1) % mp->rebuild_every) == 0 ? 1 : 0; };
     // the drift of step k sets the gate when the two largest displacements
@@ -941,6 +977,9 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     // rounding of the list predicate); the build queued right after it runs
     // only then, or when the schedule asks for it
     HIPCHK(launch_clear_status(nb->status, ctrl, (mp->force_rebuild || scheduled(step0)) ? 1 : 0, st));
+    if (ens) HIPCHK(launch_ensemble_clear(ensbuf, st));
+    // per-bead virial of the HNEMD drive: the caller's W, else the workspace's
+    float *Wbead = mp->W ? mp->W : (hn ? at<float>(ws, L.wbuf) : nullptr);
     // the reduction of step k (energies, pair counts, completed-step count),
     // launched on its own; within the run it is the next step's merge kernel
     // that does it
@@ -968,13 +1007,18 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         kd.dt = mp->dt_fs;
         kd.T = M.T;
         for (int t = 0; t < M.T; ++t) kd.inv_mass[t] = 1.0f / mp->mass[t];
+        double vol = 1.0;
         for (int d = 0; d < 3; ++d) {
             kd.lam[d] = 1.0f;
             if (mp->strain_rate[d] != 0.0) {
                 kd.lam[d] = (float)((1.0 + mp->strain_rate[d] * (double)(step + 1)) /
                                     (1.0 + mp->strain_rate[d] * (double)step));
-                s->box[d] = box_at(step + 1, d);
+            } else if (mu[d] != 1.0) {
+                kd.lam[d] = (float)mu[d];
             }
+            const double bd = box_at(step + 1, d);
+            s->box[d] = (float)bd;
+            vol *= bd;
             kd.box[d] = s->box[d];
             kd.pbc[d] = s->pbc[d] ? 1 : 0;
         }
@@ -983,7 +1027,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         kd.top2 = at<float2>(ws, L.top2);
         kd.status = nb->status;
         kd.ctrl = ctrl;
-        if (k > 0) {
+        if (k > 0 && !ens) {
             // the previous step's reduction runs in the merge kernel
             kd.prev_partial = at<double>(ws, L.partial);
             kd.prev_blocks = L.nblocks;
@@ -1014,16 +1058,65 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
             HIPCHK(launch_build(a, st));
         }
         // every step evaluates the per-bead and total virial (Eqs. 15-16)
-        if ((rc = launch_efv(M, s, nb, U, F, mp->W, true, ws, L, st, true, v, mp))) return rc;
+        if (!ens) {
+            if ((rc = launch_efv(M, s, nb, U, F, mp->W, true, ws, L, st, 1, v, mp))) return rc;
+            continue;
+        }
+        if ((rc = launch_efv(M, s, nb, U, F, Wbead, true, ws, L, st, 2, v, mp))) return rc;
+        EnsArgs e{};
+        e.n = n;
+        e.T = M.T;
+        e.status = nb->status;
+        e.ctrl = ctrl;
+        e.partial = at<double>(ws, L.partial);
+        e.nblocks = L.nblocks;
+        e.E_slot = E_pot ? E_pot + k : nullptr;
+        e.W_slot = mp->W_trace ? mp->W_trace + 9 * (size_t)k : nullptr;
+        e.counts = mp->pair_counts;
+        e.next_gate = scheduled(step + 1);
+        e.F = F;
+        e.pos4 = at<float4>(ws, L.pos4);
+        e.x = s->x;
+        e.y = s->y;
+        e.z = s->z;
+        e.v = v;
+        e.vh = at<float>(ws, L.vh);
+        e.type = s->type;
+        e.Wb = Wbead;
+        e.hn = hn ? 1 : 0;
+        e.half_dt_accel = 0.5f * mp->dt_fs * ACCEL;
+        for (int t = 0; t < M.T; ++t) {
+            e.inv_mass[t] = 1.0f / mp->mass[t];
+            e.mass[t] = mp->mass[t];
+        }
+        e.partial2 = at<double>(ws, L.partial2);
+        e.nb2 = (n + BLOCK - 1) / BLOCK;
+        e.thermostat = mp->thermostat;
+        e.T_target = mp->T_target;
+        e.tau_T = mp->tau_T;
+        e.dt = mp->dt_fs;
+        e.kB = KB_EV;
+        e.noise = mp->thermostat == 2 ? mp->noise + 2 * (size_t)k : nullptr;
+        e.K_slot = E_kin ? E_kin + k : nullptr;
+        e.J_slot = mp->J_trace ? mp->J_trace + 3 * (size_t)k : nullptr;
+        e.volume = vol;
+        e.ens = ensbuf;
+        TimedLaunch tl(3, st);
+        HIPCHK(launch_ensemble_step(e, st));
     }
     // the last step's reduction (the earlier ones ran in the next step's merge kernel)
-    if (n_steps > 0) HIPCHK(reduce_step(n_steps - 1));
+    if (n_steps > 0 && !ens) HIPCHK(reduce_step(n_steps - 1));
     int32_t c[4] = {0, 0, 0, 0};
+    double psum[3] = {0.0, 0.0, 0.0};
     HIPCHK(hipMemcpyAsync(c, ctrl, sizeof c, hipMemcpyDeviceToHost, st));
+    if (ens) HIPCHK(hipMemcpyAsync(psum, ensbuf + 13, sizeof psum, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     mp->n_rebuilds = c[1];
     mp->step = step0 + c[2];
-    for (int d = 0; d < 3; ++d) s->box[d] = box_at(mp->step, d);
+    for (int d = 0; d < 3; ++d) {
+        s->box[d] = (float)box_at(mp->step, d);
+        if (ens && c[2] > 0) mp->P_out[d] = psum[d] / (double)c[2];
+    }
     return read_status(nb, nullptr, st);
 }
 

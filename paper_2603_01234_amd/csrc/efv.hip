@@ -73,17 +73,20 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
 // gathers).  The batched and the served gathers split and add in the same way.
 constexpr int GATHER_BEADS = BLOCK / GATHER_LANES;
 
-template <int NT, bool VIR, bool MD>
+// MD: 0 plain evaluation, 1 NVE step (second half-kick fused), 2 ensemble
+// step (forces with the HNEMD drive when HN, per-bead virial; no kick)
+template <int NT, bool VIR, int MD, bool HN>
 __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
-    __shared__ double red[NPART][BLOCK / 64];
+    constexpr int NP = MD == 2 ? NPART : NPART_NVE;
+    __shared__ double red[NP][BLOCK / 64];
     if (MD && a.freeze && (a.freeze[0] & FREEZE_MASK)) return;  // uniform over the grid
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int q = threadIdx.x % GATHER_LANES;
     const int i = tile * GATHER_BEADS + (int)(threadIdx.x / GATHER_LANES);
     const int n = a.n;
-    double acc[NPART];
+    double acc[NP];
 #pragma unroll
-    for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NP; ++c) acc[c] = 0.0;
     int nR_in = 0, nA_in = 0;  // pairs inside the interaction cutoffs (work accounting)
     float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, W[9];
 #pragma unroll
@@ -109,6 +112,17 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
         nA_in += __shfl_xor(nA_in, o);
     }
     if (i < n && q == 0) {
+        if (HN) {
+            // HNEMD drive W_i^T F_e (its mean is removed by the ensemble kernels)
+            float fe[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) fe[b] = W[b] * a.Fe[0] + W[3 + b] * a.Fe[1] + W[6 + b] * a.Fe[2];
+            Fx += fe[0];
+            Fy += fe[1];
+            Fz += fe[2];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc[13 + b] = (double)fe[b];
+        }
         a.F[i] = Fx;
         a.F[n + i] = Fy;
         a.F[2 * n + i] = Fz;
@@ -123,7 +137,7 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
 #pragma unroll
             for (int c = 0; c < 9; ++c) acc[1 + c] = (double)W[c];
         }
-        if (MD) {
+        if (MD == 1) {
             // second half-kick from the half-step velocity; the step's new
             // state (x, v) is committed to the caller's arrays only here, so
             // a step stopped by a failed rebuild leaves the previous one whole
@@ -155,14 +169,14 @@ __global__ __launch_bounds__(BLOCK) void k_efv_gather(GatherArgs a) {
     // fixed-order block sums: a butterfly within each wave (lane 0's result),
     // then the waves in order
 #pragma unroll
-    for (int c = 0; c < NPART; ++c) {
+    for (int c = 0; c < NP; ++c) {
         double v = acc[c];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
         if (__lane_id() == 0) red[c][threadIdx.x >> 6] = v;
     }
     __syncthreads();
-    if (threadIdx.x < NPART) {
+    if (threadIdx.x < NP) {
         double v = red[threadIdx.x][0];
 #pragma unroll
         for (int w = 1; w < BLOCK / 64; ++w) v += red[threadIdx.x][w];
@@ -225,26 +239,29 @@ hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds, hipStrea
     return hipErrorInvalidValue;
 }
 
-template <int NT, bool VIR, bool MD>
+template <int NT, bool VIR, int MD, bool HN>
 static hipError_t gather_t(const GatherArgs &a, hipStream_t s) {
     int nb = (a.n + GATHER_BEADS - 1) / GATHER_BEADS;
-    hipLaunchKernelGGL((k_efv_gather<NT, VIR, MD>), dim3(nb), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL((k_efv_gather<NT, VIR, MD, HN>), dim3(nb), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
+// built forms: plain with or without the virial, the NVE step (always with
+// the virial), the ensemble step with or without the HNEMD drive
 template <int NT>
-static hipError_t gather_nt(bool vir, bool md, const GatherArgs &a, hipStream_t s) {
-    if (vir) return md ? gather_t<NT, true, true>(a, s) : gather_t<NT, true, false>(a, s);
-    return md ? gather_t<NT, false, true>(a, s) : gather_t<NT, false, false>(a, s);
+static hipError_t gather_nt(bool vir, int md, bool hn, const GatherArgs &a, hipStream_t s) {
+    if (md == 2) return hn ? gather_t<NT, true, 2, true>(a, s) : gather_t<NT, true, 2, false>(a, s);
+    if (md == 1) return gather_t<NT, true, 1, false>(a, s);
+    return vir ? gather_t<NT, true, 0, false>(a, s) : gather_t<NT, false, 0, false>(a, s);
 }
 
-hipError_t launch_efv_gather(int T, bool vir, bool md, const GatherArgs &a, hipStream_t s) {
+hipError_t launch_efv_gather(int T, bool vir, int md, bool hn, const GatherArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     switch (T) {
-        case 1: return gather_nt<1>(vir, md, a, s);
-        case 2: return gather_nt<2>(vir, md, a, s);
-        case 3: return gather_nt<3>(vir, md, a, s);
-        case 4: return gather_nt<4>(vir, md, a, s);
+        case 1: return gather_nt<1>(vir, md, hn, a, s);
+        case 2: return gather_nt<2>(vir, md, hn, a, s);
+        case 3: return gather_nt<3>(vir, md, hn, a, s);
+        case 4: return gather_nt<4>(vir, md, hn, a, s);
     }
     return hipErrorInvalidValue;
 }

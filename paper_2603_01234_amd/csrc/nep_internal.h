@@ -22,8 +22,11 @@ constexpr int TAB_PER_PAIR = NR * KB + NA * KB + NA * (KB - 1);  // 81 + 63 + 56
 constexpr uint32_t J_MASK = 0x1FFFFFFu;
 constexpr int CODE_SHIFT = 25;
 constexpr float ACCEL = 9.648533212e-5f;  // nm/fs^2 per (eV/nm)/amu
-// per-block partial sums: U, W (9), kinetic energy, radial pairs, angular pairs
-constexpr int NPART = 13;
+constexpr double KB_EV = 8.617333262e-5;   // Boltzmann constant, eV/K
+// per-block partial sums: U, W (9), kinetic energy, radial pairs, angular
+// pairs, and (ensemble steps with the HNEMD drive) the driving force (3)
+constexpr int NPART = 16;
+constexpr int NPART_NVE = 13;   // components the plain and NVE gathers sum
 // lanes per bead in the gathers: lane q takes slots q, q + 4, ... of the row,
 // and the lane sums are combined by a shuffle butterfly (the same order in the
 // single-system, batched MD and fitness gathers)
@@ -103,6 +106,7 @@ struct GatherArgs {
     const float *ref;       // [3][n] build positions
     float skin_gate;        // 0.99 skin
     float2 *top2;           // [blocks] or null: per-block pairs of that test
+    float Fe[3];            // ensemble step with the HNEMD drive: F_e (1/nm)
 };
 
 // Cells are numbered tile by tile: tiles of CELL_TILE^3 cells in (z, y, x)
@@ -281,7 +285,10 @@ __device__ __forceinline__ int lm_l(int lm) { return lm < 3 ? 1 : lm < 8 ? 2 : l
 hipError_t launch_pack(int n, int T, const float *x, const float *y, const float *z, const uint8_t *type,
                        float4 *pos4, hipStream_t s);
 hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds_bytes, hipStream_t s);
-hipError_t launch_efv_gather(int T, bool virial, bool md, const GatherArgs &a, hipStream_t s);
+// md: 0 plain evaluation, 1 NVE step (second half-kick and commit fused in),
+// 2 ensemble step (forces, per-bead virial and, with hn, the HNEMD drive; the
+// kick follows in the ensemble kernels)
+hipError_t launch_efv_gather(int T, bool virial, int md, bool hn, const GatherArgs &a, hipStream_t s);
 // top2 (optional): the gather blocks' pairs of the rebuild test; the reduction
 // sets NEP_FLAG_SKIN in skin_status when they call for a rebuild
 hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, double *W_tot,
@@ -419,25 +426,30 @@ __device__ __forceinline__ float2 merge_top2(const float2 *top2, int n) {
 // the completed step in ctrl[2] and sets the rebuild gate ctrl[0] to the
 // schedule's next_gate (the next drift may still switch it on).  Once the
 // status carries a freeze flag nothing but the gate is written.
+// With NP = NPART (ensemble steps) it also leaves, in ens, the mean driving
+// force (ens[0..2] = the block sums of components 13..15 times inv_n) and the
+// step's total virial (ens[3..11]).
+template <int NP = NPART_NVE>
 __device__ __forceinline__ void reduce_partials(const double *__restrict__ partial, int nblocks, double *E_tot,
                                                 double *W_tot, double *K_tot, double *E_slot, double *K_slot,
                                                 double *W_slot, double *counts, const int32_t *status,
-                                                int32_t *ctrl, int next_gate) {
-    __shared__ double red[NPART][BLOCK];
-    double acc[NPART];
+                                                int32_t *ctrl, int next_gate, double *ens = nullptr,
+                                                double inv_n = 0.0) {
+    __shared__ double red[NP][BLOCK];
+    double acc[NP];
 #pragma unroll
-    for (int c = 0; c < NPART; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NP; ++c) acc[c] = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
 #pragma unroll
-        for (int c = 0; c < NPART; ++c) acc[c] += partial[(size_t)b * NPART + c];
+        for (int c = 0; c < NP; ++c) acc[c] += partial[(size_t)b * NPART + c];
     }
 #pragma unroll
-    for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] = acc[c];
+    for (int c = 0; c < NP; ++c) red[c][threadIdx.x] = acc[c];
     __syncthreads();
     for (int s = BLOCK / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s) {
 #pragma unroll
-            for (int c = 0; c < NPART; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+            for (int c = 0; c < NP; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
         }
         __syncthreads();
     }
@@ -459,6 +471,10 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ parti
     }
     if (W_tot && threadIdx.x < 9) W_tot[threadIdx.x] = red[1 + threadIdx.x][0];
     if (W_slot && threadIdx.x < 9) W_slot[threadIdx.x] = red[1 + threadIdx.x][0];
+    if constexpr (NP == NPART) {
+        if (ens && threadIdx.x < 3) ens[threadIdx.x] = red[13 + threadIdx.x][0] * inv_n;
+        if (ens && threadIdx.x < 9) ens[3 + threadIdx.x] = red[1 + threadIdx.x][0];
+    }
 }
 
 // The compression factor sigma of the lists (status[3], float bits): the
@@ -507,6 +523,43 @@ __device__ __forceinline__ float kick_drift_bead(int i, int n, int t, float k, f
     return dx * dx + dy * dy + dz * dz;
 }
 
+
+// ---- ensemble steps (thermostat, per-call barostat, HNEMD drive) ----
+// ens (doubles, workspace): [0..2] mean driving force of the step, [3..11]
+// the step's total virial, [12] the thermostat factor lambda, [13..15] the
+// running sum of the diagonal pressure over the call's steps.
+constexpr int ENS_DOUBLES = 16;
+struct EnsArgs {
+    int n, T;
+    const int32_t *status;  // freeze test
+    int32_t *ctrl;          // MD control words (completed-step count, gate)
+    // after the gather
+    const double *partial;  // gather blocks [nblocks][NPART]
+    int nblocks;
+    double *E_slot, *W_slot, *counts;
+    int next_gate;
+    // finish: drive without its mean, second half-kick, commit
+    float *F;               // [3][n] total force (in: with the drive, out: mean removed)
+    const float4 *pos4;
+    float *x, *y, *z, *v;
+    const float *vh;
+    const uint8_t *type;
+    const float *Wb;        // [9][n] per-bead virial of the step (HNEMD) or null
+    int hn;                 // 1: remove the mean drive and sum the heat current
+    float half_dt_accel;
+    float inv_mass[MAXT], mass[MAXT];
+    double *partial2;       // finish blocks [nb][8]: K, Kxx, Kyy, Kzz, Jx, Jy, Jz
+    int nb2;
+    // thermostat and traces
+    int thermostat;         // 0 none, 1 Berendsen, 2 Bussi
+    double T_target, tau_T, dt, kB;
+    const double *noise;    // [2] this step's R and S (Bussi) or null
+    double *K_slot, *J_slot;
+    double volume;          // box volume after this step's drift (nm^3)
+    double *ens;
+};
+hipError_t launch_ensemble_step(const EnsArgs &e, hipStream_t s);
+hipError_t launch_ensemble_clear(double *ens, hipStream_t s);
 
 // ---- batched evaluation (fitness loop) ----
 struct SysDesc {           // one structure of the batch

@@ -115,6 +115,7 @@ class Replica:
         self.n_rebuilds = 0
         self.lists_valid = False
         self.perm = None   # after sort(): original index of the bead at each position
+        self.P_out = None  # mean diagonal pressure of the last ensemble call (eV/nm^3)
 
     # -- buffers ----------------------------------------------------------------
     def _alloc_lists(self, cap, cap_A):
@@ -210,22 +211,33 @@ class Replica:
            strain_rate=(0.0, 0.0, 0.0), E_pot: Optional[torch.Tensor] = None,
            E_kin: Optional[torch.Tensor] = None,
            pair_counts: Optional[torch.Tensor] = None, regrow: bool = True, sort_every: int = 0,
-           W_trace: Optional[torch.Tensor] = None, per_bead_virial: bool = False):
+           W_trace: Optional[torch.Tensor] = None, per_bead_virial: bool = False, ensemble: Optional[dict] = None,
+           J_trace: Optional[torch.Tensor] = None):
         """nep_md_step; after a rebuild overflow the rows are regrown and the
         remaining steps resumed with a forced rebuild (x, v, F are those of the
         last completed step, so the trajectory continues unchanged).  With
         sort_every > 0 the beads are put back into cell order (sort()) every
         sort_every steps.  W_trace: float64 [n_steps, 9] total virial per step;
-        per_bead_virial: self.W holds the per-bead virial at the final step."""
+        per_bead_virial: self.W holds the per-bead virial at the final step.
+        ensemble: nep_md_params ensemble fields (thermostat, T_target, tau_T,
+        noise: float64 device tensor [n_steps, 2], barostat, P_target, tau_P,
+        beta, P_in, Fe); J_trace: float64 [n_steps, 3] heat current per step.
+        The call's mean diagonal pressure is left in self.P_out."""
         if per_bead_virial and self.W is None:
             self.W = torch.zeros((9, max(self.n, 1)), dtype=torch.float32, device=self.device)
         if sort_every and sort_every > 0:
             done = 0
             while done < n_steps:
                 k = min(int(sort_every), n_steps - done)
+                ens = None
+                if ensemble is not None:
+                    ens = dict(ensemble)
+                    if ens.get("noise") is not None:
+                        ens["noise"] = ens["noise"][done:]
                 self.md(k, dt, masses, rebuild_every, strain_rate,
                         None if E_pot is None else E_pot[done:], None if E_kin is None else E_kin[done:],
-                        pair_counts, regrow, 0, None if W_trace is None else W_trace[done:], per_bead_virial)
+                        pair_counts, regrow, 0, None if W_trace is None else W_trace[done:], per_bead_virial,
+                        ens, None if J_trace is None else J_trace[done:])
                 done += k
                 if done < n_steps:
                     self.sort()
@@ -250,6 +262,23 @@ class Replica:
             mp.pair_counts = _ptr(pair_counts)
             mp.W_trace = None if W_trace is None else W_trace.data_ptr() + 72 * done_total
             mp.W = _ptr(self.W) if per_bead_virial else None
+            mp.J_trace = None if J_trace is None else J_trace.data_ptr() + 24 * done_total
+            for d in range(3):
+                mp.P_in[d] = float("nan")
+            if ensemble:
+                e = ensemble
+                mp.thermostat = int(e.get("thermostat", 0))
+                mp.T_target = float(e.get("T_target", 0.0))
+                mp.tau_T = float(e.get("tau_T", 0.0))
+                noise = e.get("noise")
+                mp.noise = None if noise is None else noise.data_ptr() + 16 * done_total
+                mp.barostat = int(e.get("barostat", 0))
+                mp.tau_P = float(e.get("tau_P", 0.0))
+                mp.beta = float(e.get("beta", 0.0))
+                for d in range(3):
+                    mp.P_target[d] = float(e.get("P_target", (0.0, 0.0, 0.0))[d])
+                    mp.P_in[d] = float(e.get("P_in", (float("nan"),) * 3)[d])
+                    mp.Fe[d] = float(e.get("Fe", (0.0, 0.0, 0.0))[d])
             s, nb = self.c_system(), self.c_neighbors()
             ep = None if E_pot is None else E_pot.data_ptr() + 8 * done_total
             ek = None if E_kin is None else E_kin.data_ptr() + 8 * done_total
@@ -260,6 +289,7 @@ class Replica:
             self.n_rebuilds += int(mp.n_rebuilds)
             for d in range(3):
                 self.box[d] = s.box[d]
+            self.P_out = np.array([mp.P_out[d] for d in range(3)])
             done_total += done
             remaining -= done
             if code == B.NEP_ERR_NEIGHBOR_OVERFLOW and regrow:
@@ -272,6 +302,29 @@ class Replica:
                 return self
             B.check(code)
             return self
+
+    def npt(self, n_calls: int, steps_per_call: int, dt: float, masses: Sequence[float], P_target, tau_P: float,
+            beta: float, thermostat: int = 1, T_target: float = 300.0, tau_T: float = 100.0, rebuild_every: int = 10,
+            noise: Optional[torch.Tensor] = None, E_pot=None, E_kin=None, P_in=None):
+        """NPT as a sequence of nep_md_step calls: the barostat factor of a
+        call comes from the mean pressure of the call before (P_in of the
+        first call, non-finite: unscaled).  Returns the per-call boxes and mean
+        pressures (eV/nm^3)."""
+        P = np.full(3, np.nan) if P_in is None else np.asarray(P_in, np.float64)
+        boxes, pressures = [], []
+        for c in range(n_calls):
+            ens = dict(thermostat=thermostat, T_target=T_target, tau_T=tau_T, barostat=1, P_target=P_target,
+                       tau_P=tau_P, beta=beta, P_in=tuple(P))
+            if noise is not None:
+                ens["noise"] = noise[c * steps_per_call:]
+            k0 = c * steps_per_call
+            self.md(steps_per_call, dt, masses, rebuild_every,
+                    E_pot=None if E_pot is None else E_pot[k0:], E_kin=None if E_kin is None else E_kin[k0:],
+                    ensemble=ens)
+            P = self.P_out.copy()
+            boxes.append(np.asarray(self.box, np.float64).copy())
+            pressures.append(P.copy())
+        return np.array(boxes), np.array(pressures)
 
     # -- host views (original numbering unless internal=True) ---------------------
     def _unperm(self, a: np.ndarray, internal: bool) -> np.ndarray:
