@@ -154,6 +154,50 @@ def cpu_baseline(spec, params, system, pos, min_seconds=10.0, single_core_second
                                       f"density and model on one thread ({el1:.1f} s wall)"}}
 
 
+def ensembles_leg(rep, dt, masses, every, steps=100, sort_every=100):
+    """The ensemble forms of the MD step on the 216,000-bead state the timed
+    window left: NVE for reference, Bussi NVT at 300 K, NPT as calls of 10
+    steps (Berendsen barostat at 0.1 GPa with a Berendsen thermostat), and
+    HNEMD (F_e = 0.1/nm along z, Berendsen thermostat).  Wall clock over
+    `steps` steps each, with the per-bead and total virial every step."""
+    import torch
+    import oracle
+    n = rep.n
+    out = {"workload": f"config1 state, {n} beads, {steps} steps per form", "steps": steps}
+    rng = np.random.default_rng(2603)
+    noise = torch.from_numpy(np.stack([rng.normal(size=steps), rng.chisquare(3 * n - 4, size=steps)], axis=1)).cuda()
+    Jt = torch.zeros((steps, 3), dtype=torch.float64, device="cuda")
+    Ek = torch.zeros(steps, dtype=torch.float64, device="cuda")
+    forms = {
+        "nve": None,
+        "nvt_bussi": dict(thermostat=2, T_target=300.0, tau_T=100.0, noise=noise),
+        "hnemd_berendsen": dict(thermostat=1, T_target=300.0, tau_T=100.0, Fe=(0.0, 0.0, 0.1)),
+    }
+    for name, ens in forms.items():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep.md(steps, dt, masses, rebuild_every=every, sort_every=sort_every, ensemble=ens,
+               E_kin=Ek, J_trace=Jt if name.startswith("hnemd") else None)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"ms_per_step": round(el * 1e3 / steps, 4), "bead_steps_per_s": round(n * steps / el, 1),
+                     "T_end_K": round(2 * float(Ek[-1]) / ((3 * n - 3) * oracle.KB_EV), 1)}
+        if name.startswith("hnemd"):
+            out[name]["J_mean_eV_nm_per_fs"] = [round(float(x), 6) for x in Jt.mean(0).cpu().numpy()]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    boxes, P = rep.npt(steps // 10, 10, dt, masses, P_target=(0.1 * 6.241509,) * 3, tau_P=1000.0, beta=0.05,
+                       thermostat=1, T_target=300.0, tau_T=100.0, rebuild_every=every)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["npt_berendsen"] = {"ms_per_step": round(el * 1e3 / steps, 4), "bead_steps_per_s": round(n * steps / el, 1),
+                            "calls": steps // 10, "P_last_GPa": [round(float(x) / 6.241509, 4) for x in P[-1]],
+                            "box_last_nm": [round(float(x), 4) for x in boxes[-1]]}
+    out["note"] = ("ensemble steps add four small kernels to the NVE step (sums, drive-free half-kick and commit, "
+                   "thermostat factor, velocity scale); NPT is a sequence of 10-step calls, each synchronising once")
+    return out
+
+
 def batched_leg(reps: int = 3, plain_candidates: int = 2):
     """Fitness workload: 64 candidates x 2000 structures per family pair, one
     persistent launch per family (autotuned) against the plain loop of one
@@ -360,6 +404,7 @@ def main():
                     help="put the beads back into cell order every so many MD steps (0: never)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fitness leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-ensembles", action="store_true", help="skip the NVT / NPT / HNEMD leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -516,6 +561,9 @@ def main():
         torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, params, system, rep.positions().astype(np.float64))
+    if not args.no_ensembles:
+        print("bench: ensembles leg", file=sys.stderr, flush=True)
+        out["ensembles"] = ensembles_leg(rep, dt, masses, every, sort_every=args.sort_every)
     model.close()
     if not args.no_batched:
         print("bench: batched fitness leg", file=sys.stderr, flush=True)
