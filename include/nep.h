@@ -404,6 +404,50 @@ int nep_batch_autotune(const nep_model *models, int n_models, const nep_system *
                        void *ws, size_t ws_bytes, void *stream, nep_batch_config *best, float *ms);
 
 /* ------------------------------------------------------------------------ */
+/* the training loop: SNES over the batched fitness evaluation (Sec. II.A)    */
+/* ------------------------------------------------------------------------ */
+/* The paper optimises the parameters with the separable natural evolution
+ * strategy (SNES, Schaul et al. 2011) on a loss of energy, force and virial
+ * RMSEs (per bead, per component, per bead) plus L1 and L2 regularisation
+ * with weights lambda_e, lambda_f, lambda_v, lambda_1, lambda_2.  A generation
+ * on the device: nep_snes_sample, nep_models_load_params (candidates become
+ * the parameters of existing models), nep_compute_efv_batch (their RMSEs), and
+ * nep_snes_update.  All three calls are asynchronous on the stream. */
+typedef struct {
+    double lambda_e, lambda_f, lambda_v;   /* weights of RMSE_E (eV/bead), RMSE_F (eV/nm), RMSE_W (eV/bead) */
+    double lambda_1, lambda_2;             /* weights of mean |z| and sqrt(mean z^2) over the parameters */
+    double eta_mu, eta_sigma;              /* learning rates (SNES defaults: 1 and (3 + ln d)/(5 sqrt d)) */
+} nep_snes_params;
+
+/* Replaces the parameters of n_models existing models by the rows of params
+ * (device [n_models][nep_param_count] floats, the flat layout above): the
+ * flat copy and the derived tables are rewritten on the device with the
+ * arithmetic of nep_model_create, so the result equals a model created from
+ * the same vector.  The models must share n_types and n_hidden.  Calls that
+ * use the models must follow on the same stream (the models change in stream
+ * order).  Non-finite parameters are not checked here. */
+int nep_models_load_params(nep_model *models, int n_models, const float *params, void *stream);
+
+/* z[k][p] = mu[p] + sigma[p] s[k][p] for k < pop (device arrays; s holds
+ * standard normal draws, an input so that any caller can reproduce them). */
+int nep_snes_sample(int pop, size_t dim, const float *mu, const float *sigma, const float *s, float *z,
+                    void *stream);
+
+/* One SNES update.  loss (device double [pop]) receives
+ *   L_k = lambda_e rmse[k][0] + lambda_f rmse[k][1] + lambda_v rmse[k][2]
+ *         + lambda_1 mean_p |z[k][p]| + lambda_2 sqrt(mean_p z[k][p]^2),
+ * order (device int32 [pop] or NULL) the candidates from best to worst
+ * (lower loss first, ties by index, non-finite losses last); then with the
+ * utilities u_r = max(0, ln(pop/2 + 1) - ln r) / sum_j max(0, ...) - 1/pop
+ * of the ranks r = 1..pop,
+ *   mu    += eta_mu sigma sum_r u_r s_(r),
+ *   sigma *= exp(eta_sigma/2 sum_r u_r (s_(r)^2 - 1)).
+ * 2 <= pop <= 1024. */
+int nep_snes_update(int pop, size_t dim, const float *s, const float *z, const double *rmse,
+                    const nep_snes_params *h, float *mu, float *sigma, double *loss, int32_t *order,
+                    void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* kernel timing (benchmark support)                                         */
 /* ------------------------------------------------------------------------ */
 /* While enabled, the library records a HIP event pair on the launching stream

@@ -42,7 +42,8 @@ EXPORTS = ["nep_param_count", "nep_model_create", "nep_model_destroy", "nep_work
            "nep_build_neighbors", "nep_compute_efv", "nep_md_step", "nep_check_status",
            "nep_last_error", "nep_timing_begin", "nep_timing_end", "nep_batch_workspace_bytes",
            "nep_compute_efv_batch", "nep_batch_autotune", "nep_md_batch_workspace_bytes", "nep_md_step_batch",
-           "nep_sort_system", "nep_compute_efv_noalloc"]
+           "nep_sort_system", "nep_compute_efv_noalloc", "nep_models_load_params", "nep_snes_sample",
+           "nep_snes_update"]
 
 NEP_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -82,6 +83,11 @@ class BatchConfig(ctypes.Structure):
 
 class Labels(ctypes.Structure):
     _fields_ = [("E", c_void_p), ("F", c_void_p), ("W", c_void_p)]
+
+
+class SnesParams(ctypes.Structure):
+    _fields_ = [("lambda_e", c_double), ("lambda_f", c_double), ("lambda_v", c_double), ("lambda_1", c_double),
+                ("lambda_2", c_double), ("eta_mu", c_double), ("eta_sigma", c_double)]
 
 
 class MdParams(ctypes.Structure):
@@ -148,6 +154,13 @@ def lib():
         L.nep_compute_efv_noalloc.argtypes = [c_void_p, POINTER(System), POINTER(Neighbors), c_void_p, c_void_p,
                                               c_void_p, c_void_p, c_void_p, c_void_p]
         L.nep_compute_efv_noalloc.restype = c_int
+        L.nep_models_load_params.argtypes = [c_void_p, c_int, c_void_p, c_void_p]
+        L.nep_models_load_params.restype = c_int
+        L.nep_snes_sample.argtypes = [c_int, c_size_t, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+        L.nep_snes_sample.restype = c_int
+        L.nep_snes_update.argtypes = [c_int, c_size_t, c_void_p, c_void_p, c_void_p, POINTER(SnesParams), c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p]
+        L.nep_snes_update.restype = c_int
         L.nep_last_error.argtypes = []
         L.nep_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -281,3 +294,16 @@ def nep_md_step_batch(model, reps, dt: float, masses, rebuild_every: int, E_pot,
 
 def nep_sort_system(model, sys: System, v, F, U, perm, nb: Neighbors, ws_ptr, ws_bytes, stream) -> int:
     return lib().nep_sort_system(model, ctypes.byref(sys), v, F, U, perm, ctypes.byref(nb), ws_ptr, ws_bytes, stream)
+
+
+def nep_models_load_params(models, params_ptr, stream) -> int:
+    m = (c_void_p * len(models))(*models)
+    return lib().nep_models_load_params(m, len(models), params_ptr, stream)
+
+
+def nep_snes_sample(pop: int, dim: int, mu, sigma, s, z, stream) -> int:
+    return lib().nep_snes_sample(int(pop), int(dim), mu, sigma, s, z, stream)
+
+
+def nep_snes_update(pop: int, dim: int, s, z, rmse, h: SnesParams, mu, sigma, loss, order, stream) -> int:
+    return lib().nep_snes_update(int(pop), int(dim), s, z, rmse, ctypes.byref(h), mu, sigma, loss, order, stream)

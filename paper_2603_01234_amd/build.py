@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnep.so")
-SOURCES = ["api.hip", "neighbors.hip", "efv.hip", "integrate.hip", "batch.hip", "md_batch.hip", "ensemble.hip"]
+SOURCES = ["api.hip", "neighbors.hip", "efv.hip", "integrate.hip", "batch.hip", "md_batch.hip", "ensemble.hip", "snes.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

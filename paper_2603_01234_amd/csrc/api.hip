@@ -1328,6 +1328,55 @@ int nep_batch_autotune(const nep_model *models, int n_models, const nep_system *
     return rc;
 }
 
+int nep_models_load_params(nep_model *models, int n_models, const float *params, void *stream) {
+    if (n_models < 0 || (n_models > 0 && (!models || !params))) return fail(NEP_ERR_ARG, "models or params are null");
+    if (n_models == 0) return NEP_OK;
+    int rc;
+    for (int m = 0; m < n_models; ++m)
+        if ((rc = check_model(models[m]))) return rc;
+    const Model &M0 = models[0]->m;
+    for (int m = 1; m < n_models; ++m)
+        if (models[m]->m.T != M0.T || models[m]->m.H != M0.H)
+            return fail(NEP_ERR_ARG, "models must share n_types and n_hidden");
+    hipStream_t st = (hipStream_t)stream;
+    for (int m0 = 0; m0 < n_models; m0 += DERIVE_MAX) {
+        const int cnt = std::min(DERIVE_MAX, n_models - m0);
+        DeriveArgs a{};
+        a.T = M0.T;
+        a.H = M0.H;
+        a.HP = M0.HP;
+        a.n_params = M0.n_params;
+        a.params = params + (size_t)m0 * M0.n_params;
+        for (int k = 0; k < cnt; ++k) {
+            a.tab[k] = models[m0 + k]->m.d_tab;
+            a.ann[k] = models[m0 + k]->m.d_ann;
+            a.flat[k] = models[m0 + k]->m.d_params;
+        }
+        HIPCHK(launch_derive_tables(a, cnt, st));
+    }
+    return NEP_OK;
+}
+
+int nep_snes_sample(int pop, size_t dim, const float *mu, const float *sigma, const float *s, float *z,
+                    void *stream) {
+    if (pop < 0 || (pop > 0 && dim > 0 && (!mu || !sigma || !s || !z))) return fail(NEP_ERR_ARG, "null array");
+    HIPCHK(launch_snes_sample(pop, dim, mu, sigma, s, z, (hipStream_t)stream));
+    return NEP_OK;
+}
+
+int nep_snes_update(int pop, size_t dim, const float *s, const float *z, const double *rmse,
+                    const nep_snes_params *h, float *mu, float *sigma, double *loss, int32_t *order,
+                    void *stream) {
+    if (pop < 2 || pop > 1024) return fail(NEP_ERR_ARG, "population must be 2..1024");
+    if (dim < 1 || !s || !z || !rmse || !h || !mu || !sigma || !loss)
+        return fail(NEP_ERR_ARG, "null array or empty parameter vector");
+    const double w[7] = {h->lambda_e, h->lambda_f, h->lambda_v, h->lambda_1, h->lambda_2, h->eta_mu, h->eta_sigma};
+    for (double x : w)
+        if (!std::isfinite(x) || x < 0.0) return fail(NEP_ERR_ARG, "weights and rates must be finite and >= 0");
+    HIPCHK(launch_snes_update(pop, dim, s, z, rmse, *h, mu, sigma, loss, order, (hipStream_t)stream));
+    return NEP_OK;
+}
+
 int nep_check_status(const nep_neighbors *nb, int32_t out[4], void *stream) {
     if (!nb || !nb->status) return fail(NEP_ERR_ARG, "status is null");
     return read_status(nb, out, (hipStream_t)stream);

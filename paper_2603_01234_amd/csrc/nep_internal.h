@@ -561,6 +561,23 @@ struct EnsArgs {
 hipError_t launch_ensemble_step(const EnsArgs &e, hipStream_t s);
 hipError_t launch_ensemble_clear(double *ens, hipStream_t s);
 
+// ---- SNES on the device (the training loop around the fitness kernel) ----
+constexpr int DERIVE_MAX = 64;   // models per derivation launch
+struct DeriveArgs {
+    int T, H, HP;
+    size_t n_params;
+    const float *params;         // [n_models][n_params] flat vectors (layout of nep.h)
+    float *tab[DERIVE_MAX];      // each model's pair tables
+    float *ann[DERIVE_MAX];      // each model's network table
+    float *flat[DERIVE_MAX];     // each model's copy of the flat vector
+};
+hipError_t launch_derive_tables(const DeriveArgs &a, int n_models, hipStream_t s);
+hipError_t launch_snes_sample(int pop, size_t dim, const float *mu, const float *sigma, const float *s, float *z,
+                              hipStream_t st);
+hipError_t launch_snes_update(int pop, size_t dim, const float *s, const float *z, const double *rmse,
+                              const nep_snes_params &h, float *mu, float *sigma, double *loss, int32_t *order,
+                              hipStream_t st);
+
 // ---- batched evaluation (fitness loop) ----
 struct SysDesc {           // one structure of the batch
     int n;

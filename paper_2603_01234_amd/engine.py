@@ -441,6 +441,58 @@ class FitnessBatch:
         return out
 
 
+class SnesTrainer:
+    """The training loop of the paper (Sec. II.A) on the device: SNES over a
+    population of candidate parameter vectors, each scored by the persistent
+    fitness kernel against reference labels.  mu and sigma stay on the device;
+    a generation is four stream-ordered library calls (sample, load the
+    candidates into the population's models, batched RMSEs, update), with the
+    standard normal draws either given or drawn with torch on the device."""
+
+    def __init__(self, spec, mu0: np.ndarray, sigma0, pop: int, replicas: Sequence[Replica], labels,
+                 weights=(1.0, 1.0, 0.1, 0.0, 0.0), eta=None, seed: int = 0, device: str = "cuda"):
+        self.pop = int(pop)
+        self.dim = int(mu0.size)
+        self.device = torch.device(device)
+        self.models = [Model.from_spec(spec, mu0.astype(np.float32)) for _ in range(self.pop)]
+        self.batch = FitnessBatch(self.models, replicas)
+        self.batch.set_labels(*labels)
+        dev = self.device
+        self.mu = torch.as_tensor(np.asarray(mu0, np.float32), device=dev).contiguous()
+        sig = np.broadcast_to(np.asarray(sigma0, np.float32), (self.dim,)).copy()
+        self.sigma = torch.as_tensor(sig, device=dev).contiguous()
+        self.z = torch.empty((self.pop, self.dim), dtype=torch.float32, device=dev)
+        self.loss = torch.empty(self.pop, dtype=torch.float64, device=dev)
+        self.order = torch.empty(self.pop, dtype=torch.int32, device=dev)
+        if eta is None:
+            eta = (1.0, (3.0 + math.log(self.dim)) / (5.0 * math.sqrt(self.dim)))
+        self.h = B.SnesParams(*[float(x) for x in weights], float(eta[0]), float(eta[1]))
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(int(seed))
+        self.rmse = None
+
+    def generation(self, s: Optional[torch.Tensor] = None, cfg: Optional[B.BatchConfig] = None):
+        """One generation; s: float32 [pop, dim] standard normals on the
+        device (drawn here when None).  Returns s."""
+        if s is None:
+            s = torch.randn((self.pop, self.dim), generator=self.gen, device=self.device, dtype=torch.float32)
+        s = s.contiguous()
+        st = _stream()
+        B.check(B.nep_snes_sample(self.pop, self.dim, self.mu.data_ptr(), self.sigma.data_ptr(), s.data_ptr(),
+                                  self.z.data_ptr(), st))
+        B.check(B.nep_models_load_params([m.handle for m in self.models], self.z.data_ptr(), st))
+        res = self.batch.evaluate(cfg=cfg, rmse=True)
+        self.rmse = res["rmse"]
+        B.check(B.nep_snes_update(self.pop, self.dim, s.data_ptr(), self.z.data_ptr(), self.rmse.data_ptr(), self.h,
+                                  self.mu.data_ptr(), self.sigma.data_ptr(), self.loss.data_ptr(),
+                                  self.order.data_ptr(), st))
+        return s
+
+    def close(self):
+        for m in self.models:
+            m.close()
+
+
 def replica_footprint(model: Model, n: int, box, pbc, skin: float, pos=None) -> int:
     """Device bytes a Replica of n beads holds: state, lists and workspace."""
     cap, cap_A = estimate_caps(n, np.asarray(box, np.float32), pbc, float(model.rc_R.max()),
