@@ -198,6 +198,56 @@ def ensembles_leg(rep, dt, masses, every, steps=100, sort_every=100):
     return out
 
 
+def snes_leg(generations: int = 5):
+    """The training loop (Sec. II.A): SNES with 64 candidates on the 1000
+    water-like structures of the fitness workload, every step on the device
+    (sample, load the candidates, one persistent fitness launch, loss, ranking
+    and update).  The labels are the base set's energies, forces and virials
+    from the single-structure GPU path; the search starts from the base set
+    perturbed by 0.05 with sigma 0.05."""
+    import torch
+    import workloads as W
+    from paper_2603_01234_amd import engine
+    fw = W.config3()
+    spec = fw.specs[0]
+    idx = [k for k in range(len(fw.systems)) if fw.family[k] == 0]
+    base = fw.base_params[0]
+    m0 = engine.Model.from_spec(spec, base.astype(np.float32))
+    reps = []
+    E_lab, F_lab, W_lab = [], [], []
+    for k in idx:
+        sysm = fw.systems[k]
+        r = engine.Replica(m0, sysm.pos_f32(), sysm.types, sysm.box, sysm.pbc, skin=0.0)
+        r.efv(per_bead_virial=False)
+        E_lab.append(float(r.E_tot.cpu()[0]))
+        F_lab.append(r.forces().astype(np.float64))
+        W_lab.append(r.W_tot.cpu().numpy())
+        reps.append(r)
+    rng = np.random.default_rng(2603)
+    mu0 = base + 0.05 * rng.normal(size=base.size)
+    tr = engine.SnesTrainer(spec, mu0, 0.05, 64, reps, (E_lab, np.concatenate(F_lab), W_lab),
+                            weights=(1.0, 1.0, 0.1, 1e-4, 1e-4), seed=7)
+    best, _ = tr.batch.autotune([(m, s) for m in range(8) for s in range(len(reps))])
+    tr.generation(cfg=best)                        # warm-up generation
+    torch.cuda.synchronize()
+    losses = []
+    t0 = time.perf_counter()
+    for _ in range(generations):
+        tr.generation(cfg=best)
+        losses.append(float(tr.loss.min().cpu()))
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / generations
+    beads = 64 * sum(r.n for r in reps)
+    out = {"workload": "SNES, 64 candidates x 1000 water-like structures (N log-uniform 32-1024), H = 30",
+           "parameters": int(base.size), "generations": generations, "ms_per_generation": round(el * 1e3, 3),
+           "bead_evals_per_s": round(beads / el, 1), "best_loss_per_generation": [round(x, 5) for x in losses],
+           "note": "each generation: sample, derive the 64 candidates' tables, one persistent fitness launch, "
+                   "loss/rank/update; the fitness call synchronises once"}
+    tr.close()
+    m0.close()
+    return out
+
+
 def batched_leg(reps: int = 3, plain_candidates: int = 2):
     """Fitness workload: 64 candidates x 2000 structures per family pair, one
     persistent launch per family (autotuned) against the plain loop of one
@@ -405,6 +455,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched fitness leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-ensembles", action="store_true", help="skip the NVT / NPT / HNEMD leg")
+    ap.add_argument("--no-snes", action="store_true", help="skip the SNES training-loop leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -568,6 +619,9 @@ def main():
     if not args.no_batched:
         print("bench: batched fitness leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg()
+    if not args.no_snes:
+        print("bench: SNES leg", file=sys.stderr, flush=True)
+        out["snes"] = snes_leg()
     if not args.no_served:
         print("bench: serving leg", file=sys.stderr, flush=True)
         out["served"] = served_leg()

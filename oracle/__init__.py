@@ -46,7 +46,9 @@ class _MdOpts(ctypes.Structure):
     _fields_ = [("thermostat", ctypes.c_int), ("T_target", ctypes.c_double), ("tau_T", ctypes.c_double),
                 ("noise", ctypes.POINTER(ctypes.c_double)), ("kB", ctypes.c_double),
                 ("barostat", ctypes.c_int), ("P_target", ctypes.c_double * 3), ("tau_P", ctypes.c_double),
-                ("beta", ctypes.c_double), ("P_in", ctypes.c_double * 3), ("Fe", ctypes.c_double * 3)]
+                ("beta", ctypes.c_double), ("P_in", ctypes.c_double * 3), ("Fe", ctypes.c_double * 3),
+                ("n_groups", ctypes.c_int), ("group_start", ctypes.POINTER(ctypes.c_int)),
+                ("F_sum", ctypes.POINTER(ctypes.c_double)), ("W_sum", ctypes.POINTER(ctypes.c_double))]
 
 
 KB_EV = 8.617333262e-5   # Boltzmann constant, eV/K (CODATA, exact since 2019)
@@ -217,12 +219,16 @@ class MDRun:
 
 def md_ens(spec, params, pos, vel, types, masses, box, pbc, dt, n_steps, step0=0, strain_rate=None, box0=None,
            thermostat=0, T_target=300.0, tau_T=100.0, noise=None, barostat=0, P_target=(0.0, 0.0, 0.0),
-           tau_P=1000.0, beta=0.0, P_in=(np.nan, np.nan, np.nan), Fe=(0.0, 0.0, 0.0), n_threads: int = 0) -> MDRun:
+           tau_P=1000.0, beta=0.0, P_in=(np.nan, np.nan, np.nan), Fe=(0.0, 0.0, 0.0), group_start=None,
+           n_threads: int = 0) -> MDRun:
     """FP64 velocity Verlet with a thermostat (1 Berendsen, 2 Bussi: noise
     [n_steps, 2] of (R, S)), a per-call Berendsen barostat (scale factor from
     P_in, eV/nm^3) and the HNEMD driving force F_e (1/nm).  Returns pos, vel,
     F, box and per-step E_pot, E_kin, W [n_steps, 3, 3], J [n_steps, 3]
-    and the mean diagonal pressure P_out (eV/nm^3)."""
+    and the mean diagonal pressure P_out (eV/nm^3).  group_start [N_CG + 1]:
+    the centre of mass of the atoms of each bead (contiguous ranges) is held
+    fixed, and F_sum [N_CG, 3] / W_sum [N_CG, 3, 3] accumulate the beads'
+    total atomic forces and virials over the steps (Eqs. 12, 14)."""
     lib = _load()
     pos = np.array(pos, dtype=np.float64).reshape(-1, 3).copy()
     vel = np.array(vel, dtype=np.float64).reshape(-1, 3).copy()
@@ -249,6 +255,15 @@ def md_ens(spec, params, pos, vel, types, masses, box, pbc, dt, n_steps, step0=0
         o.P_target[d] = float(P_target[d])
         o.P_in[d] = float(P_in[d])
         o.Fe[d] = float(Fe[d])
+    gs = Fs = Ws = None
+    if group_start is not None:
+        gs = np.ascontiguousarray(group_start, dtype=np.int32)
+        ng = gs.size - 1
+        Fs, Ws = np.zeros((ng, 3)), np.zeros((ng, 9))
+        o.n_groups = ng
+        o.group_start = gs.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        o.F_sum = Fs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        o.W_sum = Ws.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     m = _model(spec)
     rc = lib.or_md_ens(ctypes.byref(m), _ptr(params), n, _ptr(pos), _ptr(vel), _ptr(types, ctypes.c_int),
                        _ptr(masses), _ptr(box), _ptr(box0), _ptr(pbc_a, ctypes.c_int), float(dt), int(n_steps),
@@ -257,4 +272,13 @@ def md_ens(spec, params, pos, vel, types, masses, box, pbc, dt, n_steps, step0=0
     if rc != 0:
         raise ValueError("oracle md_ens failed")
     return MDRun(pos=pos, vel=vel, F=F, box=box, E_pot=Ep[:n_steps], E_kin=Ek[:n_steps],
-                 W=Wt[:n_steps].reshape(-1, 3, 3), J=Jt[:n_steps], P_out=Pout)
+                 W=Wt[:n_steps].reshape(-1, 3, 3), J=Jt[:n_steps], P_out=Pout,
+                 F_sum=Fs, W_sum=None if Ws is None else Ws.reshape(-1, 3, 3))
+
+
+def virial_correction(W_bead_mean, n_atoms: int, n_beads: int, T: float):
+    """The virial correction of the CG labels (Eq. 17): the total virial
+    gains (N_AA - N_CG) k_B T I for the kinetic contribution of the degrees of
+    freedom the coarse-graining removes.  W_bead_mean [N_CG, 3, 3]; returns
+    the corrected total (3, 3)."""
+    return np.asarray(W_bead_mean).sum(axis=0) + (n_atoms - n_beads) * KB_EV * T * np.eye(3)

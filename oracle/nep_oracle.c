@@ -729,6 +729,12 @@ typedef struct {
     double P_target[3], tau_P, beta;   /* eV/nm^3, fs, 1/(eV/nm^3) */
     double P_in[3];          /* sets this call's scale factor (non-finite: none) */
     double Fe[3];            /* 1/nm */
+    /* constrained bead centres of mass (Sec. II.C.1): atoms of bead I are
+       group_start[I] .. group_start[I+1]-1; n_groups 0 = no constraint */
+    int n_groups;
+    const int *group_start;
+    double *F_sum;           /* [n_groups][3] += sum_{i in I} f_i every step (Eq. 12) */
+    double *W_sum;           /* [n_groups][9] += sum_{i in I} W_i every step (Eq. 14) */
 } or_md_opts;
 
 int or_md_ens(const or_model *m, const double *params, int n, double *pos, double *vel,
@@ -743,6 +749,7 @@ int or_md_ens(const or_model *m, const double *params, int n, double *pos, doubl
     double *Wb = (double *)malloc(sizeof(double) * 9 * N);
     double E, Wt[9];
     int hnemd = o && (o->Fe[0] != 0.0 || o->Fe[1] != 0.0 || o->Fe[2] != 0.0);
+    int con = o && o->n_groups > 0;
     double mu[3] = {1.0, 1.0, 1.0};
     if (o && o->barostat == 1) {
         for (int d = 0; d < 3; ++d) {
@@ -755,11 +762,22 @@ int or_md_ens(const or_model *m, const double *params, int n, double *pos, doubl
         }
     }
     double Psum[3] = {0.0, 0.0, 0.0};
-    /* forces at the starting positions (the plain potential force) */
+    /* forces at the starting positions (the plain potential force; with the
+       constraint, its projection, which is not accumulated) */
     if (or_efv(m, params, n, pos, types, box, pbc, 0, NULL, U, F, NULL, &E, NULL, NULL, n_threads) < 0) {
         free(U); free(Wb);
         return -1;
     }
+    if (con)
+        for (int g = 0; g < o->n_groups; ++g) {
+            double FI[3] = {0.0, 0.0, 0.0}, MI = 0.0;
+            for (int i = o->group_start[g]; i < o->group_start[g + 1]; ++i) {
+                MI += mass_by_type[types[i]];
+                for (int a = 0; a < 3; ++a) FI[a] += F[3 * i + a];
+            }
+            for (int i = o->group_start[g]; i < o->group_start[g + 1]; ++i)
+                for (int a = 0; a < 3; ++a) F[3 * i + a] -= mass_by_type[types[i]] / MI * FI[a];
+        }
     for (int s = 0; s < n_steps; ++s) {
         for (int i = 0; i < n; ++i) {
             double a = 0.5 * dt * accel / mass_by_type[types[i]];
@@ -785,6 +803,26 @@ int or_md_ens(const or_model *m, const double *params, int n, double *pos, doubl
         if (or_efv(m, params, n, pos, types, box, pbc, 0, NULL, U, F, Wb, &E, Wt, NULL, n_threads) < 0) {
             free(U); free(Wb);
             return -1;
+        }
+        if (con) {
+            /* the centre of mass of every bead's atoms is held fixed: the
+               constraint force on atom i is -(m_i / M_I) sum_{k in I} f_k, so
+               the bead's atoms feel no net force; the accumulated bead force
+               and virial are the unconstrained sums (Eqs. 12, 14) */
+            for (int g = 0; g < o->n_groups; ++g) {
+                double FI[3] = {0.0, 0.0, 0.0}, WI[9] = {0.0}, MI = 0.0;
+                for (int i = o->group_start[g]; i < o->group_start[g + 1]; ++i) {
+                    MI += mass_by_type[types[i]];
+                    for (int a = 0; a < 3; ++a) FI[a] += F[3 * i + a];
+                    for (int a = 0; a < 9; ++a) WI[a] += Wb[9 * i + a];
+                }
+                for (int a = 0; a < 3; ++a) o->F_sum[3 * g + a] += FI[a];
+                for (int a = 0; a < 9; ++a) o->W_sum[9 * g + a] += WI[a];
+                for (int i = o->group_start[g]; i < o->group_start[g + 1]; ++i) {
+                    double w = mass_by_type[types[i]] / MI;
+                    for (int a = 0; a < 3; ++a) F[3 * i + a] -= w * FI[a];
+                }
+            }
         }
         if (hnemd) {
             double mean[3] = {0.0, 0.0, 0.0};

@@ -191,3 +191,91 @@ def test_heat_current_is_the_time_derivative_of_r_times_site_energy():
     J_full = J1 + (v1 * E1[:, None]).sum(axis=0)
     print("dG/dt", dGdt, "J", J_full)
     np.testing.assert_allclose(J_full, dGdt, rtol=2e-4, atol=1e-6 * np.abs(dGdt).max())
+
+
+# --------------------------------------------------------------------------
+# constrained bead centres of mass (Sec. II.C.1, Eqs. 9, 12, 14, 17)
+# --------------------------------------------------------------------------
+def _aa_water(n_side=3, seed=13, T=300.0):
+    spec = W.water_aa_spec(16)
+    params = W.draw_params(spec, np.random.default_rng(seed))
+    sysm, gs = W.water_atomistic(np.random.SeedSequence(seed), n_side, temperature=T)
+    return spec, params, sysm, gs
+
+
+def _coms(pos, masses, gs, box):
+    """Molecule centres of mass with each molecule unwrapped by minimum image
+    about its first atom."""
+    out = []
+    for g in range(gs.size - 1):
+        a, b = gs[g], gs[g + 1]
+        d = pos[a:b] - pos[a]
+        d -= box * np.round(d / box)
+        m = masses[a:b]
+        out.append(pos[a] + (m[:, None] * d).sum(axis=0) / m.sum())
+    return np.array(out)
+
+
+def test_constraint_holds_every_bead_centre_of_mass():
+    spec, params, sysm, gs = _aa_water()
+    pos = sysm.pos_f32().astype(np.float64)
+    mb = sysm.masses[sysm.types]
+    r = oracle.md_ens(spec, params, pos, sysm.vel, sysm.types, sysm.masses, sysm.box, PER, 0.5, 40, group_start=gs)
+    c0 = _coms(pos, mb, gs, sysm.box)
+    c1 = _coms(r.pos, mb, gs, sysm.box)
+    d = c1 - c0
+    d -= sysm.box * np.round(d / sysm.box)
+    assert np.abs(d).max() < 1e-12
+    p = (mb[:, None] * r.vel).reshape(-1, 3, 3).sum(axis=1)
+    assert np.abs(p).max() < 1e-12 * np.abs(mb[:, None] * r.vel).max()
+    # the atoms did move inside their molecules
+    assert np.abs(r.pos - pos).max() > 1e-4
+    # the total NEP force vanishes, so the beads' forces sum to zero every step
+    assert np.abs(r.F_sum.sum(axis=0)).max() < 1e-9 * np.abs(r.F_sum).max()
+
+
+def test_constrained_nve_conserves_energy_to_second_order():
+    """The constraint forces do no work (the constrained velocities are zero),
+    so the constrained run is NVE: the energy error falls ~4x per halving of dt."""
+    spec, params, sysm, gs = _aa_water(seed=14, T=500.0)
+    pos = sysm.pos_f32().astype(np.float64)
+    errs = []
+    for dt, n in ((0.5, 40), (0.25, 80)):
+        r = oracle.md_ens(spec, params, pos, sysm.vel, sysm.types, sysm.masses, sysm.box, PER, dt, n,
+                          group_start=gs)
+        E = r.E_pot + r.E_kin
+        errs.append(np.abs(E - E[0]).max())
+    assert 3.0 < errs[0] / errs[1] < 5.5, errs
+
+
+def test_single_atom_beads_give_the_static_force_and_virial():
+    """Every atom its own bead: the constraint holds every atom in place, so
+    the time-averaged bead force and virial are the static force and per-atom
+    virial of the starting configuration."""
+    spec, params, sysm, _ = _aa_water(n_side=2, seed=15)
+    pos = sysm.pos_f32().astype(np.float64)
+    n = sysm.n
+    gs = np.arange(n + 1)
+    r = oracle.md_ens(spec, params, pos, np.zeros((n, 3)), sysm.types, sysm.masses, sysm.box, PER, 0.5, 6,
+                      group_start=gs)
+    e = oracle.efv(spec, params, pos, sysm.types, sysm.box, PER)
+    np.testing.assert_array_equal(r.pos, pos)
+    np.testing.assert_allclose(r.F_sum / 6, e.F, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(r.W_sum / 6, e.W, rtol=1e-13, atol=1e-13)
+
+
+def test_one_bead_holding_every_atom_is_plain_nve():
+    spec, params, sysm, _ = _aa_water(n_side=2, seed=16)
+    pos = sysm.pos_f32().astype(np.float64)
+    v = sysm.vel - (sysm.masses[sysm.types][:, None] * sysm.vel).sum(0) / sysm.masses[sysm.types].sum()
+    a = oracle.md_ens(spec, params, pos, v, sysm.types, sysm.masses, sysm.box, PER, 0.5, 20)
+    b = oracle.md_ens(spec, params, pos, v, sysm.types, sysm.masses, sysm.box, PER, 0.5, 20,
+                      group_start=[0, sysm.n])
+    np.testing.assert_allclose(b.pos, a.pos, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(b.E_pot, a.E_pot, rtol=1e-12)
+
+
+def test_virial_correction_adds_the_removed_kinetic_degrees_of_freedom():
+    Wb = np.random.default_rng(1).normal(size=(5, 3, 3))
+    got = oracle.virial_correction(Wb, 15, 5, 300.0)
+    np.testing.assert_allclose(got, Wb.sum(0) + 10 * 8.617333262e-5 * 300.0 * np.eye(3), rtol=1e-15)

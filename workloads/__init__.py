@@ -302,6 +302,57 @@ def gold_nanowire(seed_seq: np.random.SeedSequence, n_target: int = 200_000,
                   masses, vel, name="au_aacg_wire")
 
 
+O_MASS, H_MASS = 15.999, 1.008   # amu
+OH_BOND, HOH_ANGLE = 0.09572, 104.52   # nm, degrees
+
+
+def water_aa_spec(n_hidden: int = 60) -> ModelSpec:
+    """A two-type atomistic water model (0 = O, 1 = H) standing in for the
+    paper's NEP-AA water, whose trained weights are not available: radial
+    cutoff 0.5 nm, angular 0.4 nm, 60 neurons."""
+    return ModelSpec(n_types=2, n_hidden=n_hidden, rc_R=np.full((2, 2), 0.5), rc_A=np.full((2, 2), 0.4))
+
+
+def water_atomistic(seed_seq: np.random.SeedSequence, n_side: int, density: float = WATER_DENSITY,
+                    jitter: float = 0.03, temperature: float = 300.0):
+    """n_side^3 rigid-geometry water molecules (O, H, H, contiguous) with random
+    orientations on a jittered simple-cubic lattice of molecule centres, in a
+    periodic cube at `density` molecules per nm^3.  Velocities are Maxwell at
+    `temperature` with every molecule's centre-of-mass velocity removed.
+    Returns (System of 3 n_side^3 atoms, group_start [n_mol + 1])."""
+    s_pos, s_rot, s_vel = seed_seq.spawn(3)
+    rng = np.random.default_rng(s_pos)
+    a = density ** (-1.0 / 3.0)
+    L = n_side * a
+    centres = _jittered_sc(rng, n_side, a, jitter)
+    nm = centres.shape[0]
+    half = math.radians(HOH_ANGLE) / 2.0
+    local = np.array([[0.0, 0.0, 0.0],
+                      [OH_BOND * math.sin(half), 0.0, OH_BOND * math.cos(half)],
+                      [-OH_BOND * math.sin(half), 0.0, OH_BOND * math.cos(half)]])
+    m = np.array([O_MASS, H_MASS, H_MASS])
+    local -= (m[:, None] * local).sum(axis=0) / m.sum()
+    rr = np.random.default_rng(s_rot)
+    q = rr.normal(size=(nm, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    R = np.stack([np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+                  np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+                  np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], 1)
+    pos = (centres[:, None, :] + np.einsum("mab,kb->mka", R, local)).reshape(-1, 3)
+    pos = np.mod(pos, L)
+    types = np.tile(np.array([0, 1, 1], np.uint8), nm)
+    masses = np.array([O_MASS, H_MASS])
+    mb = masses[types]
+    v = maxwell_velocities(np.random.default_rng(s_vel), mb, temperature)
+    v = v.reshape(nm, 3, 3)
+    mm = mb.reshape(nm, 3)
+    v -= (mm[:, :, None] * v).sum(axis=1, keepdims=True) / mm.sum(axis=1)[:, None, None]
+    sysm = System(pos, types, np.array([L, L, L]), np.array([True, True, True]), masses, v.reshape(-1, 3),
+                  name=f"water_aa_{nm}")
+    return sysm, np.arange(0, 3 * nm + 1, 3, dtype=np.int32)
+
+
 # ---------------------------------------------------------------------------
 # the five workloads
 # ---------------------------------------------------------------------------
