@@ -248,6 +248,39 @@ def snes_leg(generations: int = 5):
     return out
 
 
+def labels_leg(steps: int = 100):
+    """Constrained-MD label generation (Sec. II.C.1) with a synthetic two-type
+    atomistic water model (H = 60, cutoffs 0.5/0.4 nm): the paper's 1536-atom /
+    512-bead box and a 192,000-atom / 64,000-bead box, `steps` constrained NVE
+    steps of 0.5 fs each, accumulating bead forces and virials every step."""
+    import torch
+    import workloads as W
+    from paper_2603_01234_amd import engine
+    spec = W.water_aa_spec(60)
+    params = W.draw_params(spec, np.random.default_rng(2603))
+    model = engine.Model.from_spec(spec, params)
+    out = {"workload": "constrained NVE of atomistic water, beads = molecule centres of mass, dt 0.5 fs",
+           "steps": steps}
+    for n_side in (8, 40):
+        sysm, gs = W.water_atomistic(np.random.SeedSequence(n_side), n_side, temperature=300.0)
+        rep = engine.Replica(model, sysm.pos_f32(), sysm.types, sysm.box, sysm.pbc, skin=0.1, vel=sysm.vel)
+        rep.efv(per_bead_virial=False)
+        rep.constrained_labels(gs, 5, 0.5, sysm.masses, 300.0)          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F, Wb, Wt = rep.constrained_labels(gs, steps, 0.5, sysm.masses, 300.0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"atoms_{sysm.n}"] = {"beads": int(gs.size - 1), "ms_per_step": round(el * 1e3 / steps, 4),
+                                  "atom_steps_per_s": round(sysm.n * steps / el, 1),
+                                  "mean_bead_force_norm_eV_nm": round(float(np.linalg.norm(F, axis=1).mean()), 4),
+                                  "corrected_pressure_GPa": round(float(np.trace(Wt)) / (3 * np.prod(sysm.box))
+                                                                  * 0.1602176634, 4)}
+        del rep
+    model.close()
+    return out
+
+
 def batched_leg(reps: int = 3, plain_candidates: int = 2):
     """Fitness workload: 64 candidates x 2000 structures per family pair, one
     persistent launch per family (autotuned) against the plain loop of one
@@ -456,6 +489,7 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-ensembles", action="store_true", help="skip the NVT / NPT / HNEMD leg")
     ap.add_argument("--no-snes", action="store_true", help="skip the SNES training-loop leg")
+    ap.add_argument("--no-labels", action="store_true", help="skip the constrained label-generation leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -622,6 +656,9 @@ def main():
     if not args.no_snes:
         print("bench: SNES leg", file=sys.stderr, flush=True)
         out["snes"] = snes_leg()
+    if not args.no_labels:
+        print("bench: label-generation leg", file=sys.stderr, flush=True)
+        out["labels"] = labels_leg()
     if not args.no_served:
         print("bench: serving leg", file=sys.stderr, flush=True)
         out["served"] = served_leg()

@@ -212,6 +212,24 @@ int nep_compute_efv_noalloc(nep_model model, const nep_system *sys, const nep_ne
 /* ------------------------------------------------------------------------ */
 /* velocity-Verlet MD                                                        */
 /* ------------------------------------------------------------------------ */
+/* Constrained bead centres of mass, for generating coarse-grained training
+ * labels (Sec. II.C.1): every bead I is a contiguous range of atoms whose
+ * centre of mass R_I = sum_i C_Ii r_i (Eq. 9, mass weights) is held fixed by
+ * the constraint force -(m_i/M_I) sum_{k in I} f_k on its atoms (applied to
+ * the incoming force at the start of a call, and after every force
+ * evaluation; it does no work, so the run is NVE).  After every step the
+ * library adds the bead's total atomic force sum_{i in I} f_i (the mean force
+ * of Eq. 12 once divided by the step count) and its virial sum_{i in I} W_i
+ * (Eq. 14) to double accumulators.  The virial correction of Eq. 17 is the
+ * caller's: it adds (N_AA - N_CG) k_B T to the diagonal of the total. */
+typedef struct {
+    int n_groups;                 /* N_CG */
+    const int32_t *group_start;   /* device [n_groups + 1]: bead I holds atoms group_start[I] ..
+                                     group_start[I+1] - 1 (ascending, covering 0 .. n) */
+    double *F_sum;                /* device [3][n_groups]: += sum_{i in I} f_i after every step */
+    double *W_sum;                /* device [9][n_groups]: += sum_{i in I} W_i after every step */
+} nep_constraint;
+
 typedef struct {
     float dt_fs;              /* time step */
     int n_steps;              /* steps in this call */
@@ -253,6 +271,7 @@ typedef struct {
                                  step gains W_i^T F_e minus its mean over the beads */
     double *J_trace;          /* device [n_steps][3] or NULL: potential heat current sum_i W_i v_i
                                  after every step (eV nm/fs; with a thermostat, after its scaling) */
+    const nep_constraint *constraint;  /* host struct or NULL: constrained bead centres of mass */
 } nep_md_params;
 
 /* Advances sys by n_steps of velocity Verlet (the paper's MD runs in an
@@ -269,7 +288,7 @@ typedef struct {
  * or NULL (site energies at the last step).  E_pot / E_kin: device double
  * [n_steps] traces or NULL; params->W_trace and params->W as above.
  *
- * Ensembles (thermostat, barostat or F_e set): each step runs the gather
+ * Ensembles (thermostat, barostat, F_e or a constraint set): each step runs the gather
  * without the fused kick, then four small kernels (sums, drive without its
  * mean and second half-kick, thermostat factor, velocity scaling).  The
  * force F passed in is used as is for the first half-kick (the plain

@@ -90,6 +90,10 @@ class SnesParams(ctypes.Structure):
                 ("lambda_2", c_double), ("eta_mu", c_double), ("eta_sigma", c_double)]
 
 
+class Constraint(ctypes.Structure):
+    _fields_ = [("n_groups", c_int), ("group_start", c_void_p), ("F_sum", c_void_p), ("W_sum", c_void_p)]
+
+
 class MdParams(ctypes.Structure):
     _fields_ = [("dt_fs", c_float), ("n_steps", c_int), ("rebuild_every", c_int), ("force_rebuild", c_int),
                 ("mass", c_float * 4),
@@ -97,7 +101,8 @@ class MdParams(ctypes.Structure):
                 ("n_rebuilds", c_int), ("pair_counts", c_void_p), ("W_trace", c_void_p), ("W", c_void_p),
                 ("thermostat", c_int), ("T_target", c_float), ("tau_T", c_float), ("noise", c_void_p),
                 ("barostat", c_int), ("P_target", c_double * 3), ("tau_P", c_double), ("beta", c_double),
-                ("P_in", c_double * 3), ("P_out", c_double * 3), ("Fe", c_float * 3), ("J_trace", c_void_p)]
+                ("P_in", c_double * 3), ("P_out", c_double * 3), ("Fe", c_float * 3), ("J_trace", c_void_p),
+                ("constraint", POINTER(Constraint))]
 
 
 _lib = None

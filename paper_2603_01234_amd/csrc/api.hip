@@ -947,7 +947,12 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(mp->Fe[d])) return fail(NEP_ERR_ARG, "F_e must be finite");
     const bool hn = mp->Fe[0] != 0.0f || mp->Fe[1] != 0.0f || mp->Fe[2] != 0.0f;
-    const bool ens = mp->thermostat != 0 || mp->barostat != 0 || hn;
+    const nep_constraint *con = mp->constraint;
+    if (con) {
+        if (con->n_groups < 1 || con->n_groups > s->n || !con->group_start || !con->F_sum || !con->W_sum)
+            return fail(NEP_ERR_ARG, "a constraint needs 1 <= n_groups <= n and its device arrays");
+    }
+    const bool ens = mp->thermostat != 0 || mp->barostat != 0 || hn || con;
     for (int d = 0; d < 3; ++d) mp->P_out[d] = NAN;
     WsLayout L;
     if ((rc = check_ws(M, s, nb, ws, ws_bytes, L))) return rc;
@@ -978,8 +983,29 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     // only then, or when the schedule asks for it
     HIPCHK(launch_clear_status(nb->status, ctrl, (mp->force_rebuild || scheduled(step0)) ? 1 : 0, st));
     if (ens) HIPCHK(launch_ensemble_clear(ensbuf, st));
-    // per-bead virial of the HNEMD drive: the caller's W, else the workspace's
-    float *Wbead = mp->W ? mp->W : (hn ? at<float>(ws, L.wbuf) : nullptr);
+    // per-bead virial of the HNEMD drive and of the constrained beads: the
+    // caller's W, else the workspace's
+    float *Wbead = mp->W ? mp->W : ((hn || con) ? at<float>(ws, L.wbuf) : nullptr);
+    EnsArgs base{};
+    base.n = n;
+    base.T = M.T;
+    base.status = nb->status;
+    base.ctrl = ctrl;
+    base.F = F;
+    base.type = s->type;
+    base.Wb = Wbead;
+    for (int t = 0; t < M.T; ++t) {
+        base.inv_mass[t] = 1.0f / mp->mass[t];
+        base.mass[t] = mp->mass[t];
+    }
+    if (con) {
+        base.n_groups = con->n_groups;
+        base.group_start = con->group_start;
+        base.F_sum = con->F_sum;
+        base.W_sum = con->W_sum;
+        // the incoming force must satisfy the constraint too
+        HIPCHK(launch_constraint_project(base, st));
+    }
     // the reduction of step k (energies, pair counts, completed-step count),
     // launched on its own; within the run it is the next step's merge kernel
     // that does it
@@ -1063,11 +1089,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
             continue;
         }
         if ((rc = launch_efv(M, s, nb, U, F, Wbead, true, ws, L, st, 2, v, mp))) return rc;
-        EnsArgs e{};
-        e.n = n;
-        e.T = M.T;
-        e.status = nb->status;
-        e.ctrl = ctrl;
+        EnsArgs e = base;
         e.partial = at<double>(ws, L.partial);
         e.nblocks = L.nblocks;
         e.E_slot = E_pot ? E_pot + k : nullptr;

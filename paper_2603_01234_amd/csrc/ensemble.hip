@@ -11,6 +11,9 @@
 // After the ensemble-mode gather (forces, virial, drive; no kick):
 //   k_ens_reduce   one workgroup: energy, virial and pair-count sums, the MD
 //                  bookkeeping, the mean drive
+//   k_con_project  one thread per bead (constrained label runs, Sec. II.C.1):
+//                  the bead's total atomic force and virial accumulated
+//                  (Eqs. 12, 14) and the centre-of-mass constraint force
 //   k_ens_finish   one thread per bead: drive without its mean, second
 //                  half-kick, commit of x and v, per-block kinetic tensor and
 //                  heat current
@@ -25,6 +28,46 @@ constexpr int ENS_P2 = 8;  // finish-block record: K, Kxx, Kyy, Kzz, Jx, Jy, Jz,
 __global__ __launch_bounds__(BLOCK) void k_ens_reduce(EnsArgs e) {
     reduce_partials<NPART>(e.partial, e.nblocks, nullptr, nullptr, nullptr, e.E_slot, nullptr, e.W_slot, e.counts,
                            e.status, e.ctrl, e.next_gate, e.ens, 1.0 / (double)e.n);
+}
+
+// one thread per bead (a contiguous range of atoms): the bead's total atomic
+// force and virial, added to the accumulators when acc is set, and the
+// constraint force -(m_i/M_I) F_I on each of its atoms, which leaves the
+// bead's centre of mass unaccelerated
+__global__ __launch_bounds__(BLOCK) void k_con_project(EnsArgs e, int acc) {
+    if (e.status[0] & FREEZE_MASK) return;
+    const int g = blockIdx.x * BLOCK + threadIdx.x;
+    if (g >= e.n_groups) return;
+    const int n = e.n;
+    // a range outside [0, n) is clamped (the caller's table is not trusted)
+    const int a0 = max(0, min(e.group_start[g], n)), a1 = max(a0, min(e.group_start[g + 1], n));
+    double FI[3] = {0.0, 0.0, 0.0}, MI = 0.0;
+    for (int i = a0; i < a1; ++i) {
+        MI += (double)e.mass[min((int)e.type[i], e.T - 1)];
+        for (int b = 0; b < 3; ++b) FI[b] += (double)e.F[(size_t)b * n + i];
+    }
+    if (acc) {
+        for (int b = 0; b < 3; ++b) e.F_sum[(size_t)b * e.n_groups + g] += FI[b];
+        for (int c = 0; c < 9; ++c) {
+            double w = 0.0;
+            for (int i = a0; i < a1; ++i) w += (double)e.Wb[(size_t)c * n + i];
+            e.W_sum[(size_t)c * e.n_groups + g] += w;
+        }
+    }
+    if (!(MI > 0.0)) return;
+    for (int i = a0; i < a1; ++i) {
+        const double w = (double)e.mass[min((int)e.type[i], e.T - 1)] / MI;
+        for (int b = 0; b < 3; ++b) {
+            float *f = e.F + (size_t)b * n + i;
+            *f = (float)((double)*f - w * FI[b]);
+        }
+    }
+}
+
+hipError_t launch_constraint_project(const EnsArgs &e, hipStream_t s) {
+    if (e.n == 0 || e.n_groups == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_con_project, dim3((e.n_groups + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, e, 0);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(BLOCK) void k_ens_finish(EnsArgs e) {
@@ -159,6 +202,8 @@ hipError_t launch_ensemble_step(const EnsArgs &e, hipStream_t s) {
     if (e.n == 0) return hipSuccess;
     const int nb = (e.n + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL(k_ens_reduce, dim3(1), dim3(BLOCK), 0, s, e);
+    if (e.n_groups > 0)
+        hipLaunchKernelGGL(k_con_project, dim3((e.n_groups + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, e, 1);
     hipLaunchKernelGGL(k_ens_finish, dim3(nb), dim3(BLOCK), 0, s, e);
     hipLaunchKernelGGL(k_ens_thermo, dim3(1), dim3(BLOCK), 0, s, e);
     if (e.thermostat) hipLaunchKernelGGL(k_ens_scale, dim3(nb), dim3(BLOCK), 0, s, e);

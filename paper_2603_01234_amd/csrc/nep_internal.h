@@ -557,8 +557,14 @@ struct EnsArgs {
     double *K_slot, *J_slot;
     double volume;          // box volume after this step's drift (nm^3)
     double *ens;
+    // constrained bead centres of mass (n_groups 0: none)
+    int n_groups;
+    const int32_t *group_start;
+    double *F_sum, *W_sum;  // [3][n_groups], [9][n_groups]
 };
 hipError_t launch_ensemble_step(const EnsArgs &e, hipStream_t s);
+// the constraint projection of F alone (start of a call; nothing accumulated)
+hipError_t launch_constraint_project(const EnsArgs &e, hipStream_t s);
 hipError_t launch_ensemble_clear(double *ens, hipStream_t s);
 
 // ---- SNES on the device (the training loop around the fitness kernel) ----

@@ -263,6 +263,8 @@ class Replica:
             mp.W_trace = None if W_trace is None else W_trace.data_ptr() + 72 * done_total
             mp.W = _ptr(self.W) if per_bead_virial else None
             mp.J_trace = None if J_trace is None else J_trace.data_ptr() + 24 * done_total
+            con = None if ensemble is None else ensemble.get("constraint")
+            mp.constraint = None if con is None else ctypes.pointer(con)
             for d in range(3):
                 mp.P_in[d] = float("nan")
             if ensemble:
@@ -325,6 +327,28 @@ class Replica:
             boxes.append(np.asarray(self.box, np.float64).copy())
             pressures.append(P.copy())
         return np.array(boxes), np.array(pressures)
+
+    def constrained_labels(self, group_start: np.ndarray, n_steps: int, dt: float, masses: Sequence[float],
+                           T_label: float, rebuild_every: int = 10, E_pot=None, E_kin=None):
+        """CG training labels by constrained MD (Sec. II.C.1): NVE with the
+        centre of mass of each bead's atoms (contiguous ranges given by
+        group_start) held fixed, accumulating the beads' total atomic force
+        and virial every step.  Returns the time-averaged bead forces
+        [N_CG, 3] (Eq. 12), bead virials [N_CG, 3, 3] (Eq. 14) and the total
+        virial with the correction (N_AA - N_CG) k_B T_label I (Eqs. 16-17);
+        the accumulation runs in the library's kernels.  The atoms must stay
+        in the given order (no sort)."""
+        gs = torch.as_tensor(np.asarray(group_start, np.int32), device=self.device).contiguous()
+        G = gs.numel() - 1
+        Fs = torch.zeros((3, G), dtype=torch.float64, device=self.device)
+        Ws = torch.zeros((9, G), dtype=torch.float64, device=self.device)
+        con = B.Constraint(G, gs.data_ptr(), Fs.data_ptr(), Ws.data_ptr())
+        self.md(n_steps, dt, masses, rebuild_every, E_pot=E_pot, E_kin=E_kin, ensemble=dict(constraint=con))
+        F = (Fs / n_steps).T.cpu().numpy()
+        Wb = (Ws / n_steps).T.cpu().numpy().reshape(G, 3, 3)
+        kB = 8.617333262e-5
+        Wtot = Wb.sum(axis=0) + (self.n - G) * kB * T_label * np.eye(3)
+        return F, Wb, Wtot
 
     # -- host views (original numbering unless internal=True) ---------------------
     def _unperm(self, a: np.ndarray, internal: bool) -> np.ndarray:
