@@ -227,7 +227,7 @@ def snes_leg(generations: int = 5):
     mu0 = base + 0.05 * rng.normal(size=base.size)
     tr = engine.SnesTrainer(spec, mu0, 0.05, 64, reps, (E_lab, np.concatenate(F_lab), W_lab),
                             weights=(1.0, 1.0, 0.1, 1e-4, 1e-4), seed=7)
-    best, _ = tr.batch.autotune([(m, s) for m in range(8) for s in range(len(reps))])
+    best = tr.batch.autotune([(m, s) for m in range(8) for s in range(len(reps))])[0]
     tr.generation(cfg=best)                        # warm-up generation
     torch.cuda.synchronize()
     losses = []
@@ -329,7 +329,10 @@ def batched_leg(reps: int = 3, plain_candidates: int = 2):
         beads = sum(fb.replicas[s].n for _, s in work)
         # autotune on the first 8 candidates (all structures)
         sample = [(m, s) for (m, s) in work if m < 8]
-        best, ms = fb.autotune(sample)
+        best, ms, tried, _ = fb.autotune(sample)
+        t1 = time.perf_counter()
+        _, _, _, hit = fb.autotune(sample)
+        t_cached = time.perf_counter() - t1
         fb.evaluate(work, cfg=best)                      # warm-up at full size
         times = []
         for _ in range(reps):
@@ -359,8 +362,15 @@ def batched_leg(reps: int = 3, plain_candidates: int = 2):
                         "batched_ms": round(t * 1e3, 2), "batched_bead_evals_per_s": round(beads / t, 1),
                         "plain_bead_evals_per_s": round(pbeads / t_plain, 1),
                         "plain_sample_items": len(pw),
-                        "autotune": {"block": best.block, "order": best.order,
-                                     "ms_per_config_on_8_candidates": [round(x, 3) for x in ms]},
+                        "autotune": {"best": {"block": best.block, "order": best.order, "wg_per_cu": best.wg_per_cu,
+                                              "schedule": ["given", "structure-major", "candidate-major",
+                                                           "blocked-8"][best.schedule]},
+                                     "search": [{"schedule": c.schedule, "order": c.order, "wg_per_cu": c.wg_per_cu,
+                                                 "block": c.block, "ms_median_of_3": round(x, 3)}
+                                                for c, x in zip(tried, ms)],
+                                     "sample": "the first 8 candidates on every structure",
+                                     "second_call_from_cache": hit,
+                                     "second_call_ms": round(t_cached * 1e3, 3)},
                         "rmse_candidate0": [float(x) for x in rm[0]],
                         "rmse_candidate1": [float(x) for x in rm[1]]})
         total_beads += beads
@@ -391,12 +401,6 @@ def served_leg(plain_requests: int = 2000):
     model = engine.Model.from_spec(sw.spec, sw.params)
     n_req = len(sw.arrivals_s)
     steps = sw.steps_per_request
-    srv = engine.Server(model, sw.replicas, skin=0.1, dt=2.0, masses=[W.WATER_MASS], rebuild_every=10)
-    t_setup = time.perf_counter()
-    for rid in range(len(sw.replicas)):          # everything fits the default budget: admit up front
-        srv._admit(rid)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t_setup
 
     def replay(submit, step, idle, n, t_first):
         t0 = time.perf_counter()
@@ -414,26 +418,58 @@ def served_leg(plain_requests: int = 2000):
             step()
         return t0
 
-    active_sizes = []
+    def serve(budget_frac):
+        srv = engine.Server(model, sw.replicas, skin=0.1, dt=2.0, masses=[W.WATER_MASS], rebuild_every=10)
+        full = sum(srv.footprint)
+        t_setup = time.perf_counter()
+        if budget_frac >= 1.0:
+            for rid in range(len(sw.replicas)):          # everything fits: admit up front
+                srv._admit(rid)
+            srv.budget = max(srv.budget, srv.used)
+        else:
+            srv.budget = int(budget_frac * full)          # admission and eviction during the trace
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t_setup
+        active_sizes = []
 
-    def srv_step():
-        active_sizes.append(len(srv.active) + min(len(srv.pending), srv.max_active))
-        srv.tick()
+        def srv_step():
+            active_sizes.append(len(srv.active) + min(len(srv.pending), srv.max_active))
+            srv.tick()
 
-    replay(lambda q, ta: srv.submit(q, int(sw.replica_of[q]), steps, ta), srv_step, srv.idle, n_req, 0)
-    done = sorted(srv.done)
-    warm = sw.warmup_requests
-    lat = np.array([d[3] - d[2] for d in done[warm:]]) * 1e3
-    meas = done[warm:]
-    t_begin = min(d[2] for d in meas)
-    t_end = max(d[3] for d in meas)
-    bead_steps = sum(d[4] for d in meas)
-    served = {"requests": n_req, "warmup_requests": warm, "ticks": srv.ticks,
-              "mean_replicas_per_tick": round(float(np.mean(active_sizes)), 1),
-              "bead_steps_per_s": round(bead_steps / (t_end - t_begin), 1),
-              "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-              "setup_s": round(t_setup, 1)}
+        replay(lambda q, ta: srv.submit(q, int(sw.replica_of[q]), steps, ta), srv_step, srv.idle, n_req, 0)
+        done = sorted(srv.done)
+        warm = sw.warmup_requests
+        lat = np.array([d[3] - d[2] for d in done[warm:]]) * 1e3
+        meas = done[warm:]
+        t_begin = min(d[2] for d in meas)
+        t_end = max(d[3] for d in meas)
+        bead_steps = sum(d[4] for d in meas)
+        out = {"budget_fraction_of_all_replicas": budget_frac, "budget_bytes": int(srv.budget),
+               "requests": n_req, "warmup_requests": warm, "ticks": srv.ticks,
+               "mean_replicas_per_tick": round(float(np.mean(active_sizes)), 1),
+               "admissions": srv.admissions, "evictions": srv.evictions,
+               "bead_steps_per_s": round(bead_steps / (t_end - t_begin), 1),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "setup_s": round(t_setup, 1)}
+        return srv, out
 
+    srv, served = serve(1.0)
+    # saturated capacity: every replica active in every tick
+    reps_all = [srv.replica(rid) for rid in range(len(sw.replicas))]
+    stepper = srv.stepper
+    stepper.step(reps_all)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ticks = 20
+    for _ in range(ticks):
+        stepper.step(reps_all)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    capacity = {"replicas_per_tick": len(reps_all), "ms_per_tick": round(el * 1e3 / ticks, 3),
+                "bead_steps_per_s": round(sum(r.n for r in reps_all) * ticks / el, 1)}
+    del srv, reps_all
+    torch.cuda.empty_cache()
+    _, served_half = serve(0.5)
     # plain FIFO loop over the first plain_requests requests, same arrival times
     reps = []
     for s in sw.replicas:
@@ -466,8 +502,12 @@ def served_leg(plain_requests: int = 2000):
     return {"workload": "config4 serving: 256 water-like replicas, N U{500..20000}, density x U(1.00,1.25), "
                         "config-0 weights, 300 K, skin 0.1 nm; Poisson 2000 req/s of 10 MD steps, "
                         "20,000 requests (first 1,000 warm-up)",
-            "offered_bead_steps_per_s": round(offered, 1), "served": served, "plain_fifo": plain,
-            "throughput_ratio": round(served["bead_steps_per_s"] / plain["bead_steps_per_s"], 2)}
+            "offered_bead_steps_per_s": round(offered, 1), "served": served, "served_half_budget": served_half,
+            "capacity_all_replicas_active": capacity, "plain_fifo": plain,
+            "throughput_ratio": round(served["bead_steps_per_s"] / plain["bead_steps_per_s"], 2),
+            "note": "served: every replica resident; served_half_budget: an HBM budget of half the replicas' "
+                    "footprint, so replicas are admitted and evicted (to host memory, lists included) during "
+                    "the trace; capacity: every replica stepping in every tick"}
 
 
 def main():

@@ -374,9 +374,18 @@ int nep_md_step_batch(nep_model model, nep_replica *replicas, int n_active, floa
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int block;       /* threads per workgroup: 64, 128 or 256 (0 = 256) */
-    int order;       /* 0: items in the given order; 1: largest structures first */
+    int order;       /* structures by index (0) or largest first (1) */
     int wg_per_cu;   /* resident workgroups per compute unit (0 = as many as fit) */
+    int schedule;    /* the order in which workgroups take the (candidate, structure) items:
+                        0 the given work order (largest structures first when order = 1),
+                        1 structure-major (every candidate of a structure together: its
+                          positions and lists stay in cache), 2 candidate-major (every structure
+                          of a candidate together: its tables stay in cache), 3 blocked (groups of
+                          8 candidates, structure-major inside a group) */
 } nep_batch_config;
+
+/* Number of configurations nep_batch_autotune tries. */
+#define NEP_BATCH_TUNE_CONFIGS 36
 
 typedef struct {
     const double *E; /* device [n_systems]: reference energy of each structure (eV) */
@@ -414,13 +423,20 @@ int nep_compute_efv_batch(const nep_model *models, int n_models, const nep_syste
                           const nep_labels *labels, double *rmse, double *item_out, float *F_out,
                           const nep_batch_config *cfg, void *ws, size_t ws_bytes, void *stream);
 
-/* Times every configuration it knows (block 64 / 128 / 256 x order 0 / 1) on
- * the given work, one warm-up and one timed run each, and returns the fastest
- * in best.  ms: host [6] or NULL, the measured times in that order.  The
- * workspace must hold nep_batch_workspace_bytes(..., NULL). */
+/* Times every configuration of its search space on the given work and returns
+ * the fastest in best: schedule 1..3 x order 0/1 x wg_per_cu (0, 2) x block
+ * (64, 128, 256), NEP_BATCH_TUNE_CONFIGS points, each timed as the median of
+ * three runs after a warm-up run.  tried: host [NEP_BATCH_TUNE_CONFIGS] or
+ * NULL, the configurations in the order of ms: host [NEP_BATCH_TUNE_CONFIGS] or
+ * NULL, the measured times (ms).  The result is kept in-process under the
+ * device and a signature of the workload (sizes, list capacities, work list);
+ * a later call with the same signature returns it without timing
+ * (*from_cache = 1; from_cache may be NULL).  The workspace must hold
+ * nep_batch_workspace_bytes(..., NULL).  Synchronises the stream. */
 int nep_batch_autotune(const nep_model *models, int n_models, const nep_system *systems,
                        const nep_neighbors *lists, int n_systems, const int32_t *work, int n_items,
-                       void *ws, size_t ws_bytes, void *stream, nep_batch_config *best, float *ms);
+                       void *ws, size_t ws_bytes, void *stream, nep_batch_config *best, float *ms,
+                       nep_batch_config *tried, int *from_cache);
 
 /* ------------------------------------------------------------------------ */
 /* the training loop: SNES over the batched fitness evaluation (Sec. II.A)    */

@@ -78,7 +78,10 @@ class Replica(ctypes.Structure):
 
 
 class BatchConfig(ctypes.Structure):
-    _fields_ = [("block", c_int), ("order", c_int), ("wg_per_cu", c_int)]
+    _fields_ = [("block", c_int), ("order", c_int), ("wg_per_cu", c_int), ("schedule", c_int)]
+
+
+NEP_BATCH_TUNE_CONFIGS = 36
 
 
 class Labels(ctypes.Structure):
@@ -146,7 +149,8 @@ def lib():
                                             c_void_p, c_size_t, c_void_p]
         L.nep_compute_efv_batch.restype = c_int
         L.nep_batch_autotune.argtypes = [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p,
-                                         c_size_t, c_void_p, POINTER(BatchConfig), POINTER(c_float)]
+                                         c_size_t, c_void_p, POINTER(BatchConfig), POINTER(c_float),
+                                         POINTER(BatchConfig), POINTER(c_int)]
         L.nep_batch_autotune.restype = c_int
         L.nep_md_batch_workspace_bytes.argtypes = [c_int]
         L.nep_md_batch_workspace_bytes.restype = c_size_t
@@ -276,13 +280,16 @@ def nep_compute_efv_batch(models, systems, lists, work, labels: Optional[Labels]
 
 
 def nep_batch_autotune(models, systems, lists, work, ws_ptr, ws_bytes, stream):
-    """Returns (best BatchConfig, [ms] per tried configuration)."""
+    """Returns (best BatchConfig, [ms] per tried configuration, [tried
+    BatchConfig], from_cache)."""
     m, sy, li, w = _batch_arrays(models, systems, lists, work)
     best = BatchConfig()
-    ms = (c_float * 6)()
+    ms = (c_float * NEP_BATCH_TUNE_CONFIGS)()
+    tried = (BatchConfig * NEP_BATCH_TUNE_CONFIGS)()
+    hit = c_int(0)
     check(lib().nep_batch_autotune(m, len(models), sy, li, len(systems), w.ctypes.data, w.shape[0], ws_ptr,
-                                   ws_bytes, stream, ctypes.byref(best), ms))
-    return best, list(ms)
+                                   ws_bytes, stream, ctypes.byref(best), ms, tried, ctypes.byref(hit)))
+    return best, list(ms), list(tried), bool(hit.value)
 
 
 def nep_md_batch_workspace_bytes(max_active: int) -> int:

@@ -386,7 +386,7 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
 
 // ---- batched evaluation: validation, layout, upload, launch ----
 struct BatchPlan {
-    int T = 0, HP = 0, BS = 256, order = 0, grid = 1, nmax = 1, capAmax = 1;
+    int T = 0, HP = 0, BS = 256, order = 0, schedule = 0, grid = 1, nmax = 1, capAmax = 1;
     size_t stride = 0;
     // workspace offsets
     size_t sys = 0, mod = 0, items = 0, list = 0, F_off = 0, records = 0, counter = 0, scratch = 0, total = 0;
@@ -417,15 +417,17 @@ int batch_check(const nep_model *models, int n_models, const nep_system *systems
 }
 
 int batch_plan(const Model &M0, const nep_system *systems, const nep_neighbors *lists, int n_systems,
-               int n_models, int n_items, int block, int order, int wg_per_cu, BatchPlan &P) {
+               int n_models, int n_items, int block, int order, int wg_per_cu, int schedule, BatchPlan &P) {
     if (!(block == 64 || block == 128 || block == 256)) return fail(NEP_ERR_ARG, "block must be 64, 128 or 256");
     if (order < 0 || order > 1) return fail(NEP_ERR_ARG, "order must be 0 or 1");
+    if (schedule < 0 || schedule > 3) return fail(NEP_ERR_ARG, "schedule must be 0..3");
     if (wg_per_cu < 0) return fail(NEP_ERR_ARG, "wg_per_cu must be >= 0");
     if (M0.T > 2) return fail(NEP_ERR_UNSUPPORTED, "batched form supports n_types <= 2");
     P.T = M0.T;
     P.HP = M0.HP;
     P.BS = block;
     P.order = order;
+    P.schedule = schedule;
     P.nmax = 1;
     P.capAmax = 1;
     for (int k = 0; k < n_systems; ++k) {
@@ -509,10 +511,23 @@ int batch_run(const nep_model *models, int n_models, const nep_system *systems, 
         foff[it] = rows;
         rows += systems[k].n;
     }
+    // the schedule: the order in which the persistent workgroups take the
+    // items (structures by index, or largest first when order == 1)
     std::vector<int4> items(list);
-    if (P.order == 1)
+    auto skey = [&](int k) -> int64_t { return P.order == 1 ? -(int64_t)systems[k].n * (n_systems + 1) + k : k; };
+    auto by = [&](auto key) {
         std::stable_sort(items.begin(), items.begin() + n_items,
-                         [&](const int4 &a, const int4 &b) { return systems[a.y].n > systems[b.y].n; });
+                         [&](const int4 &a, const int4 &b) { return key(a) < key(b); });
+    };
+    constexpr int64_t BIG = (int64_t)1 << 40;
+    if (P.schedule == 0 && P.order == 1)
+        by([&](const int4 &a) { return skey(a.y); });
+    else if (P.schedule == 1)   // structure-major: all candidates of a structure together
+        by([&](const int4 &a) { return skey(a.y) * 65536 + a.x; });
+    else if (P.schedule == 2)   // candidate-major: every structure of a candidate together
+        by([&](const int4 &a) { return (int64_t)a.x * BIG + skey(a.y) + BIG / 2; });
+    else if (P.schedule == 3)   // blocked: groups of 8 candidates, structure-major inside a group
+        by([&](const int4 &a) { return (int64_t)(a.x / 8) * BIG + (skey(a.y) + BIG / 4) * 8 + a.x % 8; });
     HIPCHK(hipMemcpyAsync(at<char>(ws, P.sys), sd.data(), sizeof(SysDesc) * sd.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(at<char>(ws, P.mod), md.data(), sizeof(ModelDesc) * md.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(at<char>(ws, P.items), items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, st));
@@ -544,9 +559,51 @@ int batch_run(const nep_model *models, int n_models, const nep_system *systems, 
     return NEP_OK;
 }
 
-constexpr int N_TUNE = 6;
-const int TUNE_BLOCK[N_TUNE] = {64, 128, 256, 64, 128, 256};
-const int TUNE_ORDER[N_TUNE] = {0, 0, 0, 1, 1, 1};
+// the autotuner's search space, in the order of its ms / tried outputs:
+// schedule (structure-major, candidate-major, blocked) x order (given,
+// largest first) x workgroups per CU (as many as fit, 2) x block size
+constexpr int N_TUNE = NEP_BATCH_TUNE_CONFIGS;
+nep_batch_config tune_config(int c) {
+    nep_batch_config cfg{};
+    const int blocks[3] = {64, 128, 256};
+    cfg.block = blocks[c % 3];
+    cfg.wg_per_cu = (c / 3) % 2 ? 2 : 0;
+    cfg.order = (c / 6) % 2;
+    cfg.schedule = 1 + c / 12;
+    return cfg;
+}
+
+// results of earlier searches, by device and workload signature
+struct TuneEntry {
+    nep_batch_config best;
+    std::vector<float> ms;
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, TuneEntry>> g_tune_cache;
+
+std::string tune_key(const Model &M0, int n_models, const nep_system *systems, const nep_neighbors *lists,
+                     int n_systems, const int32_t *work, int n_items, int dev) {
+    // FNV-1a over the shapes that decide the schedule's cost: structure sizes,
+    // list capacities and the work list
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 255u;
+            h *= 1099511628211ull;
+        }
+    };
+    for (int k = 0; k < n_systems; ++k) {
+        mix((uint64_t)systems[k].n);
+        mix((uint64_t)lists[k].cap);
+        mix((uint64_t)lists[k].cap_A);
+    }
+    for (int it = 0; it < 2 * n_items; ++it) mix((uint64_t)(uint32_t)work[it]);
+    hipDeviceProp_t prop{};
+    (void)hipGetDeviceProperties(&prop, dev);
+    return std::to_string(dev) + "/" + prop.gcnArchName + "/" + std::to_string(M0.T) + "/" + std::to_string(M0.HP) +
+           "/" + std::to_string(n_models) + "/" + std::to_string(n_systems) + "/" + std::to_string(n_items) + "/" +
+           std::to_string(h);
+}
 
 // ---- served form: host staging of the replica tables ----
 struct MdBatchCtx {
@@ -1292,10 +1349,10 @@ size_t nep_batch_workspace_bytes(const nep_model *models, int n_models, const ne
     size_t best = 0;
     for (int c = 0; c < (cfg ? 1 : N_TUNE); ++c) {
         BatchPlan P;
-        const int block = cfg ? (cfg->block ? cfg->block : 256) : TUNE_BLOCK[c];
-        const int order = cfg ? cfg->order : TUNE_ORDER[c];
-        const int wg = cfg ? cfg->wg_per_cu : 0;
-        if (batch_plan(*M0, systems, lists, n_systems, n_models, n_items, block, order, wg, P)) return 0;
+        const nep_batch_config t = cfg ? *cfg : tune_config(c);
+        if (batch_plan(*M0, systems, lists, n_systems, n_models, n_items, t.block ? t.block : 256, t.order,
+                       t.wg_per_cu, t.schedule, P))
+            return 0;
         best = std::max(best, P.total);
     }
     return best;
@@ -1310,7 +1367,7 @@ int nep_compute_efv_batch(const nep_model *models, int n_models, const nep_syste
     if ((rc = batch_check(models, n_models, systems, lists, n_systems, n_items, M0))) return rc;
     BatchPlan P;
     if ((rc = batch_plan(*M0, systems, lists, n_systems, n_models, n_items, cfg && cfg->block ? cfg->block : 256,
-                         cfg ? cfg->order : 0, cfg ? cfg->wg_per_cu : 0, P)))
+                         cfg ? cfg->order : 0, cfg ? cfg->wg_per_cu : 0, cfg ? cfg->schedule : 0, P)))
         return rc;
     return batch_run(models, n_models, systems, lists, n_systems, work, n_items, labels, rmse, item_out, F_out, P,
                      ws, ws_bytes, (hipStream_t)stream, nullptr, nullptr);
@@ -1318,36 +1375,64 @@ int nep_compute_efv_batch(const nep_model *models, int n_models, const nep_syste
 
 int nep_batch_autotune(const nep_model *models, int n_models, const nep_system *systems,
                        const nep_neighbors *lists, int n_systems, const int32_t *work, int n_items,
-                       void *ws, size_t ws_bytes, void *stream, nep_batch_config *best, float *ms) {
+                       void *ws, size_t ws_bytes, void *stream, nep_batch_config *best, float *ms,
+                       nep_batch_config *tried, int *from_cache) {
     const Model *M0 = nullptr;
     int rc;
     if (!best) return fail(NEP_ERR_ARG, "best is null");
     if ((rc = batch_check(models, n_models, systems, lists, n_systems, n_items, M0))) return rc;
+    if (n_items > 0 && !work) return fail(NEP_ERR_ARG, "work list is null");
+    if (tried)
+        for (int c = 0; c < N_TUNE; ++c) tried[c] = tune_config(c);
+    if (from_cache) *from_cache = 0;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    const std::string key = tune_key(*M0, n_models, systems, lists, n_systems, work, n_items, dev);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const auto &e : g_tune_cache)
+            if (e.first == key) {
+                *best = e.second.best;
+                if (ms) std::copy(e.second.ms.begin(), e.second.ms.end(), ms);
+                if (from_cache) *from_cache = 1;
+                return NEP_OK;
+            }
+    }
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    constexpr int REPEATS = 3;
     float best_ms = -1.0f;
-    for (int c = 0; c < N_TUNE; ++c) {
+    std::vector<float> all(N_TUNE, 0.0f);
+    for (int c = 0; c < N_TUNE && !rc; ++c) {
+        const nep_batch_config cfg = tune_config(c);
         BatchPlan P;
-        rc = batch_plan(*M0, systems, lists, n_systems, n_models, n_items, TUNE_BLOCK[c], TUNE_ORDER[c], 0, P);
-        float t = 0.0f;
-        for (int rep = 0; rep < 2 && !rc; ++rep)
+        rc = batch_plan(*M0, systems, lists, n_systems, n_models, n_items, cfg.block, cfg.order, cfg.wg_per_cu,
+                        cfg.schedule, P);
+        // one warm-up run, then the median of REPEATS timed runs
+        float t[REPEATS] = {};
+        for (int rep = 0; rep <= REPEATS && !rc; ++rep) {
             rc = batch_run(models, n_models, systems, lists, n_systems, work, n_items, nullptr, nullptr, nullptr,
                            nullptr, P, ws, ws_bytes, st, e0, e1);
-        if (!rc && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = fail(NEP_ERR_HIP, "event timing failed");
+            if (!rc && rep > 0 && hipEventElapsedTime(&t[rep - 1], e0, e1) != hipSuccess)
+                rc = fail(NEP_ERR_HIP, "event timing failed");
+        }
         if (rc) break;
-        if (ms) ms[c] = t;
-        if (best_ms < 0.0f || t < best_ms) {
-            best_ms = t;
-            best->block = TUNE_BLOCK[c];
-            best->order = TUNE_ORDER[c];
-            best->wg_per_cu = 0;
+        std::sort(t, t + REPEATS);
+        all[c] = t[REPEATS / 2];
+        if (best_ms < 0.0f || all[c] < best_ms) {
+            best_ms = all[c];
+            *best = cfg;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return rc;
+    if (rc) return rc;
+    if (ms) std::copy(all.begin(), all.end(), ms);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache.push_back({key, TuneEntry{*best, all}});
+    return NEP_OK;
 }
 
 int nep_models_load_params(nep_model *models, int n_models, const float *params, void *stream) {

@@ -350,6 +350,65 @@ class Replica:
         Wtot = Wb.sum(axis=0) + (self.n - G) * kB * T_label * np.eye(3)
         return F, Wb, Wtot
 
+    def device_bytes(self) -> int:
+        """Device memory this replica holds (state, lists, workspace)."""
+        ts = [self.xyz, self.type, self.v, self.F, self.U, self.E_tot, self.W_tot, self.status, self.ref, self.cnt,
+              self.order, self.nbr, self.rev, self.ws]
+        if self.W is not None:
+            ts.append(self.W)
+        if self.perm is not None:
+            ts.append(self.perm)
+        return int(sum(t.numel() * t.element_size() for t in ts))
+
+    # -- eviction (served form) -------------------------------------------------
+    _SNAP = ("xyz", "type", "v", "F", "U", "status", "ref", "cnt", "order", "nbr", "rev")
+
+    def snapshot(self) -> dict:
+        """Every device array of the replica (state, lists and their order,
+        the numbering map) copied to pinned host memory, so that restore()
+        continues the same trajectory bit for bit.  Only the list slots in use
+        (up to the longest row) are copied; the host buffers are kept with the
+        snapshot and reused by the next one of this replica."""
+        cnt_max = self.cnt.amax(dim=1).cpu().tolist() if self.n else [0, 0]
+        rows, rows_A = max(int(cnt_max[0]), 1), max(int(cnt_max[1]), 1)
+        parts = {k: getattr(self, k) for k in self._SNAP if k not in ("nbr", "rev")}
+        parts["nbr"] = self.nbr[:rows]
+        parts["rev"] = self.rev[:rows_A]
+        if self.perm is not None:
+            parts["perm"] = self.perm
+        pool = getattr(self, "_pinned", None) or {}
+        snap = {}
+        for k, t in parts.items():
+            buf = pool.get(k)
+            if buf is None or buf.numel() < t.numel():
+                buf = torch.empty(t.numel(), dtype=t.dtype, pin_memory=True)
+                pool[k] = buf
+            dst = buf[:t.numel()].view(t.shape)
+            dst.copy_(t, non_blocking=True)
+            snap[k] = dst
+        torch.cuda.current_stream().synchronize()
+        self._pinned = pool
+        snap.setdefault("perm", None)
+        snap.update(step=self.step, n_rebuilds=self.n_rebuilds, box=self.box.copy(), cap=self.cap,
+                    cap_A=self.cap_A, lists_valid=self.lists_valid, pool=pool)
+        return snap
+
+    def restore(self, snap: dict):
+        """The inverse of snapshot() on a replica of the same system."""
+        if (self.cap, self.cap_A) != (snap["cap"], snap["cap_A"]):
+            self._alloc_lists(snap["cap"], snap["cap_A"])
+        for k in self._SNAP:
+            src = snap[k]
+            getattr(self, k)[:src.shape[0]].copy_(src, non_blocking=True)
+        self.perm = None if snap["perm"] is None else snap["perm"].to(self.device, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        self._pinned = snap["pool"]
+        self.step, self.n_rebuilds = snap["step"], snap["n_rebuilds"]
+        self.box = snap["box"].copy()
+        self.lists_valid = snap["lists_valid"]
+        self._cstruct = None
+        return self
+
     # -- host views (original numbering unless internal=True) ---------------------
     def _unperm(self, a: np.ndarray, internal: bool) -> np.ndarray:
         if internal or self.perm is None:
@@ -629,13 +688,18 @@ class Server:
                 return False
             self._evict(victim)
         h = self.host[rid]
-        r = Replica(self.model, h["pos"], h["types"], h["box"], h["pbc"], skin=self.skin, vel=h["vel"])
-        r.step = h["step"]
-        if self.sort_every > 0:
-            r.sort()                                # cell order, lists built
-        r.efv(per_bead_virial=False)                # lists and forces at the stored positions
+        r = Replica(self.model, h["pos"], h["types"], h["box"], h["pbc"], skin=self.skin, vel=h["vel"],
+                    cap=h["snap"]["cap"] if "snap" in h else None, cap_A=h["snap"]["cap_A"] if "snap" in h else None)
+        if "snap" in h:
+            r.restore(h["snap"])                    # the state it was evicted with, lists included
+        else:
+            r.step = h["step"]
+            if self.sort_every > 0:
+                r.sort()                            # cell order, lists built
+            r.efv(per_bead_virial=False)            # lists and forces at the stored positions
         self.resident[rid] = r
-        self.used += need
+        self.footprint[rid] = r.device_bytes()      # the estimate replaced by what the replica holds
+        self.used += self.footprint[rid]
         self.admissions += 1
         return True
 
@@ -643,6 +707,7 @@ class Server:
         r = self.resident.pop(rid)
         h = self.host[rid]
         h["pos"], h["vel"], h["step"] = r.positions(), r.velocities(), r.step
+        h["snap"] = r.snapshot()
         self.used -= self.footprint[rid]
         self.evictions += 1
         del r

@@ -138,9 +138,39 @@ def test_batch_equals_single_structure_path(families):
 
 def test_batch_autotune_and_empty_list(families):
     spec, fb, systems, ref = families[0]
-    best, ms = fb.autotune()
-    print("autotune:", best.block, best.order, ms)
-    assert best.block in (64, 128, 256) and best.order in (0, 1)
-    assert all(t > 0 for t in ms)
+    best, ms, tried, hit = fb.autotune()
+    print("autotune:", best.block, best.order, best.wg_per_cu, best.schedule, [round(t, 3) for t in ms])
+    assert not hit
+    assert best.block in (64, 128, 256) and best.order in (0, 1) and best.schedule in (1, 2, 3)
+    assert best.wg_per_cu in (0, 2)
+    assert all(t > 0 for t in ms) and len(ms) == 36
+    # every schedule x order x occupancy x block point was tried once
+    keys = {(c.schedule, c.order, c.wg_per_cu, c.block) for c in tried}
+    assert len(keys) == 36
+    k = [(c.schedule, c.order, c.wg_per_cu, c.block) for c in tried].index(
+        (best.schedule, best.order, best.wg_per_cu, best.block))
+    assert ms[k] == min(ms)
+    # the same workload again: the cached result, no timing
+    best2, ms2, _, hit2 = fb.autotune()
+    assert hit2 and ms2 == ms
+    assert (best2.block, best2.order, best2.wg_per_cu, best2.schedule) == (best.block, best.order, best.wg_per_cu,
+                                                                          best.schedule)
     out = fb.evaluate([], items=False)
     assert torch.count_nonzero(out["rmse"]) == 0
+
+
+def test_every_schedule_gives_the_same_results(families):
+    """The schedule only decides which workgroup takes which item: items, forces
+    and RMSEs are bitwise the same under every schedule, order and block."""
+    from paper_2603_01234_amd import binding as B
+    spec, fb, systems, ref = families[1]
+    work = fb.all_pairs()
+    outs = []
+    for sch in (0, 1, 2, 3):
+        for order in (0, 1):
+            cfg = B.BatchConfig(128 if sch % 2 else 256, order, 0, sch)
+            o = fb.evaluate(work, cfg=cfg, items=True, forces=True)
+            outs.append(o)
+    for o in outs[1:]:
+        for k in ("rmse", "items", "forces"):
+            assert torch.equal(o[k], outs[0][k]), k

@@ -141,3 +141,35 @@ def test_overflow_in_one_replica_leaves_the_others_alone(serve_small):
         assert a.step == b.step
         for x, y in zip(_state(a), _state(b)):
             assert torch.equal(x, y)
+
+
+def test_eviction_and_readmission_are_bitwise_exact(serve_small):
+    """The same trace through a server whose HBM budget holds three replicas
+    (replicas are evicted to host memory and re-admitted mid-trace) and through
+    one that holds all: every replica ends in the same state, bit for bit (an
+    evicted replica keeps its lists and their order, so nothing is rebuilt)."""
+    from paper_2603_01234_amd import engine as E
+    sw = serve_small
+    model = E.Model.from_spec(sw.spec, sw.params)
+    fp = [E.replica_footprint(model, s.n, s.box, s.pbc, 0.1, s.pos_f32()) for s in sw.replicas]
+    finals = []
+    for budget in (sum(sorted(fp)[-3:]), None):
+        srv = E.Server(model, sw.replicas, skin=0.1, dt=2.0, masses=[W.WATER_MASS], hbm_budget=budget)
+        for q in range(len(sw.arrivals_s)):
+            srv.submit(q, int(sw.replica_of[q]), sw.steps_per_request, float(sw.arrivals_s[q]))
+        while not srv.idle():
+            srv.tick()
+        out = []
+        for rid in range(len(sw.replicas)):
+            if srv.replica(rid) is None:
+                srv._admit(rid)
+            r = srv.replica(rid)
+            out.append((r.step, r.positions(), r.velocities(), r.forces()))
+        finals.append((out, srv.evictions, srv.admissions))
+    (a, ev_a, ad_a), (b, ev_b, _) = finals
+    print(f"budgeted run: {ev_a} evictions, {ad_a} admissions; unbudgeted: {ev_b} evictions")
+    assert ev_a > 0 and ev_b == 0
+    for (sa, *xa), (sb, *xb) in zip(a, b):
+        assert sa == sb
+        for u, w in zip(xa, xb):
+            assert np.array_equal(u, w)
