@@ -61,8 +61,8 @@ struct TimedLaunch {
 // loop reads the record of step k-1 while the device runs step k).
 
 struct WsLayout {
-    size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, rowbuf, vh, ctrl, top2, ens, partial2, wbuf, total;
+    size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor, cell_xyz,
+        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, arow, vh, ctrl, top2, ens, partial2, wbuf, total;
     int ncell_max, nblocks;
 };
 
@@ -88,13 +88,16 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.cell_count = take((size_t)L.ncell_max * 4);
     L.cell_start = take((size_t)(L.ncell_max + 1) * 4);
     L.cell_cursor = take((size_t)L.ncell_max * 4);
+    L.cell_xyz = take((size_t)L.ncell_max * 4);
     L.cell_list = take(nn * 4);
     L.scan_tmp = take((size_t)(L.ncell_max / 1024 + 2) * 4);
     L.cell_tmp = take(nn * 4);
     L.pos_sorted = take(nn * 16);
     L.cls = take(nn * 4);
-    // row stride: both regions padded to whole 16-byte groups
-    L.rowbuf = take(nn * (size_t)(((std::max(cap, 1) + 3) & ~3) + ((std::max(cap_A, 1) + 3) & ~3)) * 4);
+    // angular keys: a 16-byte header and cap_A padded to whole 16-byte groups;
+    // at least 52 bytes per bead, since the permutation of a sort stages
+    // [12][n] floats and [n] bytes here
+    L.arow = take(nn * std::max((size_t)(4 + ((std::max(cap_A, 1) + 3) & ~3)) * 4, (size_t)52));
     L.vh = take(nn * 12);
     L.ctrl = take(4 * sizeof(int32_t));
     // per-workgroup pairs of the rebuild test (gather or drift workgroups)
@@ -212,7 +215,7 @@ int make_grid(const Model &M, const nep_system *s, float skin, int ncell_max, Nb
         double ext = s->box[d];
         long c = (long)std::floor(ext / (0.5 * target));
         if (c < 5) c = (long)std::floor(ext / target);  // too few half cells: whole cells
-        nc[d] = std::min(std::max(c, 1L), 4096L);
+        nc[d] = std::min(std::max(c, 1L), 1023L);  // cell coordinates are packed in 10 bits
     }
     while (nc[0] * nc[1] * nc[2] > ncell_max) {
         int big = 0;
@@ -293,12 +296,13 @@ int fill_nb(const Model &M, const nep_system *s, nep_neighbors *nb, void *ws, co
     a.cell_count = at<int32_t>(ws, L.cell_count);
     a.cell_start = at<int32_t>(ws, L.cell_start);
     a.cell_cursor = at<int32_t>(ws, L.cell_cursor);
+    a.cell_xyz = at<int32_t>(ws, L.cell_xyz);
     a.cell_list = at<int32_t>(ws, L.cell_list);
     a.scan_tmp = at<int32_t>(ws, L.scan_tmp);
     a.cell_tmp = at<int32_t>(ws, L.cell_tmp);
     a.pos_sorted = at<float4>(ws, L.pos_sorted);
     a.cls = at<int32_t>(ws, L.cls);
-    a.rowbuf = at<uint32_t>(ws, L.rowbuf);
+    a.arow = at<uint32_t>(ws, L.arow);
     a.order = nb->order;
     a.nbr = nb->nbr;
     a.rev = nb->rev;
@@ -898,7 +902,7 @@ int nep_sort_system(nep_model model, nep_system *s, float *v, float *F, float *U
     p.F = F;
     p.U = U;
     p.perm = perm;
-    p.tmp = at<float>(ws, L.rowbuf);  // free once the build above has run
+    p.tmp = at<float>(ws, L.arow);  // free once the build above has run
     HIPCHK(launch_permute(p, st));
     // lists for the new order
     if ((rc = fill_nb(M, s, nb, ws, L, 1, 0, a))) return rc;
@@ -1322,7 +1326,9 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
         HIPCHK(hipMemcpyAsync(at<char>(ws, BL.nbargs), hn, sizeof(NbArgs) * nsys, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(at<char>(ws, BL.nbstart), hstart, sizeof(int) * NB_BATCH_TILES * (nsys + 1),
                               hipMemcpyHostToDevice, st));
-        NbBatchArgs nbb{nsys, at<NbArgs>(ws, BL.nbargs), at<int>(ws, BL.nbstart)};
+        int row_bytes = 0;
+        for (int q = 0; q < nsys; ++q) row_bytes = std::max(row_bytes, nb_row_lds_bytes(hn[q].cap, hn[q].cap_A));
+        NbBatchArgs nbb{nsys, at<NbArgs>(ws, BL.nbargs), at<int>(ws, BL.nbstart), row_bytes};
         HIPCHK(launch_build_batch(nbb, totals, st));
     }
     HIPCHK(launch_efv_md_batch(M.T, M.HP, b, st));

@@ -10,14 +10,17 @@
 //               give every bead its rank by index within its cell, so cell
 //               contents and a cell-ordered copy of the positions are in one
 //               canonical order whatever the atomics did
-//   4. rows:    one thread per bead walks the (2m+1)^3 neighbour cells in a
-//               fixed order over the cell-ordered positions and applies the
-//               exact float32 predicate; entries go to four stacks of a
-//               row-major scratch row by class (angular inside r_c^A, angular
-//               shell, radial-only inside r_c^R, radial shell)
-//   5. transpose: scratch rows -> slot-major lists in that class order
-//   6. reverse: for every angular entry, the mirrored entry is searched among
-//               the neighbour's angular entries in its scratch row
+//   4. rows:    one wavefront per cell stages the candidates of the cell's
+//               (2m+1)^3 neighbour cells in LDS, in a fixed order (offset in
+//               (dz, dy, dx) order, then cell order), and tests the cell's
+//               beads against them with the lanes over the candidates (the
+//               exact float32 predicate); each row is assembled in LDS by
+//               class (angular inside r_c^A, angular shell, radial-only
+//               inside r_c^R, radial shell) and written slot-major into the
+//               list, with its angular part's sort keys row-major
+//   5. order:   the fused kernel's processing order, from the row lengths
+//   6. reverse: for every angular entry, the mirrored entry is looked up by
+//               its sort key among the neighbour's angular keys
 #include "nep_internal.h"
 
 // The list predicate is exact only with every float operation rounded on its
@@ -75,6 +78,27 @@ __device__ __forceinline__ int cell_coord(float x, float inv_cs, int nc) {
     float f = floorf(mul_rn(x, inv_cs));
     int k = (int)fminf(fmaxf(f, -1.0f), (float)nc);
     return k < 0 ? 0 : (k >= nc ? nc - 1 : k);
+}
+
+// grid coordinates of cell c: the inverse of cell_index
+__device__ __forceinline__ void cell_coords(int c, const int nc[3], int xyz[3]) {
+    constexpr int B = CELL_TILE;
+    const int slab = B * nc[1] * nc[0];
+    const int tz = c / slab;
+    int r = c - tz * slab;
+    const int hz = min(B, nc[2] - tz * B);
+    const int trow = B * nc[0] * hz;
+    const int ty = r / trow;
+    r -= ty * trow;
+    const int hy = min(B, nc[1] - ty * B);
+    const int tile = B * hy * hz;
+    const int tx = r / tile;
+    r -= tx * tile;
+    const int hx = min(B, nc[0] - tx * B);
+    const int yz = r / hx;
+    xyz[0] = tx * B + (r - yz * hx);
+    xyz[1] = ty * B + yz % hy;
+    xyz[2] = tz * B + yz / hy;
 }
 
 // periodic wrap into [0, L) in float32; a result that rounds to L becomes 0
@@ -190,6 +214,11 @@ __device__ __forceinline__ void scan_add_body(const NbArgs &a, int bx) {
     const int32_t v = a.cell_start[k] + off_s;
     a.cell_start[k] = v;
     a.cell_cursor[k] = v;
+    // the cell's coordinates, for the row kernel (one thread per cell here,
+    // where the row kernel would compute them in every lane of a wave)
+    int xyz[3];
+    cell_coords(k, a.nc, xyz);
+    a.cell_xyz[k] = xyz[0] | (xyz[1] << 10) | (xyz[2] << 20);
 }
 
 __global__ void k_scan_add(NbArgs a) { scan_add_body(a, blockIdx.x); }
@@ -231,9 +260,12 @@ __device__ __forceinline__ void wave_status(int32_t *status, int flags, int tota
     }
     const uint64_t act = __ballot(1);
     if (__lane_id() == __ffsll((unsigned long long)act) - 1) {
+        // every wave of a build updates the same three words: an update that
+        // cannot change a word is skipped (a stale read only costs an atomic)
         if (flags) atomicOr(&status[0], flags);
-        atomicMax(&status[1], total);
-        atomicMax(&status[2], na);
+        if (total > __hip_atomic_load(&status[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&status[1], total);
+        if (na > __hip_atomic_load(&status[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&status[2], na);
     }
 }
 
@@ -251,367 +283,458 @@ __device__ __forceinline__ bool wrap_cell(int k, int nc, int pbc, int &kw, int &
     return true;
 }
 
-// lower bound, in cell units, of the distance along one axis from a point at
-// fractional position u in its cell to the cell at the given offset
-__device__ __forceinline__ float cell_gap(int off, float u) {
-    return off > 0 ? (float)off - u : (off < 0 ? (float)(-off - 1) + u : 0.0f);
-}
+// ---- 4. rows ----
+// One wavefront per home cell.  It loads the candidates of the cell's
+// (2m+1)^3 neighbour cells once, into registers (candidate t = 64 k + lane in
+// lane `lane`, batch k), in the fixed order of the search (offset in
+// (dz, dy, dx) order, then cell order), each shifted by the periodic image of
+// its offset and tagged with its list entry and its sort key; then it tests
+// every bead of the cell against them, the lanes over the candidates.  The
+// entries of each class are appended in search order (a ballot per class and
+// each lane's count of the set bits below it), so a row is the same, entry
+// for entry, as a walk over the cells in that order.  A home bead's row is
+// assembled in LDS in four stacks (angular inside r_c^A up from 0, angular
+// shell down from A4-1, radial inside r_c^R up from A4, radial shell down
+// from A4+R4-1) and written out in class order: slot-major into the list, and
+// the angular keys row-major for the reverse search.
+//
+// The key of an entry is its neighbour-cell offset index o (0..W-1 in search
+// order) << 25 | the neighbour's position in cell order; within each class
+// the keys of a row ascend.  Bead i sits in the row of its neighbour j at the
+// mirrored offset W-1-o, so the key it has there is known before j's row is
+// read: the row kernel leaves that key in rev, and the reverse kernel finds
+// its position in j's row.
+constexpr int ROW_BATCHES = 8;                // candidates per lane held at a time
+constexpr int ROW_WIN = 64 * ROW_BATCHES;     // candidates held by the wave
+constexpr int ROW_OFF = 128;                  // room for the (2m+1)^3 <= 125 offsets
+constexpr int ROW_HOME = 64;                  // home beads whose positions are staged in LDS
+constexpr uint32_t ZERO_CODE = 62;            // image code of the zero shift, (0+2) + 5 (0+2) + 25 (0+2)
 
-// One of the four stacks of a row under construction.  Entries are kept in
-// registers four at a time and written as one aligned 16-byte store (the rows
-// of a wave lie far apart, so single 4-byte stores would each take a memory
-// transaction); a stack that grows downwards stores its groups reversed.
-// Groups that would leave the stack's region are dropped: the row then
-// overflows and is discarded anyway.
-struct RowStack {
-    uint32_t b0, b1, b2, b3;  // the last four entries, oldest first
-    int cnt;
-    __device__ __forceinline__ void push(uint32_t e, uint32_t *row, int base, int limit, bool down) {
-        b0 = b1;
-        b1 = b2;
-        b2 = b3;
-        b3 = e;
-        ++cnt;
-        if ((cnt & 3) != 0 || cnt > limit) return;
-        if (!down) *reinterpret_cast<uint4 *>(row + base + cnt - 4) = make_uint4(b0, b1, b2, b3);
-        else *reinterpret_cast<uint4 *>(row + base - cnt + 1) = make_uint4(b3, b2, b1, b0);
-    }
-    // the entries of the last, incomplete group
-    __device__ __forceinline__ void finish(uint32_t *row, int base, int limit, bool down) {
-        const int r = cnt & 3;
-        const uint32_t last[4] = {b0, b1, b2, b3};
-#pragma unroll
-        for (int q = 1; q <= 3; ++q) {
-            if (q > r) break;
-            const int k = cnt - q;  // insertion index of entry last[4 - q]
-            if (k >= limit) continue;
-            row[down ? base - k : base + k] = last[4 - q];
-        }
-    }
+struct RowsLds {
+    float4 thr[MAXT * MAXT];  // (list2R, list2A, in2A, in2R) of the type pair
+    float4 home[ROW_HOME];    // positions and tags of the cell's first beads
+    int beg[ROW_OFF];         // first cell-order index of the offset's cell
+    int pre[ROW_OFF];         // first flat candidate index of the offset
+    float sh[3][ROW_OFF];     // periodic shift of the offset
+    uint32_t code[ROW_OFF];   // image code of the offset, in entry position
+    uint8_t owner[ROW_WIN];   // offset of each candidate of the window
 };
 
-// the row of bead i; returns its flags, length and angular length
-// thr[ti T + tj] = (list2R, list2A, in2A, in2R) of the type pair, in LDS
-__device__ __forceinline__ void build_row(const NbArgs &a, const float4 *thr, const int i, int &flags_out,
-                                          int &total_out, int &na_out) {
+// bytes of dynamic LDS of the row kernel: the entries and keys of the row
+// under construction, in the order found (A4 + R4 of them, then a trash slot
+// per lane), and their classes
+__host__ __device__ __forceinline__ int row_lds_bytes(int cap, int cap_A) {
+    const int w = ((cap_A + 3) & ~3) + ((cap + 3) & ~3) + 64;
+    return w * 8 + ((w + 15) & ~15);
+}
+
+// The row kernel's workgroup is a single wavefront, whose LDS operations
+// complete in issue order: a compiler barrier with wavefront-scope fences is
+// all that orders one lane's LDS writes before another lane's reads (a
+// workgroup barrier would also wait for every global store in flight).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// number of set bits of m below this lane
+__device__ __forceinline__ int bits_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// candidates of one window, one batch of 64 per register slot
+struct Cands {
+    float x[ROW_BATCHES], y[ROW_BATCHES], z[ROW_BATCHES];
+    uint32_t ent[ROW_BATCHES];  // j | image code << 25
+    uint32_t key[ROW_BATCHES];  // offset << 25 | cell-order index
+    uint32_t types;             // 2 bits per batch
+};
+
+// Candidates [base, base + ROW_WIN) of the flat sequence into registers.
+// Lane `lane` owns offsets o = lane + 64 hf (hf = 0, 1) with cnt2[hf]
+// candidates from flat index pre2[hf].  With home_from >= 0 the lanes also
+// stage the positions of the cell's first beads (cell-order index home_from
+// on) in LDS.
+__device__ __forceinline__ void stage_window(const NbArgs &a, RowsLds &L, int base, int total, const int cnt2[2],
+                                             const int pre2[2], int home_from, int nh, Cands &C) {
+    const int lane = threadIdx.x;
+    wave_sync();  // the previous window's owners are no longer read
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+        const int lo = max(pre2[hf], base), hi = min(pre2[hf] + cnt2[hf], base + ROW_WIN);
+        for (int t = lo; t < hi; ++t) L.owner[t - base] = (uint8_t)(lane + 64 * hf);
+    }
+    wave_sync();
+    const int nw = min(ROW_WIN, total - base);
+#pragma unroll
+    for (int k = 0; k < ROW_BATCHES; ++k) {
+        const int t = 64 * k + lane;
+        const int o = t < nw ? L.owner[t] : 0;
+        const int q = t < nw ? L.beg[o] + (base + t - L.pre[o]) : 0;
+        C.key[k] = ((uint32_t)o << CODE_SHIFT) | (uint32_t)q;
+    }
+    // every load issued before any is used (lanes past the window read bead 0)
+    const bool hl = home_from >= 0 && lane < min(nh, ROW_HOME);
+    const float4 hp = hl ? a.pos_sorted[home_from + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < ROW_BATCHES; ++k) {
+        const float4 p = a.pos_sorted[C.key[k] & J_MASK];
+        C.x[k] = p.x;
+        C.y[k] = p.y;
+        C.z[k] = p.z;
+        C.ent[k] = __float_as_uint(p.w);
+    }
+    if (hl) L.home[lane] = hp;
+    C.types = 0;
+#pragma unroll
+    for (int k = 0; k < ROW_BATCHES; ++k) {
+        const int o = (int)(C.key[k] >> CODE_SHIFT);
+        const uint32_t tag = C.ent[k];
+        // a lane past the window gets a candidate at infinity: its squared
+        // distance is +inf, below no cutoff
+        if (64 * k + lane >= nw) C.x[k] = INFINITY;
+        C.x[k] = add_rn(C.x[k], L.sh[0][o]);
+        C.y[k] = add_rn(C.y[k], L.sh[1][o]);
+        C.z[k] = add_rn(C.z[k], L.sh[2][o]);
+        C.ent[k] = (tag & J_MASK) | L.code[o];
+        C.types |= (tag >> CODE_SHIFT) << (2 * k);
+    }
+    wave_sync();
+}
+
+// the rows of the beads of cell c; one wavefront, all lanes.  MT: more than
+// one bead type (per-lane thresholds)
+template <bool MT>
+__device__ __forceinline__ void row_cell(const NbArgs &a, int c, RowsLds &L, uint32_t *row, int &flags, int &most,
+                                         int &most_a) {
+    const int lane = threadIdx.x;
     const int n = a.n;
-    const float4 pi = a.pos4[i];
-    const int ti = (int)pi.w;
-    const float4 *thr_i = thr + ti * a.T;
-    int c0[3];
-    float u[3];
-    {
-        const float pv[3] = {pi.x, pi.y, pi.z};
-        for (int d = 0; d < 3; ++d) {
-            const float f = mul_rn(pv[d], a.inv_cs[d]);
-            c0[d] = cell_coord(pv[d], a.inv_cs[d], a.nc[d]);
-            u[d] = fminf(fmaxf(f - (float)c0[d], 0.0f), 1.0f);
-        }
-    }
-    const float cs[3] = {1.0f / a.inv_cs[0], 1.0f / a.inv_cs[1], 1.0f / a.inv_cs[2]};
-    // four stacks in the row: angular inside r_c^A up from 0, angular shell
-    // down from cap_A - 1, radial-only inside r_c^R up from cap_A, radial
-    // shell down from cap_A + cap - 1.  Kept in this class order, the rows let
-    // the lanes of a wave find their in-cutoff pairs in the same slots.
     const int A4 = (a.cap_A + 3) & ~3, R4 = (a.cap + 3) & ~3;
-    uint32_t *row = a.rowbuf + (size_t)i * (A4 + R4);
-    RowStack sai{0u, 0u, 0u, 0u, 0}, sas{0u, 0u, 0u, 0u, 0}, sri{0u, 0u, 0u, 0u, 0}, srs{0u, 0u, 0u, 0u, 0};
-    int flags = 0;
-    for (int dz = -a.m[2]; dz <= a.m[2]; ++dz) {
-        int kz, iz;
-        const bool vz = wrap_cell(c0[2] + dz, a.nc[2], a.pbc[2], kz, iz);
-        const float gz = cell_gap(dz, u[2]) * cs[2];
-        for (int dy = -a.m[1]; dy <= a.m[1]; ++dy) {
-            int ky, iy;
-            const bool vy = wrap_cell(c0[1] + dy, a.nc[1], a.pbc[1], ky, iy);
-            const float gy = cell_gap(dy, u[1]) * cs[1];
-            // the (up to five) cells of this row of offsets: indices and cull
-            // tests first, then every candidate range is loaded before any
-            // candidate is read, so the loads overlap instead of queueing
-            const int wx = 2 * a.m[0] + 1;
-            int cid5[5], ix5[5], s5[5], e5[5];
-            bool use5[5];
+    const int cap4 = A4 + R4;           // entries held for a row
+    const int trash = cap4;             // trash slots [cap4, cap4 + 64)
+    uint2 *rows = reinterpret_cast<uint2 *>(row);           // (entry, key) in the order found
+    uint8_t *rcls = reinterpret_cast<uint8_t *>(rows + cap4 + 64);  // their classes
+    const int w0 = 2 * a.m[0] + 1, w1 = 2 * a.m[1] + 1;
+    const int W = w0 * w1 * (2 * a.m[2] + 1);
+    const int o_home = (W - 1) / 2;  // the zero offset (always in the first half)
+    const int32_t xyz = a.cell_xyz[c];
+    const int c0[3] = {xyz & 1023, (xyz >> 10) & 1023, xyz >> 20};
+    wave_sync();  // the previous cell's tables are no longer read
+    // offsets o = lane and lane + 64: cell range, shift, image code, and the
+    // exclusive prefix of the candidate counts
+    int cnt2[2], beg2[2], pre2[2], total = 0;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                use5[k] = false;
-                cid5[k] = 0;
-                ix5[k] = 0;
-                if (k < wx) {
-                    const int dx = k - a.m[0];
-                    int kx, ix;
-                    const bool vx = wrap_cell(c0[0] + dx, a.nc[0], a.pbc[0], kx, ix);
-                    const float gx = cell_gap(dx, u[0]) * cs[0];
-                    // skip cells entirely beyond reach (a lower bound with margin)
-                    use5[k] = vx && vy && vz && !(gx * gx + gy * gy + gz * gz > a.cull2);
-                    cid5[k] = cell_index(kx, ky, kz, a.nc);
-                    ix5[k] = ix;
-                }
+    for (int hf = 0; hf < 2; ++hf) {
+        const int o = lane + 64 * hf;
+        int cid = -1;
+        if (o < W) {
+            // o = (oz w1 + oy) w0 + ox; o < 128, so the float quotients are exact
+            const int qx = (int)(((float)o + 0.5f) * (1.0f / (float)w0));
+            const int qy = (int)(((float)qx + 0.5f) * (1.0f / (float)w1));
+            const int off[3] = {o - qx * w0 - a.m[0], qx - qy * w1 - a.m[1], qy - a.m[2]};
+            int k[3], img[3];
+            bool ok = true;
+            float g2 = 0.0f;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                ok = wrap_cell(c0[d] + off[d], a.nc[d], a.pbc[d], k[d], img[d]) && ok;
+                // gap between the two cells along d: a lower bound for every
+                // bead of the home cell (the cull has the build's margin)
+                const float g = (float)max(abs(off[d]) - 1, 0) * (1.0f / a.inv_cs[d]);
+                g2 = add_rn(g2, mul_rn(g, g));
             }
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                s5[k] = use5[k] ? a.cell_start[cid5[k]] : 0;
-                e5[k] = use5[k] ? a.cell_start[cid5[k] + 1] : 0;
+            ok = ok && !(g2 > a.cull2);
+            if (ok && (img[0] < -2 || img[0] > 2 || img[1] < -2 || img[1] > 2 || img[2] < -2 || img[2] > 2)) {
+                flags |= NEP_FLAG_IMAGE_RANGE;
+                ok = false;
             }
+            if (ok) {
+                cid = cell_index(k[0], k[1], k[2], a.nc);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                if (k >= wx) break;
-                if (!use5[k]) continue;
-                const int ix = ix5[k];
-                const int s = s5[k], e = e5[k];
-                if (ix < -2 || ix > 2 || iy < -2 || iy > 2 || iz < -2 || iz > 2) { flags |= NEP_FLAG_IMAGE_RANGE; continue; }
-                // s = fl(n L), exact predicate with every operation rounded separately
-                const float sx = mul_rn((float)ix, a.box[0]);
-                const float sy = mul_rn((float)iy, a.box[1]);
-                const float sz = mul_rn((float)iz, a.box[2]);
-                const bool zero_shift = (ix == 0 && iy == 0 && iz == 0);
-                const uint32_t code = (uint32_t)((ix + 2) + 5 * (iy + 2) + 25 * (iz + 2));
-                for (int q0 = s; q0 < e; q0 += 4) {
-                    // up to four independent loads in flight before any is used
-                    float4 pb[4];
+                for (int d = 0; d < 3; ++d) L.sh[d][o] = mul_rn((float)img[d], a.box[d]);
+                L.code[o] = (uint32_t)((img[0] + 2) + 5 * (img[1] + 2) + 25 * (img[2] + 2)) << CODE_SHIFT;
+            }
+        }
+        beg2[hf] = cid >= 0 ? a.cell_start[cid] : 0;
+        cnt2[hf] = cid >= 0 ? a.cell_start[cid + 1] : 0;
+    }
 #pragma unroll
-                    for (int u4 = 0; u4 < 4; ++u4) pb[u4] = a.pos_sorted[min(q0 + u4, e - 1)];
+    for (int hf = 0; hf < 2; ++hf) {
+        const int o = lane + 64 * hf;
+        cnt2[hf] -= beg2[hf];
+        const int incl = wave_incl_scan(cnt2[hf]);
+        pre2[hf] = total + incl - cnt2[hf];
+        if (o < W) {
+            L.beg[o] = beg2[hf];
+            L.pre[o] = pre2[hf];
+        }
+        total += __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
+    }
+    // (values the same in every lane, held in scalar registers so that the
+    // loops below are uniform)
+    const int s_c = __builtin_amdgcn_readfirstlane(__shfl(beg2[0], o_home));
+    const int nh = __builtin_amdgcn_readfirstlane(__shfl(cnt2[0], o_home));
+    if (nh <= 0) return;
+    Cands C;
+    const bool one = total <= ROW_WIN;  // one window: staged once for all home beads
+    for (int h = 0; h < nh; ++h) {
+        const int qh = s_c + h;
+        // window 0 in registers (and, for the first bead, the home positions in LDS)
+        if (h == 0 || !one) stage_window(a, L, 0, total, cnt2, pre2, h == 0 ? s_c : -1, nh, C);
+        // the home bead and its type's thresholds against each candidate type
+        // (the same in every lane)
+        const float4 ph = h < ROW_HOME ? L.home[h] : a.pos_sorted[qh];
+        const uint32_t tagh = __float_as_uint(ph.w);
+        const int ih = (int)(tagh & J_MASK);
+        const int tb = (int)(tagh >> CODE_SHIFT) * a.T;
+        const float4 th0 = L.thr[tb];
+        const float4 th1 = MT ? L.thr[tb + min(1, a.T - 1)] : th0;
+        const float4 th2 = MT ? L.thr[tb + min(2, a.T - 1)] : th0;
+        const float4 th3 = MT ? L.thr[tb + min(3, a.T - 1)] : th0;
+        const uint32_t self = (uint32_t)ih | (ZERO_CODE << CODE_SHIFT);
+        // every entry inside the list cutoff in the order found (one ballot
+        // per batch), with its class: 0 angular inside r_c^A, 1 angular shell,
+        // 2 radial-only inside r_c^R, 3 radial shell; the class counts from
+        // the same ballots
+        int cnt = 0, n0 = 0, n1 = 0, n2 = 0;
+        uint64_t overlap = 0;
+        for (int base = 0; base < total; base += ROW_WIN) {
+            if (base > 0) stage_window(a, L, base, total, cnt2, pre2, -1, nh, C);
+            const int nw = min(ROW_WIN, total - base);
 #pragma unroll
-                    for (int u4 = 0; u4 < 4; ++u4) {
-                    if (q0 + u4 >= e) break;
-                    const float4 pj = pb[u4];
-                    const uint32_t tag = __float_as_uint(pj.w);
-                    const int j = (int)(tag & J_MASK);
-                    // every component is used before any test, so the candidate
-                    // arrives in one 16-byte load
-                    const float ddx = sub_rn(add_rn(pj.x, sx), pi.x);
-                    const float ddy = sub_rn(add_rn(pj.y, sy), pi.y);
-                    const float ddz = sub_rn(add_rn(pj.z, sz), pi.z);
-                    const float d2 = add_rn(add_rn(mul_rn(ddx, ddx), mul_rn(ddy, ddy)),
-                                               mul_rn(ddz, ddz));
-                    const float4 th = thr_i[tag >> CODE_SHIFT];
-                    if (!(d2 < th.x) || (j == i && zero_shift)) continue;
-                    if (d2 == 0.0f) flags |= NEP_FLAG_OVERLAP;
-                    const uint32_t entry = (uint32_t)j | (code << CODE_SHIFT);
-                    if (d2 < th.y) {
-                        if (d2 < th.z) sai.push(entry, row, 0, A4, false);
-                        else sas.push(entry, row, A4 - 1, A4, true);
-                    } else {
-                        if (d2 < th.w) sri.push(entry, row, A4, R4, false);
-                        else srs.push(entry, row, A4 + R4 - 1, R4, true);
+            for (int k = 0; k < ROW_BATCHES; ++k) {
+                if (64 * k >= nw) break;
+                const uint32_t tj = MT ? (C.types >> (2 * k)) & 3u : 0u;
+                const float4 th = tj == 0 ? th0 : (tj == 1 ? th1 : (tj == 2 ? th2 : th3));
+                // the exact predicate, every operation rounded on its own
+                const float ddx = sub_rn(C.x[k], ph.x);
+                const float ddy = sub_rn(C.y[k], ph.y);
+                const float ddz = sub_rn(C.z[k], ph.z);
+                const float d2 = add_rn(add_rn(mul_rn(ddx, ddx), mul_rn(ddy, ddy)), mul_rn(ddz, ddz));
+                const uint32_t ent = C.ent[k];
+                const uint64_t m_in = __ballot(d2 < th.x) & ~__ballot(ent == self);
+                const uint64_t m_a = __ballot(d2 < th.y), m_ai = __ballot(d2 < th.z), m_ri = __ballot(d2 < th.w);
+                overlap |= m_in & __ballot(d2 == 0.0f);
+                const bool in = d2 < th.x && ent != self;
+                const uint32_t cl = d2 < th.y ? (d2 < th.z ? 0u : 1u) : (d2 < th.w ? 2u : 3u);
+                const int pos = cnt + bits_below(m_in);
+                const int w = in && pos < cap4 ? pos : trash + lane;
+                rows[w] = make_uint2(ent, C.key[k]);
+                rcls[w] = (uint8_t)cl;
+                cnt += (int)__popcll(m_in);
+                n0 += (int)__popcll(m_in & m_a & m_ai);
+                n1 += (int)__popcll(m_in & m_a & ~m_ai);
+                n2 += (int)__popcll(m_in & ~m_a & m_ri);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (overlap) flags |= NEP_FLAG_OVERLAP;
+        const int nf = min(cnt, cap4);
+        const int nai = n0, na = n0 + n1, nri = n2, tot = cnt;
+        int fl = 0;
+        if (na > a.cap_A) fl |= NEP_FLAG_OVERFLOW_A;
+        if (tot > a.cap) fl |= NEP_FLAG_OVERFLOW_R;
+        flags |= fl;
+        most = max(most, tot);
+        most_a = max(most_a, na);
+        const bool over = fl != 0;
+        uint32_t *ar = a.arow + (size_t)ih * (4 + A4);
+        if (lane == 0) {
+            a.cnt[ih] = over ? 0 : tot;
+            a.cnt[n + ih] = over ? 0 : na;
+            a.cls[ih] = over ? 0 : (min(nai, 255) | (nri << 8));
+            *reinterpret_cast<uint4 *>(ar) = make_uint4(over ? 0u : (uint32_t)nai, over ? 0u : (uint32_t)na, 0u, 0u);
+        }
+        wave_sync();  // the row is complete
+        if (!over) {
+            // the entries in class order (found order within a class), a class at a time
+            int run[4] = {0, nai, na, na + nri};  // next slot of each class
+            for (int u0 = 0; u0 < nf; u0 += 64) {
+                const bool v = u0 + lane < nf;
+                const int cl = v ? rcls[u0 + lane] : 4;
+                const uint2 e = rows[v ? u0 + lane : 0];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t m = __ballot(cl == q);
+                    if (cl == q) {
+                        const int r = run[q] + bits_below(m);  // slot
+                        a.nbr[(size_t)r * n + ih] = e.x;
+                        if (q < 2) {
+                            // angular keys: inside r_c^A up from word 4, the shell
+                            // down from the row's end; the key this bead has in
+                            // the neighbour's row waits in rev
+                            ar[q == 0 ? 4 + r : 4 + A4 - 1 - (r - nai)] = e.y;
+                            a.rev[(size_t)r * n + ih] =
+                                (int32_t)((((uint32_t)(W - 1) - (e.y >> CODE_SHIFT)) << CODE_SHIFT) | (uint32_t)qh);
+                        }
                     }
-                    }
+                    run[q] += (int)__popcll(m);
                 }
             }
         }
+        wave_sync();  // the row is free for the next bead
     }
-    sai.finish(row, 0, A4, false);
-    sas.finish(row, A4 - 1, A4, true);
-    sri.finish(row, A4, R4, false);
-    srs.finish(row, A4 + R4 - 1, R4, true);
-    const int nai = sai.cnt, nri = sri.cnt;
-    const int na = nai + sas.cnt;
-    const int total = na + nri + srs.cnt;
-    if (na > a.cap_A) flags |= NEP_FLAG_OVERFLOW_A;
-    if (total > a.cap) flags |= NEP_FLAG_OVERFLOW_R;
-    const bool over = (flags & (NEP_FLAG_OVERFLOW_A | NEP_FLAG_OVERFLOW_R)) != 0;
-    a.cnt[i] = over ? 0 : total;
-    a.cnt[n + i] = over ? 0 : na;
-    a.cls[i] = over ? 0 : (min(nai, 255) | (nri << 8));
-    flags_out = flags;
-    total_out = total;
-    na_out = na;
 }
 
-__device__ __forceinline__ void nb_rows_body(const NbArgs &a, int bx, int gx) {
+__device__ __forceinline__ void rows_thresholds(const NbArgs &a, RowsLds &L) {
+    const int k = threadIdx.x;
+    if (k < MAXT * MAXT) L.thr[k] = make_float4(a.list2R[k], a.list2A[k], a.in2A[k], a.in2R[k]);
+}
+
+// one workgroup (a single wavefront) per cell, consecutive cells on one XCD.
+// (Measured: a cell per workgroup builds the 216,000-bead lists in 0.22 ms,
+// two, four or eight consecutive cells per workgroup in 0.30-0.44 ms; a
+// wave's cells would run one after another, each a chain of dependent loads.)
+template <bool MT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_nb_rows(NbArgs a) {
+    extern __shared__ __align__(16) uint32_t row_dyn[];
+    __shared__ RowsLds L;
     if (build_off(a)) return;  // uniform over the grid
-    __shared__ float4 thr[MAXT * MAXT];
-    if (threadIdx.x < MAXT * MAXT) {
-        const int k = threadIdx.x;
-        thr[k] = make_float4(a.list2R[k], a.list2A[k], a.in2A[k], a.in2R[k]);
-    }
-    __syncthreads();
-    const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
-    int flags = 0, total = 0, na = 0;
-    if (i < a.n) build_row(a, thr, i, flags, total, na);
-    wave_status(a.status, flags, total, na);  // every lane takes part
+    rows_thresholds(a, L);
+    int flags = 0, most = 0, most_a = 0;
+    row_cell<MT>(a, xcd_tile(blockIdx.x, gridDim.x), L, row_dyn, flags, most, most_a);
+    wave_status(a.status, flags, most, most_a);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_nb_rows(NbArgs a) { nb_rows_body(a, blockIdx.x, gridDim.x); }
-
-// row-major scratch -> slot-major lists: slot p of bead i is scratch entry p for
-// the angular prefix, and the radial-only entries, kept from the back of the
-// scratch row, follow in the order they were found.  A workgroup moves its
-// 256 beads through LDS 16 slots at a time: each wave reads 16 consecutive
-// slots of four rows, and writes one slot of 64 consecutive beads.
-//
-// The same workgroup writes the processing order of its beads for the fused
-// kernel.  A bead's cost grows with its row (an angular pair inside r_c^A costs
-// about twenty radial list entries), and a wave takes as long as its busiest
-// lane, so the beads of the block (neighbours in space for a spatially ordered
-// system) are ordered by decreasing cost, ties by index: the lanes of a wave
-// then carry similar work.  The order only decides which thread evaluates
-// which bead; every result is the same bit for bit.
-constexpr int TR_SLOTS = 16;
-
-__device__ __forceinline__ int row_src(int p, int na, int nai, int nri, int A4, int R4) {
-    if (p < nai) return p;                            // inside r_c^A
-    if (p < na) return A4 - 1 - (p - nai);            // angular shell
-    if (p < na + nri) return A4 + (p - na);           // inside r_c^R
-    return A4 + R4 - 1 - (p - na - nri);              // radial shell
-}
-
-__device__ __forceinline__ void nb_transpose_body(const NbArgs &a, int bx, int gx) {
-    if (build_off(a)) return;  // uniform over the grid
-    __shared__ uint32_t tile[TR_SLOTS][BLOCK + 4];
-    __shared__ int4 info[BLOCK];  // total, angular, inside r_c^A, inside r_c^R (radial-only)
-    __shared__ int4 cost4[BLOCK / 4];  // processing cost of each bead (-1 past the system's end)
-    __shared__ int max_total;
+// Processing order of the fused kernel.  A bead's cost grows with its row (an
+// angular pair inside r_c^A costs about twenty radial list entries), and a
+// wave takes as long as its busiest lane, so the beads of each block of 256
+// (neighbours in space for a spatially ordered system) are ordered by
+// decreasing cost, ties by index: the lanes of a wave then carry similar
+// work.  The order only decides which thread evaluates which bead; every
+// result is the same bit for bit.
+__device__ __forceinline__ void nb_order_body(const NbArgs &a, int bx, int gx) {
+    if (build_off(a) || !a.order) return;  // uniform over the grid
+    __shared__ int4 cost4[BLOCK / 4];
     const int n = a.n;
     const int i0 = xcd_tile(bx, gx) * BLOCK;
-    const int A4 = (a.cap_A + 3) & ~3, R4 = (a.cap + 3) & ~3;
-    int4 f = make_int4(0, 0, 0, 0);
-    if (i0 + (int)threadIdx.x < n) {
-        const int i = i0 + threadIdx.x;
-        const int c = a.cls[i];
-        f = make_int4(a.cnt[i], a.cnt[n + i], c & 255, c >> 8);
-    }
-    info[threadIdx.x] = f;
-    reinterpret_cast<int *>(cost4)[threadIdx.x] = i0 + (int)threadIdx.x < n ? 20 * f.z + f.x : -1;
-    if (threadIdx.x == 0) max_total = 0;
+    const int b = threadIdx.x;
+    int cost = -1;  // below every cost: past the system's end
+    if (i0 + b < n) cost = 20 * (a.cls[i0 + b] & 255) + a.cnt[i0 + b];
+    reinterpret_cast<int *>(cost4)[b] = cost;
     __syncthreads();
-    int m = f.x;
-#pragma unroll
-    for (int w = 32; w >= 1; w >>= 1) m = max(m, __shfl_xor(m, w));
-    if (__lane_id() == 0) atomicMax(&max_total, m);
-    __syncthreads();
-    const int mt = max_total;
-    if (a.order) {
-        // rank of this bead among the block's beads by decreasing cost (ties
-        // by index; the -1 of missing beads ranks below every cost), four
-        // costs per LDS read
-        const int b = threadIdx.x;
-        const int nb = min(BLOCK, n - i0);
-        const int cost = 20 * f.z + f.x;
-        int rank = 0;
+    const int nb = min(BLOCK, n - i0);
+    int rank = 0;
 #pragma unroll 4
-        for (int k4 = 0; k4 < BLOCK / 4; ++k4) {
-            const int4 c = cost4[k4];
-            const int cs[4] = {c.x, c.y, c.z, c.w};
+    for (int k4 = 0; k4 < BLOCK / 4; ++k4) {
+        const int4 c = cost4[k4];
+        const int cv[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = 4 * k4 + u;
-                rank += (cs[u] > cost || (cs[u] == cost && k < b)) ? 1 : 0;
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int k = 4 * k4 + u;
+            rank += (cv[u] > cost || (cv[u] == cost && k < b)) ? 1 : 0;
         }
-        if (b < nb) a.order[i0 + rank] = i0 + b;
     }
-    constexpr int BEADS_PER_PASS = BLOCK / TR_SLOTS;
-    const int pl = threadIdx.x % TR_SLOTS, bsub = threadIdx.x / TR_SLOTS;
-    for (int p0 = 0; p0 < mt; p0 += TR_SLOTS) {
-        // all TR_SLOTS loads are issued before any is used: unconditional, at a
-        // slot clamped into the row (and a bead clamped into the system), so
-        // none waits behind a branch; slots past a row's end are never read
-        uint32_t vals[TR_SLOTS];
-#pragma unroll
-        for (int k = 0; k < TR_SLOTS; ++k) {
-            const int b = bsub + k * BEADS_PER_PASS;
-            const int4 g = info[b];
-            const int p = min(p0 + pl, max(g.x - 1, 0));
-            const int bead = min(i0 + b, n - 1);
-            vals[k] = a.rowbuf[(size_t)bead * (A4 + R4) + row_src(p, g.y, g.z, g.w, A4, R4)];
-        }
-#pragma unroll
-        for (int k = 0; k < TR_SLOTS; ++k) tile[pl][bsub + k * BEADS_PER_PASS] = vals[k];
-        __syncthreads();
-#pragma unroll 4
-        for (int q = 0; q < TR_SLOTS; ++q)
-            if (p0 + q < f.x) a.nbr[(size_t)(p0 + q) * n + i0 + threadIdx.x] = tile[q][threadIdx.x];
-        __syncthreads();
-    }
+    if (b < nb) a.order[i0 + rank] = i0 + b;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_nb_transpose(NbArgs a) { nb_transpose_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(BLOCK) void k_nb_order(NbArgs a) { nb_order_body(a, blockIdx.x, gridDim.x); }
 
-// angular slots per thread: p = blockIdx.y + k gridDim.y (with the searches
-// ending early, two per thread measured faster than one, three or four)
+// ---- 5. reverse ----
+// angular slots per thread: p = by + k gy for slot group by of gy
 constexpr int REV_SLOTS = 2;
+// 16-byte key groups of the neighbour's row read together with its header
+constexpr int REV_GROUPS = 2;
 
-// Reverse entries of up to REV_SLOTS angular slots of bead i (slots by,
-// by + gy, ...): where each neighbour j's row holds i with the opposite
-// image.  The search scans j's angular entries in the row-major build rows,
-// where they lie together (the entries inside r_c^A from the front, the
-// angular shell entries from the end of the angular part), 16 bytes at a
-// time; the searches of one thread advance together so their loads overlap.
-// Lanes of a wave handle consecutive beads at the same slots.
-__device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int bx, int gx, int by, int gy) {
+// key number s (0-based, ascending) of a class part of a row held as 16-byte
+// groups: the part inside r_c^A runs up from the row's start, the shell part
+// down from its end
+__device__ __forceinline__ uint32_t group_key(const uint4 &g, int u, bool down) {
+    const int v = down ? 3 - u : u;
+    return v == 0 ? g.x : (v == 1 ? g.y : (v == 2 ? g.z : g.w));
+}
+
+// slot of `want` in a class part of len keys starting at group g0 of the
+// part, or -1; keys at row word 4 + 4 c + u (up) or 4 + A4 - 1 - (4 c + u)
+// (down) for group c
+__device__ __forceinline__ int find_key_from(const uint32_t *ar, int A4, bool down, int len, int g0, uint32_t want) {
+    for (int c = g0; 4 * c < len; ++c) {
+        const uint4 g = *reinterpret_cast<const uint4 *>(down ? ar + 4 + A4 - 4 * (c + 1) : ar + 4 + 4 * c);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (4 * c + u < len && group_key(g, u, down) == want) return 4 * c + u;
+    }
+    return -1;
+}
+
+// Reverse entries of up to REV_SLOTS angular slots of bead i: the slot of
+// the neighbour j's row that holds i with the opposite image.  The key that
+// i has in j's row waits in rev (left by the row kernel); the part of j's
+// row of the pair's class (the same in both rows except where rounding puts
+// the distance on the two sides of r_c^A) is read with the row's header in
+// one round of independent 16-byte loads, and the key is looked up there;
+// the rest of a long part, and the other part, only when needed.  Lanes of a
+// wave handle consecutive beads at the same slots.  The workgroups of one
+// block of beads (its slot groups) are consecutive tiles, kept on one XCD, so
+// the neighbours' rows they read stay in that XCD's L2.
+__device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int tile, int gy) {
     if (build_off(a)) return;
     const int n = a.n;
-    const int i = xcd_tile(bx, gx) * BLOCK + threadIdx.x;
+    const int by = tile % gy;
+    const int i = (tile / gy) * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int na = a.cnt[n + i];
-    const int A4 = (a.cap_A + 3) & ~3, R4 = (a.cap + 3) & ~3;
-    int p[REV_SLOTS], j[REV_SLOTS], nin[REV_SLOTS], lo[REV_SLOTS], nch[REV_SLOTS], found[REV_SLOTS];
-    int ca[REV_SLOTS], cs[REV_SLOTS];
-    bool sfirst[REV_SLOTS];
-    uint32_t want[REV_SLOTS];
-    // this bead's own class split: slots [0, nai_i) inside r_c^A, the rest in the shell
+    if (by >= na) return;
+    const int A4 = (a.cap_A + 3) & ~3;
     const int nai_i = min(a.cls[i] & 255, na);
+    int p[REV_SLOTS], j[REV_SLOTS];
+    uint32_t want[REV_SLOTS];
+    bool sh[REV_SLOTS];
 #pragma unroll
     for (int k = 0; k < REV_SLOTS; ++k) {
         p[k] = by + k * gy;
-        const uint32_t e = p[k] < na ? a.nbr[(size_t)p[k] * n + i] : 0u;
-        j[k] = (int)(e & J_MASK);
-        want[k] = (uint32_t)i | ((124u - (e >> CODE_SHIFT)) << CODE_SHIFT);
-        found[k] = -1;
-        // a pair has the same class in both rows except where rounding puts its
-        // distance on the two sides of r_c^A: search j's part of that class
-        // first, then the other part
-        sfirst[k] = p[k] >= nai_i;
+        const bool v = p[k] < na;
+        j[k] = v ? (int)(a.nbr[(size_t)p[k] * n + i] & J_MASK) : 0;
+        want[k] = v ? (uint32_t)a.rev[(size_t)p[k] * n + i] : 0u;
+        sh[k] = p[k] >= nai_i;
+    }
+    uint4 hd[REV_SLOTS], g[REV_SLOTS][REV_GROUPS];
+#pragma unroll
+    for (int k = 0; k < REV_SLOTS; ++k) {
+        const uint32_t *ar = a.arow + (size_t)j[k] * (4 + A4);
+        hd[k] = *reinterpret_cast<const uint4 *>(ar);
+#pragma unroll
+        for (int c = 0; c < REV_GROUPS; ++c)
+            g[k][c] = 4 * c < A4 ? *reinterpret_cast<const uint4 *>(sh[k] ? ar + 4 + A4 - 4 * (c + 1) : ar + 4 + 4 * c)
+                                 : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
     for (int k = 0; k < REV_SLOTS; ++k) {
-        const bool v = p[k] < na;
-        // j's angular entries (0 after an overflow of j's row): nin inside
-        // r_c^A at row positions [0, nin), the shell at [lo, A4)
-        const int naj = v ? a.cnt[n + j[k]] : 0;
-        const int nai = v ? min(a.cls[j[k]] & 255, naj) : 0;
-        nin[k] = nai;
-        lo[k] = A4 - (naj - nai);
-        ca[k] = (nai + 3) >> 2;                                         // chunks inside r_c^A
-        cs[k] = naj > nai ? (A4 - (lo[k] & ~3)) >> 2 : 0;               // chunks of the shell
-        nch[k] = ca[k] + cs[k];
-    }
-    int most = 0;
+        if (p[k] >= na) continue;
+        const uint32_t *ar = a.arow + (size_t)j[k] * (4 + A4);
+        const int nai_j = (int)hd[k].x, na_j = (int)hd[k].y;
+        const int len = sh[k] ? na_j - nai_j : nai_j;
+        int found = -1;
 #pragma unroll
-    for (int k = 0; k < REV_SLOTS; ++k) most = max(most, nch[k]);
-    for (int c = 0; c < most; ++c) {
-        bool done = true;
+        for (int c = 0; c < REV_GROUPS; ++c)
 #pragma unroll
-        for (int k = 0; k < REV_SLOTS; ++k) done = done && (c >= nch[k] || found[k] >= 0);
-        if (done) break;
-#pragma unroll
-        for (int k = 0; k < REV_SLOTS; ++k) {
-            if (c >= nch[k] || found[k] >= 0) continue;
-            const bool shell = sfirst[k] ? c < cs[k] : c >= ca[k];
-            const int cc = sfirst[k] ? (shell ? c : c - cs[k]) : (shell ? c - ca[k] : c);
-            const int q0 = shell ? (lo[k] & ~3) + 4 * cc : 4 * cc;
-            const uint4 w = *reinterpret_cast<const uint4 *>(a.rowbuf + (size_t)j[k] * (A4 + R4) + q0);
-            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = q0 + u;
-                const bool in_range = shell ? (q >= lo[k] && q < A4) : (q < nin[k]);
-                // slot of row position q: itself inside r_c^A, counted from the
-                // end of the angular part in the shell
-                if (found[k] < 0 && in_range && ws[u] == want[k]) found[k] = shell ? nin[k] + (A4 - 1 - q) : q;
-            }
+            for (int u = 0; u < 4; ++u)
+                if (4 * c + u < len && group_key(g[k][c], u, sh[k]) == want[k]) found = 4 * c + u;
+        bool shell = sh[k];
+        if (found < 0 && len > 4 * REV_GROUPS) found = find_key_from(ar, A4, shell, len, REV_GROUPS, want[k]);
+        if (found < 0) {
+            shell = !shell;
+            found = find_key_from(ar, A4, shell, shell ? na_j - nai_j : nai_j, 0, want[k]);
         }
+        const int slot = found < 0 ? -1 : (shell ? nai_j + found : found);
+        a.rev[(size_t)p[k] * n + i] = slot < 0 ? -1 : (int32_t)((size_t)slot * n + j[k]);
     }
-#pragma unroll
-    for (int k = 0; k < REV_SLOTS; ++k)
-        if (p[k] < na) a.rev[(size_t)p[k] * n + i] = found[k] < 0 ? -1 : (int32_t)((size_t)found[k] * n + j[k]);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
-    nb_reverse_body(a, blockIdx.x, gridDim.x, blockIdx.y, gridDim.y);
+    nb_reverse_body(a, xcd_tile(blockIdx.x, gridDim.x), (a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
 }
-
-
 
 hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     int nbk = (a.n + BLOCK - 1) / BLOCK;
@@ -626,21 +749,33 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_add, dim3(cbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_fill, dim3(nbk), dim3(BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_nb_rank, dim3(nbk), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_nb_rows, dim3(nbk), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_nb_transpose, dim3(nbk), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_nb_reverse, dim3(nbk, (a.cap_A + REV_SLOTS - 1) / REV_SLOTS), dim3(BLOCK), 0, s, a);
+    const size_t lds = row_lds_bytes(a.cap, a.cap_A);
+    if (a.T > 1) hipLaunchKernelGGL(k_nb_rows<true>, dim3(a.ncell), dim3(64), lds, s, a);
+    else hipLaunchKernelGGL(k_nb_rows<false>, dim3(a.ncell), dim3(64), lds, s, a);
+    if (a.order) hipLaunchKernelGGL(k_nb_order, dim3(nbk), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_nb_reverse, dim3(nbk * ((a.cap_A + REV_SLOTS - 1) / REV_SLOTS)), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
-
-
 // ---- one launch per phase over the builds of many systems ----
-// start[ph][r] is the first block of system r in phase ph (tables of
-// n_sys + 1 entries, one per tile kind: cells to clear, beads, scan blocks,
-// cells to offset, and (bead, slot-group) pairs).
-enum { NB_TILE_CLEAR = 0, NB_TILE_BEAD, NB_TILE_SCANL, NB_TILE_SCANA, NB_TILE_REV, NB_TILES };
+// start[kind][r] is the first block of system r for each tile kind (tables of
+// n_sys + 1 entries): cells to clear, beads, scan blocks, cells to offset,
+// (bead, slot-group) pairs, and runs of cells for the rows.
+enum { NB_TILE_CLEAR = 0, NB_TILE_BEAD, NB_TILE_SCANL, NB_TILE_SCANA, NB_TILE_REV, NB_TILE_ROWS, NB_TILES };
 static_assert(NB_TILES == NB_BATCH_TILES, "tile kinds of the batched build");
-enum { OP_CLEAR, OP_BIN, OP_SCANL, OP_SCANA, OP_FILL, OP_RANK, OP_ROWS, OP_TRANSPOSE, OP_REVERSE };
+enum { OP_CLEAR, OP_BIN, OP_SCANL, OP_SCANA, OP_FILL, OP_RANK, OP_ORDER, OP_REVERSE };
+
+// the last system whose first block of the given kind is <= blockIdx.x
+__device__ __forceinline__ int batch_system(const NbBatchArgs &b, int tile) {
+    const int *st = b.start + tile * (b.n_sys + 1);
+    int lo = 0, hi = b.n_sys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 template <int OP>
 __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
@@ -650,12 +785,7 @@ __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
                          : OP == OP_REVERSE ? NB_TILE_REV
                                             : NB_TILE_BEAD;
     const int *st = b.start + TILE * (b.n_sys + 1);
-    int lo = 0, hi = b.n_sys - 1;  // last system whose first block is <= blockIdx.x
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (st[mid] <= (int)blockIdx.x) lo = mid;
-        else hi = mid - 1;
-    }
+    const int lo = batch_system(b, TILE);
     const NbArgs &a = b.args[lo];
     const int bx = blockIdx.x - st[lo], gx = st[lo + 1] - st[lo];
     if constexpr (OP == OP_CLEAR) nb_clear_body(a.ncell, a.cell_count, a.status, a.clear_status, a.ctrl, bx, gx);
@@ -664,12 +794,25 @@ __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
     if constexpr (OP == OP_SCANA) scan_add_body(a, bx);
     if constexpr (OP == OP_FILL) nb_fill_body(a, bx);
     if constexpr (OP == OP_RANK) nb_rank_body(a, bx);
-    if constexpr (OP == OP_ROWS) nb_rows_body(a, bx, gx);
-    if constexpr (OP == OP_TRANSPOSE) nb_transpose_body(a, bx, gx);
+    if constexpr (OP == OP_ORDER) nb_order_body(a, bx, gx);
     if constexpr (OP == OP_REVERSE) {
-        const int nbk = (a.n + BLOCK - 1) / BLOCK;
-        nb_reverse_body(a, bx % nbk, nbk, bx / nbk, gx / nbk);
+        nb_reverse_body(a, xcd_tile(bx, gx), (a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
     }
+}
+
+// rows of many systems: a cell per workgroup
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_nb_batch_rows(NbBatchArgs b) {
+    extern __shared__ __align__(16) uint32_t row_dyn[];
+    __shared__ RowsLds L;
+    const int *st = b.start + NB_TILE_ROWS * (b.n_sys + 1);
+    const int lo = batch_system(b, NB_TILE_ROWS);
+    const NbArgs &a = b.args[lo];
+    if (build_off(a)) return;  // uniform over the workgroup
+    rows_thresholds(a, L);
+    const int bx = blockIdx.x - st[lo], gx = st[lo + 1] - st[lo];
+    int flags = 0, most = 0, most_a = 0;
+    row_cell<true>(a, xcd_tile(bx, gx), L, row_dyn, flags, most, most_a);
+    wave_status(a.status, flags, most, most_a);
 }
 
 void nb_batch_tiles(const NbArgs &a, int counts[NB_BATCH_TILES]) {
@@ -680,7 +823,10 @@ void nb_batch_tiles(const NbArgs &a, int counts[NB_BATCH_TILES]) {
     counts[NB_TILE_SCANL] = (a.ncell + SCAN_B - 1) / SCAN_B;
     counts[NB_TILE_SCANA] = cbk;
     counts[NB_TILE_REV] = nbk * ((a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
+    counts[NB_TILE_ROWS] = a.ncell;
 }
+
+int nb_row_lds_bytes(int cap, int cap_A) { return row_lds_bytes(cap, cap_A); }
 
 hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[NB_BATCH_TILES], hipStream_t s) {
     if (b.n_sys == 0) return hipSuccess;
@@ -692,8 +838,9 @@ hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[NB_BATCH_TI
     NB_LAUNCH(OP_SCANA, NB_TILE_SCANA)
     NB_LAUNCH(OP_FILL, NB_TILE_BEAD)
     NB_LAUNCH(OP_RANK, NB_TILE_BEAD)
-    NB_LAUNCH(OP_ROWS, NB_TILE_BEAD)
-    NB_LAUNCH(OP_TRANSPOSE, NB_TILE_BEAD)
+    if (totals[NB_TILE_ROWS] > 0)
+        hipLaunchKernelGGL(k_nb_batch_rows, dim3(totals[NB_TILE_ROWS]), dim3(64), b.row_bytes, s, b);
+    NB_LAUNCH(OP_ORDER, NB_TILE_BEAD)
     NB_LAUNCH(OP_REVERSE, NB_TILE_REV)
 #undef NB_LAUNCH
     return hipGetLastError();

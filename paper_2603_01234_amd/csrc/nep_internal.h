@@ -309,14 +309,15 @@ struct NbArgs {
     const uint8_t *type;
     float4 *pos4;
     int32_t *cell_id, *cell_count, *cell_start, *cell_cursor, *cell_list, *scan_tmp;
+    int32_t *cell_xyz;   // [ncell] grid coordinates of each cell, x | y << 10 | z << 20 (nc <= 1023)
     int32_t *cell_tmp;   // [n] cell members in atomic (arbitrary) order
     float4 *pos_sorted;  // [n] positions in cell order; w = bits of (index | type << 25)
     int32_t *cls;        // [n] entries inside r_c^A | entries inside r_c^R (radial-only) << 8
     float cull2;         // cells whose gap exceeds this squared distance are skipped
-    uint32_t *rowbuf;    // [n][A4 + R4] (cap_A, cap rounded up to multiples of 4) rows built
-                         // row-major in four stacks (angular inside
-                         // r_c^A, angular shell, radial inside r_c^R, radial shell), then
-                         // transposed into nbr in that class order
+    uint32_t *arow;      // [n][4 + A4] (A4: cap_A rounded up to a multiple of 4) angular sort
+                         // keys, row-major: header (entries inside r_c^A, angular entries, 0, 0),
+                         // then the keys inside r_c^A up from word 4 and the shell's down from
+                         // the row's end
     uint32_t *nbr;
     int32_t *rev, *cnt;
     float *ref;
@@ -335,13 +336,16 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s);
 // Builds of many systems, one launch per phase: args[r] as for launch_build
 // (systems with n > 0); start holds the tables of first blocks written by
 // the caller from nb_batch_tiles; totals are the last entries of the tables.
-constexpr int NB_BATCH_TILES = 5;
+constexpr int NB_BATCH_TILES = 6;
 struct NbBatchArgs {
     int n_sys;
     const NbArgs *args;
     const int *start;     // [NB_BATCH_TILES][n_sys + 1]
+    int row_bytes;        // largest nb_row_lds_bytes over the systems
 };
 void nb_batch_tiles(const NbArgs &a, int counts[NB_BATCH_TILES]);
+// LDS bytes the row kernel takes for a row of the given capacities
+int nb_row_lds_bytes(int cap, int cap_A);
 hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[NB_BATCH_TILES], hipStream_t s);
 
 // zeroes the status word and, when given, the MD control words [4] (the

@@ -89,3 +89,28 @@ def predicate_edge_pairs(rng, rc2, count, batch=8192, lo=(0.5, 0.5, 0.5)):
         out_i.append(xi[pick])
         out_j.append(xj[pick])
     return np.concatenate(out_i)[:count], np.concatenate(out_j)[:count]
+
+
+def check_reverse(rep, rows):
+    """Every angular slot p of bead i points, through rev, at the slot of its
+    neighbour j's angular part that holds i with the opposite image, and is
+    -1 exactly when j's angular part has no such entry."""
+    nbr, cnt = rep.neighbor_rows()
+    rev = rep.rev.cpu().numpy()
+    n = rep.n
+    found = 0
+    for i in rows:
+        for p in range(int(cnt[1, i])):
+            e = int(nbr[p, i])
+            j, code = e & 0x1FFFFFF, e >> 25
+            mirror = i | ((124 - code) << 25)
+            naj = int(cnt[1, j])
+            where = np.nonzero(nbr[:naj, j] == np.uint32(mirror))[0]
+            r = int(rev[p, i])
+            if where.size == 0:
+                assert r == -1, (i, p, j, r)
+                continue
+            assert where.size == 1, (i, p, j)
+            assert r == int(where[0]) * n + j, (i, p, j, r, int(where[0]))
+            found += 1
+    return found

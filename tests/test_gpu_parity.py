@@ -11,7 +11,7 @@ import pytest
 import oracle
 import workloads as W
 from oracle.neighbors_f32 import neighbor_sets
-from gpu_helpers import compare_efv, gpu_sets
+from gpu_helpers import check_reverse, compare_efv, gpu_sets
 
 pytestmark = pytest.mark.gpu
 
@@ -79,6 +79,22 @@ def test_neighbor_sets_small_boxes_with_images(box):
     _check_sets(rep, spec, system, 0.05, range(system.n))
 
 
+@pytest.mark.parametrize("case", ["config0", "image_box", "open_mixed"])
+def test_reverse_index_points_at_the_mirrored_entry(case):
+    if case == "config0":
+        spec, params, system, opts = W.config0()
+        skin = opts["skin"]
+    elif case == "image_box":
+        spec, params, system = _small_two_type(3, 12, (0.62, 0.7, 0.66), [True, True, True], H=8)
+        skin = 0.05
+    else:
+        spec, params, system = _small_two_type(5, 40, (3.0, 3.0, 3.0), [False, True, False], H=8)
+        skin = 0.1
+    rep = _replica(spec, params, system, skin=skin)
+    rep.build()
+    assert check_reverse(rep, range(system.n)) > 0
+
+
 def test_neighbor_predicate_is_never_fused():
     """Pairs at the radial and the angular list cutoff where a fused
     multiply-add and separate rounding of d2 disagree, each far from the others
@@ -129,6 +145,7 @@ def test_neighbor_sets_config1_sampled():
     rep.build()
     rows = np.random.default_rng(0).choice(system.n, 150, replace=False).tolist() + [0, system.n - 1]
     _check_sets(rep, spec, system, opts["skin"], rows)
+    assert check_reverse(rep, rows) > 0
 
 
 # ---------------------------------------------------------------------------
