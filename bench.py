@@ -510,6 +510,33 @@ def served_leg(plain_requests: int = 2000):
                     "the trace; capacity: every replica stepping in every tick"}
 
 
+def network_engines_leg(rep, model, K, dt, masses, every, args):
+    """The fused kernel with either network engine on the same state (the
+    replica after the timed window, restored between the two runs): mean
+    launch time over K steps and the steps' wall time."""
+    from paper_2603_01234_amd import binding as B
+    import torch
+    snap = rep.snapshot()
+    res = {}
+    for eng in ("valu", "mfma"):
+        rep.restore(snap)
+        model.set_network(eng)
+        B.nep_timing_begin(2 * K + 64, 0x1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep.md(K, dt, masses, rebuild_every=every, sort_every=args.sort_every)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, launches = B.nep_timing_end()
+        res[eng] = {"k_efv_main_avg_ms": round(ms[0] / max(launches[0], 1), 4),
+                    "ms_per_step": round(wall * 1e3 / K, 4)}
+    rep.restore(snap)
+    model.set_network(args.network)
+    res["note"] = ("both engines from the same snapshot of the timed state; the headline runs the engine in "
+                   "config.network")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -530,6 +557,10 @@ def main():
     ap.add_argument("--no-ensembles", action="store_true", help="skip the NVT / NPT / HNEMD leg")
     ap.add_argument("--no-snes", action="store_true", help="skip the SNES training-loop leg")
     ap.add_argument("--no-labels", action="store_true", help="skip the constrained label-generation leg")
+    ap.add_argument("--network", choices=["valu", "mfma"], default="valu",
+                    help="engine of the fused kernel's network (Eq. 2): vector ALUs or FP32 matrix cores")
+    ap.add_argument("--no-network-legs", action="store_true",
+                    help="skip the comparison of the two network engines on the timed state")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -545,7 +576,7 @@ def main():
 
     torch.cuda.set_device(0)
     spec, params, system, opts = W.config1()
-    model = engine.Model.from_spec(spec, params)
+    model = engine.Model.from_spec(spec, params).set_network(args.network)
     masses = [W.WATER_MASS]
     dt, every = opts["dt"], opts["rebuild_every"]
     K = args.steps
@@ -665,6 +696,7 @@ def main():
                    "mean_neighbours_angular_run": round(tot_A / (K * system.n), 3),
                    "row_capacity": [rep.cap, rep.cap_A],
                    "sort_every": args.sort_every,
+                   "network": args.network,
                    "timed_steps": [step_first, step_first + K - 1],
                    "rebuilds_in_timed_steps": rebuilds,
                    "virial": "per-bead and total virial every step (Eqs. 15-16)",
@@ -675,6 +707,8 @@ def main():
     }
     if kernels is not None:
         out["kernels"] = kernels
+    if not args.no_network_legs and K > 0:
+        out["network_engines"] = network_engines_leg(rep, model, K, dt, masses, every, args)
     if full_run is not None:
         out["config"]["full_run"] = full_run
     if args.copy_calibration:

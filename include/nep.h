@@ -96,6 +96,21 @@ int nep_model_create(const nep_hyper *hyper, const float *params_host, size_t n_
                      nep_model *out);
 int nep_model_destroy(nep_model model);
 
+/* Engine of the network (Eq. 2) in the single-system fused kernel
+ * (nep_compute_efv, nep_compute_efv_noalloc, nep_md_step):
+ *   NEP_NETWORK_VALU  (default) each lane contracts its bead's descriptor with
+ *                     the weights on the vector ALUs;
+ *   NEP_NETWORK_MFMA  the descriptor x hidden-layer product of the 64 beads of a
+ *                     wavefront and its transpose (dU/dq) on the FP32 matrix
+ *                     cores (16x16x4 MFMA), one bead type and a hidden width of
+ *                     at most 64 only (NEP_ERR_UNSUPPORTED otherwise).
+ * Both give the same results up to rounding (the sums over hidden units run in
+ * another order).  The batched and served forms always use the vector ALUs.
+ * Changes the model: not to be called while another call uses it. */
+#define NEP_NETWORK_VALU 0
+#define NEP_NETWORK_MFMA 1
+int nep_model_set_network(nep_model model, int engine);
+
 /* ------------------------------------------------------------------------ */
 /* system and neighbour lists                                                */
 /* ------------------------------------------------------------------------ */

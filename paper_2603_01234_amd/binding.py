@@ -43,9 +43,11 @@ EXPORTS = ["nep_param_count", "nep_model_create", "nep_model_destroy", "nep_work
            "nep_last_error", "nep_timing_begin", "nep_timing_end", "nep_batch_workspace_bytes",
            "nep_compute_efv_batch", "nep_batch_autotune", "nep_md_batch_workspace_bytes", "nep_md_step_batch",
            "nep_sort_system", "nep_compute_efv_noalloc", "nep_models_load_params", "nep_snes_sample",
-           "nep_snes_update"]
+           "nep_snes_update", "nep_model_set_network"]
 
 NEP_NOALLOC_SCRATCH_BYTES = 64 << 20
+NEP_NETWORK_VALU = 0
+NEP_NETWORK_MFMA = 1
 
 
 class NepError(RuntimeError):
@@ -124,6 +126,8 @@ def lib():
         L.nep_model_create.restype = c_int
         L.nep_model_destroy.argtypes = [c_void_p]
         L.nep_model_destroy.restype = c_int
+        L.nep_model_set_network.argtypes = [c_void_p, c_int]
+        L.nep_model_set_network.restype = c_int
         L.nep_workspace_bytes.argtypes = [c_void_p, c_int, c_int, c_int]
         L.nep_workspace_bytes.restype = c_size_t
         L.nep_build_neighbors.argtypes = [c_void_p, POINTER(System), POINTER(Neighbors), c_int, c_void_p, c_size_t,
@@ -208,6 +212,12 @@ def nep_model_create(h: Hyper, params: np.ndarray) -> int:
 
 def nep_model_destroy(model: int) -> None:
     check(lib().nep_model_destroy(model))
+
+
+def nep_model_set_network(model: int, engine: int) -> int:
+    """Returns the library's code (NEP_ERR_UNSUPPORTED for a model the
+    matrix-core network does not take)."""
+    return int(lib().nep_model_set_network(model, engine))
 
 
 def nep_workspace_bytes(model: int, n: int, cap: int, cap_A: int) -> int:

@@ -343,7 +343,7 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     size_t lds = (size_t)M.T * M.T * TAB_PER_PAIR * sizeof(float);
     {
         TimedLaunch tl(0, st);
-        HIPCHK(launch_efv_main(M.T, M.HP, a, lds, st));
+        HIPCHK(launch_efv_main(M.T, M.HP, a, lds, st, M.mfma != 0));
     }
     GatherArgs g{};
     g.n = n;
@@ -839,6 +839,15 @@ int nep_model_create(const nep_hyper *h, const float *params, size_t n_params, n
         return fail(NEP_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
     }
     *out = m;
+    return NEP_OK;
+}
+
+int nep_model_set_network(nep_model m, int engine) {
+    if (!m) return fail(NEP_ERR_ARG, "null model");
+    if (engine != NEP_NETWORK_VALU && engine != NEP_NETWORK_MFMA) return fail(NEP_ERR_ARG, "unknown network engine");
+    if (engine == NEP_NETWORK_MFMA && !efv_main_mfma_supported(m->m.T, m->m.HP))
+        return fail(NEP_ERR_UNSUPPORTED, "the matrix-core network takes one bead type and at most 64 hidden units");
+    m->m.mfma = engine == NEP_NETWORK_MFMA ? 1 : 0;
     return NEP_OK;
 }
 

@@ -42,9 +42,25 @@ hipError_t launch_pack(int n, int T, const float *x, const float *y, const float
     return hipGetLastError();
 }
 
-template <int NT, int HP>
+template <int NT, int HP, bool MF>
 __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
     extern __shared__ float smem[];
+    if constexpr (MF) {
+        // the network on the matrix cores: W0 staged once per workgroup; every
+        // lane stays to the end (lanes past the system's end with a dummy bead)
+        float *w0s = smem;
+        mf_stage_w0<HP>(a.ann, w0s);
+        __syncthreads();
+        if (a.freeze && (a.freeze[0] & FREEZE_MASK)) return;
+        const int tile = xcd_tile(blockIdx.x, gridDim.x);
+        const int t = tile * BLOCK + threadIdx.x;
+        const bool valid = t < a.n;
+        int i = valid ? (a.order ? a.order[t] : t) : 0;
+        if ((unsigned)i >= (unsigned)a.n) i = valid ? t : 0;
+        float *wl = smem + MF_WROWS * (HP + 1) + (threadIdx.x >> 6) * (64 * mf_stride<HP>() + 64);
+        main_bead<1, HP, true>(a, a.cut, (const_fp)a.tab, i, valid, w0s, wl);
+        return;
+    }
     table_ptr<NT> TB;
     if constexpr (NT > 1) {
         // per-pair type indices vary across lanes: stage the pair tables in LDS
@@ -66,6 +82,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_efv_main(EfvArgs a) {
     if ((unsigned)i >= (unsigned)a.n) i = t;
     main_bead<NT, HP>(a, a.cut, TB, i);
 }
+
 
 // GATHER_LANES lanes per bead: lane q takes slots q, q + GATHER_LANES, ... of
 // the row (lane 0 also the bead's own angular sum), and the lane sums are
@@ -210,10 +227,11 @@ hipError_t launch_reduce(const double *partial, int nblocks, double *E_tot, doub
     return hipGetLastError();
 }
 
-template <int NT, int HP>
+template <int NT, int HP, bool MF = false>
 static hipError_t main_t(const EfvArgs &a, size_t lds, hipStream_t s) {
     int nb = (a.n + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL((k_efv_main<NT, HP>), dim3(nb), dim3(BLOCK), NT > 1 ? lds : 0, s, a);
+    if constexpr (MF) lds = (size_t)mf_lds_floats<HP>(BLOCK / 64) * sizeof(float);
+    hipLaunchKernelGGL((k_efv_main<NT, HP, MF>), dim3(nb), dim3(BLOCK), (NT > 1 || MF) ? lds : 0, s, a);
     return hipGetLastError();
 }
 
@@ -228,8 +246,18 @@ static hipError_t main_nt(int HP, const EfvArgs &a, size_t lds, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds, hipStream_t s) {
+bool efv_main_mfma_supported(int T, int HP) { return T == 1 && (HP == 16 || HP == 32 || HP == 64); }
+
+hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds, hipStream_t s, bool mfma) {
     if (a.n == 0) return hipSuccess;
+    if (mfma) {
+        if (!efv_main_mfma_supported(T, HP)) return hipErrorInvalidValue;
+        switch (HP) {
+            case 16: return main_t<1, 16, true>(a, lds, s);
+            case 32: return main_t<1, 32, true>(a, lds, s);
+            case 64: return main_t<1, 64, true>(a, lds, s);
+        }
+    }
     switch (T) {
         case 1: return main_nt<1>(HP, a, lds, s);
         case 2: return main_nt<2>(HP, a, lds, s);

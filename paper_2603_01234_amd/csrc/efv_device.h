@@ -246,18 +246,194 @@ __device__ __forceinline__ void network(const int ti, const const_fp TB, const c
 
 }
 
+// ---------------- the network on the matrix cores ----------------
+// The same contraction as network() for one bead type, over the 64 beads of a
+// wavefront: Z = Q W0 - b0 (beads x ND times ND x HP) and dU/dq = DZ W0^T
+// (beads x HP times HP x ND) as FP32 16x16x4 MFMAs.  The lanes hold one bead
+// each, the MFMA operands a 16 x 4 tile of beads x k (lane l: row l % 16,
+// column l / 16) and a 4 x 16 tile of k x columns (lane l: row l / 16, column
+// l % 16), the results a 16 x 16 tile (lane l: rows 4 (l / 16) .. + 3, column
+// l % 16); the layouts are exchanged through LDS.
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int MF_WROWS = 48;  // W0 rows staged: ND = 37 padded to three 16-row tiles (zeros)
+// LDS row stride (floats) of a wavefront's bead tile: the descriptor rows,
+// then in the same 16-row blocks the hidden-unit gradients [HP][16] and the
+// descriptor gradients [48][16]
+template <int HP>
+__host__ __device__ constexpr int mf_stride() { return HP > 48 ? HP + 4 : 52; }
+template <int HP>
+__host__ __device__ constexpr int mf_lds_floats(int waves) {
+    return MF_WROWS * (HP + 1) + waves * (64 * mf_stride<HP>() + 64);
+}
+
+// stage W0 (one type) as [48][HP + 1] (the pad column spreads the columns of
+// the backward operand over the banks); rows past ND are zero
+template <int HP>
+__device__ __forceinline__ void mf_stage_w0(const float *__restrict__ ann, float *w0s) {
+    for (int e = threadIdx.x; e < MF_WROWS * HP; e += blockDim.x) {
+        const int r = e / HP, c = e % HP;
+        w0s[r * (HP + 1) + c] = r < ND ? ann[r * HP + c] : 0.0f;
+    }
+}
+
+template <int HP>
+__device__ __forceinline__ void network_mfma(const const_fp TB, const const_fp AN, const float S[1][KB],
+                                             float A[NA][LM], float *U_out, float4 *bvec_out, bool take,
+                                             const float *w0s, float *wl) {
+    constexpr int QS = mf_stride<HP>();
+    constexpr int NT16 = HP / 16;
+    const int lane = __lane_id();
+    const int r16 = lane & 15, g4 = lane >> 4;
+    float *us = wl + 64 * QS;  // per-bead sums of w1 h
+    asm volatile("" ::: "memory");
+    // descriptor of this lane's bead into its row (q_37..39 = 0 pad the last k step)
+    {
+        float *row = wl + lane * QS;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const const_fp cRq = opaque(TB + q * KB);
+            float qv = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KB; ++k) qv += cRq[k] * S[0][k];
+            row[q] = qv;
+        }
+#pragma unroll
+        for (int L = 1; L <= 4; ++L)
+#pragma unroll
+            for (int q = 0; q < NA; ++q) {
+                float qv = 0.0f;
+#pragma unroll
+                for (int l = 0; l < LM; ++l)
+                    if (lm_l(l) == L) qv += N2[l] * A[q][l] * A[q][l];
+                row[NR + (L - 1) * NA + q] = qv;
+            }
+        row[ND] = row[ND + 1] = row[ND + 2] = 0.0f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // forward, 16 beads at a time; the tile's hidden-unit gradients replace its
+    // descriptor rows once they are read
+    float b0c[NT16], w1c[NT16];
+#pragma unroll
+    for (int nt = 0; nt < NT16; ++nt) {
+        b0c[nt] = AN[ND * HP + 16 * nt + r16];
+        w1c[nt] = AN[(ND + 1) * HP + 16 * nt + r16];
+    }
+#pragma unroll 1
+    for (int mt = 0; mt < 4; ++mt) {
+        float *tile = wl + mt * 16 * QS;
+        v4f C[NT16];
+#pragma unroll
+        for (int nt = 0; nt < NT16; ++nt) C[nt] = v4f{-b0c[nt], -b0c[nt], -b0c[nt], -b0c[nt]};
+#pragma unroll
+        for (int ks = 0; ks < 10; ++ks) {
+            const float av = tile[r16 * QS + 4 * ks + g4];
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt)
+                C[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, w0s[(4 * ks + g4) * (HP + 1) + 16 * nt + r16],
+                                                             C[nt], 0, 0, 0);
+        }
+        float u[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int nt = 0; nt < NT16; ++nt) {
+            float dz[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float h = tanh_nobranch(C[nt][v]);
+                u[v] += w1c[nt] * h;
+                dz[v] = w1c[nt] * (1.0f - h * h);
+            }
+            // [m][16 beads] of the tile
+            *reinterpret_cast<float4 *>(tile + (16 * nt + r16) * 16 + 4 * g4) = make_float4(dz[0], dz[1], dz[2], dz[3]);
+        }
+        // sum over the hidden units: the 16 lanes of a column group hold them
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) u[v] += __shfl_xor(u[v], o, 16);
+        if (r16 == 0) *reinterpret_cast<float4 *>(us + 16 * mt + 4 * g4) = make_float4(u[0], u[1], u[2], u[3]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // backward: dU/dq = DZ W0^T, 16 beads at a time, written back as [48][16 beads]
+#pragma unroll 1
+    for (int mt = 0; mt < 4; ++mt) {
+        float *tile = wl + mt * 16 * QS;
+        v4f D[3] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int ks = 0; ks < HP / 4; ++ks) {
+            const float av = tile[(4 * ks + g4) * 16 + r16];
+#pragma unroll
+            for (int nt = 0; nt < 3; ++nt)
+                D[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, w0s[(16 * nt + r16) * (HP + 1) + 4 * ks + g4], D[nt],
+                                                             0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int nt = 0; nt < 3; ++nt)
+            *reinterpret_cast<float4 *>(tile + (16 * nt + r16) * 16 + 4 * g4) =
+                make_float4(D[nt][0], D[nt][1], D[nt][2], D[nt][3]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // back to one bead per lane: dU/dq of this lane's bead
+    const float *dq = wl + (lane >> 4) * 16 * QS + (lane & 15);  // dq[nu] = dq[nu * 16]
+    if (take) *U_out = us[lane] - AN[ND * HP + 2 * HP];
+    float dr[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) dr[q] = dq[q * 16];
+#pragma unroll
+    for (int L = 1; L <= 4; ++L)
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const float g = dq[(NR + (L - 1) * NA + q) * 16];
+#pragma unroll
+            for (int l = 0; l < LM; ++l)
+                if (lm_l(l) == L) A[q][l] *= 2.0f * N2[l] * g;
+        }
+    asm volatile("" ::: "memory");
+    // radial back-propagation coefficients
+    float be[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) be[k] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const const_fp cRq = opaque(TB + q * KB);
+#pragma unroll
+        for (int k = 0; k < KB; ++k) be[k] += dr[q] * cRq[k];
+    }
+    if (take) {
+        bvec_out[0] = make_float4(be[0], be[1], be[2], be[3]);
+        bvec_out[1] = make_float4(be[4], be[5], be[6], be[7]);
+        bvec_out[2] = make_float4(be[8], 0.0f, 0.0f, 0.0f);
+    }
+}
+
 // One centre bead of the fused kernel: both passes over its list and the
 // network.  The cutoff tables are passed apart from the arguments so that they
 // stay in kernel-argument memory (they are indexed by the lane's type pair).  Called with the lanes of beads that exist; for several types the
 // lanes of one wave take part in the waterfall over centre types together.
-template <int NT, int HP>
+// MF: the network on the matrix cores (one type; every lane of the wave calls
+// with its bead, a lane past the system's end with valid = false, which keeps
+// it out of the passes and the outputs); w0s and wl: the staged W0 and the
+// wavefront's scratch in LDS.
+template <int NT, int HP, bool MF = false>
 __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, const table_ptr<NT> TB,
-                                          const int i) {
+                                          const int i, const bool valid = true, const float *w0s = nullptr,
+                                          float *wl = nullptr) {
     const int n = a.n;
     const float4 pi = a.pos4[i];
     const int ti = (NT == 1) ? 0 : (int)pi.w;
-    const int cR = a.cnt[i];
-    const int cA = a.cnt[n + i];
+    const int cR = valid ? a.cnt[i] : 0;
+    const int cA = valid ? a.cnt[n + i] : 0;
 
     float S[NT][KB];
     float A[NA][LM];
@@ -316,7 +492,10 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
     // ---------------- descriptor, network (Eq. 2), back-propagation ----------------
     // evaluated with a wave-uniform centre type so the weights are scalar loads;
     // several types in one wave are handled one after the other
-    if constexpr (NT == 1) {
+    if constexpr (MF) {
+        static_assert(NT == 1, "the matrix-core network takes one bead type");
+        network_mfma<HP>((const_fp)a.tab, (const_fp)a.ann, S, A, a.U + i, a.bvec + (size_t)i * 3, valid, w0s, wl);
+    } else if constexpr (NT == 1) {
         network<NT, HP>(0, (const_fp)a.tab, (const_fp)a.ann, S, A, a.U + i, a.bvec + (size_t)i * NT * 3);
     } else {
         // the lane test goes through the ballot bit, not ti == tu, so the
@@ -392,7 +571,7 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
         fy += oy;
         fz += oz;
     }
-    a.fown[i] = make_float4(fx, fy, fz, 0.0f);
+    if (valid) a.fown[i] = make_float4(fx, fy, fz, 0.0f);
 }
 
 // Force and per-site virial of one bead from the pair terms of both beads of

@@ -47,6 +47,7 @@ struct Model {
     int HP;           // hidden width padded to a built size (8, 16, 32 or 64)
     size_t n_params;
     int device;
+    int mfma;         // 1: the network of the single-system fused kernel on the matrix cores
 };
 
 // Cutoff tables passed by value.
@@ -284,7 +285,10 @@ __device__ __forceinline__ int lm_l(int lm) { return lm < 3 ? 1 : lm < 8 ? 2 : l
 // launchers (defined in the .hip files)
 hipError_t launch_pack(int n, int T, const float *x, const float *y, const float *z, const uint8_t *type,
                        float4 *pos4, hipStream_t s);
-hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds_bytes, hipStream_t s);
+// mfma: the network on the matrix cores (one type, HP 16, 32 or 64; see
+// efv_main_mfma_supported)
+hipError_t launch_efv_main(int T, int HP, const EfvArgs &a, size_t lds_bytes, hipStream_t s, bool mfma = false);
+bool efv_main_mfma_supported(int T, int HP);
 // md: 0 plain evaluation, 1 NVE step (second half-kick and commit fused in),
 // 2 ensemble step (forces, per-bead virial and, with hn, the HNEMD drive; the
 // kick follows in the ensemble kernels)

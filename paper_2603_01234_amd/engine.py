@@ -40,6 +40,13 @@ class Model:
     def from_spec(cls, spec, params):
         return cls(spec.n_types, spec.n_hidden, spec.rc_R, spec.rc_A, params)
 
+    def set_network(self, engine: str) -> "Model":
+        """'valu' (default) or 'mfma': the network of the single-system fused
+        kernel on the vector ALUs or on the FP32 matrix cores."""
+        code = B.nep_model_set_network(self.handle, {"valu": B.NEP_NETWORK_VALU, "mfma": B.NEP_NETWORK_MFMA}[engine])
+        B.check(code)
+        return self
+
     def close(self):
         if self.handle:
             B.nep_model_destroy(self.handle)
