@@ -95,6 +95,25 @@ def test_reverse_index_points_at_the_mirrored_entry(case):
     assert check_reverse(rep, range(system.n)) > 0
 
 
+def test_neighbor_sets_crowded_cells():
+    """A dense box on a coarse grid (two whole cells per axis): cells of about
+    75 beads (more than the row kernel stages in LDS) and neighbourhoods of
+    about 2,000 candidates (several register windows per bead)."""
+    rng = np.random.default_rng(21)
+    spec = W.water_spec(8)
+    params = W.draw_params(spec, rng)
+    L = 1.9
+    pos = W.small_cluster(rng, 600, box=L, min_dist=0.1) % L
+    sysm = W.System(pos, np.zeros(600, np.uint8), np.array([L, L, L]), np.array([True, True, True]),
+                    np.array([W.WATER_MASS]))
+    rep = _replica(spec, params, sysm, skin=0.1)
+    rep.build()
+    _check_sets(rep, spec, sysm, 0.1, range(sysm.n))
+    assert check_reverse(rep, range(sysm.n)) > 0
+    rep.efv()
+    compare_efv(rep, _oracle(spec, params, rep, sysm), sysm.n, label="crowded")
+
+
 def test_neighbor_predicate_is_never_fused():
     """Pairs at the radial and the angular list cutoff where a fused
     multiply-add and separate rounding of d2 disagree, each far from the others
