@@ -642,7 +642,9 @@ __device__ __forceinline__ void nb_order_body(const NbArgs &a, int bx, int gx) {
 __global__ __launch_bounds__(BLOCK) void k_nb_order(NbArgs a) { nb_order_body(a, blockIdx.x, gridDim.x); }
 
 // ---- 5. reverse ----
-// angular slots per thread: p = by + k gy for slot group by of gy
+// REV_GY slot groups per block of beads: the thread of slot group by takes the
+// angular slots by, by + REV_GY, ... of its bead, REV_SLOTS of them at a time
+constexpr int REV_GY = 8;
 constexpr int REV_SLOTS = 2;
 // 16-byte key groups of the neighbour's row read together with its header
 constexpr int REV_GROUPS = 2;
@@ -678,62 +680,63 @@ __device__ __forceinline__ int find_key_from(const uint32_t *ar, int A4, bool do
 // wave handle consecutive beads at the same slots.  The workgroups of one
 // block of beads (its slot groups) are consecutive tiles, kept on one XCD, so
 // the neighbours' rows they read stay in that XCD's L2.
-__device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int tile, int gy) {
+__device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int tile) {
     if (build_off(a)) return;
     const int n = a.n;
-    const int by = tile % gy;
-    const int i = (tile / gy) * BLOCK + threadIdx.x;
+    const int by = tile % REV_GY;
+    const int i = (tile / REV_GY) * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int na = a.cnt[n + i];
-    if (by >= na) return;
     const int A4 = (a.cap_A + 3) & ~3;
     const int nai_i = min(a.cls[i] & 255, na);
-    int p[REV_SLOTS], j[REV_SLOTS];
-    uint32_t want[REV_SLOTS];
-    bool sh[REV_SLOTS];
+    for (int p0 = by; p0 < na; p0 += REV_GY * REV_SLOTS) {
+        int p[REV_SLOTS], j[REV_SLOTS];
+        uint32_t want[REV_SLOTS];
+        bool sh[REV_SLOTS];
 #pragma unroll
-    for (int k = 0; k < REV_SLOTS; ++k) {
-        p[k] = by + k * gy;
-        const bool v = p[k] < na;
-        j[k] = v ? (int)(a.nbr[(size_t)p[k] * n + i] & J_MASK) : 0;
-        want[k] = v ? (uint32_t)a.rev[(size_t)p[k] * n + i] : 0u;
-        sh[k] = p[k] >= nai_i;
-    }
-    uint4 hd[REV_SLOTS], g[REV_SLOTS][REV_GROUPS];
-#pragma unroll
-    for (int k = 0; k < REV_SLOTS; ++k) {
-        const uint32_t *ar = a.arow + (size_t)j[k] * (4 + A4);
-        hd[k] = *reinterpret_cast<const uint4 *>(ar);
-#pragma unroll
-        for (int c = 0; c < REV_GROUPS; ++c)
-            g[k][c] = 4 * c < A4 ? *reinterpret_cast<const uint4 *>(sh[k] ? ar + 4 + A4 - 4 * (c + 1) : ar + 4 + 4 * c)
-                                 : make_uint4(0u, 0u, 0u, 0u);
-    }
-#pragma unroll
-    for (int k = 0; k < REV_SLOTS; ++k) {
-        if (p[k] >= na) continue;
-        const uint32_t *ar = a.arow + (size_t)j[k] * (4 + A4);
-        const int nai_j = (int)hd[k].x, na_j = (int)hd[k].y;
-        const int len = sh[k] ? na_j - nai_j : nai_j;
-        int found = -1;
-#pragma unroll
-        for (int c = 0; c < REV_GROUPS; ++c)
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (4 * c + u < len && group_key(g[k][c], u, sh[k]) == want[k]) found = 4 * c + u;
-        bool shell = sh[k];
-        if (found < 0 && len > 4 * REV_GROUPS) found = find_key_from(ar, A4, shell, len, REV_GROUPS, want[k]);
-        if (found < 0) {
-            shell = !shell;
-            found = find_key_from(ar, A4, shell, shell ? na_j - nai_j : nai_j, 0, want[k]);
+        for (int k = 0; k < REV_SLOTS; ++k) {
+            p[k] = p0 + k * REV_GY;
+            const bool v = p[k] < na;
+            j[k] = v ? (int)(a.nbr[(size_t)p[k] * n + i] & J_MASK) : 0;
+            want[k] = v ? (uint32_t)a.rev[(size_t)p[k] * n + i] : 0u;
+            sh[k] = p[k] >= nai_i;
         }
-        const int slot = found < 0 ? -1 : (shell ? nai_j + found : found);
-        a.rev[(size_t)p[k] * n + i] = slot < 0 ? -1 : (int32_t)((size_t)slot * n + j[k]);
+        uint4 hd[REV_SLOTS], g[REV_SLOTS][REV_GROUPS];
+#pragma unroll
+        for (int k = 0; k < REV_SLOTS; ++k) {
+            const uint32_t *ar = a.arow + (size_t)j[k] * (4 + A4);
+            hd[k] = *reinterpret_cast<const uint4 *>(ar);
+#pragma unroll
+            for (int c = 0; c < REV_GROUPS; ++c)
+                g[k][c] = 4 * c < A4 ? *reinterpret_cast<const uint4 *>(sh[k] ? ar + 4 + A4 - 4 * (c + 1) : ar + 4 + 4 * c)
+                                     : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < REV_SLOTS; ++k) {
+            if (p[k] >= na) continue;
+            const uint32_t *ar = a.arow + (size_t)j[k] * (4 + A4);
+            const int nai_j = (int)hd[k].x, na_j = (int)hd[k].y;
+            const int len = sh[k] ? na_j - nai_j : nai_j;
+            int found = -1;
+#pragma unroll
+            for (int c = 0; c < REV_GROUPS; ++c)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (4 * c + u < len && group_key(g[k][c], u, sh[k]) == want[k]) found = 4 * c + u;
+            bool shell = sh[k];
+            if (found < 0 && len > 4 * REV_GROUPS) found = find_key_from(ar, A4, shell, len, REV_GROUPS, want[k]);
+            if (found < 0) {
+                shell = !shell;
+                found = find_key_from(ar, A4, shell, shell ? na_j - nai_j : nai_j, 0, want[k]);
+            }
+            const int slot = found < 0 ? -1 : (shell ? nai_j + found : found);
+            a.rev[(size_t)p[k] * n + i] = slot < 0 ? -1 : (int32_t)((size_t)slot * n + j[k]);
+        }
     }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
-    nb_reverse_body(a, xcd_tile(blockIdx.x, gridDim.x), (a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
+    nb_reverse_body(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 hipError_t launch_build(const NbArgs &a, hipStream_t s) {
@@ -753,7 +756,7 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     if (a.T > 1) hipLaunchKernelGGL(k_nb_rows<true>, dim3(a.ncell), dim3(64), lds, s, a);
     else hipLaunchKernelGGL(k_nb_rows<false>, dim3(a.ncell), dim3(64), lds, s, a);
     if (a.order) hipLaunchKernelGGL(k_nb_order, dim3(nbk), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_nb_reverse, dim3(nbk * ((a.cap_A + REV_SLOTS - 1) / REV_SLOTS)), dim3(BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_nb_reverse, dim3(nbk * REV_GY), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -796,7 +799,7 @@ __global__ __launch_bounds__(BLOCK) void k_nb_batch(NbBatchArgs b) {
     if constexpr (OP == OP_RANK) nb_rank_body(a, bx);
     if constexpr (OP == OP_ORDER) nb_order_body(a, bx, gx);
     if constexpr (OP == OP_REVERSE) {
-        nb_reverse_body(a, xcd_tile(bx, gx), (a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
+        nb_reverse_body(a, xcd_tile(bx, gx));
     }
 }
 
@@ -822,7 +825,7 @@ void nb_batch_tiles(const NbArgs &a, int counts[NB_BATCH_TILES]) {
     counts[NB_TILE_BEAD] = nbk;
     counts[NB_TILE_SCANL] = (a.ncell + SCAN_B - 1) / SCAN_B;
     counts[NB_TILE_SCANA] = cbk;
-    counts[NB_TILE_REV] = nbk * ((a.cap_A + REV_SLOTS - 1) / REV_SLOTS);
+    counts[NB_TILE_REV] = nbk * REV_GY;
     counts[NB_TILE_ROWS] = a.ncell;
 }
 
