@@ -325,7 +325,7 @@ struct RowsLds {
 // per lane), and their classes
 __host__ __device__ __forceinline__ int row_lds_bytes(int cap, int cap_A) {
     const int w = ((cap_A + 3) & ~3) + ((cap + 3) & ~3) + 64;
-    return w * 8 + ((w + 15) & ~15);
+    return (w * 8 + w + 15) & ~15;  // a multiple of 16 bytes
 }
 
 // The row kernel's workgroup is a single wavefront, whose LDS operations
@@ -592,10 +592,15 @@ __device__ __forceinline__ void rows_thresholds(const NbArgs &a, RowsLds &L) {
     if (k < MAXT * MAXT) L.thr[k] = make_float4(a.list2R[k], a.list2A[k], a.in2A[k], a.in2R[k]);
 }
 
-// one workgroup (a single wavefront) per cell, consecutive cells on one XCD.
-// (Measured: a cell per workgroup builds the 216,000-bead lists in 0.22 ms,
-// two, four or eight consecutive cells per workgroup in 0.30-0.44 ms; a
-// wave's cells would run one after another, each a chain of dependent loads.)
+// One workgroup (a single wavefront) per cell, consecutive cells on one XCD;
+// the hardware dispatcher balances the cells' uneven work as it goes.
+// Measured on the 216,000-bead lists (a rebuild / a launch that finds no
+// rebuild due): a cell per workgroup 0.24 ms / 15.5 us; two, four or eight
+// single-cell waves per workgroup 0.27 / 0.32 / 0.34 ms and 8.3 / 4.9 / 4.9 us
+// (a workgroup's LDS is held until its busiest cell is done); two, four or
+// eight consecutive cells per wavefront 0.30-0.44 ms; a persistent grid taking
+// cells from per-XCD counters 0.85 ms / 4.6 us (device-scope atomics from all
+// XCDs on one line serialise).
 template <bool MT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_nb_rows(NbArgs a) {
     extern __shared__ __align__(16) uint32_t row_dyn[];
