@@ -289,14 +289,13 @@ __device__ __forceinline__ bool wrap_cell(int k, int nc, int pbc, int &kw, int &
 // lane `lane`, batch k), in the fixed order of the search (offset in
 // (dz, dy, dx) order, then cell order), each shifted by the periodic image of
 // its offset and tagged with its list entry and its sort key; then it tests
-// every bead of the cell against them, the lanes over the candidates.  The
-// entries of each class are appended in search order (a ballot per class and
-// each lane's count of the set bits below it), so a row is the same, entry
-// for entry, as a walk over the cells in that order.  A home bead's row is
-// assembled in LDS in four stacks (angular inside r_c^A up from 0, angular
-// shell down from A4-1, radial inside r_c^R up from A4, radial shell down
-// from A4+R4-1) and written out in class order: slot-major into the list, and
-// the angular keys row-major for the reverse search.
+// every bead of the cell against them, the lanes over the candidates.  A home
+// bead's entries are appended in LDS in search order with their class (one
+// ballot per 64 candidates and each lane's count of the set bits below it),
+// and written out by class (angular inside r_c^A, angular shell, radial-only
+// inside r_c^R, radial shell; search order within a class): slot-major into
+// the list, and the angular keys row-major for the reverse search.  A row is
+// thus the same, entry for entry, as a walk over the cells in that order.
 //
 // The key of an entry is its neighbour-cell offset index o (0..W-1 in search
 // order) << 25 | the neighbour's position in cell order; within each class
