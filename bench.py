@@ -6,9 +6,11 @@ the 216,000-bead CG water-like box (60^3 jittered simple-cubic lattice at
 33.4 beads/nm^3, Maxwell 300 K), NEP with radial/angular cutoffs 0.8/0.5 nm,
 Chebyshev basis 8, n_max 8/6, l_max 4, 30 tanh neurons, random N(0, 0.1^2)
 weights; dt = 2 fs, 18 amu; neighbour lists rebuilt every 10 steps on a
-0.1 nm skin, and earlier whenever the two largest displacements since the
-last build add up to 0.99 skin (no pair can be missing before); beads put back
-into cell order every 100 steps.  Each step: half-kick + drift, [wrap +
+0.1 nm skin, and earlier once the two largest displacements since the last
+build add up to 0.99 skin (no pair can be missing before) and a pair test then
+finds a pair inside a cutoff that was outside the list cutoff at the build
+(--plain-skin-test: rebuilt at the first condition alone); beads put back into
+cell order every 100 steps.  Each step: half-kick + drift, [wrap +
 rebuild], fused descriptor/network/angular-force kernel, gather kernel
 (forces + second half-kick + energy sums), FP64 energy reduction.
 
@@ -561,6 +563,8 @@ def main():
                     help="engine of the fused kernel's network (Eq. 2): vector ALUs or FP32 matrix cores")
     ap.add_argument("--no-network-legs", action="store_true",
                     help="skip the comparison of the two network engines on the timed state")
+    ap.add_argument("--plain-skin-test", action="store_true",
+                    help="MD rebuild gate: the two-largest-displacements test alone, without the pair test")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for the HBM counters)")
     args = ap.parse_args()
@@ -589,6 +593,7 @@ def main():
         fr.md(5, dt, masses, rebuild_every=every)          # first-launch costs, not part of the run
         fr = engine.Replica(model, system.pos_f32(), system.types, system.box, system.pbc,
                             skin=opts["skin"], vel=system.vel)
+        fr.pair_test = not args.plain_skin_test
         fr.efv(per_bead_virial=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -607,6 +612,7 @@ def main():
     pre = args.pre_steps if args.pre_steps >= 0 else max(0, (opts["steps"] - K) // 2 - args.warmup)
     rep = engine.Replica(model, system.pos_f32(), system.types, system.box, system.pbc,
                          skin=opts["skin"], vel=system.vel)
+    rep.pair_test = not args.plain_skin_test
     rep.efv(per_bead_virial=False)          # lists + forces at t = 0
     if pre + args.warmup:
         rep.md(pre + args.warmup, dt, masses, rebuild_every=every, sort_every=args.sort_every)
@@ -699,6 +705,8 @@ def main():
                    "network": args.network,
                    "timed_steps": [step_first, step_first + K - 1],
                    "rebuilds_in_timed_steps": rebuilds,
+                   "rebuild_gate": "two-largest displacements" if args.plain_skin_test else
+                                   "two-largest displacements, then the pair test",
                    "virial": "per-bead and total virial every step (Eqs. 15-16)",
                    "virial_pressure_GPa_last_step": round(float(np.trace(W_last)) / (3 * vol) * 0.1602176634, 4),
                    "F_alg_per_bead_step": round(F_alg_bead, 1),

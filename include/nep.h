@@ -250,7 +250,8 @@ typedef struct {
     int n_steps;              /* steps in this call */
     int rebuild_every;        /* lists are rebuilt after the drift of step s when (s+1) % rebuild_every == 0,
                                  and whenever after a drift the two largest displacements since the build
-                                 add up to more than 0.99 skin */
+                                 add up to more than 0.99 skin, unless the pair test (plain_skin_test)
+                                 then finds every pair inside the cutoffs still listed */
     int force_rebuild;        /* in: rebuild after the first drift whatever the displacement (after the
                                  caller has regrown the lists of a call stopped by an overflow) */
     float mass[4];            /* amu per type */
@@ -287,6 +288,13 @@ typedef struct {
     double *J_trace;          /* device [n_steps][3] or NULL: potential heat current sum_i W_i v_i
                                  after every step (eV nm/fs; with a thermostat, after its scaling) */
     const nep_constraint *constraint;  /* host struct or NULL: constrained bead centres of mass */
+    int plain_skin_test;      /* 0: when the two-largest test fires, the pair test decides: every pair
+                                 with a bead that moved at least half of 0.99 skin since the build and
+                                 now inside an interaction cutoff must have been inside the list cutoff
+                                 at the build (any other pair moved less than 0.99 skin); found through
+                                 the build's cells, so used only after a rebuild within this call, in a
+                                 fully periodic box with every side at least 3 (r_c + skin), without
+                                 strain or barostat.  1: the two-largest test alone */
 } nep_md_params;
 
 /* Advances sys by n_steps of velocity Verlet (the paper's MD runs in an

@@ -107,7 +107,7 @@ class MdParams(ctypes.Structure):
                 ("thermostat", c_int), ("T_target", c_float), ("tau_T", c_float), ("noise", c_void_p),
                 ("barostat", c_int), ("P_target", c_double * 3), ("tau_P", c_double), ("beta", c_double),
                 ("P_in", c_double * 3), ("P_out", c_double * 3), ("Fe", c_float * 3), ("J_trace", c_void_p),
-                ("constraint", POINTER(Constraint))]
+                ("constraint", POINTER(Constraint)), ("plain_skin_test", c_int)]
 
 
 _lib = None

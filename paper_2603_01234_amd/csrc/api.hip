@@ -62,7 +62,7 @@ struct TimedLaunch {
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor, cell_xyz,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, arow, vh, ctrl, top2, ens, partial2, wbuf, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, arow, vh, ctrl, top2, ens, partial2, wbuf, fast, total;
     int ncell_max, nblocks;
 };
 
@@ -106,6 +106,8 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.ens = take(ENS_DOUBLES * sizeof(double));
     L.partial2 = take((nn + BLOCK - 1) / BLOCK * 8 * sizeof(double));
     L.wbuf = take(nn * 9 * sizeof(float));
+    // the pair test of the MD rebuild gate
+    L.fast = take(FAST_WORDS * sizeof(int32_t));
     L.total = off;
     return L;
 }
@@ -1051,7 +1053,14 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
     // since the build add up to more than 0.99 skin (the margin covers the
     // rounding of the list predicate); the build queued right after it runs
     // only then, or when the schedule asks for it
-    HIPCHK(launch_clear_status(nb->status, ctrl, (mp->force_rebuild || scheduled(step0)) ? 1 : 0, st));
+    // the pair test of the rebuild gate: in a fully periodic box whose sides are
+    // at least three list reaches, without strain or barostat
+    const float reach = reach_of(M, nb->skin);
+    bool pair_test = mp->plain_skin_test == 0;
+    for (int d = 0; d < 3; ++d)
+        pair_test = pair_test && s->pbc[d] && s->box[d] >= 3.0f * reach && mp->strain_rate[d] == 0.0 && mu[d] == 1.0;
+    int32_t *fast = pair_test ? at<int32_t>(ws, L.fast) : nullptr;
+    HIPCHK(launch_clear_status(nb->status, ctrl, (mp->force_rebuild || scheduled(step0)) ? 1 : 0, st, fast));
     if (ens) HIPCHK(launch_ensemble_clear(ensbuf, st));
     // per-bead virial of the HNEMD drive and of the constrained beads: the
     // caller's W, else the workspace's
@@ -1085,7 +1094,6 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
                              mp->W_trace ? mp->W_trace + 9 * (size_t)k : nullptr, mp->pair_counts, nb->status, ctrl,
                              scheduled(step0 + k + 1), nullptr, 0.0f, 0.0f, nullptr, st);
     };
-    const float reach = reach_of(M, nb->skin);
     for (int k = 0; k < n_steps; ++k) {
         const int64_t step = step0 + k;
         KickDriftArgs kd{};
@@ -1120,6 +1128,8 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         }
         kd.skin_gate = 0.99f * nb->skin;
         kd.reach = reach;
+        kd.fast = fast;
+        kd.tau2 = 0.25f * kd.skin_gate * kd.skin_gate;
         kd.top2 = at<float2>(ws, L.top2);
         kd.status = nb->status;
         kd.ctrl = ctrl;
@@ -1143,6 +1153,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         a.ctrl = ctrl;
         a.from_pos4 = 1;
         a.skip_clear = 1;
+        a.fast = fast;
         kd.cell_count = a.cell_count;
         kd.ncell = a.ncell;
         {
@@ -1151,6 +1162,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         }
         {
             TimedLaunch tl(2, st);
+            if (fast) HIPCHK(launch_pair_test(a, fast, st));
             HIPCHK(launch_build(a, st));
         }
         // every step evaluates the per-bead and total virial (Eqs. 15-16)

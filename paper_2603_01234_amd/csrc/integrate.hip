@@ -22,6 +22,11 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
         const float k = a.half_dt_accel * a.inv_mass[t];
         d2 = kick_drift_bead(i, a.n, t, k, a.dt, a.lam[0], a.lam[1], a.lam[2], a.x, a.y, a.z, a.v, a.vh, a.F,
                              a.pos4, a.ref);
+        // a bead past tau joins the pair test's list (past FAST_CAP only counted)
+        if (a.fast && d2 >= a.tau2) {
+            const int q = atomicAdd(&a.fast[0], 1);
+            if (q < FAST_CAP) a.fast[4 + q] = i;
+        }
     }
     const float2 t = block_top2(d2, 0.0f);
     if (threadIdx.x == 0) a.top2[blockIdx.x] = t;
@@ -30,7 +35,9 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
 // one workgroup: the previous step's reduction (which also sets the gate to
 // the schedule), then the rebuild test over the pairs of the drift's workgroups
 // with the affine shrink of the lists' compression factor sigma, updated by
-// this step's scale factors (and reset to 1 when the step rebuilds)
+// this step's scale factors (and reset to 1 when the step rebuilds).  When the
+// test fires and the pair test can decide instead, the gate is 2; the drift's
+// list count is handed to the check and reset for the next step.
 __global__ __launch_bounds__(BLOCK) void k_gate(KickDriftArgs a, int nblocks) {
     if (a.prev_partial)
         reduce_partials(a.prev_partial, a.prev_blocks, nullptr, nullptr, nullptr, a.prev_E, a.prev_K, a.prev_W,
@@ -40,7 +47,16 @@ __global__ __launch_bounds__(BLOCK) void k_gate(KickDriftArgs a, int nblocks) {
     if (threadIdx.x == 0) {
         const float lmin = fminf(1.0f, fminf(a.lam[0], fminf(a.lam[1], a.lam[2])));
         const float sig = sigma_of(a.status[3]) * lmin;
-        if (past_skin(t, a.skin_gate, (1.0f - sig) * a.reach)) a.ctrl[0] = 1;
+        int listed = 0;
+        if (a.fast) {
+            listed = a.fast[0];
+            a.fast[0] = 0;
+            a.fast[3] = listed;
+        }
+        if (a.ctrl[0] != 1 && past_skin(t, a.skin_gate, (1.0f - sig) * a.reach)) {
+            const bool pair_test = a.fast && sig == 1.0f && a.fast[1] != 0 && listed <= FAST_CAP;
+            a.ctrl[0] = pair_test ? 2 : 1;
+        }
         a.status[3] = a.ctrl[0] ? SIGMA_ONE : __float_as_int(sig);
     }
 }

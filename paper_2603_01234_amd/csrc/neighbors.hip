@@ -35,11 +35,11 @@ __device__ __forceinline__ float mul_rn(float a, float b) { return a * b; }
 __device__ __forceinline__ float add_rn(float a, float b) { return a + b; }
 __device__ __forceinline__ float sub_rn(float a, float b) { return a - b; }
 
-// A build inside an MD run is skipped when neither the drift's rebuild test
-// nor the schedule asked for one (ctrl[0] == 0), and once the run is frozen
-// after a failed build.  The test is uniform over the grid.
+// A build inside an MD run is skipped unless the drift's rebuild test, the
+// pair test or the schedule asked for one (ctrl[0] == 1), and once the run is
+// frozen after a failed build.  The test is uniform over the grid.
 __device__ __forceinline__ bool build_off(const int32_t *ctrl, const int32_t *status, int clear_status) {
-    if (ctrl && ctrl[0] == 0) return true;
+    if (ctrl && ctrl[0] != 1) return true;
     return !clear_status && (status[0] & FREEZE_MASK);
 }
 __device__ __forceinline__ bool build_off(const NbArgs &a) { return build_off(a.ctrl, a.status, a.clear_status); }
@@ -62,15 +62,17 @@ __global__ void k_nb_clear(int ncell, int32_t *cell_count, int32_t *status, int 
 }
 
 // start of an MD call: flags and maxima cleared, sigma (status[3]) kept, since
-// it belongs to the lists, which the call continues from
-__global__ void k_md_clear(int32_t *status, int32_t *ctrl, int gate0) {
+// it belongs to the lists, which the call continues from; the pair test's
+// words cleared (its cell data must come from a build of this call)
+__global__ void k_md_clear(int32_t *status, int32_t *ctrl, int gate0, int32_t *fast) {
     int t = threadIdx.x;
     if (t < 3) status[t] = 0;
     if (ctrl && t < 4) ctrl[t] = t == 0 ? gate0 : 0;
+    if (fast && t < 4) fast[t] = 0;
 }
 
-hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, int gate0, hipStream_t s) {
-    hipLaunchKernelGGL(k_md_clear, dim3(1), dim3(64), 0, s, status, ctrl, gate0);
+hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, int gate0, hipStream_t s, int32_t *fast) {
+    hipLaunchKernelGGL(k_md_clear, dim3(1), dim3(64), 0, s, status, ctrl, gate0, fast);
     return hipGetLastError();
 }
 
@@ -112,7 +114,10 @@ __device__ __forceinline__ float wrap_coord(float x, float L) {
 
 __device__ __forceinline__ void nb_bin_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
-    if (a.skip_clear && a.ctrl && bx == 0 && threadIdx.x == 0) a.ctrl[1] += 1;  // the clear phase's count
+    if (bx == 0 && threadIdx.x == 0) {
+        if (a.skip_clear && a.ctrl) a.ctrl[1] += 1;  // the clear phase's count
+        if (a.fast) a.fast[1] = 1;                  // the pair test may use this build's cells
+    }
     int i = bx * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     float p[3];
@@ -741,6 +746,104 @@ __device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int tile) {
 
 __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
     nb_reverse_body(a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// The pair test of the rebuild gate (the reasoning is with FAST_WORDS): one
+// wavefront per listed bead i.  The lanes take the cells around i's present
+// position in the build's grid (i has moved, the other beads of a pair found
+// this way by less than tau), then the other listed beads.  For every pair
+// now inside an interaction cutoff (with the margin: a pair at the edge
+// counts as inside) the build-time distance, from the build positions with
+// the same image, must lie inside the list cutoff by the margin; otherwise
+// the gate becomes 1 and the build runs.
+constexpr int PAIR_TEST_BLOCKS = 64;
+
+__device__ __forceinline__ bool pair_covered(const NbArgs &a, int tp, const float v[3], const float b[3]) {
+    const float d2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const float up = 1.0f + PAIR_TEST_MARGIN, down = 1.0f - PAIR_TEST_MARGIN;
+    if (!(d2 < a.in2R[tp] * up)) return true;  // outside both interaction cutoffs
+    const float b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    if (!(b2 < a.list2R[tp] * down)) return false;
+    if (d2 < a.in2A[tp] * up && !(b2 < a.list2A[tp] * down)) return false;
+    return true;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_pair_test(NbArgs a, const int32_t *fast) {
+    if (a.ctrl[0] != 2 || (a.status[0] & FREEZE_MASK)) return;  // uniform
+    const int cnt = min(fast[3], FAST_CAP);
+    const int lane = __lane_id();
+    const int nw = gridDim.x * (BLOCK / 64);
+    const int n = a.n;
+    bool bad = false;
+    for (int f = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); f < cnt; f += nw) {
+        const int i = fast[4 + f];
+        const float4 pi = a.pos4[i];
+        const int ti = min((int)pi.w, a.T - 1);
+        const float p[3] = {pi.x, pi.y, pi.z};
+        const float r[3] = {a.ref[i], a.ref[n + i], a.ref[2 * n + i]};
+        // i's present cell, and the boxes w it has drifted from the build's frame
+        int c[3], w[3];
+        for (int d = 0; d < 3; ++d) {
+            const float L = a.box[d];
+            float k = floorf(p[d] / L);
+            float x = p[d] - k * L;
+            if (x >= L) { x -= L; k += 1.0f; }
+            if (x < 0.0f) { x += L; k -= 1.0f; }
+            w[d] = (int)k;
+            c[d] = cell_coord(x, a.inv_cs[d], a.nc[d]);
+        }
+        const int wx = 2 * a.m[0] + 1, wy = 2 * a.m[1] + 1, wz = 2 * a.m[2] + 1;
+        for (int o = lane; o < wx * wy * wz; o += 64) {
+            const int o3[3] = {o % wx - a.m[0], (o / wx) % wy - a.m[1], o / (wx * wy) - a.m[2]};
+            int cc[3], img[3];
+            for (int d = 0; d < 3; ++d) {
+                cc[d] = c[d] + o3[d];
+                img[d] = w[d];
+                if (cc[d] < 0) { cc[d] += a.nc[d]; img[d] -= 1; }
+                if (cc[d] >= a.nc[d]) { cc[d] -= a.nc[d]; img[d] += 1; }
+            }
+            const int id = cell_index(cc[0], cc[1], cc[2], a.nc);
+            const int e = a.cell_start[id + 1];
+            for (int q = a.cell_start[id]; q < e; ++q) {
+                const float4 b = a.pos_sorted[q];  // the build position, and index | type << 25
+                const uint32_t tag = __float_as_uint(b.w);
+                const int j = (int)(tag & J_MASK);
+                if (j == i) continue;
+                const float4 pj = a.pos4[j];
+                const int tp = ti * a.T + min((int)(tag >> CODE_SHIFT), a.T - 1);
+                const float bj[3] = {b.x, b.y, b.z}, qj[3] = {pj.x, pj.y, pj.z};
+                float v[3], bv[3];
+                for (int d = 0; d < 3; ++d) {
+                    const float sh = (float)img[d] * a.box[d];
+                    v[d] = (qj[d] + sh) - p[d];
+                    bv[d] = (bj[d] + sh) - r[d];
+                }
+                if (!pair_covered(a, tp, v, bv)) bad = true;
+            }
+        }
+        // pairs of two listed beads, by the nearest image of their present positions
+        for (int g = lane; g < cnt; g += 64) {
+            const int j = fast[4 + g];
+            if (j == i) continue;
+            const float4 pj = a.pos4[j];
+            const float qj[3] = {pj.x, pj.y, pj.z};
+            const float rj[3] = {a.ref[j], a.ref[n + j], a.ref[2 * n + j]};
+            float v[3], bv[3];
+            for (int d = 0; d < 3; ++d) {
+                const float sh = -rintf((qj[d] - p[d]) / a.box[d]) * a.box[d];
+                v[d] = (qj[d] + sh) - p[d];
+                bv[d] = (rj[d] + sh) - r[d];
+            }
+            if (!pair_covered(a, ti * a.T + min((int)pj.w, a.T - 1), v, bv)) bad = true;
+        }
+    }
+    if (bad) a.ctrl[0] = 1;  // every writer stores the same value
+}
+
+hipError_t launch_pair_test(const NbArgs &a, const int32_t *fast, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_test, dim3(PAIR_TEST_BLOCKS), dim3(BLOCK), 0, s, a, fast);
+    return hipGetLastError();
 }
 
 hipError_t launch_build(const NbArgs &a, hipStream_t s) {

@@ -335,8 +335,13 @@ struct NbArgs {
     int from_pos4;     // 1 (MD): positions come from pos4 and are wrapped there, x/y/z are untouched
     int skip_clear;    // 1 (MD): the drift kernel of the step already zeroed the cell counts, so no
                        // clearing launch; the bin phase then counts the rebuild in ctrl[1]
+    int32_t *fast;     // MD with the pair test (see FAST_WORDS) or null: the bin phase marks the
+                       // cell data as this call's
 };
 hipError_t launch_build(const NbArgs &a, hipStream_t s);
+// the pair test of the rebuild gate (see FAST_WORDS), on the build's cell data;
+// a no-op unless the gate is 2
+hipError_t launch_pair_test(const NbArgs &a, const int32_t *fast, hipStream_t s);
 // Builds of many systems, one launch per phase: args[r] as for launch_build
 // (systems with n > 0); start holds the tables of first blocks written by
 // the caller from nb_batch_tiles; totals are the last entries of the tables.
@@ -354,7 +359,8 @@ hipError_t launch_build_batch(const NbBatchArgs &b, const int totals[NB_BATCH_TI
 
 // zeroes the status word and, when given, the MD control words [4] (the
 // rebuild gate ctrl[0] is set to gate0)
-hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, int gate0, hipStream_t s);
+hipError_t launch_clear_status(int32_t *status, int32_t *ctrl, int gate0, hipStream_t s,
+                               int32_t *fast = nullptr);
 
 // First half of a velocity-Verlet step.  Reads x, v, F; writes the half-step
 // velocities to vh and the drifted (and strained) positions to pos4, leaving
@@ -391,12 +397,35 @@ struct KickDriftArgs {
     int prev_blocks;
     double *prev_E, *prev_K, *prev_W, *counts;
     int next_gate;          // the schedule's gate for this step's build
+    int32_t *fast;          // or null: the pair test's words (FAST_WORDS); beads whose squared
+    float tau2;             // displacement reaches tau2 are listed for it
 };
 // the drift, then one workgroup that merges the blocks' pairs and switches
 // the rebuild gate on when they call for a rebuild
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s);
 
 // ---- the rebuild test ----
+// Gate values (ctrl[0]): 0 no build, 1 build, 2 the pair test decides (the
+// build runs only if the test turns the gate to 1).
+//
+// The pair test.  Call tau = skin_gate / 2.  Two beads that have both moved
+// less than tau since the build have a pair distance changed by less than
+// skin_gate, so such a pair is covered by the lists.  Every other pair has a
+// bead that moved at least tau; the drift lists those beads, and when the
+// two-largest test fires the check kernel looks at every pair of a listed
+// bead that is now inside an interaction cutoff: it must have been inside the
+// list cutoff at the build (then both rows hold it), with a relative margin
+// for the rounding of the list predicate.  Candidates are found through the
+// build's cell data (a bead that moved less than tau is still within reach of
+// the cells it was binned in) and, for pairs of two listed beads, through the
+// list itself.  The test is used only within an MD call whose lists were built
+// by that call, in a fully periodic box with every side at least three times
+// the list reach, without strain or barostat; otherwise the gate is 1.
+// Words: [0] beads listed by this step's drift, [1] cell data of this call's
+// build present, [2] unused, [3] the count the check reads, then the list.
+constexpr int FAST_CAP = 1024;
+constexpr int FAST_WORDS = 4 + FAST_CAP;
+constexpr float PAIR_TEST_MARGIN = 1e-5f;
 // A pair's distance changes by at most |d_i| + |d_j| (d: displacements since
 // the build; periodic images move with their bead), which is at most the sum
 // of the two largest displacements of the system.  While that sum stays below

@@ -123,6 +123,7 @@ class Replica:
         self.lists_valid = False
         self.perm = None   # after sort(): original index of the bead at each position
         self.P_out = None  # mean diagonal pressure of the last ensemble call (eV/nm^3)
+        self.pair_test = True  # MD rebuild gate: the pair test (False: the two-largest test alone)
 
     # -- buffers ----------------------------------------------------------------
     def _alloc_lists(self, cap, cap_A):
@@ -272,6 +273,7 @@ class Replica:
             mp.J_trace = None if J_trace is None else J_trace.data_ptr() + 24 * done_total
             con = None if ensemble is None else ensemble.get("constraint")
             mp.constraint = None if con is None else ctypes.pointer(con)
+            mp.plain_skin_test = 0 if self.pair_test else 1
             for d in range(3):
                 mp.P_in[d] = float("nan")
             if ensemble:

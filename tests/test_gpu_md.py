@@ -185,6 +185,71 @@ def test_fast_beads_trigger_early_rebuilds_and_stay_exact():
     compare_efv(rep, ref, system.n, label="hot")
 
 
+def _pairs_missing(rep, rc_R, rc_A):
+    """Pairs inside r_c^R (r_c^A) at the present positions that are not in
+    both beads' rows (angular classes), by brute force; pairs within 1e-5 of
+    a cutoff are left out (float32 rounding decides those)."""
+    from scipy.spatial import cKDTree
+    box = rep.box.astype(np.float64)
+    pos = np.mod(rep.positions(internal=True).astype(np.float64), box)
+    nbr, cnt = rep.neighbor_rows()
+    n = rep.n
+    j = (nbr[:, :n] & 0x1FFFFFF).astype(np.int64)
+    slot = np.arange(nbr.shape[0])[:, None]
+    own = np.arange(n, dtype=np.int64)[None, :] * n
+    keys_R = np.unique((own + j)[slot < cnt[0][None, :n]])
+    keys_A = np.unique((own + j)[slot < cnt[1][None, :n]])
+    tree = cKDTree(pos, boxsize=box)
+    missing = []
+    for rc, keys in ((rc_R, keys_R), (rc_A, keys_A)):
+        pr = tree.query_pairs(rc * (1.0 - 1e-5), output_type="ndarray").astype(np.int64)
+        both = np.isin(pr[:, 0] * n + pr[:, 1], keys) & np.isin(pr[:, 1] * n + pr[:, 0], keys)
+        missing.append(int((~both).sum()))
+    return missing
+
+
+def test_pair_test_gate_rebuilds_later_and_keeps_every_pair():
+    """Three beads ten times faster than the rest set off the two-largest test
+    every few steps.  The pair test then rebuilds only once a pair could come
+    from outside the lists: after every step count of a 40-step run (each from
+    the same start) every pair inside a cutoff is in both rows, the run rebuilds
+    less often than with the two-largest test alone, and its final forces equal
+    those of a fresh build and the oracle's."""
+    from paper_2603_01234_amd import engine as E
+    spec, params, _, opts = W.config0()
+    system = W.water_box(np.random.SeedSequence(77), 16, temperature=300.0)   # 4,096 beads, L = 4.97 nm
+    rng = np.random.default_rng(3)
+    fast = rng.choice(system.n, 3, replace=False)
+    d = rng.normal(size=(3, 3))
+    system.vel[fast] = 0.01 * d / np.linalg.norm(d, axis=1, keepdims=True)      # 10 nm/ps
+    rep = _rep(spec, params, system, opts["skin"])
+    rep.efv()
+    start = rep.snapshot()
+    rebuilds = []
+    for K in range(1, 41):
+        rep.restore(start)
+        rep.md(K, 2.0, [W.WATER_MASS], rebuild_every=1000)
+        assert _pairs_missing(rep, 0.8, 0.5) == [0, 0], f"after {K} steps"
+        rebuilds.append(rep.n_rebuilds)
+    assert rebuilds == sorted(rebuilds)            # the same trajectory, prefix by prefix
+    rep.restore(start)
+    rep.pair_test = False
+    rep.md(40, 2.0, [W.WATER_MASS], rebuild_every=1000)
+    plain = rep.n_rebuilds
+    print("rebuilds in 40 steps: pair test", rebuilds[-1], "two-largest test alone", plain)
+    assert rebuilds[-1] < plain
+    rep.restore(start)
+    rep.pair_test = True
+    rep.md(40, 2.0, [W.WATER_MASS], rebuild_every=1000)
+    fresh = E.Replica(rep.model, rep.positions(internal=True), system.types, system.box, system.pbc,
+                      skin=opts["skin"])
+    fresh.efv()
+    assert float((rep.F - fresh.F).norm() / fresh.F.norm()) < 1e-6
+    fresh.efv()
+    compare_efv(fresh, _oracle_at(fresh, spec, params, system), system.n, check_virial=False,
+                label="pair test, 40 steps")
+
+
 def test_overflow_freezes_then_resumes_bitwise():
     """Rows too short for the run: the call stops at the overflowing rebuild with a
     consistent state, the engine regrows and resumes; the trajectory equals the
