@@ -376,8 +376,10 @@ size_t nep_md_batch_workspace_bytes(int max_active);
  * forces).  One velocity-Verlet step (as nep_md_step, no strain) for each of n_active
  * replicas that share one model, batched: one drift launch over the tiles of
  * every replica, the builds of the replicas that fail the rebuild test of
- * nep_md_step (their two largest displacements add up to more than 0.99 skin) or
- * whose schedule asks for one ((step + 1) % rebuild_every == 0), one fused-
+ * nep_md_step (their two largest displacements add up to more than 0.99 skin;
+ * no pair test, as nep_md_step with plain_skin_test = 1, whose results it
+ * equals bit for bit) or whose schedule asks for one
+ * ((step + 1) % rebuild_every == 0), one fused-
  * kernel launch, one gather launch and one launch of per-replica energy sums.
  * A replica's results depend only on its own state: alone or in any mix they
  * are the same.  E_pot / E_kin: device double [n_active] or NULL.  A replica

@@ -62,7 +62,7 @@ struct TimedLaunch {
 
 struct WsLayout {
     size_t pos4, bvec, angbuf, fown, partial, U, cell_id, cell_count, cell_start, cell_cursor, cell_xyz,
-        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, arow, vh, ctrl, top2, ens, partial2, wbuf, fast, total;
+        cell_list, scan_tmp, cell_tmp, pos_sorted, cls, arow, vh, ctrl, top2, ens, partial2, wbuf, fast, pre, total;
     int ncell_max, nblocks;
 };
 
@@ -108,6 +108,8 @@ WsLayout ws_layout(int T, int n, int cap, int cap_A) {
     L.wbuf = take(nn * 9 * sizeof(float));
     // the pair test of the MD rebuild gate
     L.fast = take(FAST_WORDS * sizeof(int32_t));
+    // the drift workgroups' sums of the gather partials (first level of an MD step's reduction)
+    L.pre = take((nn + BLOCK - 1) / BLOCK * NPART * sizeof(double));
     L.total = off;
     return L;
 }
@@ -1137,6 +1139,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
             // the previous step's reduction runs in the merge kernel
             kd.prev_partial = at<double>(ws, L.partial);
             kd.prev_blocks = L.nblocks;
+            kd.pre = at<double>(ws, L.pre);
             kd.prev_E = E_pot ? E_pot + (k - 1) : nullptr;
             kd.prev_K = E_kin ? E_kin + (k - 1) : nullptr;
             kd.prev_W = mp->W_trace ? mp->W_trace + 9 * (size_t)(k - 1) : nullptr;

@@ -12,6 +12,15 @@ namespace nep {
 __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
     if (a.status[0] & FREEZE_MASK) return;  // lists invalid: leave the state untouched (uniform)
     const int i = blockIdx.x * BLOCK + threadIdx.x;
+    // first level of the previous step's reduction: this workgroup's range of
+    // the gather's block partials, summed in order
+    if (a.prev_partial && threadIdx.x < NPART_NVE) {
+        const int per = (a.prev_blocks + gridDim.x - 1) / gridDim.x;
+        const int b0 = blockIdx.x * per, b1 = min(b0 + per, a.prev_blocks);
+        double acc = 0.0;
+        for (int b = b0; b < b1; ++b) acc += a.prev_partial[(size_t)b * NPART + threadIdx.x];
+        a.pre[(size_t)blockIdx.x * NPART + threadIdx.x] = acc;
+    }
     // the cell counts of a build later in this step start from zero (cleared
     // here rather than by a launch of its own, which every step would pay)
     if (a.cell_count)
@@ -32,16 +41,16 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
     if (threadIdx.x == 0) a.top2[blockIdx.x] = t;
 }
 
-// one workgroup: the previous step's reduction (which also sets the gate to
-// the schedule), then the rebuild test over the pairs of the drift's workgroups
+// one workgroup: the previous step's reduction (second level, over the drift
+// workgroups' sums; it also sets the gate to the schedule), then the rebuild test over the pairs of the drift's workgroups
 // with the affine shrink of the lists' compression factor sigma, updated by
 // this step's scale factors (and reset to 1 when the step rebuilds).  When the
 // test fires and the pair test can decide instead, the gate is 2; the drift's
 // list count is handed to the check and reset for the next step.
 __global__ __launch_bounds__(BLOCK) void k_gate(KickDriftArgs a, int nblocks) {
     if (a.prev_partial)
-        reduce_partials(a.prev_partial, a.prev_blocks, nullptr, nullptr, nullptr, a.prev_E, a.prev_K, a.prev_W,
-                        a.counts, a.status, a.ctrl, a.next_gate);
+        reduce_partials(a.pre, nblocks, nullptr, nullptr, nullptr, a.prev_E, a.prev_K, a.prev_W, a.counts,
+                        a.status, a.ctrl, a.next_gate);
     if (a.status[0] & FREEZE_MASK) return;
     const float2 t = merge_top2(a.top2, nblocks);
     if (threadIdx.x == 0) {

@@ -19,6 +19,7 @@
 //               inside r_c^R, radial shell) and written slot-major into the
 //               list, with its angular part's sort keys row-major
 //   5. order:   the fused kernel's processing order, from the row lengths
+//               (one launch with step 6)
 //   6. reverse: for every angular entry, the mirrored entry is looked up by
 //               its sort key among the neighbour's angular keys
 #include "nep_internal.h"
@@ -648,7 +649,6 @@ __device__ __forceinline__ void nb_order_body(const NbArgs &a, int bx, int gx) {
     if (b < nb) a.order[i0 + rank] = i0 + b;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_nb_order(NbArgs a) { nb_order_body(a, blockIdx.x, gridDim.x); }
 
 // ---- 5. reverse ----
 // REV_GY slot groups per block of beads: the thread of slot group by takes the
@@ -744,8 +744,12 @@ __device__ __forceinline__ void nb_reverse_body(const NbArgs &a, int tile) {
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a) {
-    nb_reverse_body(a, xcd_tile(blockIdx.x, gridDim.x));
+// The reverse search and the processing order in one launch: the first
+// nrev workgroups search (nrev is a multiple of 8, so both parts keep the
+// XCD-aware tile map), the rest rank their blocks of beads.
+__global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a, int nrev) {
+    if ((int)blockIdx.x < nrev) nb_reverse_body(a, xcd_tile(blockIdx.x, nrev));
+    else nb_order_body(a, blockIdx.x - nrev, gridDim.x - nrev);
 }
 
 // The pair test of the rebuild gate (the reasoning is with FAST_WORDS): one
@@ -862,8 +866,8 @@ hipError_t launch_build(const NbArgs &a, hipStream_t s) {
     const size_t lds = row_lds_bytes(a.cap, a.cap_A);
     if (a.T > 1) hipLaunchKernelGGL(k_nb_rows<true>, dim3(a.ncell), dim3(64), lds, s, a);
     else hipLaunchKernelGGL(k_nb_rows<false>, dim3(a.ncell), dim3(64), lds, s, a);
-    if (a.order) hipLaunchKernelGGL(k_nb_order, dim3(nbk), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_nb_reverse, dim3(nbk * REV_GY), dim3(BLOCK), 0, s, a);
+    const int nrev = nbk * REV_GY;
+    hipLaunchKernelGGL(k_nb_reverse, dim3(nrev + (a.order ? nbk : 0)), dim3(BLOCK), 0, s, a, nrev);
     return hipGetLastError();
 }
 

@@ -395,6 +395,8 @@ struct KickDriftArgs {
     // (in place of a reduction launch of their own) into the slots below
     const double *prev_partial;
     int prev_blocks;
+    double *pre;            // [drift workgroups][NPART]: the drift workgroup's sums of consecutive
+                            // ranges of those partials, which the merge kernel then reduces
     double *prev_E, *prev_K, *prev_W, *counts;
     int next_gate;          // the schedule's gate for this step's build
     int32_t *fast;          // or null: the pair test's words (FAST_WORDS); beads whose squared

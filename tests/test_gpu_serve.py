@@ -38,7 +38,8 @@ def _state(r):
 
 def test_batched_step_equals_single_replica_path(serve_small):
     """Every replica stepped 25 times in one batch equals, bitwise, the same
-    replica advanced by nep_md_step (same rebuild decisions, same kernels)."""
+    replica advanced by nep_md_step with the same rebuild test (the two
+    largest displacements, no pair test) and the same kernels."""
     from paper_2603_01234_amd import engine as E
     sw = serve_small
     model = E.Model.from_spec(sw.spec, sw.params)
@@ -49,6 +50,7 @@ def test_batched_step_equals_single_replica_path(serve_small):
         assert all(c == 0 for c in stepper.step(batch))
     single = _reps(sw, model, ids)
     for r in single:
+        r.pair_test = False
         r.md(25, 2.0, [W.WATER_MASS], rebuild_every=10)
     for a, b in zip(batch, single):
         assert a.step == b.step == 25 and a.n_rebuilds == b.n_rebuilds
