@@ -773,7 +773,6 @@ int nep_model_create(const nep_hyper *h, const float *params, size_t n_params, n
         if (!std::isfinite(params[k])) return fail(NEP_ERR_ARG, "non-finite parameter");
     // derived coefficient tables per ordered type pair:
     //   cR'[n][k], cA'[n][k]: k = 0 entry is c_n0 + sum_k c_nk  (f_k = hfc (T_k + 1))
-    //   cA_d[n][k-1] = k c_nk                                    (T_k' = k U_{k-1})
     const size_t D = ND;
     const float *cR = params + (size_t)T * H * D + 2 * (size_t)T * H + 1;
     const float *cA = cR + (size_t)T * T * NR * KB;
@@ -789,15 +788,11 @@ int nep_model_create(const nep_hyper *h, const float *params, size_t n_params, n
             for (int k = 1; k < KB; ++k) o[q * KB + k] = r[q * KB + k];
         }
         float *oa = o + NR * KB;
-        float *od = oa + NA * KB;
         for (int q = 0; q < NA; ++q) {
             double s = 0.0;
             for (int k = 0; k < KB; ++k) s += ang[q * KB + k];
             oa[q * KB] = (float)((double)ang[q * KB] + s);
-            for (int k = 1; k < KB; ++k) {
-                oa[q * KB + k] = ang[q * KB + k];
-                od[q * (KB - 1) + k - 1] = (float)k * ang[q * KB + k];
-            }
+            for (int k = 1; k < KB; ++k) oa[q * KB + k] = ang[q * KB + k];
         }
     }
     // network table per centre type: w0 transposed to [nu][mu], b0, w1, zero-padded
@@ -1132,6 +1127,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         kd.reach = reach;
         kd.fast = fast;
         kd.tau2 = 0.25f * kd.skin_gate * kd.skin_gate;
+        kd.parity = k & 1;
         kd.top2 = at<float2>(ws, L.top2);
         kd.status = nb->status;
         kd.ctrl = ctrl;
@@ -1161,11 +1157,11 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         kd.ncell = a.ncell;
         {
             TimedLaunch tl(3, st);
-            HIPCHK(launch_kick_drift(kd, st));
+            HIPCHK(launch_kick_drift(kd, st, fast == nullptr));
         }
         {
             TimedLaunch tl(2, st);
-            if (fast) HIPCHK(launch_pair_test(a, fast, st));
+            if (fast) HIPCHK(launch_gate_pair_test(kd, a, st));
             HIPCHK(launch_build(a, st));
         }
         // every step evaluates the per-bead and total virial (Eqs. 15-16)

@@ -541,7 +541,10 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
             cheb_T(xA, TA);
             cheb_U(xA, UA);
             const table_ptr<NT> cAp = TB + tp * TAB_PER_PAIR + NR * KB;
-            const table_ptr<NT> cAd = cAp + NA * KB;
+            // T_k' = k U_{k-1}: the derivative takes the same coefficients
+            float dT[KB];
+#pragma unroll
+            for (int k = 1; k < KB; ++k) dT[k] = (float)k * UA[k - 1];
             float gv[NA], gp[NA];
 #pragma unroll
             for (int q = 0; q < NA; ++q) {
@@ -549,7 +552,7 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
 #pragma unroll
                 for (int k = 1; k < KB; ++k) {
                     G += cAp[q * KB + k] * TA[k];
-                    Gp += cAd[q * (KB - 1) + k - 1] * UA[k - 1];
+                    Gp += cAp[q * KB + k] * dT[k];
                 }
                 gv[q] = hA * G;
                 gp[q] = dhA * G + hA * xp * Gp;

@@ -12,6 +12,12 @@ namespace nep {
 __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
     if (a.status[0] & FREEZE_MASK) return;  // lists invalid: leave the state untouched (uniform)
     const int i = blockIdx.x * BLOCK + threadIdx.x;
+    // the pair test's other counter starts the next step from zero, and the
+    // verdict of the last step's test is spent
+    if (a.fast && i == 0) {
+        a.fast[a.parity ^ 1] = 0;
+        a.fast[3] = 0;
+    }
     // first level of the previous step's reduction: this workgroup's range of
     // the gather's block partials, summed in order
     if (a.prev_partial && threadIdx.x < NPART_NVE) {
@@ -33,7 +39,7 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
                              a.pos4, a.ref);
         // a bead past tau joins the pair test's list (past FAST_CAP only counted)
         if (a.fast && d2 >= a.tau2) {
-            const int q = atomicAdd(&a.fast[0], 1);
+            const int q = atomicAdd(&a.fast[a.parity], 1);
             if (q < FAST_CAP) a.fast[4 + q] = i;
         }
     }
@@ -41,40 +47,14 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
     if (threadIdx.x == 0) a.top2[blockIdx.x] = t;
 }
 
-// one workgroup: the previous step's reduction (second level, over the drift
-// workgroups' sums; it also sets the gate to the schedule), then the rebuild test over the pairs of the drift's workgroups
-// with the affine shrink of the lists' compression factor sigma, updated by
-// this step's scale factors (and reset to 1 when the step rebuilds).  When the
-// test fires and the pair test can decide instead, the gate is 2; the drift's
-// list count is handed to the check and reset for the next step.
-__global__ __launch_bounds__(BLOCK) void k_gate(KickDriftArgs a, int nblocks) {
-    if (a.prev_partial)
-        reduce_partials(a.pre, nblocks, nullptr, nullptr, nullptr, a.prev_E, a.prev_K, a.prev_W, a.counts,
-                        a.status, a.ctrl, a.next_gate);
-    if (a.status[0] & FREEZE_MASK) return;
-    const float2 t = merge_top2(a.top2, nblocks);
-    if (threadIdx.x == 0) {
-        const float lmin = fminf(1.0f, fminf(a.lam[0], fminf(a.lam[1], a.lam[2])));
-        const float sig = sigma_of(a.status[3]) * lmin;
-        int listed = 0;
-        if (a.fast) {
-            listed = a.fast[0];
-            a.fast[0] = 0;
-            a.fast[3] = listed;
-        }
-        if (a.ctrl[0] != 1 && past_skin(t, a.skin_gate, (1.0f - sig) * a.reach)) {
-            const bool pair_test = a.fast && sig == 1.0f && a.fast[1] != 0 && listed <= FAST_CAP;
-            a.ctrl[0] = pair_test ? 2 : 1;
-        }
-        a.status[3] = a.ctrl[0] ? SIGMA_ONE : __float_as_int(sig);
-    }
-}
+// one workgroup: the merge kernel (gate_body)
+__global__ __launch_bounds__(BLOCK) void k_gate(KickDriftArgs a, int nblocks) { gate_body(a, nblocks); }
 
-hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s) {
+hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s, bool gate) {
     if (a.n == 0) return hipSuccess;
     const int nb = (a.n + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL(k_kick_drift, dim3(nb), dim3(BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_gate, dim3(1), dim3(BLOCK), 0, s, a, nb);
+    if (gate) hipLaunchKernelGGL(k_gate, dim3(1), dim3(BLOCK), 0, s, a, nb);
     return hipGetLastError();
 }
 

@@ -43,7 +43,14 @@ __device__ __forceinline__ bool build_off(const int32_t *ctrl, const int32_t *st
     if (ctrl && ctrl[0] != 1) return true;
     return !clear_status && (status[0] & FREEZE_MASK);
 }
-__device__ __forceinline__ bool build_off(const NbArgs &a) { return build_off(a.ctrl, a.status, a.clear_status); }
+// Gate 2: the pair test decides (its verdict in fast[3]).
+__device__ __forceinline__ bool build_off(const NbArgs &a) {
+    if (a.ctrl && a.ctrl[0] == 2) {
+        if (!(a.fast && a.fast[3])) return true;
+        return !a.clear_status && (a.status[0] & FREEZE_MASK);
+    }
+    return build_off(a.ctrl, a.status, a.clear_status);
+}
 
 // Every phase of the build is a body taking its block index and block count,
 // so that the same code runs as one kernel per system or as one kernel over
@@ -117,7 +124,7 @@ __device__ __forceinline__ void nb_bin_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
     if (bx == 0 && threadIdx.x == 0) {
         if (a.skip_clear && a.ctrl) a.ctrl[1] += 1;  // the clear phase's count
-        if (a.fast) a.fast[1] = 1;                  // the pair test may use this build's cells
+        if (a.fast) a.fast[2] = 1;                  // the pair test may use this build's cells
     }
     int i = bx * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
@@ -752,14 +759,15 @@ __global__ __launch_bounds__(BLOCK) void k_nb_reverse(NbArgs a, int nrev) {
     else nb_order_body(a, blockIdx.x - nrev, gridDim.x - nrev);
 }
 
-// The pair test of the rebuild gate (the reasoning is with FAST_WORDS): one
-// wavefront per listed bead i.  The lanes take the cells around i's present
-// position in the build's grid (i has moved, the other beads of a pair found
-// this way by less than tau), then the other listed beads.  For every pair
-// now inside an interaction cutoff (with the margin: a pair at the edge
-// counts as inside) the build-time distance, from the build positions with
-// the same image, must lie inside the list cutoff by the margin; otherwise
-// the gate becomes 1 and the build runs.
+// The merge kernel and the pair test of the rebuild gate (the reasoning is
+// with FAST_WORDS) in one launch: workgroup 0 runs the merge kernel's work,
+// the others one wavefront per listed bead i.  The lanes take the cells around
+// i's present position in the build's grid (i has moved, the other beads of a
+// pair found this way by less than tau), then the other listed beads.  For
+// every pair now inside an interaction cutoff (with the margin: a pair at the
+// edge counts as inside) the build-time distance, from the build positions
+// with the same image, must lie inside the list cutoff by the margin;
+// otherwise the verdict word is set, and a gate of 2 becomes a build.
 constexpr int PAIR_TEST_BLOCKS = 64;
 
 __device__ __forceinline__ bool pair_covered(const NbArgs &a, int tp, const float v[3], const float b[3]) {
@@ -772,14 +780,22 @@ __device__ __forceinline__ bool pair_covered(const NbArgs &a, int tp, const floa
     return true;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_pair_test(NbArgs a, const int32_t *fast) {
-    if (a.ctrl[0] != 2 || (a.status[0] & FREEZE_MASK)) return;  // uniform
-    const int cnt = min(fast[3], FAST_CAP);
+__global__ __launch_bounds__(BLOCK) void k_gate_pair_test(KickDriftArgs kd, int nblocks, NbArgs a) {
+    if (blockIdx.x == 0) {
+        gate_body(kd, nblocks);
+        return;
+    }
+    int32_t *fast = kd.fast;
+    // uniform: frozen, no cell data of this call's build yet, or more beads
+    // listed than the list holds (then the gate is 1 in any case)
+    if ((a.status[0] & FREEZE_MASK) || !fast[2]) return;
+    const int cnt = fast[kd.parity];
+    if (cnt > FAST_CAP) return;
     const int lane = __lane_id();
-    const int nw = gridDim.x * (BLOCK / 64);
+    const int nw = (gridDim.x - 1) * (BLOCK / 64);
     const int n = a.n;
     bool bad = false;
-    for (int f = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); f < cnt; f += nw) {
+    for (int f = (blockIdx.x - 1) * (BLOCK / 64) + (threadIdx.x >> 6); f < cnt; f += nw) {
         const int i = fast[4 + f];
         const float4 pi = a.pos4[i];
         const int ti = min((int)pi.w, a.T - 1);
@@ -841,12 +857,13 @@ __global__ __launch_bounds__(BLOCK) void k_pair_test(NbArgs a, const int32_t *fa
             if (!pair_covered(a, ti * a.T + min((int)pj.w, a.T - 1), v, bv)) bad = true;
         }
     }
-    if (bad) a.ctrl[0] = 1;  // every writer stores the same value
+    if (bad) fast[3] = 1;  // every writer stores the same value
 }
 
-hipError_t launch_pair_test(const NbArgs &a, const int32_t *fast, hipStream_t s) {
+hipError_t launch_gate_pair_test(const KickDriftArgs &k, const NbArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pair_test, dim3(PAIR_TEST_BLOCKS), dim3(BLOCK), 0, s, a, fast);
+    const int nb = (a.n + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(k_gate_pair_test, dim3(1 + PAIR_TEST_BLOCKS), dim3(BLOCK), 0, s, k, nb, a);
     return hipGetLastError();
 }
 

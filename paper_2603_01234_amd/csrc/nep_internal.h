@@ -18,7 +18,7 @@ constexpr int ND = NR + NA * 4;  // 37 descriptor components
 constexpr int MAXT = 4;
 constexpr int MAXH = 64;
 constexpr int BLOCK = 256;
-constexpr int TAB_PER_PAIR = NR * KB + NA * KB + NA * (KB - 1);  // 81 + 63 + 56
+constexpr int TAB_PER_PAIR = NR * KB + NA * KB;  // 81 + 63
 constexpr uint32_t J_MASK = 0x1FFFFFFu;
 constexpr int CODE_SHIFT = 25;
 constexpr float ACCEL = 9.648533212e-5f;  // nm/fs^2 per (eV/nm)/amu
@@ -339,9 +339,7 @@ struct NbArgs {
                        // cell data as this call's
 };
 hipError_t launch_build(const NbArgs &a, hipStream_t s);
-// the pair test of the rebuild gate (see FAST_WORDS), on the build's cell data;
-// a no-op unless the gate is 2
-hipError_t launch_pair_test(const NbArgs &a, const int32_t *fast, hipStream_t s);
+
 // Builds of many systems, one launch per phase: args[r] as for launch_build
 // (systems with n > 0); start holds the tables of first blocks written by
 // the caller from nb_batch_tiles; totals are the last entries of the tables.
@@ -401,10 +399,15 @@ struct KickDriftArgs {
     int next_gate;          // the schedule's gate for this step's build
     int32_t *fast;          // or null: the pair test's words (FAST_WORDS); beads whose squared
     float tau2;             // displacement reaches tau2 are listed for it
+    int parity;             // which of the two list counters this step's drift uses
 };
 // the drift, then one workgroup that merges the blocks' pairs and switches
 // the rebuild gate on when they call for a rebuild
-hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s);
+// with gate = false the merge kernel is left to launch_gate_pair_test
+hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s, bool gate = true);
+// the merge kernel of the drift (k) and, in the same launch, the pair test of
+// the rebuild gate (see FAST_WORDS) on the build's cell data (a)
+hipError_t launch_gate_pair_test(const KickDriftArgs &k, const NbArgs &a, hipStream_t s);
 
 // ---- the rebuild test ----
 // Gate values (ctrl[0]): 0 no build, 1 build, 2 the pair test decides (the
@@ -423,8 +426,12 @@ hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t s);
 // list itself.  The test is used only within an MD call whose lists were built
 // by that call, in a fully periodic box with every side at least three times
 // the list reach, without strain or barostat; otherwise the gate is 1.
-// Words: [0] beads listed by this step's drift, [1] cell data of this call's
-// build present, [2] unused, [3] the count the check reads, then the list.
+// The check runs beside the merge kernel (one launch), whenever beads are
+// listed, and leaves its verdict for the build to combine with the gate.
+// Words: [0], [1] beads listed by the drift of steps of even and odd parity
+// (the drift clears the other one for the next step), [2] cell data of this
+// call's build present, [3] a listed pair came from outside the lists (cleared
+// by the drift), then the list.
 constexpr int FAST_CAP = 1024;
 constexpr int FAST_WORDS = 4 + FAST_CAP;
 constexpr float PAIR_TEST_MARGIN = 1e-5f;
@@ -534,6 +541,30 @@ constexpr int32_t SIGMA_ONE = 0x3f800000;  // bits of 1.0f
 // rebuild
 __device__ __forceinline__ bool past_skin(float2 t, float skin_gate, float shrink = 0.0f) {
     return sqrtf(t.x) + sqrtf(t.y) + shrink > skin_gate;
+}
+
+// The merge kernel's work (one workgroup): the previous step's reduction
+// (second level, over the drift workgroups' sums; it also sets the gate to the
+// schedule), then the rebuild test over the pairs of the drift's workgroups
+// with the affine shrink of the lists' compression factor sigma, updated by
+// this step's scale factors (and reset to 1 when the step rebuilds).  When the
+// test fires and the pair test can decide instead, the gate is 2.
+__device__ __forceinline__ void gate_body(const KickDriftArgs &a, int nblocks) {
+    if (a.prev_partial)
+        reduce_partials(a.pre, nblocks, nullptr, nullptr, nullptr, a.prev_E, a.prev_K, a.prev_W, a.counts,
+                        a.status, a.ctrl, a.next_gate);
+    if (a.status[0] & FREEZE_MASK) return;
+    const float2 t = merge_top2(a.top2, nblocks);
+    if (threadIdx.x == 0) {
+        const float lmin = fminf(1.0f, fminf(a.lam[0], fminf(a.lam[1], a.lam[2])));
+        const float sig = sigma_of(a.status[3]) * lmin;
+        if (a.ctrl[0] != 1 && past_skin(t, a.skin_gate, (1.0f - sig) * a.reach)) {
+            const bool pair_test =
+                a.fast && sig == 1.0f && a.fast[2] != 0 && a.fast[a.parity] <= FAST_CAP;
+            a.ctrl[0] = pair_test ? 2 : 1;
+        }
+        a.status[3] = a.ctrl[0] ? SIGMA_ONE : __float_as_int(sig);
+    }
 }
 
 // First half-kick and drift of bead i (kick k = dt/2 ACCEL / m of its type):

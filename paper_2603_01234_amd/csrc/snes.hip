@@ -57,7 +57,7 @@ __global__ void k_derive_tables(DeriveArgs a) {
             } else {
                 v = r[q * KB + k];
             }
-        } else if (o < NR * KB + NA * KB) {
+        } else {
             const int oo = o - NR * KB, q = oo / KB, k = oo % KB;
             if (k == 0) {
                 double s = 0.0;
@@ -66,10 +66,6 @@ __global__ void k_derive_tables(DeriveArgs a) {
             } else {
                 v = ang[q * KB + k];
             }
-        } else {
-            // k c_nk for T_k' = k U_{k-1}
-            const int oo = o - NR * KB - NA * KB, q = oo / (KB - 1), k = oo % (KB - 1) + 1;
-            v = (float)k * ang[q * KB + k];
         }
         tab[e] = v;
     }
