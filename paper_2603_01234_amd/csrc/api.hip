@@ -183,9 +183,18 @@ int check_ws(const Model &M, const nep_system *s, const nep_neighbors *nb, void 
     return NEP_OK;
 }
 
-Cut make_cut(const Model &M) {
+// Lmax: the largest box side of the systems evaluated with the cutoffs.  A
+// pair's separation is formed at each end from coordinates of magnitude up to
+// about Lmax + 1 nm (MD drifts them past the box until the next wrap), with
+// two roundings per component; the two ends differ by at most about
+// 2^-22 (Lmax + 1) per component.  delta takes four times that length, with
+// room for the rounding of the squares.
+Cut make_cut(const Model &M, double Lmax) {
     Cut c{};
+    const double delta = 1e-6 * (Lmax + 1.0) + 1e-6;
     for (int k = 0; k < M.T * M.T; ++k) {
+        const double rw = (double)M.rcA[k] + delta;
+        c.rcA2w[k] = (float)(rw * rw);
         c.rcR[k] = M.rcR[k];
         c.inv_rcR[k] = 1.0f / M.rcR[k];
         c.rcR2[k] = M.rcR[k] * M.rcR[k];
@@ -337,7 +346,7 @@ int launch_efv(const Model &M, const nep_system *s, const nep_neighbors *nb, flo
     a.params = M.d_params;
     a.tab = M.d_tab;
     a.ann = M.d_ann;
-    a.cut = make_cut(M);
+    a.cut = make_cut(M, std::max((double)s->box[0], std::max((double)s->box[1], (double)s->box[2])));
     a.U = U ? U : at<float>(ws, L.U);
     a.bvec = at<float4>(ws, L.bvec);
     a.angbuf = at<float4>(ws, L.angbuf);
@@ -546,7 +555,10 @@ int batch_run(const nep_model *models, int n_models, const nep_system *systems, 
     b.items = at<int4>(ws, P.items);
     b.sys = at<SysDesc>(ws, P.sys);
     b.mod = at<ModelDesc>(ws, P.mod);
-    b.cut = make_cut(models[0]->m);
+    double Lmax = 0.0;
+    for (int k = 0; k < n_systems; ++k)
+        for (int d = 0; d < 3; ++d) Lmax = std::max(Lmax, (double)systems[k].box[d]);
+    b.cut = make_cut(models[0]->m, Lmax);
     b.counter = at<int>(ws, P.counter);
     b.scratch = at<char>(ws, P.scratch);
     b.scratch_stride = P.stride;
@@ -1308,7 +1320,10 @@ int nep_md_step_batch(nep_model model, nep_replica *reps, int n_active, float dt
         b.inv_mass[t] = 1.0f / mass[t];
         b.mass[t] = mass[t];
     }
-    b.cut = make_cut(M);
+    double Lmax = 0.0;
+    for (int r = 0; r < n_active; ++r)
+        for (int d = 0; d < 3; ++d) Lmax = std::max(Lmax, (double)reps[r].sys->box[d]);
+    b.cut = make_cut(M, Lmax);
     b.tab = M.d_tab;
     b.ann = M.d_ann;
     b.E_pot = E_pot;

@@ -564,12 +564,15 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
             oy = s * uy + (vy - uv * uy) * ir;
             oz = s * uz + (vz - uv * uz) * ir;
         }
-        // deliver dU_i/dr_ij to the slot where j lists i; a slot whose mirror
-        // does not exist (rounding at the list edge) is zeroed by its owner
-        if (r >= 0)
-            a.angbuf[r] = make_float4(ox, oy, oz, 0.0f);
-        else
-            a.angbuf[(size_t)p * n + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        // deliver dU_i/dr_ij to the slot where j lists i, for every pair that
+        // j may find inside r_c^A (zero past it); a slot whose mirror does not
+        // exist (rounding at the list edge) is zeroed by its owner
+        if (g.d2 < cut.rcA2w[tp]) {
+            if (r >= 0)
+                a.angbuf[r] = make_float4(ox, oy, oz, 0.0f);
+            else
+                a.angbuf[(size_t)p * n + i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
         fx += ox;
         fy += oy;
         fz += oz;
@@ -669,8 +672,9 @@ __device__ __forceinline__ void gather_bead(const GatherArgs &a, const Cut &cut,
                 W[6] += g.dz * fx; W[7] += g.dz * fy; W[8] += g.dz * fz;
             }
         }
-        if (p < cA) {
-            const float4 fj = a.angbuf[(size_t)p * n + i];  // dU_j/dr_ji, angular part
+        // dU_j/dr_ji, angular part: delivered by j for every pair inside r_c^A
+        if (p < cA && g.d2 < cut.rcA2[tp]) {
+            const float4 fj = a.angbuf[(size_t)p * n + i];
             Fx -= fj.x;
             Fy -= fj.y;
             Fz -= fj.z;

@@ -54,6 +54,12 @@ struct Model {
 struct Cut {
     float rcR[MAXT * MAXT], inv_rcR[MAXT * MAXT], rcR2[MAXT * MAXT];
     float rcA[MAXT * MAXT], inv_rcA[MAXT * MAXT], rcA2[MAXT * MAXT];
+    // (r_c^A + delta)^2: an angular partial is delivered (zero beyond r_c^A)
+    // for every pair its owner finds inside this, and read by the bead at the
+    // other end only for a pair it finds inside r_c^A.  The two ends compute
+    // the pair's distance with different roundings; delta bounds the
+    // difference for coordinates up to the box length (see make_cut).
+    float rcA2w[MAXT * MAXT];
 };
 
 struct EfvArgs {
