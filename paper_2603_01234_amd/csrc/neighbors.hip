@@ -15,10 +15,9 @@
 //               (offset in (dz, dy, dx) order, then cell order), and tests the
 //               cell's beads against them with the lanes over the candidates
 //               (the exact float32 predicate); each row is assembled in LDS by
-//               class (angular inside r_c^A, angular shell in two halves by
-//               distance, radial-only inside r_c^R, radial shell) and written
-//               slot-major into the list, with its angular part's sort keys
-//               row-major
+//               class (angular inside r_c^A, angular shell, radial-only
+//               inside r_c^R, radial shell) and written slot-major into the
+//               list, with its angular part's sort keys row-major
 //   5. order:   the fused kernel's processing order, from the row lengths
 //               (one launch with step 6)
 //   6. reverse: for every angular entry, the mirrored entry is looked up by
@@ -306,11 +305,10 @@ __device__ __forceinline__ bool wrap_cell(int k, int nc, int pbc, int &kw, int &
 // every bead of the cell against them, the lanes over the candidates.  A home
 // bead's entries are appended in LDS in search order with their class (one
 // ballot per 64 candidates and each lane's count of the set bits below it),
-// and written out by class (angular inside r_c^A, the nearer and the farther
-// half of the angular shell, radial-only inside r_c^R, radial shell; search
-// order within a class): slot-major into the list, and the angular keys
-// row-major for the reverse search.  A row is thus the same, entry for entry,
-// as a walk over the cells in that order.
+// and written out by class (angular inside r_c^A, angular shell, radial-only
+// inside r_c^R, radial shell; search order within a class): slot-major into
+// the list, and the angular keys row-major for the reverse search.  A row is
+// thus the same, entry for entry, as a walk over the cells in that order.
 //
 // The key of an entry is its neighbour-cell offset index o (0..W-1 in search
 // order) << 25 | the neighbour's position in cell order; within each class
@@ -324,14 +322,8 @@ constexpr int ROW_OFF = 128;                  // room for the (2m+1)^3 <= 125 of
 constexpr int ROW_HOME = 64;                  // home beads whose positions are staged in LDS
 constexpr uint32_t ZERO_CODE = 62;            // image code of the zero shift, (0+2) + 5 (0+2) + 25 (0+2)
 
-// The angular shell is written nearer half first: the entries that come inside
-// r_c^A as beads move are mostly near its inner edge, and a wave runs its
-// angular work up to the last slot where any of its lanes has a pair inside.
-constexpr float SHELL_SPLIT = 0.5f;
-
 struct RowsLds {
     float4 thr[MAXT * MAXT];  // (list2R, list2A, in2A, in2R) of the type pair
-    float thm[MAXT * MAXT];   // squared boundary between the two halves of the angular shell
     float4 home[ROW_HOME];    // positions and tags of the cell's first beads
     int beg[ROW_OFF];         // first cell-order index of the offset's cell
     int pre[ROW_OFF];         // first flat candidate index of the offset
@@ -522,16 +514,12 @@ __device__ __forceinline__ void row_cell(const NbArgs &a, int c, RowsLds &L, uin
         const float4 th1 = MT ? L.thr[tb + min(1, a.T - 1)] : th0;
         const float4 th2 = MT ? L.thr[tb + min(2, a.T - 1)] : th0;
         const float4 th3 = MT ? L.thr[tb + min(3, a.T - 1)] : th0;
-        const float tm0 = L.thm[tb];
-        const float tm1 = MT ? L.thm[tb + min(1, a.T - 1)] : tm0;
-        const float tm2 = MT ? L.thm[tb + min(2, a.T - 1)] : tm0;
-        const float tm3 = MT ? L.thm[tb + min(3, a.T - 1)] : tm0;
         const uint32_t self = (uint32_t)ih | (ZERO_CODE << CODE_SHIFT);
         // every entry inside the list cutoff in the order found (one ballot
-        // per batch), with its class: 0 angular inside r_c^A, 1 and 2 the
-        // nearer and farther half of the angular shell, 3 radial-only inside
-        // r_c^R, 4 radial shell; the class counts from the same ballots
-        int cnt = 0, n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+        // per batch), with its class: 0 angular inside r_c^A, 1 angular shell,
+        // 2 radial-only inside r_c^R, 3 radial shell; the class counts from
+        // the same ballots
+        int cnt = 0, n0 = 0, n1 = 0, n2 = 0;
         uint64_t overlap = 0;
         for (int base = 0; base < total; base += ROW_WIN) {
             if (base > 0) stage_window(a, L, base, total, cnt2, pre2, -1, nh, C);
@@ -541,7 +529,6 @@ __device__ __forceinline__ void row_cell(const NbArgs &a, int c, RowsLds &L, uin
                 if (64 * k >= nw) break;
                 const uint32_t tj = MT ? (C.types >> (2 * k)) & 3u : 0u;
                 const float4 th = tj == 0 ? th0 : (tj == 1 ? th1 : (tj == 2 ? th2 : th3));
-                const float tm = tj == 0 ? tm0 : (tj == 1 ? tm1 : (tj == 2 ? tm2 : tm3));
                 // the exact predicate, every operation rounded on its own
                 const float ddx = sub_rn(C.x[k], ph.x);
                 const float ddy = sub_rn(C.y[k], ph.y);
@@ -550,25 +537,23 @@ __device__ __forceinline__ void row_cell(const NbArgs &a, int c, RowsLds &L, uin
                 const uint32_t ent = C.ent[k];
                 const uint64_t m_in = __ballot(d2 < th.x) & ~__ballot(ent == self);
                 const uint64_t m_a = __ballot(d2 < th.y), m_ai = __ballot(d2 < th.z), m_ri = __ballot(d2 < th.w);
-                const uint64_t m_am = __ballot(d2 < tm);
                 overlap |= m_in & __ballot(d2 == 0.0f);
                 const bool in = d2 < th.x && ent != self;
-                const uint32_t cl = d2 < th.y ? (d2 < th.z ? 0u : (d2 < tm ? 1u : 2u)) : (d2 < th.w ? 3u : 4u);
+                const uint32_t cl = d2 < th.y ? (d2 < th.z ? 0u : 1u) : (d2 < th.w ? 2u : 3u);
                 const int pos = cnt + bits_below(m_in);
                 const int w = in && pos < cap4 ? pos : trash + lane;
                 rows[w] = make_uint2(ent, C.key[k]);
                 rcls[w] = (uint8_t)cl;
                 cnt += (int)__popcll(m_in);
                 n0 += (int)__popcll(m_in & m_a & m_ai);
-                n1 += (int)__popcll(m_in & m_a & ~m_ai & m_am);
-                n2 += (int)__popcll(m_in & m_a & ~m_ai & ~m_am);
-                n3 += (int)__popcll(m_in & ~m_a & m_ri);
+                n1 += (int)__popcll(m_in & m_a & ~m_ai);
+                n2 += (int)__popcll(m_in & ~m_a & m_ri);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
         if (overlap) flags |= NEP_FLAG_OVERLAP;
         const int nf = min(cnt, cap4);
-        const int nai = n0, na = n0 + n1 + n2, nri = n3, tot = cnt;
+        const int nai = n0, na = n0 + n1, nri = n2, tot = cnt;
         int fl = 0;
         if (na > a.cap_A) fl |= NEP_FLAG_OVERFLOW_A;
         if (tot > a.cap) fl |= NEP_FLAG_OVERFLOW_R;
@@ -585,28 +570,34 @@ __device__ __forceinline__ void row_cell(const NbArgs &a, int c, RowsLds &L, uin
         }
         wave_sync();  // the row is complete
         if (!over) {
-            // the entries in class order (found order within a class), a class at a time
-            int run[5] = {0, nai, nai + n1, na, na + nri};  // next slot of each class
+            // the entries in class order (found order within a class), 64 at a
+            // time: each lane's slot from its class's ballot, then one store
+            // of each kind for the lanes together
+            int run[4] = {0, nai, na, na + nri};  // next slot of each class
             for (int u0 = 0; u0 < nf; u0 += 64) {
                 const bool v = u0 + lane < nf;
-                const int cl = v ? rcls[u0 + lane] : 5;
+                const int cl = v ? rcls[u0 + lane] : 4;
                 const uint2 e = rows[v ? u0 + lane : 0];
+                uint64_t mine = 0;
+                int start = 0;
 #pragma unroll
-                for (int q = 0; q < 5; ++q) {
+                for (int q = 0; q < 4; ++q) {
                     const uint64_t m = __ballot(cl == q);
-                    if (cl == q) {
-                        const int r = run[q] + bits_below(m);  // slot
-                        a.nbr[(size_t)r * n + ih] = e.x;
-                        if (q < 3) {
-                            // angular keys: inside r_c^A up from word 4, the shell
-                            // down from the row's end; the key this bead has in
-                            // the neighbour's row waits in rev
-                            ar[q == 0 ? 4 + r : 4 + A4 - 1 - (r - nai)] = e.y;
-                            a.rev[(size_t)r * n + ih] =
-                                (int32_t)((((uint32_t)(W - 1) - (e.y >> CODE_SHIFT)) << CODE_SHIFT) | (uint32_t)qh);
-                        }
-                    }
+                    mine = cl == q ? m : mine;
+                    start = cl == q ? run[q] : start;
                     run[q] += (int)__popcll(m);
+                }
+                const int r = start + bits_below(mine);  // slot
+                if (v) {
+                    a.nbr[(size_t)r * n + ih] = e.x;
+                    if (cl < 2) {
+                        // angular keys: inside r_c^A up from word 4, the shell
+                        // down from the row's end; the key this bead has in the
+                        // neighbour's row waits in rev
+                        ar[cl == 0 ? 4 + r : 4 + A4 - 1 - (r - nai)] = e.y;
+                        a.rev[(size_t)r * n + ih] =
+                            (int32_t)((((uint32_t)(W - 1) - (e.y >> CODE_SHIFT)) << CODE_SHIFT) | (uint32_t)qh);
+                    }
                 }
             }
         }
@@ -616,12 +607,7 @@ __device__ __forceinline__ void row_cell(const NbArgs &a, int c, RowsLds &L, uin
 
 __device__ __forceinline__ void rows_thresholds(const NbArgs &a, RowsLds &L) {
     const int k = threadIdx.x;
-    if (k < MAXT * MAXT) {
-        L.thr[k] = make_float4(a.list2R[k], a.list2A[k], a.in2A[k], a.in2R[k]);
-        const float ri = sqrtf(a.in2A[k]), rl = sqrtf(a.list2A[k]);
-        const float rm = ri + SHELL_SPLIT * (rl - ri);
-        L.thm[k] = rm * rm;
-    }
+    if (k < MAXT * MAXT) L.thr[k] = make_float4(a.list2R[k], a.list2A[k], a.in2A[k], a.in2R[k]);
 }
 
 // One workgroup (a single wavefront) per cell, consecutive cells on one XCD;
