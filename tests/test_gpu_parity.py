@@ -237,6 +237,35 @@ def test_efv_parity_config2_sampled():
     compare_efv(rep, ref, system.n, targets=targets, label="config2-sampled")
 
 
+def test_partials_are_read_only_where_written():
+    """An angular partial is stored only for a pair its reader may find inside
+    r_c^A, and read only where the reader finds it inside.  With the
+    workspace filled with NaN first, a slot read without a store in the same
+    evaluation turns a force into NaN.  The beads sit in the far corner of a
+    100 nm periodic box, where the two ends' roundings of a separation differ
+    most, at water density (many pairs within 1e-4 nm of r_c^A): forces stay
+    finite and match the oracle, also after MD steps on a NaN-filled
+    workspace."""
+    spec, params, _, opts = W.config0()
+    small = W.water_box(np.random.SeedSequence(101), 10, temperature=300.0)   # 1,000 beads, 3.1 nm
+    L = 100.0
+    pos = small.pos + (L - float(small.box[0]) - 0.1)
+    system = W.System(pos, small.types, np.array([L, L, L]), np.array([True, True, True]), small.masses,
+                      small.vel)
+    rep = _replica(spec, params, system, opts["skin"])
+    rep.build()
+    rep.ws.fill_(255)
+    rep.efv()
+    assert bool(torch.isfinite(rep.F[:, :rep.n]).all()) and bool(torch.isfinite(rep.U[:rep.n]).all())
+    compare_efv(rep, _oracle(spec, params, rep, system), system.n, label="corner of a 100 nm box")
+    rep.ws.fill_(255)
+    rep.md(5, 2.0, [W.WATER_MASS], rebuild_every=10)
+    assert bool(torch.isfinite(rep.F[:, :rep.n]).all()) and bool(torch.isfinite(rep.xyz[:, :rep.n]).all())
+    rep.ws.fill_(255)
+    rep.efv()
+    compare_efv(rep, _oracle(spec, params, rep, system), system.n, label="after 5 MD steps")
+
+
 def test_efv_is_bitwise_deterministic():
     spec, params, system, opts = W.config0()
     rep = _replica(spec, params, system, skin=opts["skin"])
