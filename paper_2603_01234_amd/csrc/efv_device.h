@@ -74,12 +74,14 @@ struct RowStream {
 
 // Slots 0, 1, ... of row i (c entries) in S interleaved sets (slot p belongs
 // to set p mod S), each with its own registers: a set's position is loaded S
-// slots ahead and its entry 2 S slots ahead.  Each load writes the register
-// its previous value was just read from, so the loop carries no register
-// copies: a copy at the back edge waits for the load it copies, which leaves
-// the single-set stream (RowStream) only one slot of look-ahead.  The loads
-// are unconditional and clamped to the row's last entry; body(p, g) runs for
-// slots p < c, in slot order.
+// slots ahead and its entry 2 S slots ahead.  The rounds of S slots are
+// unrolled by two, the entries of even rounds in X and of odd rounds in Y, so
+// each load writes the register whose value was just used (an entry once its
+// pair is decoded and its successor's position issued) and the loop carries
+// no register copies: a copy at the back edge would wait for the load it
+// copies and take the look-ahead away.  The loads are unconditional and
+// clamped to the row's last entry; body(p, g) runs for slots p < c, in slot
+// order.
 template <int S, class Body>
 __device__ __forceinline__ void for_each_slot(const uint32_t *__restrict__ nbr, const float4 *__restrict__ pos4,
                                               int n, int i, int c, const float4 &pi, const float box[3],
@@ -87,25 +89,29 @@ __device__ __forceinline__ void for_each_slot(const uint32_t *__restrict__ nbr, 
     if (c <= 0) return;
     const int last = c - 1;
     auto entry = [&](int p) { return nbr[(size_t)min(p, last) * n + i]; };
-    uint32_t e[S], ahead[S];
+    uint32_t X[S], Y[S];
     float4 P[S];
 #pragma unroll
-    for (int k = 0; k < S; ++k) e[k] = entry(k);
-    // issued in the loop's own order (position, entry; set by set), so the
-    // waits at the loop head are the same from either edge
+    for (int k = 0; k < S; ++k) X[k] = entry(k);
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        P[k] = pos4[e[k] & J_MASK];
-        ahead[k] = entry(S + k);
+        P[k] = pos4[X[k] & J_MASK];
+        Y[k] = entry(S + k);
     }
-    for (int p = 0; p < c; p += S) {
+    for (int p = 0; p < c; p += 2 * S) {
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-            const PairGeom g = geom_of(e[k], P[k], pi, box);
-            e[k] = ahead[k];
-            P[k] = pos4[e[k] & J_MASK];
-            ahead[k] = entry(p + 2 * S + k);
+            const PairGeom g = geom_of(X[k], P[k], pi, box);
+            P[k] = pos4[Y[k] & J_MASK];
+            X[k] = entry(p + 2 * S + k);
             if (k == 0 || p + k < c) body(p + k, g);
+        }
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const PairGeom g = geom_of(Y[k], P[k], pi, box);
+            P[k] = pos4[X[k] & J_MASK];
+            Y[k] = entry(p + 3 * S + k);
+            if (p + S + k < c) body(p + S + k, g);
         }
     }
 }
@@ -447,9 +453,11 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
         for (int l = 0; l < LM; ++l) A[q][l] = 0.0f;
 
     // ---------------- pass 1: descriptor sums ----------------
-    // (five-set stream: the radial-only slots are short, so one slot of
-    // look-ahead does not cover the position loads; 2, 3, 4, 5 and 6 sets
-    // measured 373, 367, 364, 362 and 364 us on a hot 216,000-bead system)
+    // (three-set stream, rounds unrolled by two: the radial-only slots are
+    // short, so one slot of look-ahead does not cover the position loads;
+    // before the unrolling took the back-edge copies away, 2, 3, 4, 5 and 6
+    // sets measured 373, 367, 364, 362 and 364 us on a hot 216,000-bead
+    // system, and with it three and five sets are within 1% of each other)
     auto pass1 = [&](const int p, const PairGeom &g) {
         const int tj = (NT == 1) ? 0 : g.tj;
         const int tp = ti * NT + tj;
@@ -487,7 +495,7 @@ __device__ __forceinline__ void main_bead(const EfvArgs &a, const Cut &cut, cons
             }
         }
     };
-    for_each_slot<5>(a.nbr, a.pos4, n, i, cR, pi, a.box, pass1);
+    for_each_slot<3>(a.nbr, a.pos4, n, i, cR, pi, a.box, pass1);
 
     // ---------------- descriptor, network (Eq. 2), back-propagation ----------------
     // evaluated with a wave-uniform centre type so the weights are scalar loads;
