@@ -185,10 +185,11 @@ def test_fast_beads_trigger_early_rebuilds_and_stay_exact():
     compare_efv(rep, ref, system.n, label="hot")
 
 
-def _pairs_missing(rep, rc_R, rc_A):
+def _pairs_missing(rep, rc_R, rc_A, types=None):
     """Pairs inside r_c^R (r_c^A) at the present positions that are not in
     both beads' rows (angular classes), by brute force; pairs within 1e-5 of
-    a cutoff are left out (float32 rounding decides those)."""
+    a cutoff are left out (float32 rounding decides those).  rc_R, rc_A: one
+    cutoff, or per-type-pair tables with the beads' types."""
     from scipy.spatial import cKDTree
     box = rep.box.astype(np.float64)
     pos = np.mod(rep.positions(internal=True).astype(np.float64), box)
@@ -202,7 +203,13 @@ def _pairs_missing(rep, rc_R, rc_A):
     tree = cKDTree(pos, boxsize=box)
     missing = []
     for rc, keys in ((rc_R, keys_R), (rc_A, keys_A)):
-        pr = tree.query_pairs(rc * (1.0 - 1e-5), output_type="ndarray").astype(np.int64)
+        rc = np.atleast_2d(np.asarray(rc, dtype=np.float64))
+        pr = tree.query_pairs(float(rc.max()) * (1.0 - 1e-5), output_type="ndarray").astype(np.int64)
+        if rc.size > 1:
+            d = pos[pr[:, 1]] - pos[pr[:, 0]]
+            d -= box * np.round(d / box)
+            cut = rc[types[pr[:, 0]], types[pr[:, 1]]] * (1.0 - 1e-5)
+            pr = pr[np.sqrt((d * d).sum(1)) < cut]
         both = np.isin(pr[:, 0] * n + pr[:, 1], keys) & np.isin(pr[:, 1] * n + pr[:, 0], keys)
         missing.append(int((~both).sum()))
     return missing
@@ -248,6 +255,38 @@ def test_pair_test_gate_rebuilds_later_and_keeps_every_pair():
     fresh.efv()
     compare_efv(fresh, _oracle_at(fresh, spec, params, system), system.n, check_virial=False,
                 label="pair test, 40 steps")
+
+
+def test_pair_test_gate_two_types():
+    """The pair test with per-type-pair cutoffs (Au-like and CG-like beads,
+    r_c^R 0.6 / 0.8 / 1.0 nm): after every step count of a 30-step run with
+    three fast beads, every pair inside its cutoffs is in both rows, and the
+    run rebuilds less often than with the two-largest test alone."""
+    rng = np.random.default_rng(21)
+    spec = W.aacg_gold_spec(16)
+    params = W.draw_params(spec, rng)
+    system = W.water_random_sites(rng, 1500, 12.0)          # L = 5.0 nm
+    system.types = rng.integers(0, 2, system.n).astype(np.uint8)
+    masses = [196.967, 787.868]
+    system.vel = W.maxwell_velocities(rng, np.asarray(masses)[system.types], 300.0)
+    fast = rng.choice(system.n, 3, replace=False)
+    d = rng.normal(size=(3, 3))
+    system.vel[fast] = 0.01 * d / np.linalg.norm(d, axis=1, keepdims=True)
+    rep = _rep(spec, params, system, 0.1)
+    rep.efv()
+    start = rep.snapshot()
+    rebuilds = []
+    for K in range(1, 31):
+        rep.restore(start)
+        rep.md(K, 2.0, masses, rebuild_every=1000)
+        assert _pairs_missing(rep, spec.rc_R, spec.rc_A, system.types) == [0, 0], f"after {K} steps"
+        rebuilds.append(rep.n_rebuilds)
+    assert rebuilds == sorted(rebuilds)
+    rep.restore(start)
+    rep.pair_test = False
+    rep.md(30, 2.0, masses, rebuild_every=1000)
+    print("rebuilds in 30 steps: pair test", rebuilds[-1], "two-largest test alone", rep.n_rebuilds)
+    assert rebuilds[-1] < rep.n_rebuilds
 
 
 def test_overflow_freezes_then_resumes_bitwise():
