@@ -251,7 +251,9 @@ typedef struct {
     int rebuild_every;        /* lists are rebuilt after the drift of step s when (s+1) % rebuild_every == 0,
                                  and whenever after a drift the two largest displacements since the build
                                  add up to more than 0.99 skin, unless the pair test (plain_skin_test)
-                                 then finds every pair inside the cutoffs still listed */
+                                 then finds every pair inside the cutoffs still listed; where the pair test
+                                 runs, once the call has built lists the schedule instead rebuilds lists that
+                                 have served rebuild_every steps */
     int force_rebuild;        /* in: rebuild after the first drift whatever the displacement (after the
                                  caller has regrown the lists of a call stopped by an overflow) */
     float mass[4];            /* amu per type */
@@ -294,7 +296,8 @@ typedef struct {
                                  at the build (any other pair moved less than 0.99 skin); found through
                                  the build's cells, so used only after a rebuild within this call, in a
                                  fully periodic box with every side at least 3 (r_c + skin), without
-                                 strain or barostat.  1: the two-largest test alone */
+                                 strain or barostat.  1: the two-largest test alone and the schedule
+                                 by step number */
 } nep_md_params;
 
 /* Advances sys by n_steps of velocity Verlet (the paper's MD runs in an

@@ -1140,6 +1140,7 @@ int nep_md_step(nep_model model, nep_system *s, float *v, nep_md_params *mp, nep
         kd.fast = fast;
         kd.tau2 = 0.25f * kd.skin_gate * kd.skin_gate;
         kd.parity = k & 1;
+        kd.rebuild_every = mp->rebuild_every;
         kd.top2 = at<float2>(ws, L.top2);
         kd.status = nb->status;
         kd.ctrl = ctrl;

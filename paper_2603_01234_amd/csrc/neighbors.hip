@@ -75,7 +75,7 @@ __global__ void k_nb_clear(int ncell, int32_t *cell_count, int32_t *status, int 
 __global__ void k_md_clear(int32_t *status, int32_t *ctrl, int gate0, int32_t *fast) {
     int t = threadIdx.x;
     if (t < 3) status[t] = 0;
-    if (ctrl && t < 4) ctrl[t] = t == 0 ? gate0 : 0;
+    if (ctrl && t < 4) ctrl[t] = t == 0 ? gate0 : (t == 3 ? -1 : 0);  // [3]: no list built by this call yet
     if (fast && t < 4) fast[t] = 0;
 }
 
@@ -124,7 +124,10 @@ __device__ __forceinline__ void nb_bin_body(const NbArgs &a, int bx) {
     if (build_off(a)) return;
     if (bx == 0 && threadIdx.x == 0) {
         if (a.skip_clear && a.ctrl) a.ctrl[1] += 1;  // the clear phase's count
-        if (a.fast) a.fast[2] = 1;                  // the pair test may use this build's cells
+        if (a.fast) {
+            a.fast[2] = 1;  // the pair test may use this build's cells
+            a.ctrl[3] = 0;  // the new lists have served no step yet
+        }
     }
     int i = bx * blockDim.x + threadIdx.x;
     if (i >= a.n) return;

@@ -406,6 +406,8 @@ struct KickDriftArgs {
     int32_t *fast;          // or null: the pair test's words (FAST_WORDS); beads whose squared
     float tau2;             // displacement reaches tau2 are listed for it
     int parity;             // which of the two list counters this step's drift uses
+    int rebuild_every;      // with fast: the largest number of steps a list serves once the call
+                            // has built one (ctrl[3] counts them; before, the schedule's gate)
 };
 // the drift, then one workgroup that merges the blocks' pairs and switches
 // the rebuild gate on when they call for a rebuild
@@ -564,6 +566,12 @@ __device__ __forceinline__ void gate_body(const KickDriftArgs &a, int nblocks) {
     if (threadIdx.x == 0) {
         const float lmin = fminf(1.0f, fminf(a.lam[0], fminf(a.lam[1], a.lam[2])));
         const float sig = sigma_of(a.status[3]) * lmin;
+        // with the pair test, the schedule counts the steps the lists have
+        // served since this call built them (ctrl[3] >= 0 once it has)
+        if (a.fast && a.ctrl[3] >= 0) {
+            a.ctrl[3] += 1;
+            a.ctrl[0] = a.ctrl[3] >= a.rebuild_every ? 1 : 0;
+        }
         if (a.ctrl[0] != 1 && past_skin(t, a.skin_gate, (1.0f - sig) * a.reach)) {
             const bool pair_test =
                 a.fast && sig == 1.0f && a.fast[2] != 0 && a.fast[a.parity] <= FAST_CAP;

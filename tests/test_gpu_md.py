@@ -259,9 +259,10 @@ def test_pair_test_gate_rebuilds_later_and_keeps_every_pair():
 
 def test_pair_test_gate_two_types():
     """The pair test with per-type-pair cutoffs (Au-like and CG-like beads,
-    r_c^R 0.6 / 0.8 / 1.0 nm): after every step count of a 30-step run with
-    three fast beads, every pair inside its cutoffs is in both rows, and the
-    run rebuilds less often than with the two-largest test alone."""
+    r_c^R 0.6 / 0.8 / 1.0 nm) and a schedule of at most 7 steps per list:
+    after every step count of a 30-step run with three fast beads, every pair
+    inside its cutoffs is in both rows, and the run rebuilds less often than
+    with the two-largest test alone and the schedule by step number."""
     rng = np.random.default_rng(21)
     spec = W.aacg_gold_spec(16)
     params = W.draw_params(spec, rng)
@@ -278,13 +279,13 @@ def test_pair_test_gate_two_types():
     rebuilds = []
     for K in range(1, 31):
         rep.restore(start)
-        rep.md(K, 2.0, masses, rebuild_every=1000)
+        rep.md(K, 2.0, masses, rebuild_every=7)
         assert _pairs_missing(rep, spec.rc_R, spec.rc_A, system.types) == [0, 0], f"after {K} steps"
         rebuilds.append(rep.n_rebuilds)
     assert rebuilds == sorted(rebuilds)
     rep.restore(start)
     rep.pair_test = False
-    rep.md(30, 2.0, masses, rebuild_every=1000)
+    rep.md(30, 2.0, masses, rebuild_every=7)
     print("rebuilds in 30 steps: pair test", rebuilds[-1], "two-largest test alone", rep.n_rebuilds)
     assert rebuilds[-1] < rep.n_rebuilds
 
