@@ -489,7 +489,8 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ parti
                                                 double *W_slot, double *counts, const int32_t *status,
                                                 int32_t *ctrl, int next_gate, double *ens = nullptr,
                                                 double inv_n = 0.0) {
-    __shared__ double red[NP][BLOCK];
+    __shared__ double wsum[NP][BLOCK / 64];
+    __shared__ double tot[NP];
     double acc[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) acc[c] = 0.0;
@@ -497,16 +498,25 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ parti
 #pragma unroll
         for (int c = 0; c < NP; ++c) acc[c] += partial[(size_t)b * NPART + c];
     }
+    // a butterfly within each wave (every lane ends with the same sum), then
+    // the waves in order
 #pragma unroll
-    for (int c = 0; c < NP; ++c) red[c][threadIdx.x] = acc[c];
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+    for (int c = 0; c < NP; ++c) {
 #pragma unroll
-            for (int c = 0; c < NP; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
-        }
-        __syncthreads();
+        for (int o = 32; o >= 1; o >>= 1) acc[c] += __shfl_xor(acc[c], o);
     }
+    if (__lane_id() == 0) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c) wsum[c][threadIdx.x >> 6] = acc[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < NP) {
+        double v = wsum[threadIdx.x][0];
+#pragma unroll
+        for (int w = 1; w < BLOCK / 64; ++w) v += wsum[threadIdx.x][w];
+        tot[threadIdx.x] = v;
+    }
+    __syncthreads();
     const int st0 = status ? status[0] : 0;
     if (threadIdx.x == 0 && ctrl) {
         ctrl[0] = next_gate;
@@ -514,20 +524,20 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ parti
     }
     if (st0 & FREEZE_MASK) return;
     if (threadIdx.x == 0) {
-        if (E_tot) *E_tot = red[0][0];
-        if (E_slot) *E_slot = red[0][0];
-        if (K_tot) *K_tot = red[10][0];
-        if (K_slot) *K_slot = red[10][0];
+        if (E_tot) *E_tot = tot[0];
+        if (E_slot) *E_slot = tot[0];
+        if (K_tot) *K_tot = tot[10];
+        if (K_slot) *K_slot = tot[10];
         if (counts) {
-            counts[0] += red[11][0];
-            counts[1] += red[12][0];
+            counts[0] += tot[11];
+            counts[1] += tot[12];
         }
     }
-    if (W_tot && threadIdx.x < 9) W_tot[threadIdx.x] = red[1 + threadIdx.x][0];
-    if (W_slot && threadIdx.x < 9) W_slot[threadIdx.x] = red[1 + threadIdx.x][0];
+    if (W_tot && threadIdx.x < 9) W_tot[threadIdx.x] = tot[1 + threadIdx.x];
+    if (W_slot && threadIdx.x < 9) W_slot[threadIdx.x] = tot[1 + threadIdx.x];
     if constexpr (NP == NPART) {
-        if (ens && threadIdx.x < 3) ens[threadIdx.x] = red[13 + threadIdx.x][0] * inv_n;
-        if (ens && threadIdx.x < 9) ens[3 + threadIdx.x] = red[1 + threadIdx.x][0];
+        if (ens && threadIdx.x < 3) ens[threadIdx.x] = tot[13 + threadIdx.x] * inv_n;
+        if (ens && threadIdx.x < 9) ens[3 + threadIdx.x] = tot[1 + threadIdx.x];
     }
 }
 
@@ -558,6 +568,17 @@ __device__ __forceinline__ bool past_skin(float2 t, float skin_gate, float shrin
 // this step's scale factors (and reset to 1 when the step rebuilds).  When the
 // test fires and the pair test can decide instead, the gate is 2.
 __device__ __forceinline__ void gate_body(const KickDriftArgs &a, int nblocks) {
+    // the words the decision reads, loaded before the reductions so that
+    // their latency overlaps them (no other workgroup writes them meanwhile)
+    int32_t st3 = 0, age = -1, cells = 0, listed = 0;
+    if (threadIdx.x == 0) {
+        st3 = a.status[3];
+        if (a.fast) {
+            age = a.ctrl[3];
+            cells = a.fast[2];
+            listed = a.fast[a.parity];
+        }
+    }
     if (a.prev_partial)
         reduce_partials(a.pre, nblocks, nullptr, nullptr, nullptr, a.prev_E, a.prev_K, a.prev_W, a.counts,
                         a.status, a.ctrl, a.next_gate);
@@ -565,16 +586,15 @@ __device__ __forceinline__ void gate_body(const KickDriftArgs &a, int nblocks) {
     const float2 t = merge_top2(a.top2, nblocks);
     if (threadIdx.x == 0) {
         const float lmin = fminf(1.0f, fminf(a.lam[0], fminf(a.lam[1], a.lam[2])));
-        const float sig = sigma_of(a.status[3]) * lmin;
+        const float sig = sigma_of(st3) * lmin;
         // with the pair test, the schedule counts the steps the lists have
         // served since this call built them (ctrl[3] >= 0 once it has)
-        if (a.fast && a.ctrl[3] >= 0) {
-            a.ctrl[3] += 1;
-            a.ctrl[0] = a.ctrl[3] >= a.rebuild_every ? 1 : 0;
+        if (a.fast && age >= 0) {
+            a.ctrl[3] = age + 1;
+            a.ctrl[0] = age + 1 >= a.rebuild_every ? 1 : 0;
         }
         if (a.ctrl[0] != 1 && past_skin(t, a.skin_gate, (1.0f - sig) * a.reach)) {
-            const bool pair_test =
-                a.fast && sig == 1.0f && a.fast[2] != 0 && a.fast[a.parity] <= FAST_CAP;
+            const bool pair_test = a.fast && sig == 1.0f && cells != 0 && listed <= FAST_CAP;
             a.ctrl[0] = pair_test ? 2 : 1;
         }
         a.status[3] = a.ctrl[0] ? SIGMA_ONE : __float_as_int(sig);
