@@ -257,6 +257,51 @@ def test_pair_test_gate_rebuilds_later_and_keeps_every_pair():
                 label="pair test, 40 steps")
 
 
+def _md_call(rep, n_steps, rebuild_every, force_rebuild, plain_skin_test):
+    """One nep_md_step call (NVE, dt 2 fs) with the rebuild options given;
+    returns the number of builds it made."""
+    from paper_2603_01234_amd import binding as B
+    from paper_2603_01234_amd import engine as E
+    mp = B.MdParams()
+    mp.dt_fs = 2.0
+    mp.n_steps = n_steps
+    mp.rebuild_every = rebuild_every
+    mp.force_rebuild = int(force_rebuild)
+    mp.plain_skin_test = int(plain_skin_test)
+    for t in range(4):
+        mp.mass[t] = W.WATER_MASS
+    for d in range(3):
+        mp.box0[d] = float(rep.box0[d])
+        mp.P_in[d] = float("nan")
+    mp.step = int(rep.step)
+    s, nb = rep.c_system(), rep.c_neighbors()
+    B.check(B.nep_md_step(rep.model.handle, s, rep.v.data_ptr(), mp, nb, rep.F.data_ptr(), rep.U.data_ptr(),
+                          None, None, rep.ws.data_ptr(), rep.ws_bytes, E._stream()))
+    return int(mp.n_rebuilds)
+
+
+def test_schedule_counts_list_age_with_the_pair_test():
+    """A call that starts with a forced build, in a cold 1,728-bead box where
+    no bead comes near half the skin: with the pair test the schedule rebuilds
+    lists that have served rebuild_every = 3 steps (builds after the drifts of
+    steps 0, 3, 6, 9); with the two-largest test alone it rebuilds at the step
+    numbers s with (s + 1) % 3 == 0 (steps 0, 2, 5, 8).  Each count is of a run
+    of K steps from the same start."""
+    spec, params, _, _ = W.config0()
+    system = W.water_box(np.random.SeedSequence(21), 12, temperature=10.0)   # L = 3.7 nm, three list reaches
+    rep = _rep(spec, params, system, 0.1)
+    rep.efv()
+    start = rep.snapshot()
+    by_age, by_step = [], []
+    for K in range(1, 11):
+        rep.restore(start)
+        by_age.append(_md_call(rep, K, 3, True, False))
+        rep.restore(start)
+        by_step.append(_md_call(rep, K, 3, True, True))
+    assert by_step == [1, 1, 2, 2, 2, 3, 3, 3, 4, 4], by_step
+    assert by_age == [1, 1, 1, 2, 2, 2, 3, 3, 3, 4], by_age
+
+
 def test_pair_test_gate_two_types():
     """The pair test with per-type-pair cutoffs (Au-like and CG-like beads,
     r_c^R 0.6 / 0.8 / 1.0 nm) and a schedule of at most 7 steps per list:
