@@ -821,34 +821,62 @@ __global__ __launch_bounds__(BLOCK) void k_gate_pair_test(KickDriftArgs kd, int 
             w[d] = (int)k;
             c[d] = cell_coord(x, a.inv_cs[d], a.nc[d]);
         }
+        // the (2m+1)^3 <= 125 neighbour cells, two per lane (o = lane, lane + 64):
+        // both cells' ranges, then their members four at a time (build records,
+        // then present positions), each set of loads issued together; a lane
+        // past the offsets has empty ranges, and a short run repeats a member
         const int wx = 2 * a.m[0] + 1, wy = 2 * a.m[1] + 1, wz = 2 * a.m[2] + 1;
-        for (int o = lane; o < wx * wy * wz; o += 64) {
+        const int W3 = wx * wy * wz;
+        int beg[2], end[2], img[2][3];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int o = lane + 64 * h < W3 ? lane + 64 * h : 0;
             const int o3[3] = {o % wx - a.m[0], (o / wx) % wy - a.m[1], o / (wx * wy) - a.m[2]};
-            int cc[3], img[3];
+            int cc[3];
             for (int d = 0; d < 3; ++d) {
                 cc[d] = c[d] + o3[d];
-                img[d] = w[d];
-                if (cc[d] < 0) { cc[d] += a.nc[d]; img[d] -= 1; }
-                if (cc[d] >= a.nc[d]) { cc[d] -= a.nc[d]; img[d] += 1; }
+                img[h][d] = w[d];
+                if (cc[d] < 0) { cc[d] += a.nc[d]; img[h][d] -= 1; }
+                if (cc[d] >= a.nc[d]) { cc[d] -= a.nc[d]; img[h][d] += 1; }
             }
             const int id = cell_index(cc[0], cc[1], cc[2], a.nc);
-            const int e = a.cell_start[id + 1];
-            for (int q = a.cell_start[id]; q < e; ++q) {
-                const float4 b = a.pos_sorted[q];  // the build position, and index | type << 25
-                const uint32_t tag = __float_as_uint(b.w);
-                const int j = (int)(tag & J_MASK);
-                if (j == i) continue;
-                const float4 pj = a.pos4[j];
-                const int tp = ti * a.T + min((int)(tag >> CODE_SHIFT), a.T - 1);
-                const float bj[3] = {b.x, b.y, b.z}, qj[3] = {pj.x, pj.y, pj.z};
-                float v[3], bv[3];
-                for (int d = 0; d < 3; ++d) {
-                    const float sh = (float)img[d] * a.box[d];
-                    v[d] = (qj[d] + sh) - p[d];
-                    bv[d] = (bj[d] + sh) - r[d];
+            beg[h] = a.cell_start[id];
+            end[h] = a.cell_start[id + 1];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (lane + 64 * h >= W3) end[h] = beg[h];
+        for (int k = 0; beg[0] + k < end[0] || beg[1] + k < end[1]; k += 4) {
+            float4 b[2][4], pj[2][4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = beg[h] + k + u;
+                    b[h][u] = a.pos_sorted[q < end[h] ? q : (end[h] > beg[h] ? end[h] - 1 : 0)];
                 }
-                if (!pair_covered(a, tp, v, bv)) bad = true;
-            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pj[h][u] = a.pos4[__float_as_uint(b[h][u].w) & J_MASK];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t tag = __float_as_uint(b[h][u].w);  // index | type << 25
+                    const int j = (int)(tag & J_MASK);
+                    if (beg[h] + k + u >= end[h] || j == i) continue;
+                    const int tp = ti * a.T + min((int)(tag >> CODE_SHIFT), a.T - 1);
+                    const float bj[3] = {b[h][u].x, b[h][u].y, b[h][u].z};
+                    const float qj[3] = {pj[h][u].x, pj[h][u].y, pj[h][u].z};
+                    float v[3], bv[3];
+                    for (int d = 0; d < 3; ++d) {
+                        const float sh = (float)img[h][d] * a.box[d];
+                        v[d] = (qj[d] + sh) - p[d];
+                        bv[d] = (bj[d] + sh) - r[d];
+                    }
+                    if (!pair_covered(a, tp, v, bv)) bad = true;
+                }
         }
         // pairs of two listed beads, by the nearest image of their present positions
         for (int g = lane; g < cnt; g += 64) {
