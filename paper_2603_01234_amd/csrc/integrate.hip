@@ -10,41 +10,49 @@ namespace nep {
 
 
 __global__ __launch_bounds__(BLOCK) void k_kick_drift(KickDriftArgs a) {
-    if (a.status[0] & FREEZE_MASK) return;  // lists invalid: leave the state untouched (uniform)
     const int i = blockIdx.x * BLOCK + threadIdx.x;
+    // every read is issued before the freeze test (nothing is written before
+    // it), so that the test's latency overlaps theirs
+    const bool frozen = (a.status[0] & FREEZE_MASK) != 0;
+    int t = 0;
+    BeadIn in{};
+    if (i < a.n) {
+        t = min((int)a.type[i], a.T - 1);
+        in = kick_drift_read(i, a.n, a.x, a.y, a.z, a.v, a.F, a.ref);
+    }
+    // first level of the previous step's reduction: this workgroup's range of
+    // the gather's block partials, summed in order
+    double acc = 0.0;
+    const bool sums = a.prev_partial && threadIdx.x < NPART_NVE;
+    if (sums) {
+        const int per = (a.prev_blocks + gridDim.x - 1) / gridDim.x;
+        const int b0 = blockIdx.x * per, b1 = min(b0 + per, a.prev_blocks);
+        for (int b = b0; b < b1; ++b) acc += a.prev_partial[(size_t)b * NPART + threadIdx.x];
+    }
+    if (frozen) return;  // lists invalid: leave the state untouched (uniform)
     // the pair test's other counter starts the next step from zero, and the
     // verdict of the last step's test is spent
     if (a.fast && i == 0) {
         a.fast[a.parity ^ 1] = 0;
         a.fast[3] = 0;
     }
-    // first level of the previous step's reduction: this workgroup's range of
-    // the gather's block partials, summed in order
-    if (a.prev_partial && threadIdx.x < NPART_NVE) {
-        const int per = (a.prev_blocks + gridDim.x - 1) / gridDim.x;
-        const int b0 = blockIdx.x * per, b1 = min(b0 + per, a.prev_blocks);
-        double acc = 0.0;
-        for (int b = b0; b < b1; ++b) acc += a.prev_partial[(size_t)b * NPART + threadIdx.x];
-        a.pre[(size_t)blockIdx.x * NPART + threadIdx.x] = acc;
-    }
+    if (sums) a.pre[(size_t)blockIdx.x * NPART + threadIdx.x] = acc;
     // the cell counts of a build later in this step start from zero (cleared
     // here rather than by a launch of its own, which every step would pay)
     if (a.cell_count)
         for (int c = i; c < a.ncell; c += gridDim.x * BLOCK) a.cell_count[c] = 0;
     float d2 = 0.0f;
     if (i < a.n) {
-        const int t = min((int)a.type[i], a.T - 1);
         const float k = a.half_dt_accel * a.inv_mass[t];
-        d2 = kick_drift_bead(i, a.n, t, k, a.dt, a.lam[0], a.lam[1], a.lam[2], a.x, a.y, a.z, a.v, a.vh, a.F,
-                             a.pos4, a.ref);
+        d2 = kick_drift_write(in, i, a.n, t, k, a.dt, a.lam[0], a.lam[1], a.lam[2], a.vh, a.pos4, a.ref);
         // a bead past tau joins the pair test's list (past FAST_CAP only counted)
         if (a.fast && d2 >= a.tau2) {
             const int q = atomicAdd(&a.fast[a.parity], 1);
             if (q < FAST_CAP) a.fast[4 + q] = i;
         }
     }
-    const float2 t = block_top2(d2, 0.0f);
-    if (threadIdx.x == 0) a.top2[blockIdx.x] = t;
+    const float2 tt = block_top2(d2, 0.0f);
+    if (threadIdx.x == 0) a.top2[blockIdx.x] = tt;
 }
 
 // one workgroup: the merge kernel (gate_body)

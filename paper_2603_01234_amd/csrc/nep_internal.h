@@ -604,27 +604,40 @@ __device__ __forceinline__ void gate_body(const KickDriftArgs &a, int nblocks) {
 // First half-kick and drift of bead i (kick k = dt/2 ACCEL / m of its type):
 // half-step velocity to vh, new position (scaled by lam) to pos4, build
 // reference scaled in place.  Returns the squared distance from the bead's
-// build position.
-__device__ __forceinline__ float kick_drift_bead(int i, int n, int t, float k, float dt, float l0, float l1,
-                                                 float l2, const float *x, const float *y, const float *z,
-                                                 const float *v, float *vh, const float *F, float4 *pos4,
-                                                 float *ref) {
-    const float vx = v[i] + k * F[i];
-    const float vy = v[n + i] + k * F[n + i];
-    const float vz = v[2 * n + i] + k * F[2 * n + i];
+// build position.  Split into the reads and the rest, so that a caller can
+// issue the reads before a test that decides whether to write.
+struct BeadIn {
+    float x, y, z, vx, vy, vz, fx, fy, fz, rx, ry, rz;
+};
+__device__ __forceinline__ BeadIn kick_drift_read(int i, int n, const float *x, const float *y, const float *z,
+                                                  const float *v, const float *F, const float *ref) {
+    return BeadIn{x[i],     y[i],         z[i],         v[i],   v[n + i],     v[2 * n + i],
+                  F[i],     F[n + i],     F[2 * n + i], ref[i], ref[n + i],   ref[2 * n + i]};
+}
+__device__ __forceinline__ float kick_drift_write(const BeadIn &b, int i, int n, int t, float k, float dt, float l0,
+                                                  float l1, float l2, float *vh, float4 *pos4, float *ref) {
+    const float vx = b.vx + k * b.fx;
+    const float vy = b.vy + k * b.fy;
+    const float vz = b.vz + k * b.fz;
     vh[i] = vx;
     vh[n + i] = vy;
     vh[2 * n + i] = vz;
-    const float px = (x[i] + dt * vx) * l0;
-    const float py = (y[i] + dt * vy) * l1;
-    const float pz = (z[i] + dt * vz) * l2;
-    const float rx = ref[i] * l0, ry = ref[n + i] * l1, rz = ref[2 * n + i] * l2;
+    const float px = (b.x + dt * vx) * l0;
+    const float py = (b.y + dt * vy) * l1;
+    const float pz = (b.z + dt * vz) * l2;
+    const float rx = b.rx * l0, ry = b.ry * l1, rz = b.rz * l2;
     ref[i] = rx;
     ref[n + i] = ry;
     ref[2 * n + i] = rz;
     pos4[i] = make_float4(px, py, pz, (float)t);
     const float dx = px - rx, dy = py - ry, dz = pz - rz;
     return dx * dx + dy * dy + dz * dz;
+}
+__device__ __forceinline__ float kick_drift_bead(int i, int n, int t, float k, float dt, float l0, float l1,
+                                                 float l2, const float *x, const float *y, const float *z,
+                                                 const float *v, float *vh, const float *F, float4 *pos4,
+                                                 float *ref) {
+    return kick_drift_write(kick_drift_read(i, n, x, y, z, v, F, ref), i, n, t, k, dt, l0, l1, l2, vh, pos4, ref);
 }
 
 
